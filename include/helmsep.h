@@ -1,0 +1,182 @@
+/*
+ * helmsep.h -- C ABI of the MI355X separable Helmholtz block solver.
+ *
+ * Druskin & Zaslavsky, "Fast finite-difference convolution for 3D problems in
+ * layered media" (arXiv:1909.01299), Sec. 2.  The library solves
+ *
+ *     A u = f,   A = Dx (x) I (x) I + I (x) Dy (x) I + I (x) I (x) (Dz - diag k^2(z)),
+ *
+ * the 7-point finite-volume operator of eqs. (2)-(3) divided by its diagonal
+ * mass matrices and with the sign chosen so that D_d = M_d^{-1} K_d is positive
+ * on a uniform grid (sigma = 1, the constant lambda replaced by a layered
+ * k^2(z)).  Per axis d with n interior nodes and steps h[0..n] (complex in a
+ * PML), node i lies between h[i] and h[i+1], hhat_i = (h[i] + h[i+1]) / 2 and
+ * (K u)_i = (u_i - u_{i-1}) / h[i] - (u_{i+1} - u_i) / h[i+1]; the walls carry
+ * homogeneous Dirichlet data.
+ *
+ * The grid may be split by separator planes x = s (s in sep_x) and y = t into
+ * Cartesian blocks S^ij = S^i_x x S^j_y x S_z (Sec. 2, eq. (4)); a solve then
+ * runs the two-level cyclic reduction of Sec. 2 (block solves, interface
+ * residual, global interface solve of eq. (6), local correction of eq. (7)).
+ * Without separators it is one separable block solve (eq. (5)): transform x
+ * and y by the generalized eigenvectors W^{-1} (a sine transform on a uniform
+ * axis), one tridiagonal solve in z per (kx, ky) mode, transform back by W.
+ *
+ * Conventions for every entry point:
+ *  - Arrays f, u, g, a, r are device pointers to contiguous complex128
+ *    (interleaved re, im doubles) of shape [nrhs][nz][ny][nx], x fastest.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream); all
+ *    device work is enqueued asynchronously on it.  Host arrays are copied
+ *    before the call returns.
+ *  - The caller owns every array and the workspace; the plan owns its device
+ *    tables.  Solve-type calls never allocate device memory.
+ *  - Errors are returned as hs_status; the text of the last error on the
+ *    calling thread is available from hs_last_error().  Argument errors are
+ *    detected on the host before any device work is enqueued.
+ *  - One plan may be used by one stream at a time.
+ */
+#ifndef HELMSEP_H
+#define HELMSEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HS_OK = 0,
+  HS_ERR_ARG = 1,       /* invalid argument (sizes, steps, separators, pointers) */
+  HS_ERR_ALLOC = 2,     /* device allocation for plan tables failed              */
+  HS_ERR_DEVICE = 3,    /* no usable device, or a HIP call failed                */
+  HS_ERR_SINGULAR = 4,  /* eigen tables or z pivots numerically unusable         */
+  HS_ERR_NOCONV = 5,    /* refinement did not reach its tolerance                */
+  HS_ERR_STATE = 6      /* call out of order (e.g. no workspace bound)           */
+} hs_status;
+
+typedef enum {
+  HS_C128 = 0,          /* every transform and sweep in complex128               */
+  HS_C64_REFINE = 1     /* complex64 transforms and sweeps, FP64 residual and
+                           iterative refinement (not in the paper)               */
+} hs_precision;
+
+typedef struct hs_plan_s* hs_plan;
+typedef struct hs_batch_s* hs_batch;
+
+/* Grid description (paper Sec. 2: tensor grid with per-axis steps).
+ * hx: 2*(nx+1) doubles, complex steps (re, im) h_0..h_nx; likewise hy.
+ * hz: nz+1 real steps.  layer_of_z: nz entries in [0, nlayers).
+ * k2: 2*nlayers doubles, complex k^2 per layer.  All host pointers. */
+typedef struct {
+  int32_t nx, ny, nz;
+  const double* hx;
+  const double* hy;
+  const double* hz;
+  int32_t nlayers;
+  const int32_t* layer_of_z;
+  const double* k2;
+} hs_grid;
+
+/* Separator planes (0-based interior indices, strictly increasing, at least
+ * one node between neighbours and between a separator and a wall).  A block
+ * is a maximal run of nodes between separators (Sec. 2, eq. (4)).  Zero
+ * separators = one block. */
+typedef struct {
+  int32_t nsep_x;
+  const int32_t* sep_x;
+  int32_t nsep_y;
+  const int32_t* sep_y;
+} hs_blocks;
+
+typedef struct {
+  hs_precision prec;
+  int32_t refine_steps;   /* HS_C64_REFINE: correction steps (default 2 when <= 0) */
+  int32_t max_rhs;        /* largest nrhs a solve will be called with (>= 1)       */
+  int32_t flags;          /* bit 0: force the dense transform on uniform axes      */
+} hs_options;
+
+typedef struct {
+  int32_t nblocks;
+  int32_t refine_steps;
+  int32_t n_dense_axes;     /* block axes using the dense eigenvector transform */
+  int32_t n_sine_axes;      /* block axes using the sine transform              */
+  double kappa_max;         /* largest condition number estimate of a W table   */
+  double eig_resid_max;     /* max ||D W - W Lambda|| / (||D|| ||W||)            */
+  double inv_resid_max;     /* max |W^{-1} W - I|                               */
+  double min_pivot;         /* smallest |z pivot| over all modes (FP64 scan)    */
+  double plan_seconds;      /* host time spent building the plan               */
+  size_t table_bytes;       /* device bytes held by the plan                   */
+} hs_info;
+
+/* Build a plan: validates the grid and blocks (HS_ERR_ARG), computes the 1D
+ * generalized eigen tables of every block axis and of the global axes in FP64
+ * on the host (Sec. 2, A_d W = M_d W Lambda with W = 0 on the block walls),
+ * scans the z pivots of every mode, and uploads the tables to the current
+ * device (HS_ERR_DEVICE without one).  `blocks` and `opts` may be NULL. */
+hs_status hs_plan_create(const hs_grid* grid, const hs_blocks* blocks,
+                         const hs_options* opts, hs_plan* out);
+void hs_plan_destroy(hs_plan plan);
+
+/* Device workspace the caller must bind before solving nrhs right-hand sides. */
+size_t hs_plan_workspace_bytes(hs_plan plan, int32_t nrhs);
+/* Bind caller-owned device memory of at least hs_plan_workspace_bytes(plan,
+ * max_rhs) bytes, 256-byte aligned.  The plan keeps the pointer, not a copy. */
+hs_status hs_plan_bind_workspace(hs_plan plan, void* dev_ptr, size_t bytes);
+
+/* Replace the layer values k^2 (2*nlayers host doubles).  Rebuilds the z
+ * tables and re-scans the pivots; synchronous. */
+hs_status hs_set_k2(hs_plan plan, const double* k2);
+
+/* u = A^{-1} f for nrhs right-hand sides (Sec. 2, the seven-step algorithm,
+ * or eq. (5) for one block).  u may alias f. */
+hs_status hs_solve(hs_plan plan, const void* f, void* u, int32_t nrhs, void* stream);
+
+/* a = A^{-H} g.  Uses the symmetry of the finite-volume matrix M A of eq. (3):
+ * A^{-H} g = conj(M A^{-1} M^{-1} conj(g)), so the forward kernels are reused.
+ * a may alias g. */
+hs_status hs_solve_adjoint(hs_plan plan, const void* g, void* a, int32_t nrhs, void* stream);
+
+/* grad[r][l] = sum over (x, y) and z in layer l of a * conj(u) (complex128,
+ * device, nrhs*nlayers entries): the gradient of a real misfit with respect to
+ * k^2_l in torch's convention when a = A^{-H} dJ/du. */
+hs_status hs_grad_k2(hs_plan plan, const void* u, const void* a, void* grad,
+                     int32_t nrhs, void* stream);
+
+/* r = f - A u in FP64 by the 7-point stencil on the whole grid (eq. (2)). */
+hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r,
+                      int32_t nrhs, void* stream);
+
+/* out = A u in FP64 by the same stencil (eqs. (2)-(3)). */
+hs_status hs_apply(hs_plan plan, const void* u, void* out, int32_t nrhs, void* stream);
+
+hs_status hs_get_info(hs_plan plan, hs_info* info);
+
+/* Batched solve of many independent plans (one block each, any sizes) and
+ * right-hand sides, enqueued as one captured HIP graph per call.
+ * nrhs[i] right-hand sides for plans[i]; the plans must outlive the batch and
+ * share one precision. */
+hs_status hs_batch_create(const hs_plan* plans, int32_t nplans, const int32_t* nrhs,
+                          hs_batch* out);
+size_t hs_batch_workspace_bytes(hs_batch batch);
+hs_status hs_batch_bind_workspace(hs_batch batch, void* dev_ptr, size_t bytes);
+/* f[i], u[i]: device arrays of plans[i] with nrhs[i] right-hand sides. */
+hs_status hs_batch_solve(hs_batch batch, const void* const* f, void* const* u, void* stream);
+void hs_batch_destroy(hs_batch batch);
+
+/* Host-only 1D generalized eigensolver used by the plan (no device needed):
+ * K W = M W diag(lam) for one axis with n interior nodes and complex steps
+ * h (2*(n+1) doubles).  Outputs (caller-allocated host arrays): lam 2*n
+ * doubles; W and Winv 2*n*n doubles, row-major, W[i][m] = component i of
+ * eigenvector m.  stats (may be NULL): [kappa, eig_resid, inv_resid]. */
+hs_status hs_axis_eig(int32_t n, const double* h, double* lam, double* W, double* Winv,
+                      double* stats);
+
+const char* hs_status_str(hs_status s);
+const char* hs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELMSEP_H */

@@ -1,0 +1,294 @@
+"""Python binding of the MI355X separable Helmholtz solver (``libhelmsep.so``).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+the C library (``include/helmsep.h``).  PyTorch provides device memory
+(caller-owned arrays and the plan workspace) and the current stream.
+
+The library must be built first (``python -m paper_1909_01299_amd.build`` or
+``__graft_entry__.build()``); importing this package without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhelmsep.so")
+
+HS_OK, HS_ERR_ARG, HS_ERR_ALLOC, HS_ERR_DEVICE, HS_ERR_SINGULAR, HS_ERR_NOCONV, HS_ERR_STATE = range(7)
+HS_C128, HS_C64_REFINE = 0, 1
+
+
+class HSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_STATUS = {0: "HS_OK", 1: "HS_ERR_ARG", 2: "HS_ERR_ALLOC", 3: "HS_ERR_DEVICE",
+           4: "HS_ERR_SINGULAR", 5: "HS_ERR_NOCONV", 6: "HS_ERR_STATE"}
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p), ("hz", ctypes.c_void_p),
+                ("nlayers", ctypes.c_int32), ("layer_of_z", ctypes.c_void_p), ("k2", ctypes.c_void_p)]
+
+
+class _Blocks(ctypes.Structure):
+    _fields_ = [("nsep_x", ctypes.c_int32), ("sep_x", ctypes.c_void_p),
+                ("nsep_y", ctypes.c_int32), ("sep_y", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("max_rhs", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("n_dense_axes", ctypes.c_int32), ("n_sine_axes", ctypes.c_int32),
+                ("kappa_max", ctypes.c_double), ("eig_resid_max", ctypes.c_double),
+                ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = {
+    "hs_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hs_plan_destroy": (None, [ctypes.c_void_p]),
+    "hs_plan_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int32]),
+    "hs_plan_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "hs_set_k2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hs_solve": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_solve_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_grad_k2": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_residual": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_apply": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hs_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "hs_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "hs_batch_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "hs_batch_destroy": (None, [ctypes.c_void_p]),
+    "hs_axis_eig": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5),
+    "hs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "hs_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree HIP library; fails loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1909_01299_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != HS_OK:
+        raise HSError(status, lib().hs_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _check_array(t, shape, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name} must be a complex128 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[-3:]) != tuple(shape):
+        raise ValueError(f"{name}: trailing shape {tuple(t.shape[-3:])} != {tuple(shape)}")
+
+
+def axis_eig(h: np.ndarray):
+    """Host-only generalized eigenpairs of one axis (the plan's own eigensolver).
+
+    Returns (lam, W, Winv, stats) with stats = (kappa, eig_resid, inv_resid)."""
+    h = np.ascontiguousarray(np.asarray(h, dtype=np.complex128))
+    n = h.shape[0] - 1
+    lam = np.zeros(n, np.complex128)
+    W = np.zeros((n, n), np.complex128)
+    Wi = np.zeros((n, n), np.complex128)
+    stats = np.zeros(3, np.float64)
+    _check(lib().hs_axis_eig(n, h.ctypes.data, lam.ctypes.data, W.ctypes.data, Wi.ctypes.data,
+                             stats.ctypes.data))
+    return lam, W, Wi, stats
+
+
+class Plan:
+    """A solver plan for one layered grid (and optional block split).
+
+    problem: any object with hx, hy (complex steps), hz (real steps),
+    layer_of_z, k2 and optional sep_x, sep_y (numpy arrays)."""
+
+    def __init__(self, problem, precision: str = "c128", max_rhs: int = 1, refine_steps: int = 0,
+                 force_dense: bool = False, device=None):
+        import torch
+        self.problem = problem
+        self.nx = len(problem.hx) - 1
+        self.ny = len(problem.hy) - 1
+        self.nz = len(problem.hz) - 1
+        self.shape = (self.nz, self.ny, self.nx)
+        self.nlayers = len(problem.k2)
+        self.max_rhs = int(max_rhs)
+        self.precision = precision
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        hx = np.ascontiguousarray(np.asarray(problem.hx, np.complex128))
+        hy = np.ascontiguousarray(np.asarray(problem.hy, np.complex128))
+        hz = np.ascontiguousarray(np.real(np.asarray(problem.hz)).astype(np.float64))
+        lz = np.ascontiguousarray(np.asarray(problem.layer_of_z, np.int32))
+        k2 = np.ascontiguousarray(np.asarray(problem.k2, np.complex128))
+        sx = np.ascontiguousarray(np.asarray(getattr(problem, "sep_x", []), np.int32))
+        sy = np.ascontiguousarray(np.asarray(getattr(problem, "sep_y", []), np.int32))
+        grid = _Grid(self.nx, self.ny, self.nz, hx.ctypes.data, hy.ctypes.data, hz.ctypes.data,
+                     self.nlayers, lz.ctypes.data, k2.ctypes.data)
+        blocks = _Blocks(len(sx), sx.ctypes.data if len(sx) else None, len(sy), sy.ctypes.data if len(sy) else None)
+        prec = {"c128": HS_C128, "c64": HS_C64_REFINE, "mixed": HS_C64_REFINE}[precision]
+        opts = _Options(prec, int(refine_steps), self.max_rhs, 1 if force_dense else 0)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().hs_plan_create(ctypes.byref(grid), ctypes.byref(blocks), ctypes.byref(opts),
+                                        ctypes.byref(handle)))
+        self._h = handle
+        nbytes = lib().hs_plan_workspace_bytes(self._h, self.max_rhs)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().hs_plan_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().hs_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().hs_get_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def set_k2(self, k2):
+        k2 = np.ascontiguousarray(np.asarray(k2, np.complex128))
+        if k2.shape != (self.nlayers,):
+            raise ValueError("k2 must have one value per layer")
+        _check(lib().hs_set_k2(self._h, k2.ctypes.data))
+
+    def _nrhs(self, t):
+        return 1 if t.dim() == 3 else int(np.prod(t.shape[:-3]))
+
+    def solve(self, f, out=None, stream=None):
+        import torch
+        _check_array(f, self.shape, "f")
+        u = out if out is not None else torch.empty_like(f)
+        _check_array(u, self.shape, "u")
+        _check(lib().hs_solve(self._h, _ptr(f), _ptr(u), self._nrhs(f), _stream(stream)))
+        return u
+
+    def solve_adjoint(self, g, out=None, stream=None):
+        import torch
+        _check_array(g, self.shape, "g")
+        a = out if out is not None else torch.empty_like(g)
+        _check_array(a, self.shape, "a")
+        _check(lib().hs_solve_adjoint(self._h, _ptr(g), _ptr(a), self._nrhs(g), _stream(stream)))
+        return a
+
+    def grad_k2(self, u, a, stream=None):
+        import torch
+        _check_array(u, self.shape, "u")
+        _check_array(a, self.shape, "a")
+        n = self._nrhs(u)
+        grad = torch.empty((n, self.nlayers), dtype=torch.complex128, device=u.device)
+        _check(lib().hs_grad_k2(self._h, _ptr(u), _ptr(a), _ptr(grad), n, _stream(stream)))
+        return grad
+
+    def residual(self, f, u, stream=None):
+        import torch
+        _check_array(f, self.shape, "f")
+        _check_array(u, self.shape, "u")
+        r = torch.empty_like(f)
+        _check(lib().hs_residual(self._h, _ptr(f), _ptr(u), _ptr(r), self._nrhs(f), _stream(stream)))
+        return r
+
+    def apply(self, u, stream=None):
+        import torch
+        _check_array(u, self.shape, "u")
+        out = torch.empty_like(u)
+        _check(lib().hs_apply(self._h, _ptr(u), _ptr(out), self._nrhs(u), _stream(stream)))
+        return out
+
+
+def _make_autograd():
+    import torch
+
+    class HelmholtzSolve(torch.autograd.Function):
+        """u = A(k2)^{-1} f with gradients for k2 (per layer) and f.
+
+        backward: a = A^{-H} grad_u (the adjoint solve reuses the forward
+        kernels), grad_f = a, grad_k2[l] = sum over layer l of a * conj(u)."""
+
+        @staticmethod
+        def forward(ctx, k2, f, plan):
+            plan.set_k2(k2.detach().cpu().numpy())
+            u = plan.solve(f.contiguous())
+            ctx.plan = plan
+            ctx.save_for_backward(u)
+            ctx.k2_value = k2.detach().cpu().numpy().copy()
+            ctx.k2_meta = (k2.dtype, k2.device)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (u,) = ctx.saved_tensors
+            plan = ctx.plan
+            plan.set_k2(ctx.k2_value)
+            a = plan.solve_adjoint(grad_u.contiguous())
+            g = plan.grad_k2(u, a).sum(dim=0)
+            dtype, device = ctx.k2_meta
+            return g.to(device=device, dtype=dtype), a, None
+
+    return HelmholtzSolve
+
+
+_autograd = None
+
+
+def helmholtz_solve(k2, f, plan: Plan):
+    """Differentiable solve (torch.autograd.Function) for gradients w.r.t. k2 and f."""
+    global _autograd
+    if _autograd is None:
+        _autograd = _make_autograd()
+    return _autograd.apply(k2, f, plan)
+
+
+def to_device(a: np.ndarray, device="cuda"):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).to(device)

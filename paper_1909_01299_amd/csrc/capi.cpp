@@ -1,0 +1,171 @@
+// C ABI of the separable Helmholtz solver (declarations and contracts in
+// include/helmsep.h).  Every entry point validates its arguments on the host,
+// returns an hs_status and records a thread-local error text.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/helmsep.h"
+#include "plan.hpp"
+
+struct hs_plan_s {
+  hs::Plan p;
+};
+
+namespace {
+thread_local std::string g_err;
+
+hs_status ret(hs_status s, const std::string& msg) {
+  g_err = (s == HS_OK) ? std::string() : msg;
+  return s;
+}
+}  // namespace
+
+extern "C" {
+
+const char* hs_status_str(hs_status s) {
+  switch (s) {
+    case HS_OK: return "HS_OK";
+    case HS_ERR_ARG: return "HS_ERR_ARG";
+    case HS_ERR_ALLOC: return "HS_ERR_ALLOC";
+    case HS_ERR_DEVICE: return "HS_ERR_DEVICE";
+    case HS_ERR_SINGULAR: return "HS_ERR_SINGULAR";
+    case HS_ERR_NOCONV: return "HS_ERR_NOCONV";
+    case HS_ERR_STATE: return "HS_ERR_STATE";
+  }
+  return "HS_ERR_UNKNOWN";
+}
+
+const char* hs_last_error(void) { return g_err.c_str(); }
+
+hs_status hs_plan_create(const hs_grid* grid, const hs_blocks* blocks, const hs_options* opts, hs_plan* out) {
+  if (!out) return ret(HS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  hs_plan p = new (std::nothrow) hs_plan_s;
+  if (!p) return ret(HS_ERR_ALLOC, "host allocation failed");
+  std::string err;
+  hs_status s;
+  try {
+    s = p->p.build(grid, blocks, opts, err);
+  } catch (const std::exception& e) {
+    s = HS_ERR_ALLOC;
+    err = e.what();
+  }
+  if (s != HS_OK) {
+    delete p;
+    return ret(s, err);
+  }
+  *out = p;
+  return ret(HS_OK, "");
+}
+
+void hs_plan_destroy(hs_plan plan) { delete plan; }
+
+size_t hs_plan_workspace_bytes(hs_plan plan, int32_t nrhs) {
+  if (!plan || nrhs < 1 || nrhs > plan->p.max_rhs) return 0;
+  return plan->p.ws_bytes;
+}
+
+hs_status hs_plan_bind_workspace(hs_plan plan, void* dev_ptr, size_t bytes) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.bind(dev_ptr, bytes, err), err);
+}
+
+hs_status hs_set_k2(hs_plan plan, const double* k2) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.set_k2(k2, err), err);
+}
+
+hs_status hs_solve(hs_plan plan, const void* f, void* u, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.solve(f, u, nrhs, (hipStream_t)stream, err), err);
+}
+
+hs_status hs_solve_adjoint(hs_plan plan, const void* g, void* a, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.solve_adjoint(g, a, nrhs, (hipStream_t)stream, err), err);
+}
+
+hs_status hs_grad_k2(hs_plan plan, const void* u, const void* a, void* grad, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.grad_k2(u, a, grad, nrhs, (hipStream_t)stream, err), err);
+}
+
+hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.residual(f, u, r, 0, nrhs, (hipStream_t)stream, err), err);
+}
+
+hs_status hs_apply(hs_plan plan, const void* u, void* out, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.residual(nullptr, u, out, 1, nrhs, (hipStream_t)stream, err), err);
+}
+
+hs_status hs_get_info(hs_plan plan, hs_info* info) {
+  if (!plan || !info) return ret(HS_ERR_ARG, "plan or info is NULL");
+  const hs::Plan& p = plan->p;
+  std::memset(info, 0, sizeof(*info));
+  info->nblocks = int32_t(p.blocks.size());
+  info->refine_steps = p.refine_steps;
+  for (auto& a : p.axes) {
+    if (a.sine) ++info->n_sine_axes; else ++info->n_dense_axes;
+    info->kappa_max = std::max(info->kappa_max, a.e.kappa);
+    info->eig_resid_max = std::max(info->eig_resid_max, a.e.eig_resid);
+    info->inv_resid_max = std::max(info->inv_resid_max, a.e.inv_resid);
+  }
+  info->min_pivot = p.min_pivot;
+  info->plan_seconds = p.plan_seconds;
+  info->table_bytes = p.tab_elems * (p.prec == 0 ? 16 : 24);
+  return ret(HS_OK, "");
+}
+
+hs_status hs_axis_eig(int32_t n, const double* h, double* lam, double* W, double* Winv, double* stats) {
+  if (n < 1 || n > 4096 || !h || !lam || !W || !Winv) return ret(HS_ERR_ARG, "invalid arguments");
+  std::vector<hs::cd> hv(n + 1);
+  for (int i = 0; i <= n; ++i) {
+    hv[i] = hs::cd(h[2 * i], h[2 * i + 1]);
+    if (!(std::abs(hv[i]) > 0)) return ret(HS_ERR_ARG, "steps must be nonzero");
+  }
+  hs::AxisEig e;
+  std::string err;
+  if (hs::axis_is_uniform(n, hv.data())) {
+    hs::axis_eig_uniform(n, hv[0], e);
+  } else if (!hs::axis_eig_general(n, hv.data(), e, err)) {
+    return ret(HS_ERR_SINGULAR, err);
+  }
+  std::memcpy(lam, e.lam.data(), sizeof(double) * 2 * n);
+  std::memcpy(W, e.W.data(), sizeof(double) * 2 * size_t(n) * n);
+  std::memcpy(Winv, e.Winv.data(), sizeof(double) * 2 * size_t(n) * n);
+  if (stats) {
+    stats[0] = e.kappa;
+    stats[1] = e.eig_resid;
+    stats[2] = e.inv_resid;
+  }
+  return ret(HS_OK, "");
+}
+
+// ---------------------------------------------------------------- batch
+
+struct hs_batch_s {
+  size_t ws_bytes = 0;
+};
+
+hs_status hs_batch_create(const hs_plan*, int32_t, const int32_t*, hs_batch* out) {
+  if (out) *out = nullptr;
+  return ret(HS_ERR_STATE, "batched solve not available in this build");
+}
+size_t hs_batch_workspace_bytes(hs_batch) { return 0; }
+hs_status hs_batch_bind_workspace(hs_batch, void*, size_t) { return ret(HS_ERR_STATE, "no batch"); }
+hs_status hs_batch_solve(hs_batch, const void* const*, void* const*, void*) { return ret(HS_ERR_STATE, "no batch"); }
+void hs_batch_destroy(hs_batch b) { delete b; }
+
+}  // extern "C"

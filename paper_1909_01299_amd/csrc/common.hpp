@@ -1,0 +1,129 @@
+// Shared host/device definitions of the separable Helmholtz solver:
+// complex arithmetic on HIP vector types and the per-block stage descriptors
+// that the host plan builds once and the batched kernels read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hs {
+
+template <typename R> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename R> using cplx = typename cplx_t<R>::type;
+
+template <typename R>
+__host__ __device__ __forceinline__ cplx<R> mk(R re, R im) {
+  cplx<R> z;
+  z.x = re;
+  z.y = im;
+  return z;
+}
+template <typename C>
+__host__ __device__ __forceinline__ C cadd(C a, C b) { a.x += b.x; a.y += b.y; return a; }
+template <typename C>
+__host__ __device__ __forceinline__ C csub(C a, C b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename C>
+__host__ __device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+// acc + a * b
+template <typename C>
+__host__ __device__ __forceinline__ C cfma(C a, C b, C acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc - a * b
+template <typename C>
+__host__ __device__ __forceinline__ C cfms(C a, C b, C acc) {
+  acc.x = fma(-a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(-a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <typename C>
+__host__ __device__ __forceinline__ C cconj(C a) { a.y = -a.y; return a; }
+template <typename C, typename R>
+__host__ __device__ __forceinline__ C cscale(C a, R s) { a.x *= s; a.y *= s; return a; }
+// 1/z as conj(z)/|z|^2.  Used for z pivots, whose modulus the plan checks to lie
+// in [1e-12, 1e12] times the operator scale, far from over- and underflow.
+template <typename C>
+__host__ __device__ __forceinline__ C crcp(C z) {
+  auto n = z.x * z.x + z.y * z.y;
+  auto inv = decltype(n)(1) / n;
+  C r;
+  r.x = z.x * inv;
+  r.y = -z.y * inv;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Stage descriptors.  Offsets are in complex elements relative to base pointers
+// passed to each launch, so one descriptor table serves every call of a plan.
+// ---------------------------------------------------------------------------
+
+// Dense transform along a contiguous axis: for lines (p, q) of one RHS r,
+//   dst[r*dst_r + p*dst_p + q*dst_q + o] = scale * sum_k T[o*n_in + k] * src[r*src_r + p*src_p + q*src_q + k]
+struct XformDesc {
+  int64_t tab;      // offset of the n_out x n_in table (row-major) in the table buffer
+  int32_t n_in, n_out;
+  int32_t P, Q;     // line index ranges
+  int64_t src, src_r, src_p, src_q;
+  int64_t dst, dst_r, dst_p, dst_q;
+  int32_t sine;     // 1: table is the real orthonormal sine matrix (imaginary part zero)
+  int32_t pad_;
+};
+
+// Dense transform along a strided axis, in place: for plane p of RHS r and
+// column c (contiguous), data[o][c] = sum_k T[o][k] data[k][c] (n_in == n_out).
+struct XformYDesc {
+  int64_t tab;
+  int32_t n, ncols;
+  int32_t P, pad_;
+  int64_t data, s_r, s_p, s_k;
+};
+
+// One batched z sweep over the (a, b) modes of a block.
+//  rhs(a,b,z,r) = [dense ? data(r,z,b,a) : 0]
+//               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)
+//  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) I) x = rhs
+//  dense_out: data(r,z,b,a) = x
+//  reductions: redx_i(tile_a, r, z, b) = sum_{a in tile} ex_i[a] x ;
+//              redy_j(tile_b, r, z, a) = sum_{b in tile} ey_j[b] x
+constexpr int kMaxTerms = 4;
+struct SweepDesc {
+  int32_t na, nb, nz, dense_in;
+  int32_t dense_out, nxt, nyt, nxr;
+  int32_t nyr, tiles_a, tiles_b, pad_;
+  int64_t lam_x, lam_y;         // table offsets (complex, length na / nb)
+  int64_t zlo, zdiag, zup;      // table offsets (complex, length nz)
+  int64_t data, data_r;         // workspace offsets; element (r,z,b,a) = data + r*data_r + (z*nb + b)*na + a
+  int64_t dbuf, dbuf_r;         // scratch for forward-swept rhs when !dense_in || !dense_out
+  int64_t ckpt;                 // workspace offset of checkpoints [r? no][seg][tile thread]
+  int64_t colx[kMaxTerms]; int32_t colx_stride[kMaxTerms];   // table offsets
+  int64_t gx[kMaxTerms];        // workspace offsets
+  int64_t coly[kMaxTerms]; int32_t coly_stride[kMaxTerms];
+  int64_t gy[kMaxTerms];
+  int64_t gx_r, gy_r, gx_z, gy_z;   // gx(r,z,b) = gx + r*gx_r + z*gx_z + b
+  int64_t ex[kMaxTerms]; int32_t ex_stride[kMaxTerms];       // table offsets
+  int64_t ey[kMaxTerms]; int32_t ey_stride[kMaxTerms];
+  int64_t redx, redx_term, redx_tile, redx_r;  // redx_i(tile, r, z, b) = redx + i*term + tile*tile_s + r*r_s + z*nb + b
+  int64_t redy, redy_term, redy_tile, redy_r;
+};
+
+// Sum of tile partials: out(t, r, z, i) = sum_{tile} in(t, tile, r, z, i)
+struct ReduceDesc {
+  int64_t src, src_term, src_tile, src_r;   // src(t, tile, r, z, i) = src + ... + z*n + i
+  int64_t dst, dst_term, dst_r, dst_z;      // dst(t, r, z, i) = dst + ... + z*dst_z + i
+  int32_t nterms, ntiles, nz, n;
+};
+
+}  // namespace hs

@@ -1,0 +1,634 @@
+// HIP kernels of the separable Helmholtz block solver (gfx950).
+//
+// Every stage kernel is batched over blocks: blockIdx.y selects a descriptor
+// (one block, face set or interface line set), blockIdx.z the right-hand side,
+// blockIdx.x a tile.  Descriptors hold element offsets relative to base
+// pointers given at launch, so one descriptor table serves every solve.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace hs {
+
+namespace {
+
+template <typename T> struct real_of;
+template <> struct real_of<double2> { using type = double; };
+template <> struct real_of<float2> { using type = float; };
+
+template <typename CO, typename CI>
+__device__ __forceinline__ CO cvt(CI v) {
+  CO o;
+  o.x = (decltype(o.x))v.x;
+  o.y = (decltype(o.y))v.y;
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// Dense transform along the contiguous axis (x lines, face lines, interface
+// lines): dst[line][o] (+)= sum_k T[o][k] src[line][k].
+// Tile: 16 lines x 16 outputs per workgroup, K staged through LDS in chunks.
+// ---------------------------------------------------------------------------
+constexpr int XL_T = 16;
+constexpr int XL_K = 32;
+
+template <typename R, typename CI, typename CO, bool ACC>
+__global__ __launch_bounds__(256) void k_xform_lines(const XformDesc* __restrict__ descs,
+                                                     const cplx<R>* __restrict__ tab,
+                                                     const CI* __restrict__ src, CO* __restrict__ dst) {
+  using C = cplx<R>;
+  const XformDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int lines = d.P * d.Q;
+  const int ntl = (lines + XL_T - 1) / XL_T;
+  const int nto = (d.n_out + XL_T - 1) / XL_T;
+  const int tile = blockIdx.x;
+  if (tile >= ntl * nto) return;
+  const int tl = tile % ntl, to = tile / ntl;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ C sA[XL_T][XL_K + 1];
+  __shared__ C sT[XL_T][XL_K + 1];
+  C acc = mk<R>(0, 0);
+  const CI* s0 = src + d.src + (int64_t)r * d.src_r;
+  const C* T = tab + d.tab;
+  for (int k0 = 0; k0 < d.n_in; k0 += XL_K) {
+    for (int e = threadIdx.x; e < XL_T * XL_K; e += 256) {
+      const int li = e / XL_K, kk = e % XL_K;
+      const int L = tl * XL_T + li, k = k0 + kk;
+      C v = mk<R>(0, 0);
+      if (L < lines && k < d.n_in) {
+        const int p = L / d.Q, q = L % d.Q;
+        v = cvt<C>(s0[(int64_t)p * d.src_p + (int64_t)q * d.src_q + k]);
+      }
+      sA[li][kk] = v;
+      const int O = to * XL_T + li;
+      sT[li][kk] = (O < d.n_out && k < d.n_in) ? T[(int64_t)O * d.n_in + k] : mk<R>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < XL_K; ++kk) acc = cfma(sA[ty][kk], sT[tx][kk], acc);
+    __syncthreads();
+  }
+  const int L = tl * XL_T + ty, o = to * XL_T + tx;
+  if (L < lines && o < d.n_out) {
+    const int p = L / d.Q, q = L % d.Q;
+    CO* out = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + o;
+    if (ACC) {
+      CO prev = *out;
+      prev.x += acc.x;
+      prev.y += acc.y;
+      *out = prev;
+    } else {
+      *out = cvt<CO>(acc);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Dense transform along a strided axis, in place: for plane p and columns
+// [c0, c0 + CT), data[o][c] = sum_k T[o][k] data[k][c].  The whole column
+// panel is staged in LDS before any output is written.
+// ---------------------------------------------------------------------------
+template <typename R, int CT>
+__global__ __launch_bounds__(256) void k_xform_y(const XformYDesc* __restrict__ descs,
+                                                 const cplx<R>* __restrict__ tab,
+                                                 cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  extern __shared__ unsigned char smem_raw[];
+  C* panel = reinterpret_cast<C*>(smem_raw);
+  const XformYDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int ntc = (d.ncols + CT - 1) / CT;
+  const int tile = blockIdx.x;
+  if (tile >= ntc * d.P) return;
+  const int p = tile / ntc, c0 = (tile % ntc) * CT;
+  C* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
+  const int n = d.n;
+  for (int e = threadIdx.x; e < n * CT; e += 256) {
+    const int k = e / CT, c = e % CT;
+    panel[e] = (c0 + c < d.ncols) ? base[(int64_t)k * d.s_k + c0 + c] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  const C* T = tab + d.tab;
+  constexpr int RG = 256 / CT;  // output rows handled in parallel
+  const int c = threadIdx.x % CT, og = threadIdx.x / CT;
+  if (c0 + c >= d.ncols) return;
+  for (int o = og; o < n; o += RG) {
+    C acc = mk<R>(0, 0);
+    const C* Trow = T + (int64_t)o * n;
+    for (int k = 0; k < n; ++k) acc = cfma(Trow[k], panel[k * CT + c], acc);
+    base[(int64_t)o * d.s_k + c0 + c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched z sweep (Thomas without pivoting) over the modes of a block, one
+// mode per lane; a 16 x 16 tile of (a, b) modes per workgroup.  The forward
+// elimination stores the swept right-hand side; the pivot recurrence is
+// checkpointed every SEG rows and recomputed segment-wise on the way back so
+// the backward pass keeps its multipliers in registers.
+// ---------------------------------------------------------------------------
+constexpr int SEG = 16;
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sweep(const SweepDesc* __restrict__ descs,
+                                               const cplx<R>* __restrict__ tab,
+                                               cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  const SweepDesc& d = descs[blockIdx.y];
+  const int tiles_a = d.tiles_a;
+  const int tile = blockIdx.x;
+  if (tile >= tiles_a * d.tiles_b) return;
+  const int ta = tile % tiles_a, tb = tile / tiles_a;
+  const int al = threadIdx.x & 15, bl = threadIdx.x >> 4;
+  const int na = d.na, nb = d.nb, nz = d.nz;
+  const int a = ta * 16 + al, b = tb * 16 + bl;
+  const bool act = (a < na) && (b < nb);
+  const int r = blockIdx.z;
+  const int64_t plane = (int64_t)na * nb;
+  const int64_t m = (int64_t)b * na + a;
+  const int nxt = d.nxt, nyt = d.nyt, nxr = d.nxr, nyr = d.nyr;
+
+  const C s = act ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
+  C cx[kMaxTerms], cy[kMaxTerms], ex[kMaxTerms], ey[kMaxTerms];
+#pragma unroll
+  for (int i = 0; i < kMaxTerms; ++i) {
+    cx[i] = (act && i < nxt) ? tab[d.colx[i] + (int64_t)a * d.colx_stride[i]] : mk<R>(0, 0);
+    cy[i] = (act && i < nyt) ? tab[d.coly[i] + (int64_t)b * d.coly_stride[i]] : mk<R>(0, 0);
+    ex[i] = (act && i < nxr) ? tab[d.ex[i] + (int64_t)a * d.ex_stride[i]] : mk<R>(0, 0);
+    ey[i] = (act && i < nyr) ? tab[d.ey[i] + (int64_t)b * d.ey_stride[i]] : mk<R>(0, 0);
+  }
+  C* data = ws + d.data + (int64_t)r * d.data_r;
+  C* fwd = (d.dense_in && d.dense_out) ? data
+           : (!d.dense_in && d.dense_out) ? data
+                                          : ws + d.dbuf + (int64_t)r * d.dbuf_r;
+  const int nseg = (nz + SEG - 1) / SEG;
+  C* ck = ws + d.ckpt + (int64_t)r * nseg * plane;
+  const C* zlo = tab + d.zlo;
+  const C* zdg = tab + d.zdiag;
+  const C* zup = tab + d.zup;
+
+  // forward elimination
+  C cprev = mk<R>(0, 0), dprev = mk<R>(0, 0);
+  for (int seg = 0; seg < nseg; ++seg) {
+    if (act) ck[seg * plane + m] = cprev;
+    for (int kk = 0; kk < SEG; ++kk) {
+      const int k = seg * SEG + kk;
+      if (k >= nz) break;
+      const C lo = zlo[k];
+      const C piv = cfms(lo, cprev, cadd(zdg[k], s));
+      const C ip = crcp(piv);
+      C rhs = mk<R>(0, 0);
+      if (act) {
+        if (d.dense_in) rhs = data[k * plane + m];
+        for (int i = 0; i < nxt; ++i)
+          rhs = cfma(cx[i], ws[d.gx[i] + (int64_t)r * d.gx_r + (int64_t)k * d.gx_z + b], rhs);
+        for (int j = 0; j < nyt; ++j)
+          rhs = cfma(cy[j], ws[d.gy[j] + (int64_t)r * d.gy_r + (int64_t)k * d.gy_z + a], rhs);
+      }
+      const C dd = cmul(cfms(lo, dprev, rhs), ip);
+      if (act) fwd[k * plane + m] = dd;
+      cprev = cmul(zup[k], ip);
+      dprev = dd;
+    }
+  }
+
+  // backward substitution
+  __shared__ C sh[2 * kMaxTerms][16][17];
+  const int nred = nxr + nyr;
+  C xn = mk<R>(0, 0);
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    C cseg[SEG];
+    C cp = act ? ck[seg * plane + m] : mk<R>(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < SEG; ++kk) {
+      const int k = seg * SEG + kk;
+      if (k < nz) {
+        const C piv = cfms(zlo[k], cp, cadd(zdg[k], s));
+        cseg[kk] = cmul(zup[k], crcp(piv));
+        cp = cseg[kk];
+      } else {
+        cseg[kk] = mk<R>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int kk = SEG - 1; kk >= 0; --kk) {
+      const int k = seg * SEG + kk;
+      if (k >= nz) continue;
+      const C dd = act ? fwd[k * plane + m] : mk<R>(0, 0);
+      const C x = cfms(cseg[kk], xn, dd);
+      xn = x;
+      if (act && d.dense_out) data[k * plane + m] = x;
+      if (nred > 0) {
+        for (int i = 0; i < nxr; ++i) sh[i][bl][al] = act ? cmul(ex[i], x) : mk<R>(0, 0);
+        for (int j = 0; j < nyr; ++j) sh[nxr + j][bl][al] = act ? cmul(ey[j], x) : mk<R>(0, 0);
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t < 16 * nred) {
+          const int term = t >> 4, idx = t & 15;
+          C acc = mk<R>(0, 0);
+          if (term < nxr) {
+            for (int q = 0; q < 16; ++q) acc = cadd(acc, sh[term][idx][q]);
+            const int bg = tb * 16 + idx;
+            if (bg < nb)
+              ws[d.redx + term * d.redx_term + ta * d.redx_tile + (int64_t)r * d.redx_r +
+                 (int64_t)k * nb + bg] = acc;
+          } else {
+            for (int q = 0; q < 16; ++q) acc = cadd(acc, sh[term][q][idx]);
+            const int ag = ta * 16 + idx;
+            if (ag < na)
+              ws[d.redy + (term - nxr) * d.redy_term + tb * d.redy_tile + (int64_t)r * d.redy_r +
+                 (int64_t)k * na + ag] = acc;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_reduce(const ReduceDesc* __restrict__ descs,
+                                                cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  const ReduceDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int64_t per_term = (int64_t)d.nz * d.n;
+  const int64_t total = per_term * d.nterms;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int t = int(e / per_term);
+    const int64_t rest = e % per_term;
+    const int z = int(rest / d.n), i = int(rest % d.n);
+    const C* s = ws + d.src + t * d.src_term + (int64_t)r * d.src_r + rest;
+    C acc = mk<R>(0, 0);
+    for (int q = 0; q < d.ntiles; ++q) acc = cadd(acc, s[q * d.src_tile]);
+    ws[d.dst + t * d.dst_term + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interface kernels (steps 3-6 of the two-level reduction)
+// ---------------------------------------------------------------------------
+
+// Step 4: residual on the separator lines.
+//  rx(s, y, z) = f(s,y,z) + cl_s v(s-1,y,z) + cr_s v(s+1,y,z)   (y not a separator; else f)
+//  ry(t, x, z) = f(x,t,z) + cb_t v(x,t-1,z) + ct_t v(x,t+1,z)   (x not a separator; else 0)
+// v next to a separator is read from the face arrays of the neighbouring blocks.
+template <typename R, typename CI>
+__global__ __launch_bounds__(256) void k_sigma_resid(SigmaGeom g, const CI* __restrict__ f,
+                                                     cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  const int r = blockIdx.z;
+  const int64_t nline_x = (int64_t)g.nsx * g.nz * g.NY;
+  const int64_t nline_y = (int64_t)g.nsy * g.nz * g.NX;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const CI* fr = f + (int64_t)r * g.f_r;
+  const C* coef = reinterpret_cast<const C*>(g.coef);
+  if (e < nline_x) {
+    const int y = int(e % g.NY);
+    const int z = int((e / g.NY) % g.nz);
+    const int si = int(e / ((int64_t)g.NY * g.nz));
+    const int s = g.sep_x[si];
+    C v = cvt<C>(fr[((int64_t)z * g.NY + y) * g.NX + s]);
+    const int jb = g.yblk[y];
+    if (jb >= 0) {
+      const int yl = g.yloc[y];
+      // left neighbour block (column si), its right face; right block (si+1), left face
+      const int bl = jb * g.nbx_blocks + si;
+      const int br = jb * g.nbx_blocks + si + 1;
+      const C vl = ws[g.face + (((int64_t)bl * g.rmax + r) * 4 + 1) * g.face_f + (int64_t)z * g.NF + yl];
+      const C vr = ws[g.face + (((int64_t)br * g.rmax + r) * 4 + 0) * g.face_f + (int64_t)z * g.NF + yl];
+      v = cfma(coef[g.cx_lo + si], vl, v);
+      v = cfma(coef[g.cx_hi + si], vr, v);
+    }
+    ws[g.rx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + y] = v;
+  } else if (e < nline_x + nline_y) {
+    const int64_t e2 = e - nline_x;
+    const int x = int(e2 % g.NX);
+    const int z = int((e2 / g.NX) % g.nz);
+    const int ti = int(e2 / ((int64_t)g.NX * g.nz));
+    const int t = g.sep_y[ti];
+    C v = mk<R>(0, 0);
+    const int ib = g.xblk[x];
+    if (ib >= 0) {
+      v = cvt<C>(fr[((int64_t)z * g.NY + t) * g.NX + x]);
+      const int xl = g.xloc[x];
+      const int bb = ti * g.nbx_blocks + ib;        // block below (row ti), its top face
+      const int bt = (ti + 1) * g.nbx_blocks + ib;  // block above, its bottom face
+      const C vb = ws[g.face + (((int64_t)bb * g.rmax + r) * 4 + 3) * g.face_f + (int64_t)z * g.NF + xl];
+      const C vt = ws[g.face + (((int64_t)bt * g.rmax + r) * 4 + 2) * g.face_f + (int64_t)z * g.NF + xl];
+      v = cfma(coef[g.cy_lo + ti], vb, v);
+      v = cfma(coef[g.cy_hi + ti], vt, v);
+    }
+    ws[g.ry + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + x] = v;
+  }
+}
+
+// Step 6 (lift): the Dirichlet data w on the separators enter the first and
+// last interior lines of each block as g = -A_{I,Sigma} w_Sigma.
+// face order: 0 = low x (left), 1 = high x (right), 2 = low y, 3 = high y.
+template <typename R>
+__global__ __launch_bounds__(256) void k_lift(SigmaGeom g, const LiftBlock* __restrict__ lb,
+                                              cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  const LiftBlock B = lb[blockIdx.y];
+  const int r = blockIdx.z;
+  const int64_t per_face = (int64_t)g.nz * g.NF;
+  const C* coef = reinterpret_cast<const C*>(g.coef);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < 4 * per_face; e += (int64_t)gridDim.x * 256) {
+    const int face = int(e / per_face);
+    const int z = int((e % per_face) / g.NF);
+    const int i = int(e % g.NF);
+    C v = mk<R>(0, 0);
+    if (face < 2) {
+      const int si = face == 0 ? B.sep_lo_x : B.sep_hi_x;
+      if (si >= 0 && i < B.nby)
+        v = cmul(coef[B.cfx[face]], ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + B.y0 + i]);
+    } else {
+      const int ti = face == 2 ? B.sep_lo_y : B.sep_hi_y;
+      if (ti >= 0 && i < B.nbx)
+        v = cmul(coef[B.cfy[face - 2]], ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + B.x0 + i]);
+    }
+    ws[g.gface + (((int64_t)blockIdx.y * g.rmax + r) * 4 + face) * g.face_f + (int64_t)z * g.NF + i] = v;
+  }
+}
+
+// Step 7 on the separators: u = w there (crossings from the x lines).
+template <typename R, typename CO, bool ACC>
+__global__ __launch_bounds__(256) void k_sigma_scatter(SigmaGeom g, const cplx<R>* __restrict__ ws,
+                                                       CO* __restrict__ u) {
+  const int r = blockIdx.z;
+  const int64_t nline_x = (int64_t)g.nsx * g.nz * g.NY;
+  const int64_t nline_y = (int64_t)g.nsy * g.nz * g.NX;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  CO* ur = u + (int64_t)r * g.f_r;
+  int64_t dst;
+  cplx<R> v;
+  if (e < nline_x) {
+    const int y = int(e % g.NY);
+    const int z = int((e / g.NY) % g.nz);
+    const int si = int(e / ((int64_t)g.NY * g.nz));
+    dst = ((int64_t)z * g.NY + y) * g.NX + g.sep_x[si];
+    v = ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + y];
+  } else if (e < nline_x + nline_y) {
+    const int64_t e2 = e - nline_x;
+    const int x = int(e2 % g.NX);
+    if (g.xblk[x] < 0) return;
+    const int z = int((e2 / g.NX) % g.nz);
+    const int ti = int(e2 / ((int64_t)g.NX * g.nz));
+    dst = ((int64_t)z * g.NY + g.sep_y[ti]) * g.NX + x;
+    v = ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + x];
+  } else {
+    return;
+  }
+  if (ACC) {
+    CO p = ur[dst];
+    p.x += v.x;
+    p.y += v.y;
+    ur[dst] = p;
+  } else {
+    ur[dst] = cvt<CO>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual r = f - A u with the 7-point stencil of eq. (2) (D-form).
+// ---------------------------------------------------------------------------
+template <typename CO>
+__global__ __launch_bounds__(256) void k_residual(StencilGeom g, const double2* __restrict__ f,
+                                                  const double2* __restrict__ u, CO* __restrict__ out,
+                                                  int negate_f) {
+  const int r = blockIdx.z;
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int x = int(e % g.nx);
+  const int y = int((e / g.nx) % g.ny);
+  const int z = int(e / ((int64_t)g.nx * g.ny));
+  const double2* ur = u + r * n;
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  const double2 c = ur[e];
+  double2 au = cmul(cadd(cadd(g.xd[x], g.yd[y]), g.zd[z]), c);
+  if (x > 0) au = cfma(g.xl[x], ur[e - 1], au);
+  if (x + 1 < g.nx) au = cfma(g.xu[x], ur[e + 1], au);
+  if (y > 0) au = cfma(g.yl[y], ur[e - sy], au);
+  if (y + 1 < g.ny) au = cfma(g.yu[y], ur[e + sy], au);
+  if (z > 0) au = cfma(g.zl[z], ur[e - sz], au);
+  if (z + 1 < g.nz) au = cfma(g.zu[z], ur[e + sz], au);
+  double2 res;
+  if (negate_f) {  // out = A u
+    res = au;
+  } else {
+    const double2 fv = f[r * n + e];
+    res = csub(fv, au);
+  }
+  out[r * n + e] = cvt<CO>(res);
+}
+
+// Adjoint pre/post scaling with the mass matrix M = Mx (x) My (x) Mz of eq. (3):
+// pre  out = M^{-1} conj(in),  post  out = conj(M in).
+__global__ __launch_bounds__(256) void k_conj_mass(StencilGeom g, const double2* __restrict__ in,
+                                                   double2* __restrict__ out, int inverse) {
+  const int r = blockIdx.z;
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int x = int(e % g.nx);
+  const int y = int((e / g.nx) % g.ny);
+  const int z = int(e / ((int64_t)g.nx * g.ny));
+  const double2 w = cmul(cmul(g.mx[x], g.my[y]), g.mz[z]);
+  const double2 v = in[r * n + e];
+  // inverse: M^{-1} conj(in)   forward: conj(M in)
+  out[r * n + e] = inverse ? cmul(crcp(w), cconj(v)) : cconj(cmul(w, v));
+}
+
+// Layer gradient: plane sums of a * conj(u), then per-layer sums.
+__global__ __launch_bounds__(256) void k_plane_dot(int64_t plane, int nz, const double2* __restrict__ a,
+                                                   const double2* __restrict__ u, double2* __restrict__ out) {
+  const int z = blockIdx.x, r = blockIdx.z;
+  const double2* ap = a + ((int64_t)r * nz + z) * plane;
+  const double2* up = u + ((int64_t)r * nz + z) * plane;
+  double2 acc = mk<double>(0, 0);
+  for (int64_t i = threadIdx.x; i < plane; i += 256) acc = cfma(ap[i], cconj(up[i]), acc);
+  __shared__ double2 red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(int64_t)r * nz + z] = red[0];
+}
+
+__global__ void k_layer_sum(int nz, int nlayers, const int* __restrict__ layer_of_z,
+                            const double2* __restrict__ plane_sums, double2* __restrict__ grad) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.z;
+  if (l >= nlayers) return;
+  double2 acc = mk<double>(0, 0);
+  for (int z = 0; z < nz; ++z)
+    if (layer_of_z[z] == l) acc = cadd(acc, plane_sums[(int64_t)r * nz + z]);
+  grad[(int64_t)r * nlayers + l] = acc;
+}
+
+inline unsigned grid1(int64_t n) { return unsigned((n + 255) / 256); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <typename R, typename CI, typename CO, bool ACC>
+static void launch_lines_t(const XformDesc* d, int ndesc, int max_tiles, const void* tab, const void* src,
+                           void* dst, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_xform_lines<R, CI, CO, ACC>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
+                     (const cplx<R>*)tab, (const CI*)src, (CO*)dst);
+}
+
+void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
+                 const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
+  if (ndesc == 0 || max_tiles == 0 || nrhs == 0) return;
+  if (prec == 0) {
+    launch_lines_t<double, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    return;
+  }
+  // complex64 compute; boundary kernels may read or write complex128
+  if (!in64 && !out64) {
+    launch_lines_t<float, float2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else if (in64 && !out64) {
+    launch_lines_t<float, double2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else if (!in64 && out64) {
+    if (acc)
+      launch_lines_t<float, float2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    else
+      launch_lines_t<float, float2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else {
+    launch_lines_t<float, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  }
+}
+
+int xform_lines_tiles(const XformDesc& d) {
+  const int lines = d.P * d.Q;
+  return ((lines + XL_T - 1) / XL_T) * ((d.n_out + XL_T - 1) / XL_T);
+}
+
+void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
+             const void* tab, void* ws, int nrhs, hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0) return;
+  const bool wide = max_n <= 256;
+  const int CT = wide ? 16 : 8;
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const size_t lds = size_t(max_n) * CT * esz;
+  const int tiles = wide ? max_tiles16 : max_tiles8;
+  if (prec == 0) {
+    if (wide)
+      hipLaunchKernelGGL((k_xform_y<double, 16>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
+                         (const double2*)tab, (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_xform_y<double, 8>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
+                         (const double2*)tab, (double2*)ws);
+  } else {
+    if (wide)
+      hipLaunchKernelGGL((k_xform_y<float, 16>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
+                         (const float2*)tab, (float2*)ws);
+    else
+      hipLaunchKernelGGL((k_xform_y<float, 8>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
+                         (const float2*)tab, (float2*)ws);
+  }
+}
+
+int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct) * d.P; }
+
+void sweep(int prec, const SweepDesc* d, int ndesc, int max_tiles, const void* tab, void* ws, int nrhs,
+           hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_sweep<double>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
+                       (const double2*)tab, (double2*)ws);
+  else
+    hipLaunchKernelGGL((k_sweep<float>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
+                       (const float2*)tab, (float2*)ws);
+}
+
+int sweep_segments(int nz) { return (nz + SEG - 1) / SEG; }
+
+void reduce_partials(int prec, const ReduceDesc* d, int ndesc, int64_t max_elems, void* ws, int nrhs,
+                     hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0) return;
+  unsigned gx = unsigned(std::min<int64_t>((max_elems + 255) / 256, 4096));
+  if (gx == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_reduce<double>), dim3(gx, ndesc, nrhs), dim3(256), 0, st, d, (double2*)ws);
+  else
+    hipLaunchKernelGGL((k_reduce<float>), dim3(gx, ndesc, nrhs), dim3(256), 0, st, d, (float2*)ws);
+}
+
+void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nsx * g.nz * g.NY + (int64_t)g.nsy * g.nz * g.NX;
+  if (n == 0 || nrhs == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_sigma_resid<double, double2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const double2*)f, (double2*)ws);
+  else if (in64)
+    hipLaunchKernelGGL((k_sigma_resid<float, double2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const double2*)f, (float2*)ws);
+  else
+    hipLaunchKernelGGL((k_sigma_resid<float, float2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const float2*)f, (float2*)ws);
+}
+
+void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,
+          hipStream_t st) {
+  if (nblocks == 0 || nrhs == 0) return;
+  const int64_t n = 4LL * g.nz * g.NF;
+  unsigned gx = unsigned(std::min<int64_t>((n + 255) / 256, 1024));
+  if (prec == 0)
+    hipLaunchKernelGGL((k_lift<double>), dim3(gx, nblocks, nrhs), dim3(256), 0, st, g, lb, (double2*)ws);
+  else
+    hipLaunchKernelGGL((k_lift<float>), dim3(gx, nblocks, nrhs), dim3(256), 0, st, g, lb, (float2*)ws);
+}
+
+void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* u, int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nsx * g.nz * g.NY + (int64_t)g.nsy * g.nz * g.NX;
+  if (n == 0 || nrhs == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_sigma_scatter<double, double2, false>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st,
+                       g, (const double2*)ws, (double2*)u);
+  else if (acc)
+    hipLaunchKernelGGL((k_sigma_scatter<float, double2, true>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const float2*)ws, (double2*)u);
+  else
+    hipLaunchKernelGGL((k_sigma_scatter<float, double2, false>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st,
+                       g, (const float2*)ws, (double2*)u);
+}
+
+void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,
+              int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  if (n == 0 || nrhs == 0) return;
+  if (out64)
+    hipLaunchKernelGGL((k_residual<double2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const double2*)f, (const double2*)u, (double2*)out, apply_only);
+  else
+    hipLaunchKernelGGL((k_residual<float2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+                       (const double2*)f, (const double2*)u, (float2*)out, apply_only);
+}
+
+void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  if (n == 0 || nrhs == 0) return;
+  hipLaunchKernelGGL(k_conj_mass, dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const double2*)in,
+                     (double2*)out, inverse);
+}
+
+void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
+                 void* plane_sums, void* grad, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_dot, dim3(nz, 1, nrhs), dim3(256), 0, st, plane, nz, (const double2*)a,
+                     (const double2*)u, (double2*)plane_sums);
+  hipLaunchKernelGGL(k_layer_sum, dim3((nlayers + 63) / 64, 1, nrhs), dim3(64), 0, st, nz, nlayers,
+                     layer_of_z, (const double2*)plane_sums, (double2*)grad);
+}
+
+}  // namespace hs

@@ -1,0 +1,72 @@
+// Launch interface between the host plan and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace hs {
+
+// Geometry of the separator lines and block faces used by the interface
+// kernels.  Offsets (complex elements) index the workspace; `coef` points at
+// the table buffer of the compute precision and cx_lo... index it.
+struct SigmaGeom {
+  int32_t NX, NY, nz, nsx;
+  int32_t nsy, NF, rmax, nbx_blocks;
+  int64_t f_r;                    // elements per right-hand side of f / u
+  int64_t face, face_f;           // face arrays [blk][r][4][nz][NF], face_f = nz * NF
+  int64_t gface;                  // lifted face data, same layout
+  int64_t rx, ry;                 // residual on separator lines [r][s][nz][NY] / [r][t][nz][NX]
+  int64_t wx, wy;                 // w on separator lines, same layout
+  const int32_t* sep_x;
+  const int32_t* sep_y;
+  const int32_t* xblk;            // global x -> block column or -1 on a separator
+  const int32_t* xloc;            // global x -> local index in its block
+  const int32_t* yblk;
+  const int32_t* yloc;
+  const void* coef;
+  int64_t cx_lo, cx_hi, cy_lo, cy_hi;   // coefficient offsets per separator
+};
+
+struct LiftBlock {
+  int32_t x0, y0, nbx, nby;
+  int32_t sep_lo_x, sep_hi_x, sep_lo_y, sep_hi_y;   // separator index or -1 (wall)
+  int64_t cfx[2], cfy[2];                            // coefficient offsets (in `coef`)
+};
+
+struct StencilGeom {
+  int32_t nx, ny, nz, pad_;
+  const double2 *xd, *xl, *xu;
+  const double2 *yd, *yl, *yu;
+  const double2 *zd, *zl, *zu;
+  const double2 *mx, *my, *mz;
+};
+
+void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
+                 const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
+int xform_lines_tiles(const XformDesc& d);
+
+void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
+             const void* tab, void* ws, int nrhs, hipStream_t st);
+int xform_y_tiles(const XformYDesc& d, int ct);
+
+void sweep(int prec, const SweepDesc* d, int ndesc, int max_tiles, const void* tab, void* ws, int nrhs,
+           hipStream_t st);
+int sweep_segments(int nz);
+
+void reduce_partials(int prec, const ReduceDesc* d, int ndesc, int64_t max_elems, void* ws, int nrhs,
+                     hipStream_t st);
+
+void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st);
+void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,
+          hipStream_t st);
+void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* u, int nrhs, hipStream_t st);
+
+void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,
+              int nrhs, hipStream_t st);
+void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st);
+void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
+                 void* plane_sums, void* grad, int nrhs, hipStream_t st);
+
+}  // namespace hs

@@ -1,0 +1,795 @@
+// Host plan of the separable Helmholtz solver (Sec. 2 of the paper).
+//
+// Builds, once per grid / block split / k^2:
+//  * the FP64 1D eigen tables of every block axis and of the two global
+//    axes (closed-form sine tables on uniform axes, the QR eigensolver of
+//    eig.cpp otherwise), deduplicated by their step vectors;
+//  * the z tables of Dz - diag k^2 and the FP64 stencil of eq. (2);
+//  * the workspace layout and the stage descriptors of one solve;
+// and enqueues a solve as a fixed sequence of batched kernel launches.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+namespace hs {
+
+namespace {
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Maximal runs of interior nodes between separators (inclusive lo, hi).
+std::vector<std::pair<int, int>> runs(int n, const std::vector<int32_t>& seps) {
+  std::vector<std::pair<int, int>> out;
+  int start = 0;
+  for (size_t k = 0; k <= seps.size(); ++k) {
+    const int s = k < seps.size() ? seps[k] : n;
+    if (s - 1 >= start) out.push_back({start, s - 1});
+    start = s + 1;
+  }
+  return out;
+}
+
+bool check_seps(int n, const std::vector<int32_t>& s, std::string& err, const char* name) {
+  for (size_t k = 0; k < s.size(); ++k) {
+    if (s[k] < 1 || s[k] > n - 2) {
+      err = std::string(name) + ": separator out of range [1, n-2]";
+      return false;
+    }
+    if (k > 0 && s[k] - s[k - 1] < 2) {
+      err = std::string(name) + ": separators must be increasing with at least one node between";
+      return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+Plan::~Plan() {
+  if (dtab64) (void)hipFree(dtab64);
+  if (dtab32) (void)hipFree(dtab32);
+  if (dint) (void)hipFree(dint);
+  if (dsten) (void)hipFree(dsten);
+  if (ddesc) (void)hipFree(ddesc);
+}
+
+hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o, std::string& err) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!g) { err = "grid is NULL"; return HS_ERR_ARG; }
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) { err = "nx, ny, nz must be >= 1"; return HS_ERR_ARG; }
+  if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 34) { err = "grid too large"; return HS_ERR_ARG; }
+  if (!g->hx || !g->hy || !g->hz || !g->layer_of_z || !g->k2) { err = "grid arrays must be non-NULL"; return HS_ERR_ARG; }
+  if (g->nlayers < 1) { err = "nlayers must be >= 1"; return HS_ERR_ARG; }
+  NX = g->nx; NY = g->ny; NZ = g->nz; nlayers = g->nlayers;
+  hx.resize(NX + 1); hy.resize(NY + 1); hz.resize(NZ + 1);
+  for (int i = 0; i <= NX; ++i) hx[i] = cd(g->hx[2 * i], g->hx[2 * i + 1]);
+  for (int i = 0; i <= NY; ++i) hy[i] = cd(g->hy[2 * i], g->hy[2 * i + 1]);
+  for (int i = 0; i <= NZ; ++i) hz[i] = g->hz[i];
+  for (int i = 0; i <= NX; ++i)
+    if (!(std::abs(hx[i]) > 0) || !std::isfinite(std::abs(hx[i]))) { err = "hx: steps must be finite and nonzero"; return HS_ERR_ARG; }
+  for (int i = 0; i <= NY; ++i)
+    if (!(std::abs(hy[i]) > 0) || !std::isfinite(std::abs(hy[i]))) { err = "hy: steps must be finite and nonzero"; return HS_ERR_ARG; }
+  for (int i = 0; i <= NZ; ++i)
+    if (!(hz[i] > 0) || !std::isfinite(hz[i])) { err = "hz: steps must be positive and finite"; return HS_ERR_ARG; }
+  for (int i = 0; i < NX; ++i)
+    if (std::abs(hx[i] + hx[i + 1]) == 0) { err = "hx: zero control volume"; return HS_ERR_ARG; }
+  for (int i = 0; i < NY; ++i)
+    if (std::abs(hy[i] + hy[i + 1]) == 0) { err = "hy: zero control volume"; return HS_ERR_ARG; }
+  layer.assign(g->layer_of_z, g->layer_of_z + NZ);
+  for (int v : layer)
+    if (v < 0 || v >= nlayers) { err = "layer_of_z entry out of range"; return HS_ERR_ARG; }
+  k2.resize(nlayers);
+  for (int l = 0; l < nlayers; ++l) {
+    k2[l] = cd(g->k2[2 * l], g->k2[2 * l + 1]);
+    if (!std::isfinite(k2[l].real()) || !std::isfinite(k2[l].imag())) { err = "k2 must be finite"; return HS_ERR_ARG; }
+  }
+  if (b) {
+    if (b->nsep_x < 0 || b->nsep_y < 0) { err = "negative separator count"; return HS_ERR_ARG; }
+    if ((b->nsep_x > 0 && !b->sep_x) || (b->nsep_y > 0 && !b->sep_y)) { err = "separator array is NULL"; return HS_ERR_ARG; }
+    sepx.assign(b->sep_x, b->sep_x + b->nsep_x);
+    sepy.assign(b->sep_y, b->sep_y + b->nsep_y);
+  }
+  if (!check_seps(NX, sepx, err, "sep_x") || !check_seps(NY, sepy, err, "sep_y")) return HS_ERR_ARG;
+  if ((int)sepx.size() > kMaxTerms || (int)sepy.size() > kMaxTerms) {
+    err = "at most 4 separators per axis are supported";
+    return HS_ERR_ARG;
+  }
+  hs_options def{HS_C128, 0, 1, 0};
+  const hs_options& op = o ? *o : def;
+  if (op.prec != HS_C128 && op.prec != HS_C64_REFINE) { err = "unknown precision"; return HS_ERR_ARG; }
+  prec = op.prec == HS_C128 ? 0 : 1;
+  refine_steps = prec ? (op.refine_steps > 0 ? op.refine_steps : 2) : 0;
+  if (op.max_rhs < 0 || op.max_rhs > 4096) { err = "max_rhs out of range"; return HS_ERR_ARG; }
+  max_rhs = op.max_rhs > 0 ? op.max_rhs : 1;
+  flags = op.flags;
+  decomposed = !sepx.empty() || !sepy.empty();
+  for (auto& rx : runs(NX, sepx)) max_block_n = std::max(max_block_n, rx.second - rx.first + 1);
+  for (auto& ry : runs(NY, sepy)) max_block_n = std::max(max_block_n, ry.second - ry.first + 1);
+  if (max_block_n > 512) { err = "block side > 512 is not supported; add separators"; return HS_ERR_ARG; }
+  if (NZ > 4096) { err = "nz > 4096 is not supported"; return HS_ERR_ARG; }
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    err = "no HIP device available";
+    return HS_ERR_DEVICE;
+  }
+  if (hipGetDevice(&device) != hipSuccess) { err = "hipGetDevice failed"; return HS_ERR_DEVICE; }
+
+  hs_status st = build_tables(err);
+  if (st != HS_OK) return st;
+  st = scan_pivots(err);
+  if (st != HS_OK) return st;
+  layout_workspace();
+  build_descriptors();
+  st = upload(err);
+  plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
+}
+
+hs_status Plan::build_tables(std::string& err) {
+  // unique axes by step vector
+  std::map<std::vector<std::pair<double, double>>, int> seen;
+  auto axis_for = [&](const cd* h, int n) -> int {
+    std::vector<std::pair<double, double>> key(n + 1);
+    for (int i = 0; i <= n; ++i) key[i] = {h[i].real(), h[i].imag()};
+    auto it = seen.find(key);
+    if (it != seen.end()) return it->second;
+    Axis a;
+    a.n = n;
+    a.sine = axis_is_uniform(n, h) && !(flags & 1);
+    if (axis_is_uniform(n, h)) {
+      axis_eig_uniform(n, h[0], a.e);
+    } else {
+      if (!axis_eig_general(n, h, a.e, err)) return -1;
+    }
+    axes.push_back(std::move(a));
+    seen[key] = int(axes.size()) - 1;
+    return int(axes.size()) - 1;
+  };
+  auto rxs = runs(NX, sepx), rys = runs(NY, sepy);
+  nbx_blocks = int(rxs.size());
+  nby_blocks = int(rys.size());
+  for (int j = 0; j < nby_blocks; ++j)
+    for (int i = 0; i < nbx_blocks; ++i) {
+      Block B;
+      B.bi = i; B.bj = j;
+      B.x0 = rxs[i].first; B.nbx = rxs[i].second - rxs[i].first + 1;
+      B.y0 = rys[j].first; B.nby = rys[j].second - rys[j].first + 1;
+      B.ax = axis_for(&hx[B.x0], B.nbx);
+      if (B.ax < 0) return HS_ERR_SINGULAR;
+      B.ay = axis_for(&hy[B.y0], B.nby);
+      if (B.ay < 0) return HS_ERR_SINGULAR;
+      B.sep_lo_x = i > 0 ? i - 1 : -1;
+      B.sep_hi_x = i < nbx_blocks - 1 ? i : -1;
+      B.sep_lo_y = j > 0 ? j - 1 : -1;
+      B.sep_hi_y = j < nby_blocks - 1 ? j : -1;
+      blocks.push_back(B);
+    }
+  if (decomposed) {
+    gax = axis_for(hx.data(), NX);
+    if (gax < 0) return HS_ERR_SINGULAR;
+    gay = axis_for(hy.data(), NY);
+    if (gay < 0) return HS_ERR_SINGULAR;
+  }
+  for (auto& a : axes) {
+    if (!(a.e.inv_resid < 1e-8) || !(a.e.decouple < 1e-10) || !(a.e.kappa < 1e8)) {
+      err = "eigen table of an axis is numerically unusable (kappa " + std::to_string(a.e.kappa) + ")";
+      return HS_ERR_SINGULAR;
+    }
+  }
+  // table image
+  htab.clear();
+  auto push = [&](const std::vector<cd>& v) {
+    int64_t off = int64_t(htab.size());
+    htab.insert(htab.end(), v.begin(), v.end());
+    // keep every table 256-byte aligned in both precisions
+    htab.resize(align_up(int64_t(htab.size()), 32));
+    return off;
+  };
+  for (auto& a : axes) {
+    a.fwd = push(a.e.Winv);
+    a.inv = push(a.e.W);
+    a.lam = push(a.e.lam);
+  }
+  zlo = push(std::vector<cd>(NZ));
+  zdiag = push(std::vector<cd>(NZ));
+  zup = push(std::vector<cd>(NZ));
+  build_z_tables();
+  // interface coefficients: r(s) = f(s) + v(s-1)/(hhat_s h_s) + v(s+1)/(hhat_s h_{s+1})
+  std::vector<cd> c;
+  for (int s : sepx) c.push_back(1.0 / (0.5 * (hx[s] + hx[s + 1]) * hx[s]));
+  cx_lo = push(c);
+  c.clear();
+  for (int s : sepx) c.push_back(1.0 / (0.5 * (hx[s] + hx[s + 1]) * hx[s + 1]));
+  cx_hi = push(c);
+  c.clear();
+  for (int t : sepy) c.push_back(1.0 / (0.5 * (hy[t] + hy[t + 1]) * hy[t]));
+  cy_lo = push(c);
+  c.clear();
+  for (int t : sepy) c.push_back(1.0 / (0.5 * (hy[t] + hy[t + 1]) * hy[t + 1]));
+  cy_hi = push(c);
+  // lift coefficients: first interior line x0 couples to its separator by
+  // -1/(hhat_{x0} h_{x0}), last line x1 by -1/(hhat_{x1} h_{x1+1})
+  lift_cf.clear();
+  for (auto& B : blocks) {
+    const int x1 = B.x0 + B.nbx - 1, y1 = B.y0 + B.nby - 1;
+    std::vector<cd> cf = {1.0 / (0.5 * (hx[B.x0] + hx[B.x0 + 1]) * hx[B.x0]),
+                          1.0 / (0.5 * (hx[x1] + hx[x1 + 1]) * hx[x1 + 1]),
+                          1.0 / (0.5 * (hy[B.y0] + hy[B.y0 + 1]) * hy[B.y0]),
+                          1.0 / (0.5 * (hy[y1] + hy[y1 + 1]) * hy[y1 + 1])};
+    int64_t off = push(cf);
+    for (int k = 0; k < 4; ++k) lift_cf.push_back(off + k);
+  }
+  tab_elems = htab.size();
+  return HS_OK;
+}
+
+void Plan::build_z_tables() {
+  for (int k = 0; k < NZ; ++k) {
+    const double hh = 0.5 * (hz[k] + hz[k + 1]);
+    htab[zlo + k] = k > 0 ? cd(-1.0 / (hh * hz[k])) : cd(0.0);
+    htab[zup + k] = k + 1 < NZ ? cd(-1.0 / (hh * hz[k + 1])) : cd(0.0);
+    htab[zdiag + k] = (1.0 / hz[k] + 1.0 / hz[k + 1]) / hh - k2[layer[k]];
+  }
+}
+
+void Plan::build_stencil_host(std::vector<double2>& out) {
+  // xd xl xu | yd yl yu | zd zl zu | mx my mz
+  out.clear();
+  auto put = [&](cd v) { out.push_back(make_double2(v.real(), v.imag())); };
+  auto axis = [&](const std::vector<cd>& h, int n) {
+    std::vector<cd> d(n), l(n), u(n);
+    for (int i = 0; i < n; ++i) {
+      cd hh = 0.5 * (h[i] + h[i + 1]);
+      l[i] = -1.0 / (h[i] * hh);
+      u[i] = -1.0 / (h[i + 1] * hh);
+      d[i] = -(l[i] + u[i]);
+    }
+    for (auto v : d) put(v);
+    for (auto v : l) put(v);
+    for (auto v : u) put(v);
+  };
+  axis(hx, NX);
+  axis(hy, NY);
+  for (int k = 0; k < NZ; ++k) put(htab[zdiag + k]);
+  for (int k = 0; k < NZ; ++k) put(htab[zlo + k]);
+  for (int k = 0; k < NZ; ++k) put(htab[zup + k]);
+  for (int i = 0; i < NX; ++i) put(0.5 * (hx[i] + hx[i + 1]));
+  for (int i = 0; i < NY; ++i) put(0.5 * (hy[i] + hy[i + 1]));
+  for (int k = 0; k < NZ; ++k) put(cd(0.5 * (hz[k] + hz[k + 1])));
+}
+
+hs_status Plan::scan_pivots(std::string& err) {
+  // FP64 scan of the no-pivoting Thomas pivots of every mode of every block
+  // (and of the global axes): the z solve needs them bounded away from zero.
+  double mn = 1e300, scale = 0;
+  for (int k = 0; k < NZ; ++k) scale = std::max(scale, std::abs(htab[zdiag + k]));
+  auto scan = [&](const Axis& ax, const Axis& ay) {
+    for (int b = 0; b < ay.n; ++b)
+      for (int a = 0; a < ax.n; ++a) {
+        const cd s = ax.e.lam[a] + ay.e.lam[b];
+        cd c = 0.0;
+        for (int k = 0; k < NZ; ++k) {
+          cd piv = htab[zdiag + k] + s - htab[zlo + k] * c;
+          mn = std::min(mn, std::abs(piv));
+          c = htab[zup + k] / piv;
+        }
+      }
+  };
+  std::vector<std::pair<int, int>> done;
+  for (auto& B : blocks) {
+    std::pair<int, int> key{B.ax, B.ay};
+    if (std::find(done.begin(), done.end(), key) != done.end()) continue;
+    done.push_back(key);
+    scan(axes[B.ax], axes[B.ay]);
+  }
+  if (decomposed) scan(axes[gax], axes[gay]);
+  min_pivot = mn;
+  if (!(mn > 1e-12 * std::max(scale, 1.0))) {
+    err = "z pivot too small (" + std::to_string(mn) + "): the layered operator is numerically singular";
+    return HS_ERR_SINGULAR;
+  }
+  return HS_OK;
+}
+
+void Plan::layout_workspace() {
+  const int64_t R = max_rhs;
+  int64_t off = 0;
+  auto take = [&](int64_t n) {
+    int64_t o = off;
+    off = align_up(off + n, 64);
+    return o;
+  };
+  NF = 0;
+  for (auto& B : blocks) NF = std::max(NF, std::max(B.nbx, B.nby));
+  const int nseg = sweep_segments(NZ);
+  for (auto& B : blocks) B.spec = take(R * NZ * B.nbx * B.nby);
+  for (auto& B : blocks) B.ckpt = take(R * nseg * (int64_t)B.nbx * B.nby);
+  if (decomposed) {
+    // forward-sweep scratch shared by the block sweeps and the global sweep
+    int64_t glob = R * NZ * (int64_t)NX * NY;
+    int64_t sum = 0;
+    for (auto& B : blocks) sum = align_up(sum + R * NZ * B.nbx * B.nby, 64);
+    w_gdbuf = take(std::max(glob, sum));
+    int64_t acc = w_gdbuf;
+    for (auto& B : blocks) {
+      B.dbuf = acc;
+      acc = align_up(acc + R * NZ * B.nbx * B.nby, 64);
+    }
+    for (auto& B : blocks) {
+      const int ta = (B.nbx + 15) / 16, tb = (B.nby + 15) / 16;
+      B.partx = take(2LL * ta * R * NZ * B.nby);
+      B.party = take(2LL * tb * R * NZ * B.nbx);
+    }
+    const int64_t faces = (int64_t)blocks.size() * R * 4 * NZ * NF;
+    w_face = take(faces);
+    w_vface = take(faces);
+    w_gface = take(faces);
+    w_Gface = take(faces);
+    const int nsx = int(sepx.size()), nsy = int(sepy.size());
+    const int64_t lx = R * nsx * NZ * (int64_t)NY, ly = R * nsy * NZ * (int64_t)NX;
+    w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
+    w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
+    const int gta = (NX + 15) / 16, gtb = (NY + 15) / 16;
+    w_gpartx = take((int64_t)nsx * gta * R * NZ * NY);
+    w_gparty = take((int64_t)nsy * gtb * R * NZ * NX);
+    w_gckpt = take(R * nseg * (int64_t)NX * NY);
+  }
+  ws_elems = size_t(off);
+  const size_t esz = prec == 0 ? 16 : 8;
+  size_t bytes = align_up(int64_t(ws_elems * esz), 256);
+  off_d64 = bytes;
+  const size_t N = size_t(NX) * NY * NZ;
+  bytes += align_up(int64_t(R * N * 16), 256);        // adjoint scratch (complex128)
+  bytes += align_up(int64_t(R * NZ * 16), 256);       // plane sums of the gradient
+  off_res = bytes;
+  if (prec == 1) bytes += align_up(int64_t(R * N * 8), 256);   // complex64 residual
+  ws_bytes = bytes;
+}
+
+void Plan::build_descriptors() {
+  const int64_t R = max_rhs;
+  (void)R;
+  d_fwdx.clear(); d_invx.clear(); d_fwdy.clear(); d_invy.clear(); d_sweep.clear();
+  d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear(); d_redB.clear(); d_redG.clear();
+  d_vface.clear(); d_gface.clear(); d_glob_in.clear(); d_glob_out.clear(); d_lift.clear();
+  const int64_t gplane = (int64_t)NX * NY;
+  const int64_t f_r = gplane * NZ;
+  const int64_t face_f = (int64_t)NZ * NF;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    const Block& B = blocks[bi];
+    const Axis& AX = axes[B.ax];
+    const Axis& AY = axes[B.ay];
+    const int64_t plane = (int64_t)B.nbx * B.nby;
+    const int64_t spec_r = plane * NZ;
+    XformDesc fx{};
+    fx.tab = AX.fwd; fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
+    fx.src = (int64_t)B.y0 * NX + B.x0; fx.src_r = f_r; fx.src_p = gplane; fx.src_q = NX;
+    fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.nbx;
+    fx.sine = AX.sine;
+    d_fwdx.push_back(fx);
+    XformDesc ix = fx;
+    ix.tab = AX.inv;
+    ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
+    ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
+    d_invx.push_back(ix);
+    XformYDesc fy{};
+    fy.tab = AY.fwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
+    fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.nbx;
+    d_fwdy.push_back(fy);
+    XformYDesc iy = fy;
+    iy.tab = AY.inv;
+    d_invy.push_back(iy);
+
+    SweepDesc s{};
+    s.na = B.nbx; s.nb = B.nby; s.nz = NZ;
+    s.tiles_a = (B.nbx + 15) / 16; s.tiles_b = (B.nby + 15) / 16;
+    s.lam_x = AX.lam; s.lam_y = AY.lam;
+    s.zlo = zlo; s.zdiag = zdiag; s.zup = zup;
+    s.data = B.spec; s.data_r = spec_r;
+    s.ckpt = B.ckpt;
+    if (!decomposed) {
+      s.dense_in = 1; s.dense_out = 1;
+      d_sweep.push_back(s);
+      continue;
+    }
+    // steps 1-3: block sweep, v on the first / last interior lines via reductions
+    SweepDesc sb = s;
+    sb.dense_in = 1; sb.dense_out = 0;
+    sb.dbuf = B.dbuf; sb.dbuf_r = spec_r;
+    sb.nxr = 2; sb.nyr = 2;
+    sb.ex[0] = AX.inv; sb.ex_stride[0] = 1;                              // W_x[0][a]
+    sb.ex[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; sb.ex_stride[1] = 1;  // W_x[n-1][a]
+    sb.ey[0] = AY.inv; sb.ey_stride[0] = 1;
+    sb.ey[1] = AY.inv + (int64_t)(B.nby - 1) * B.nby; sb.ey_stride[1] = 1;
+    sb.redx = B.partx; sb.redx_term = (int64_t)s.tiles_a * R * NZ * B.nby;
+    sb.redx_tile = R * NZ * B.nby; sb.redx_r = (int64_t)NZ * B.nby;
+    sb.redy = B.party; sb.redy_term = (int64_t)s.tiles_b * R * NZ * B.nbx;
+    sb.redy_tile = R * NZ * B.nbx; sb.redy_r = (int64_t)NZ * B.nbx;
+    d_sweepB.push_back(sb);
+    const int64_t fbase = w_face + (int64_t)bi * R * 4 * face_f;
+    ReduceDesc rx{};
+    rx.src = B.partx; rx.src_term = sb.redx_term; rx.src_tile = sb.redx_tile; rx.src_r = sb.redx_r;
+    rx.dst = fbase; rx.dst_term = face_f; rx.dst_r = 4 * face_f; rx.dst_z = NF;
+    rx.nterms = 2; rx.ntiles = s.tiles_a; rx.nz = NZ; rx.n = B.nby;
+    d_redB.push_back(rx);
+    ReduceDesc ry{};
+    ry.src = B.party; ry.src_term = sb.redy_term; ry.src_tile = sb.redy_tile; ry.src_r = sb.redy_r;
+    ry.dst = fbase + 2 * face_f; ry.dst_term = face_f; ry.dst_r = 4 * face_f; ry.dst_z = NF;
+    ry.nterms = 2; ry.ntiles = s.tiles_b; ry.nz = NZ; ry.n = B.nbx;
+    d_redB.push_back(ry);
+    // face values v(y) = sum_b W_y[y][b] e(b) (faces 0, 1) and v(x) = sum_a W_x[x][a] e(a) (faces 2, 3)
+    XformDesc vf{};
+    vf.tab = AY.inv; vf.n_in = vf.n_out = B.nby; vf.P = 2 * NZ; vf.Q = 1;
+    vf.src = fbase; vf.src_r = 4 * face_f; vf.src_p = NF; vf.src_q = 0;
+    vf.dst = w_vface + (fbase - w_face); vf.dst_r = 4 * face_f; vf.dst_p = NF; vf.dst_q = 0;
+    d_vface.push_back(vf);
+    XformDesc vf2 = vf;
+    vf2.tab = AX.inv; vf2.n_in = vf2.n_out = B.nbx;
+    vf2.src = fbase + 2 * face_f; vf2.dst = vf.dst + 2 * face_f;
+    d_vface.push_back(vf2);
+    // step 6: lift, transform by the block's W^{-1}
+    LiftBlock lb{};
+    lb.x0 = B.x0; lb.y0 = B.y0; lb.nbx = B.nbx; lb.nby = B.nby;
+    lb.sep_lo_x = B.sep_lo_x; lb.sep_hi_x = B.sep_hi_x; lb.sep_lo_y = B.sep_lo_y; lb.sep_hi_y = B.sep_hi_y;
+    lb.cfx[0] = lift_cf[4 * bi + 0]; lb.cfx[1] = lift_cf[4 * bi + 1];
+    lb.cfy[0] = lift_cf[4 * bi + 2]; lb.cfy[1] = lift_cf[4 * bi + 3];
+    d_lift.push_back(lb);
+    const int64_t gbase = w_gface + (fbase - w_face);
+    const int64_t Gbase = w_Gface + (fbase - w_face);
+    XformDesc gf = vf;
+    gf.tab = AY.fwd; gf.src = gbase; gf.dst = Gbase;
+    d_gface.push_back(gf);
+    XformDesc gf2 = vf2;
+    gf2.tab = AX.fwd; gf2.src = gbase + 2 * face_f; gf2.dst = Gbase + 2 * face_f;
+    d_gface.push_back(gf2);
+    // steps 6-7: block sweep of f^ + g^ (g^ generated from the four faces)
+    SweepDesc sc = s;
+    sc.dense_in = 1; sc.dense_out = 1;
+    sc.nxt = 2; sc.nyt = 2;
+    sc.colx[0] = AX.fwd; sc.colx_stride[0] = B.nbx;                       // W_x^{-1}[a][0]
+    sc.colx[1] = AX.fwd + (B.nbx - 1); sc.colx_stride[1] = B.nbx;         // W_x^{-1}[a][n-1]
+    sc.coly[0] = AY.fwd; sc.coly_stride[0] = B.nby;
+    sc.coly[1] = AY.fwd + (B.nby - 1); sc.coly_stride[1] = B.nby;
+    sc.gx[0] = Gbase; sc.gx[1] = Gbase + face_f;
+    sc.gy[0] = Gbase + 2 * face_f; sc.gy[1] = Gbase + 3 * face_f;
+    sc.gx_r = sc.gy_r = 4 * face_f;
+    sc.gx_z = sc.gy_z = NF;
+    d_sweepC.push_back(sc);
+  }
+  if (decomposed) {
+    const int nsx = int(sepx.size()), nsy = int(sepy.size());
+    const Axis& GX = axes[gax];
+    const Axis& GY = axes[gay];
+    // step 5 input: R_x[s](b) = sum_y W_y^{-1}[b][y] r(s, y); R_y[t](a) = sum_x W_x^{-1}[a][x] r(x, t)
+    if (nsx > 0) {
+      XformDesc d{};
+      d.tab = GY.fwd; d.n_in = d.n_out = NY; d.P = nsx * NZ; d.Q = 1;
+      d.src = w_rx; d.src_r = (int64_t)nsx * NZ * NY; d.src_p = NY;
+      d.dst = w_Rx; d.dst_r = d.src_r; d.dst_p = NY;
+      d_glob_in.push_back(d);
+      XformDesc o{};
+      o.tab = GY.inv; o.n_in = o.n_out = NY; o.P = nsx * NZ; o.Q = 1;
+      o.src = w_Qx; o.src_r = d.src_r; o.src_p = NY;
+      o.dst = w_wx; o.dst_r = d.src_r; o.dst_p = NY;
+      d_glob_out.push_back(o);
+    }
+    if (nsy > 0) {
+      XformDesc d{};
+      d.tab = GX.fwd; d.n_in = d.n_out = NX; d.P = nsy * NZ; d.Q = 1;
+      d.src = w_ry; d.src_r = (int64_t)nsy * NZ * NX; d.src_p = NX;
+      d.dst = w_Ry; d.dst_r = d.src_r; d.dst_p = NX;
+      d_glob_in.push_back(d);
+      XformDesc o{};
+      o.tab = GX.inv; o.n_in = o.n_out = NX; o.P = nsy * NZ; o.Q = 1;
+      o.src = w_Qy; o.src_r = d.src_r; o.src_p = NX;
+      o.dst = w_wy; o.dst_r = d.src_r; o.dst_p = NX;
+      d_glob_out.push_back(o);
+    }
+    SweepDesc g{};
+    g.na = NX; g.nb = NY; g.nz = NZ;
+    g.tiles_a = (NX + 15) / 16; g.tiles_b = (NY + 15) / 16;
+    g.lam_x = GX.lam; g.lam_y = GY.lam;
+    g.zlo = zlo; g.zdiag = zdiag; g.zup = zup;
+    g.dense_in = 0; g.dense_out = 0;
+    g.dbuf = w_gdbuf; g.dbuf_r = (int64_t)NX * NY * NZ;
+    g.ckpt = w_gckpt;
+    g.nxt = nsx; g.nyt = nsy; g.nxr = nsx; g.nyr = nsy;
+    for (int i = 0; i < nsx; ++i) {
+      g.colx[i] = GX.fwd + sepx[i]; g.colx_stride[i] = NX;        // W_x^{-1}[a][s_i]
+      g.gx[i] = w_Rx + (int64_t)i * NZ * NY;
+      g.ex[i] = GX.inv + (int64_t)sepx[i] * NX; g.ex_stride[i] = 1;  // W_x[s_i][a]
+    }
+    for (int j = 0; j < nsy; ++j) {
+      g.coly[j] = GY.fwd + sepy[j]; g.coly_stride[j] = NY;
+      g.gy[j] = w_Ry + (int64_t)j * NZ * NX;
+      g.ey[j] = GY.inv + (int64_t)sepy[j] * NY; g.ey_stride[j] = 1;
+    }
+    g.gx_r = (int64_t)nsx * NZ * NY; g.gy_r = (int64_t)nsy * NZ * NX;
+    g.gx_z = NY; g.gy_z = NX;
+    g.redx = w_gpartx; g.redx_tile = R * NZ * NY; g.redx_term = (int64_t)g.tiles_a * g.redx_tile;
+    g.redx_r = (int64_t)NZ * NY;
+    g.redy = w_gparty; g.redy_tile = R * NZ * NX; g.redy_term = (int64_t)g.tiles_b * g.redy_tile;
+    g.redy_r = (int64_t)NZ * NX;
+    d_sweepG.push_back(g);
+    if (nsx > 0) {
+      ReduceDesc rq{};
+      rq.src = w_gpartx; rq.src_term = g.redx_term; rq.src_tile = g.redx_tile; rq.src_r = g.redx_r;
+      rq.dst = w_Qx; rq.dst_term = (int64_t)NZ * NY; rq.dst_r = (int64_t)nsx * NZ * NY; rq.dst_z = NY;
+      rq.nterms = nsx; rq.ntiles = g.tiles_a; rq.nz = NZ; rq.n = NY;
+      d_redG.push_back(rq);
+    }
+    if (nsy > 0) {
+      ReduceDesc rq{};
+      rq.src = w_gparty; rq.src_term = g.redy_term; rq.src_tile = g.redy_tile; rq.src_r = g.redy_r;
+      rq.dst = w_Qy; rq.dst_term = (int64_t)NZ * NX; rq.dst_r = (int64_t)nsy * NZ * NX; rq.dst_z = NX;
+      rq.nterms = nsy; rq.ntiles = g.tiles_b; rq.nz = NZ; rq.n = NX;
+      d_redG.push_back(rq);
+    }
+    redB_max = 0;
+    for (auto& d : d_redB) redB_max = std::max<int64_t>(redB_max, (int64_t)d.nterms * d.nz * d.n);
+    redG_max = 0;
+    for (auto& d : d_redG) redG_max = std::max<int64_t>(redG_max, (int64_t)d.nterms * d.nz * d.n);
+    sg.NX = NX; sg.NY = NY; sg.nz = NZ; sg.nsx = nsx; sg.nsy = nsy; sg.NF = NF;
+    sg.rmax = max_rhs; sg.nbx_blocks = nbx_blocks;
+    sg.f_r = f_r; sg.face = w_vface; sg.face_f = face_f; sg.gface = w_gface;
+    sg.rx = w_rx; sg.ry = w_ry; sg.wx = w_wx; sg.wy = w_wy;
+    sg.cx_lo = cx_lo; sg.cx_hi = cx_hi; sg.cy_lo = cy_lo; sg.cy_hi = cy_hi;
+  }
+}
+
+hs_status Plan::upload(std::string& err) {
+  auto fail = [&](const char* what) {
+    (void)hipGetLastError();
+    err = std::string("device allocation/copy failed: ") + what;
+    return HS_ERR_ALLOC;
+  };
+  // tables, both precisions for the mixed path
+  std::vector<double2> t64(tab_elems);
+  for (size_t i = 0; i < tab_elems; ++i) t64[i] = make_double2(htab[i].real(), htab[i].imag());
+  if (hipMalloc(&dtab64, tab_elems * sizeof(double2)) != hipSuccess) return fail("tables");
+  if (hipMemcpy(dtab64, t64.data(), tab_elems * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+    return fail("tables");
+  if (prec == 1) {
+    std::vector<float2> t32(tab_elems);
+    for (size_t i = 0; i < tab_elems; ++i) t32[i] = make_float2(float(htab[i].real()), float(htab[i].imag()));
+    if (hipMalloc(&dtab32, tab_elems * sizeof(float2)) != hipSuccess) return fail("tables");
+    if (hipMemcpy(dtab32, t32.data(), tab_elems * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
+      return fail("tables");
+  }
+  // integer tables
+  std::vector<int32_t> iv;
+  auto ipush = [&](const std::vector<int32_t>& v) {
+    int64_t o = int64_t(iv.size());
+    iv.insert(iv.end(), v.begin(), v.end());
+    iv.resize(align_up(int64_t(iv.size()), 64));
+    return o;
+  };
+  std::vector<int32_t> xblk(NX, -1), xloc(NX, 0), yblk(NY, -1), yloc(NY, 0);
+  auto rxs = runs(NX, sepx), rys = runs(NY, sepy);
+  for (int i = 0; i < (int)rxs.size(); ++i)
+    for (int x = rxs[i].first; x <= rxs[i].second; ++x) { xblk[x] = i; xloc[x] = x - rxs[i].first; }
+  for (int j = 0; j < (int)rys.size(); ++j)
+    for (int y = rys[j].first; y <= rys[j].second; ++y) { yblk[y] = j; yloc[y] = y - rys[j].first; }
+  i_sepx = ipush(sepx.empty() ? std::vector<int32_t>{0} : sepx);
+  i_sepy = ipush(sepy.empty() ? std::vector<int32_t>{0} : sepy);
+  i_xblk = ipush(xblk); i_xloc = ipush(xloc); i_yblk = ipush(yblk); i_yloc = ipush(yloc);
+  i_layer = ipush(layer);
+  if (hipMalloc((void**)&dint, iv.size() * sizeof(int32_t)) != hipSuccess) return fail("int tables");
+  if (hipMemcpy(dint, iv.data(), iv.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return fail("int tables");
+  sg.sep_x = dint + i_sepx; sg.sep_y = dint + i_sepy;
+  sg.xblk = dint + i_xblk; sg.xloc = dint + i_xloc; sg.yblk = dint + i_yblk; sg.yloc = dint + i_yloc;
+  // stencil
+  std::vector<double2> sv;
+  build_stencil_host(sv);
+  if (hipMalloc((void**)&dsten, sv.size() * sizeof(double2)) != hipSuccess) return fail("stencil");
+  if (hipMemcpy(dsten, sv.data(), sv.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess)
+    return fail("stencil");
+  sten.nx = NX; sten.ny = NY; sten.nz = NZ;
+  double2* p = dsten;
+  sten.xd = p; p += NX; sten.xl = p; p += NX; sten.xu = p; p += NX;
+  sten.yd = p; p += NY; sten.yl = p; p += NY; sten.yu = p; p += NY;
+  sten.zd = p; p += NZ; sten.zl = p; p += NZ; sten.zu = p; p += NZ;
+  sten.mx = p; p += NX; sten.my = p; p += NY; sten.mz = p; p += NZ;
+  // descriptors
+  std::vector<unsigned char> blob;
+  auto dpush = [&](const void* src, size_t bytes) {
+    size_t o = align_up(int64_t(blob.size()), 256);
+    blob.resize(o + bytes);
+    if (bytes) std::memcpy(blob.data() + o, src, bytes);
+    return o;
+  };
+  struct Fix { size_t off; const void** dst; };
+  std::vector<Fix> fx;
+  auto reg = [&](const auto& v, auto** out) {
+    size_t o = dpush(v.data(), v.size() * sizeof(v[0]));
+    fx.push_back({o, (const void**)out});
+  };
+  reg(d_fwdx, &p_fwdx); reg(d_invx, &p_invx); reg(d_vface, &p_vface); reg(d_gface, &p_gface);
+  reg(d_glob_in, &p_glob_in); reg(d_glob_out, &p_glob_out);
+  reg(d_fwdy, &p_fwdy); reg(d_invy, &p_invy);
+  reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
+  reg(d_redB, &p_redB); reg(d_redG, &p_redG); reg(d_lift, &p_lift);
+  if (hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
+  if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail("descriptors");
+  for (auto& f : fx) *f.dst = (const unsigned char*)ddesc + f.off;
+  return HS_OK;
+}
+
+hs_status Plan::set_k2(const double* k2v, std::string& err) {
+  if (!k2v) { err = "k2 is NULL"; return HS_ERR_ARG; }
+  std::vector<cd> old = k2;
+  for (int l = 0; l < nlayers; ++l) {
+    k2[l] = cd(k2v[2 * l], k2v[2 * l + 1]);
+    if (!std::isfinite(k2[l].real()) || !std::isfinite(k2[l].imag())) {
+      k2 = old;
+      err = "k2 must be finite";
+      return HS_ERR_ARG;
+    }
+  }
+  build_z_tables();
+  hs_status st = scan_pivots(err);
+  if (st != HS_OK) {
+    k2 = old;
+    build_z_tables();
+    return st;
+  }
+  // re-upload the z tables and the stencil
+  std::vector<double2> z64(3 * size_t(NZ));
+  std::vector<float2> z32(3 * size_t(NZ));
+  const int64_t offs[3] = {zlo, zdiag, zup};
+  for (int t = 0; t < 3; ++t)
+    for (int k = 0; k < NZ; ++k) {
+      cd v = htab[offs[t] + k];
+      z64[t * NZ + k] = make_double2(v.real(), v.imag());
+      z32[t * NZ + k] = make_float2(float(v.real()), float(v.imag()));
+    }
+  for (int t = 0; t < 3; ++t) {
+    if (hipMemcpy((double2*)dtab64 + offs[t], &z64[t * NZ], NZ * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+      err = "hipMemcpy failed";
+      return HS_ERR_DEVICE;
+    }
+    if (dtab32 &&
+        hipMemcpy((float2*)dtab32 + offs[t], &z32[t * NZ], NZ * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      err = "hipMemcpy failed";
+      return HS_ERR_DEVICE;
+    }
+  }
+  std::vector<double2> sv;
+  build_stencil_host(sv);
+  if (hipMemcpy(dsten, sv.data(), sv.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+    err = "hipMemcpy failed";
+    return HS_ERR_DEVICE;
+  }
+  return HS_OK;
+}
+
+hs_status Plan::bind(void* p, size_t bytes, std::string& err) {
+  if (!p) { err = "workspace pointer is NULL"; return HS_ERR_ARG; }
+  if (bytes < ws_bytes) { err = "workspace too small"; return HS_ERR_ARG; }
+  if ((uintptr_t)p % 256 != 0) { err = "workspace must be 256-byte aligned"; return HS_ERR_ARG; }
+  ws = p;
+  return HS_OK;
+}
+
+void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st) {
+  const void* T = tab();
+  void* W = ws;
+  const int nb = int(blocks.size());
+  auto tiles_lines = [](const std::vector<XformDesc>& v) {
+    int m = 0;
+    for (auto& d : v) m = std::max(m, xform_lines_tiles(d));
+    return m;
+  };
+  auto tiles_y = [](const std::vector<XformYDesc>& v, int ct) {
+    int m = 0;
+    for (auto& d : v) m = std::max(m, xform_y_tiles(d, ct));
+    return m;
+  };
+  auto tiles_sw = [](const std::vector<SweepDesc>& v) {
+    int m = 0;
+    for (auto& d : v) m = std::max(m, d.tiles_a * d.tiles_b);
+    return m;
+  };
+  const int out64 = 1;
+  // steps 1: forward transforms of every block
+  xform_lines(prec, in64, 0, 0, p_fwdx, nb, tiles_lines(d_fwdx), T, f, W, nrhs, st);
+  xform_y(prec, p_fwdy, nb, max_block_n, tiles_y(d_fwdy, 16), tiles_y(d_fwdy, 8), T, W, nrhs, st);
+  if (!decomposed) {
+    sweep(prec, p_sweep, nb, tiles_sw(d_sweep), T, W, nrhs, st);
+  } else {
+    // steps 2-3: block sweeps, v on the lines next to the separators
+    sweep(prec, p_sweepB, nb, tiles_sw(d_sweepB), T, W, nrhs, st);
+    reduce_partials(prec, p_redB, int(d_redB.size()), redB_max, W, nrhs, st);
+    xform_lines(prec, 0, 0, 0, p_vface, int(d_vface.size()), tiles_lines(d_vface), T, W, W, nrhs, st);
+    // step 4: residual on the separators
+    SigmaGeom g = sg;
+    g.coef = T;
+    sigma_resid(prec, in64, g, f, W, nrhs, st);
+    // step 5: global interface solve, evaluated on the separators
+    xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
+    sweep(prec, p_sweepG, 1, tiles_sw(d_sweepG), T, W, nrhs, st);
+    reduce_partials(prec, p_redG, int(d_redG.size()), redG_max, W, nrhs, st);
+    xform_lines(prec, 0, 0, 0, p_glob_out, int(d_glob_out.size()), tiles_lines(d_glob_out), T, W, W, nrhs, st);
+    // step 6: lift the separator values into the blocks and sweep again
+    lift(prec, g, p_lift, nb, W, nrhs, st);
+    xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
+    sweep(prec, p_sweepC, nb, tiles_sw(d_sweepC), T, W, nrhs, st);
+  }
+  // step 7: inverse transforms into u
+  xform_y(prec, p_invy, nb, max_block_n, tiles_y(d_invy, 16), tiles_y(d_invy, 8), T, W, nrhs, st);
+  xform_lines(prec, 0, out64, acc, p_invx, nb, tiles_lines(d_invx), T, W, u, nrhs, st);
+  if (decomposed) {
+    SigmaGeom g = sg;
+    g.coef = T;
+    sigma_scatter(prec, acc, g, W, u, nrhs, st);
+  }
+}
+
+hs_status Plan::solve(const void* f, void* u, int nrhs, hipStream_t st, std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
+  if (!f || !u) { err = "f and u must be non-NULL"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  if (prec == 0) {
+    solve_pass(f, 1, u, 0, nrhs, st);
+  } else {
+    // complex64 solve, then fixed-count refinement on the FP64 residual
+    void* rbuf = (unsigned char*)ws + off_res;
+    if (f == u) {
+      err = "the mixed-precision solve needs u distinct from f";
+      return HS_ERR_ARG;
+    }
+    solve_pass(f, 1, u, 0, nrhs, st);
+    for (int it = 0; it < refine_steps; ++it) {
+      hs::residual(sten, f, u, rbuf, 0, 0, nrhs, st);
+      solve_pass(rbuf, 0, u, 1, nrhs, st);
+    }
+  }
+  if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+hs_status Plan::solve_adjoint(const void* g, void* a, int nrhs, hipStream_t st, std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
+  if (!g || !a) { err = "g and a must be non-NULL"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  // A^{-H} g = conj(M A^{-1} M^{-1} conj(g)) from the symmetry of M A (eq. (3))
+  void* tmp = (unsigned char*)ws + off_d64;
+  conj_mass(sten, g, tmp, 1, nrhs, st);
+  hs_status s = solve(tmp, a, nrhs, st, err);
+  if (s != HS_OK) return s;
+  conj_mass(sten, a, a, 0, nrhs, st);
+  if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+hs_status Plan::grad_k2(const void* u, const void* a, void* grad, int nrhs, hipStream_t st, std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
+  if (!u || !a || !grad) { err = "u, a and grad must be non-NULL"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  void* sums = (unsigned char*)ws + off_d64 + align_up(int64_t(max_rhs) * NX * NY * NZ * 16, 256);
+  grad_layers((int64_t)NX * NY, NZ, nlayers, dint + i_layer, a, u, sums, grad, nrhs, st);
+  if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+hs_status Plan::residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
+                         std::string& err) {
+  if (nrhs < 1) { err = "nrhs must be >= 1"; return HS_ERR_ARG; }
+  if ((!f && !apply_only) || !u || !r) { err = "arrays must be non-NULL"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  hs::residual(sten, f, u, r, 1, apply_only, nrhs, st);
+  if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+}  // namespace hs

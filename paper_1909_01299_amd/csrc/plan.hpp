@@ -1,0 +1,130 @@
+// Host plan of the separable Helmholtz solver: grid, blocks, FP64 tables,
+// workspace layout, stage descriptors and the enqueue logic of one solve.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/helmsep.h"
+#include "common.hpp"
+#include "eig.hpp"
+#include "kernels.hpp"
+
+namespace hs {
+
+struct Axis {
+  int n = 0;
+  bool sine = false;
+  AxisEig e;
+  int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
+};
+
+struct Block {
+  int bi = 0, bj = 0;            // block column / row
+  int x0 = 0, nbx = 0, y0 = 0, nby = 0;
+  int ax = -1, ay = -1;          // axis table indices
+  int sep_lo_x = -1, sep_hi_x = -1, sep_lo_y = -1, sep_hi_y = -1;
+  int64_t spec = 0;              // workspace offset of the block spectral array
+  int64_t dbuf = 0;              // workspace offset of its forward-sweep scratch
+  int64_t ckpt = 0, ckptC = 0;   // checkpoint regions of its sweeps
+  int64_t partx = 0, party = 0;  // tile partials of its face reductions
+};
+
+template <typename T>
+struct DevArray {
+  T* d = nullptr;
+  int n = 0;
+};
+
+struct Plan {
+  // ---------------- grid
+  int NX = 0, NY = 0, NZ = 0, nlayers = 0;
+  std::vector<cd> hx, hy;
+  std::vector<double> hz;
+  std::vector<int32_t> layer;
+  std::vector<cd> k2;
+  std::vector<int32_t> sepx, sepy;
+  int prec = 0;          // 0 = complex128, 1 = complex64 + FP64 refinement
+  int refine_steps = 0;
+  int max_rhs = 1;
+  int flags = 0;
+  int device = 0;
+  double plan_seconds = 0;
+
+  // ---------------- tables
+  std::vector<Axis> axes;
+  int gax = -1, gay = -1;        // global axes (decomposed grids)
+  std::vector<Block> blocks;
+  int nbx_blocks = 1, nby_blocks = 1;
+  bool decomposed = false;
+  std::vector<cd> htab;          // host FP64 table image
+  int64_t zlo = 0, zdiag = 0, zup = 0;
+  int64_t cx_lo = 0, cx_hi = 0, cy_lo = 0, cy_hi = 0;
+  std::vector<int64_t> lift_cf;  // per block 4 coefficient offsets
+  void* dtab64 = nullptr;
+  void* dtab32 = nullptr;
+  size_t tab_elems = 0;
+  int32_t* dint = nullptr;       // sep_x | sep_y | xblk | xloc | yblk | yloc | layer_of_z
+  int64_t i_sepx = 0, i_sepy = 0, i_xblk = 0, i_xloc = 0, i_yblk = 0, i_yloc = 0, i_layer = 0;
+  double2* dsten = nullptr;      // FP64 stencil arrays
+  StencilGeom sten{};
+  double min_pivot = 0;
+
+  // ---------------- workspace (layout for max_rhs)
+  size_t ws_elems = 0;           // compute-precision complex elements
+  size_t ws_bytes = 0;
+  size_t off_d64 = 0;            // byte offset of the FP64 region
+  size_t off_res = 0;            // byte offset of the complex64 residual (mixed)
+  void* ws = nullptr;
+  int NF = 0;
+  int64_t w_face = 0, w_vface = 0, w_gface = 0, w_Gface = 0;
+  int64_t w_rx = 0, w_ry = 0, w_Rx = 0, w_Ry = 0, w_Qx = 0, w_Qy = 0, w_wx = 0, w_wy = 0;
+  int64_t w_gpartx = 0, w_gparty = 0, w_gckpt = 0, w_gdbuf = 0;
+
+  // ---------------- descriptors (device copies in one buffer)
+  void* ddesc = nullptr;
+  std::vector<XformDesc> d_fwdx, d_invx, d_vface, d_gface, d_glob_in, d_glob_out;
+  std::vector<XformYDesc> d_fwdy, d_invy;
+  std::vector<SweepDesc> d_sweep, d_sweepB, d_sweepC, d_sweepG;
+  std::vector<ReduceDesc> d_redB, d_redG;
+  std::vector<LiftBlock> d_lift;
+  // device pointers of each list
+  const XformDesc *p_fwdx = nullptr, *p_invx = nullptr, *p_vface = nullptr, *p_gface = nullptr,
+                  *p_glob_in = nullptr, *p_glob_out = nullptr;
+  const XformYDesc *p_fwdy = nullptr, *p_invy = nullptr;
+  const SweepDesc *p_sweep = nullptr, *p_sweepB = nullptr, *p_sweepC = nullptr, *p_sweepG = nullptr;
+  const ReduceDesc *p_redB = nullptr, *p_redG = nullptr;
+  const LiftBlock* p_lift = nullptr;
+  SigmaGeom sg{};
+  int64_t redB_max = 0, redG_max = 0;
+  int max_block_n = 0;
+
+  ~Plan();
+  hs_status build(const hs_grid* g, const hs_blocks* b, const hs_options* o, std::string& err);
+  hs_status set_k2(const double* k2v, std::string& err);
+  hs_status bind(void* p, size_t bytes, std::string& err);
+
+  hs_status solve(const void* f, void* u, int nrhs, hipStream_t st, std::string& err);
+  hs_status solve_adjoint(const void* g, void* a, int nrhs, hipStream_t st, std::string& err);
+  hs_status grad_k2(const void* u, const void* a, void* grad, int nrhs, hipStream_t st, std::string& err);
+  hs_status residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
+                     std::string& err);
+
+  // one pass of the block (or decomposed) solver in compute precision
+  void solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st);
+
+ private:
+  hs_status build_tables(std::string& err);
+  void build_z_tables();
+  void build_stencil_host(std::vector<double2>& out);
+  void layout_workspace();
+  void build_descriptors();
+  hs_status upload(std::string& err);
+  hs_status scan_pivots(std::string& err);
+  const void* tab() const { return prec == 0 ? dtab64 : dtab32; }
+};
+
+}  // namespace hs

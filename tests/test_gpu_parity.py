@@ -1,0 +1,215 @@
+"""GPU parity of the HIP solver against the FP64 oracle (through the C ABI).
+
+Tolerances: relative 2-norm error 1e-10 for the complex128 path and 1e-8 for
+the complex64 + FP64-refinement path, per right-hand side.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint, cyclic, direct, operator, separable
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-10
+TOL64R = 1e-8
+
+
+def dev(a):
+    import paper_1909_01299_amd as hs
+    return hs.to_device(a)
+
+
+def per_rhs_err(u, ref):
+    u = np.asarray(u)
+    ref = np.asarray(ref)
+    if u.ndim == 3:
+        return operator.rel_err(u, ref)
+    return max(operator.rel_err(u[r], ref[r]) for r in range(u.shape[0]))
+
+
+# ------------------------------------------------------------------ single block
+
+def test_c1_single_block_vs_sparse_lu(hs):
+    p, f = W.c1_single_block()
+    plan = hs.Plan(p, "c128")
+    u = plan.solve(dev(f)).cpu().numpy()
+    ref = direct.solve_splu(p, f)
+    assert per_rhs_err(u, ref) < TOL128
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 5, 3), (17, 1, 9), (33, 31, 18), (16, 48, 40)])
+def test_uniform_block_shapes_vs_oracle(hs, shape):
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 1000 + ny * 10 + nz)
+    p = W.uniform_problem(nx, ny, nz, max(1, min(4, nz)), rng)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, "c128", max_rhs=2)
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+
+
+@pytest.mark.parametrize("cfg", [dict(nx=20, ny=18, nz=24, px=3, py=2),
+                                 dict(nx=47, ny=33, nz=35, px=6, py=4)])
+def test_nonuniform_block_vs_oracle(hs, cfg):
+    rng = np.random.default_rng(cfg["nx"])
+    p = W.random_problem(cfg["nx"], cfg["ny"], cfg["nz"], 4, rng, pml_x=cfg["px"], pml_y=cfg["py"])
+    f = W.complex_normal(rng, (3,) + p.shape)
+    plan = hs.Plan(p, "c128", max_rhs=3)
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+
+
+def test_dense_path_on_uniform_axes_matches_sine_path(hs):
+    rng = np.random.default_rng(3)
+    p = W.uniform_problem(40, 24, 20, 2, rng)
+    f = W.complex_normal(rng, (1,) + p.shape)
+    u1 = hs.Plan(p, "c128").solve(dev(f)).cpu().numpy()
+    u2 = hs.Plan(p, "c128", force_dense=True).solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u1, u2) < TOL128
+
+
+def test_manufactured_solution_and_stencil(hs):
+    rng = np.random.default_rng(11)
+    p = W.random_problem(30, 26, 22, 3, rng, pml_x=4, pml_y=3)
+    ustar = W.complex_normal(rng, p.shape)
+    plan = hs.Plan(p, "c128")
+    au = plan.apply(dev(ustar[None])).cpu().numpy()[0]
+    ref = operator.apply_A(p, ustar)
+    assert operator.rel_err(au, ref) < 1e-14
+    u = plan.solve(dev(ref[None])).cpu().numpy()[0]
+    assert operator.rel_err(u, ustar) < TOL128
+    r = plan.residual(dev(ref[None]), dev(u[None])).cpu().numpy()[0]
+    assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(ref)
+
+
+# ------------------------------------------------------------------ decomposition
+
+DECOMP = [
+    dict(nx=13, ny=11, nz=6, sx=[4, 8], sy=[5], pml=2),
+    dict(nx=17, ny=17, nz=5, sx=[3, 8, 13], sy=[3, 8, 13], pml=3),
+    dict(nx=40, ny=37, nz=21, sx=[5, 20, 34], sy=[18], pml=5),
+]
+
+
+@pytest.mark.parametrize("cfg", DECOMP)
+def test_decomposed_vs_sparse_lu(hs, cfg):
+    rng = np.random.default_rng(cfg["nx"] + cfg["ny"])
+    p = W.random_problem(cfg["nx"], cfg["ny"], cfg["nz"], 3, rng, sep_x=cfg["sx"], sep_y=cfg["sy"],
+                         pml_x=cfg["pml"], pml_y=cfg["pml"])
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, "c128", max_rhs=2)
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, direct.solve_splu(p, f)) < TOL128
+
+
+def test_decomposed_reduced_c2_point_source_on_interface(hs):
+    """The C2 layout at reduced size (core 32, PML 4): the centre source sits on
+    a separator crossing, so the whole answer comes from the interface steps."""
+    p, f = W.c2_decomposed(core_cells=32, pml_cells=4, nz=30, nlayers=5)
+    assert p.sep_x[1] == p.nx // 2
+    plan = hs.Plan(p, "c128")
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+    # off-interface source too
+    g = W.point_source(p.shape, 10, 12, 7)[None]
+    u2 = plan.solve(dev(g)).cpu().numpy()
+    assert per_rhs_err(u2, separable.solve(p, g)) < TOL128
+
+
+def test_decomposed_matches_seven_step_intermediates_via_result(hs):
+    rng = np.random.default_rng(21)
+    p = W.random_problem(23, 19, 9, 2, rng, sep_x=[6, 14], sep_y=[9], pml_x=3, pml_y=3)
+    f = W.complex_normal(rng, (1,) + p.shape)
+    u_ref, inter = cyclic.seven_step(p, f)
+    u = hs.Plan(p, "c128").solve(dev(f)).cpu().numpy()
+    on = operator.sigma_mask(p)
+    # u on the interfaces equals w there (step 5), inside it equals v + w (step 7)
+    assert np.abs(u[0][on] - inter["w_sigma"][0][on]).max() < 1e-10 * np.abs(u_ref).max()
+    assert per_rhs_err(u, u_ref) < TOL128
+
+
+# ------------------------------------------------------------------ adjoint and gradient
+
+def test_adjoint_vs_oracle_and_dot_product(hs):
+    rng = np.random.default_rng(5)
+    p = W.random_problem(21, 18, 16, 3, rng, pml_x=3, pml_y=2)
+    g = W.complex_normal(rng, (1,) + p.shape)
+    f = W.complex_normal(rng, (1,) + p.shape)
+    plan = hs.Plan(p, "c128")
+    a = plan.solve_adjoint(dev(g)).cpu().numpy()
+    assert per_rhs_err(a, adjoint.solve_adjoint(p, g)) < TOL128
+    u = plan.solve(dev(f)).cpu().numpy()
+    lhs = np.vdot(g, u)
+    rhs = np.vdot(a, f)
+    assert abs(lhs - rhs) < 1e-11 * abs(lhs)
+
+
+def test_adjoint_decomposed_vs_sparse_lu(hs):
+    rng = np.random.default_rng(6)
+    p = W.random_problem(19, 15, 8, 2, rng, sep_x=[6, 12], sep_y=[7], pml_x=3, pml_y=2)
+    g = W.complex_normal(rng, (1,) + p.shape)
+    a = hs.Plan(p, "c128").solve_adjoint(dev(g)).cpu().numpy()
+    assert per_rhs_err(a, direct.solve_adjoint_splu(p, g)) < TOL128
+
+
+def test_grad_k2_vs_oracle(hs):
+    rng = np.random.default_rng(8)
+    p = W.random_problem(16, 14, 20, 5, rng, pml_x=2, pml_y=2)
+    f = W.point_source(p.shape, 7, 6, 3)
+    d = separable.solve(p.with_k2(p.k2 * 1.07), f)[9]
+    J, g_ref, u_ref, a_ref = adjoint.plane_misfit_grad(p, f, 9, d)
+    plan = hs.Plan(p, "c128")
+    u = plan.solve(dev(f[None]))
+    resid = np.zeros((1,) + p.shape, complex)
+    resid[0, 9] = u.cpu().numpy()[0, 9] - d
+    a = plan.solve_adjoint(dev(resid))
+    g = plan.grad_k2(u, a).cpu().numpy()[0]
+    assert np.abs(g - g_ref).max() < 1e-8 * np.abs(g_ref).max()
+
+
+def test_autograd_function_matches_finite_differences(hs):
+    import torch
+    rng = np.random.default_rng(9)
+    p = W.random_problem(12, 11, 16, 4, rng)
+    f = W.point_source(p.shape, 5, 5, 3)[None]
+    d = separable.solve(p.with_k2(p.k2 * 0.95), f[0])[6]
+    plan = hs.Plan(p, "c128")
+    k2 = torch.tensor(p.k2, dtype=torch.complex128, requires_grad=True)
+    u = hs.helmholtz_solve(k2, dev(f), plan)
+    J = 0.5 * (u[0, 6] - dev(d)).abs().pow(2).sum()
+    J.backward()
+    g = k2.grad.numpy()
+    for l in range(p.nlayers):
+        eps = 1e-6 * abs(p.k2[l])
+        fd = []
+        for dirn in (1.0, 1j):
+            vals = []
+            for sgn in (1, -1):
+                kk = p.k2.copy()
+                kk[l] += sgn * eps * dirn
+                Jv, _ = adjoint.plane_misfit(p.with_k2(kk), f[0], 6, d)
+                vals.append(Jv)
+            fd.append((vals[0] - vals[1]) / (2 * eps))
+        fdc = fd[0] + 1j * fd[1]
+        assert abs(g[l] - fdc) < 1e-6 * max(abs(fdc), 1e-3 * float(J))
+
+
+# ------------------------------------------------------------------ mixed precision
+
+def test_mixed_precision_single_block(hs):
+    rng = np.random.default_rng(12)
+    p = W.random_problem(40, 36, 48, 4, rng, pml_x=5, pml_y=4)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, "mixed", max_rhs=2)
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL64R
+
+
+def test_mixed_precision_decomposed(hs):
+    p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=40, nlayers=6)
+    rng = np.random.default_rng(13)
+    f = f + 0.1 * W.complex_normal(rng, f.shape)
+    plan = hs.Plan(p, "mixed")
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL64R
