@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the separable Helmholtz solver on one MI355X.
+
+Workload (one step = one full solve of the decomposed grid):
+  uniform core 256 x 256 (h = 1) + 16 PML cells per side (steps 1.2^k (1+0.5i)),
+  287 x 287 interior nodes, nz = 200 in 20 layers, 4 x 4 blocks (separators at
+  15, 143, 271 on x and y) solved by the two-level interface reduction;
+  unit point source at the grid centre; complex128.  Inputs are resident in
+  HBM before the timed region.
+
+Prints one JSON line: unknowns*RHS/s of the complex128 solve, the mixed
+complex64 + FP64-refinement solve beside it, the roofline of the dominant
+kernel from hipEvents recorded on the solve's stream, and the FP64 CPU oracle
+timed on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12            # B/s
+PEAK_F64 = 78.6e12           # flop/s, FP64 vector = FP64 MFMA on MI355X
+PEAK_F32 = 157.3e12          # flop/s, FP32
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1909_01299_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1909_01299_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def time_solves(plan, f, u, steps, warmup, profile=True):
+    import torch
+    for _ in range(warmup):
+        plan.solve(f, out=u)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+        plan.profile_read()          # reset accumulators
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve(f, out=u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = plan.profile_read() if profile else []
+    if profile:
+        plan.profile(False)
+    return dt, stages
+
+
+def roofline(stages, prec):
+    """Dominant stage by total time; bound from its algorithmic bytes/flops."""
+    if not stages:
+        return None
+    top = max(stages, key=lambda s: s["ms"])
+    avg_s = top["ms"] / top["launches"] / 1e3
+    peak_flops = PEAK_F64 if prec == "c128" else PEAK_F32
+    t_mem = top["bytes_per_launch"] / PEAK_HBM
+    t_alu = top["flops_per_launch"] / peak_flops
+    name = top["name"]
+    if t_mem >= t_alu:
+        bound, achieved, peak, unit = "hbm", top["bytes_per_launch"] / avg_s / 1e9, PEAK_HBM / 1e9, "GB/s"
+    else:
+        bound = "mfma" if name.startswith("xform") or "xform" in name else "alu"
+        achieved, peak, unit = top["flops_per_launch"] / avg_s / 1e12, peak_flops / 1e12, "TFLOP/s"
+    return {"kernel": name, "bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4), "avg_launch_us": round(avg_s * 1e6, 2),
+            "bytes_per_launch": top["bytes_per_launch"], "flops_per_launch": top["flops_per_launch"]}
+
+
+def traffic_for(kernel_stage: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, only while the kernel sources are unchanged."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    rec = d.get("stages", {}).get(kernel_stage)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, f, repeat_budget_s=20.0):
+    """The FP64 oracle (undecomposed generalized-eigen separable solve) on the
+    host: plan (eigendecomposition) excluded, solve timed."""
+    from oracle import separable
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    t0 = time.perf_counter()
+    solver = separable.SeparableSolver(problem)
+    t_plan = time.perf_counter() - t0
+    times = []
+    u = None
+    while True:
+        t0 = time.perf_counter()
+        u = solver.solve(f)
+        times.append(time.perf_counter() - t0)
+        if sum(times) > repeat_budget_s / 2 or len(times) >= 3:
+            break
+    t = float(np.median(times))
+    return u, {"value": problem.unknowns * f.shape[0] / t, "unit": "unknowns*RHS/s", "cores": cores,
+               "kind": "oracle", "sample": f"full workload, {f.shape[0]} RHS, median of {len(times)} solves "
+                                         f"({t:.2f} s each; eigen tables {t_plan:.2f} s excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--core", type=int, default=256, help="uniform core cells per axis")
+    ap.add_argument("--pml", type=int, default=16)
+    ap.add_argument("--nz", type=int, default=200)
+    ap.add_argument("--layers", type=int, default=20)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver has no multi-GPU path "
+              "(sharding by right-hand side and frequency needs no communication; "
+              "see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
+    nrhs = f_np.shape[0]
+    f = hs.to_device(f_np)
+    u = torch.empty_like(f)
+
+    plan = hs.Plan(p, "c128", max_rhs=nrhs)
+    info = plan.info()
+    dt, stages = time_solves(plan, f, u, args.steps, args.warmup)
+    ms = dt / args.steps * 1e3
+    value = p.unknowns * nrhs / (dt / args.steps)
+    u_gpu = u.cpu().numpy()
+
+    mixed = None
+    if not args.no_mixed:
+        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs)
+        um = torch.empty_like(f)
+        dtm, stages_m = time_solves(plan_m, f, um, args.steps, args.warmup)
+        mixed = {"value": p.unknowns * nrhs / (dtm / args.steps), "ms_per_step": dtm / args.steps * 1e3,
+                 "refine_steps": plan_m.info()["refine_steps"], "u": um.cpu().numpy(),
+                 "roofline": roofline(stages_m, "c64")}
+        del plan_m
+
+    cpu = None
+    rel_err = rel_err_mixed = None
+    if not args.no_cpu_baseline:
+        u_ref, cpu = cpu_baseline(p, f_np)
+        rel_err = float(np.linalg.norm(u_gpu - u_ref) / np.linalg.norm(u_ref))
+        if mixed is not None:
+            rel_err_mixed = float(np.linalg.norm(mixed["u"] - u_ref) / np.linalg.norm(u_ref))
+
+    rf = roofline(stages, "c128")
+    if rf is not None:
+        rf["traffic"] = traffic_for(rf["kernel"])
+    line = {
+        "metric": "unknowns*RHS/s (decomposed 3D Helmholtz solve, complex128)",
+        "value": value,
+        "unit": "unknowns*RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"c2_decomposed {p.nx}x{p.ny}x{p.nz}, 4x4 blocks + interface reduction, "
+                               f"PML {args.pml}/side, {args.layers} layers, centre point source",
+                   "unknowns": p.unknowns, "nrhs": nrhs, "blocks": info["nblocks"]},
+        "rel_err_vs_oracle": rel_err,
+        "roofline": rf,
+        "cpu_baseline": cpu,
+        "mixed_c64_refine": None if mixed is None else {
+            "value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
+            "refine_steps": mixed["refine_steps"], "rel_err_vs_oracle": rel_err_mixed,
+            "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"]},
+        "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
+        "plan_seconds": info["plan_seconds"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

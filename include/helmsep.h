@@ -152,6 +152,25 @@ hs_status hs_apply(hs_plan plan, const void* u, void* out, int32_t nrhs, void* s
 
 hs_status hs_get_info(hs_plan plan, hs_info* info);
 
+/* Per-stage timing.  While enabled, every stage of a solve is bracketed by
+ * hipEvents recorded on the solve's stream (events come from a pool created
+ * here, so solves still allocate nothing).  hs_profile_read synchronizes on
+ * the recorded events and returns, per stage, the accumulated milliseconds,
+ * the number of launches and the algorithmic bytes and flops of one launch
+ * (compulsory reads and writes of the stage's inputs and outputs; 8 flops per
+ * complex multiply-add of a dense transform, the Thomas count of a z sweep).
+ * Reading resets the accumulators. */
+typedef struct {
+  char name[32];
+  double ms;
+  int64_t launches;
+  double bytes_per_launch;
+  double flops_per_launch;
+} hs_stage_time;
+
+hs_status hs_profile_enable(hs_plan plan, int32_t on);
+hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int32_t* n_out);
+
 /* Batched solve of many independent plans (one block each, any sizes) and
  * right-hand sides, enqueued as one captured HIP graph per call.
  * nrhs[i] right-hand sides for plans[i]; the plans must outlive the batch and

@@ -59,6 +59,11 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class StageTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("ms", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("bytes_per_launch", ctypes.c_double), ("flops_per_launch", ctypes.c_double)]
+
+
 EXPORTS = {
     "hs_plan_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hs_plan_destroy": (None, [ctypes.c_void_p]),
@@ -76,6 +81,8 @@ EXPORTS = {
     "hs_batch_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
+    "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "hs_axis_eig": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5),
     "hs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "hs_last_error": (ctypes.c_char_p, []),
@@ -195,6 +202,19 @@ class Plan:
         inf = Info()
         _check(lib().hs_get_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def profile(self, on: bool = True):
+        """Record hipEvents around every stage of subsequent solves."""
+        _check(lib().hs_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self) -> list:
+        """Per-stage accumulated time since the last read (synchronizes)."""
+        buf = (StageTime * 64)()
+        n = ctypes.c_int32()
+        _check(lib().hs_profile_read(self._h, buf, 64, ctypes.byref(n)))
+        return [dict(name=buf[i].name.decode(), ms=buf[i].ms, launches=buf[i].launches,
+                     bytes_per_launch=buf[i].bytes_per_launch, flops_per_launch=buf[i].flops_per_launch)
+                for i in range(min(n.value, 64))]
 
     def set_k2(self, k2):
         k2 = np.ascontiguousarray(np.asarray(k2, np.complex128))

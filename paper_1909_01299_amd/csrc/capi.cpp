@@ -128,6 +128,21 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   return ret(HS_OK, "");
 }
 
+hs_status hs_profile_enable(hs_plan plan, int32_t on) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.profile_enable(on != 0, err), err);
+}
+
+hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int32_t* n_out) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  int n = 0;
+  hs_status s = plan->p.profile_read(out, max_out, &n, err);
+  if (n_out) *n_out = n;
+  return ret(s, err);
+}
+
 hs_status hs_axis_eig(int32_t n, const double* h, double* lam, double* W, double* Winv, double* stats) {
   if (n < 1 || n > 4096 || !h || !lam || !W || !Winv) return ret(HS_ERR_ARG, "invalid arguments");
   std::vector<hs::cd> hv(n + 1);

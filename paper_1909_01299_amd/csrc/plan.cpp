@@ -50,6 +50,7 @@ bool check_seps(int n, const std::vector<int32_t>& s, std::string& err, const ch
 }  // namespace
 
 Plan::~Plan() {
+  for (auto e : ev_pool) (void)hipEventDestroy(e);
   if (dtab64) (void)hipFree(dtab64);
   if (dtab32) (void)hipFree(dtab32);
   if (dint) (void)hipFree(dint);
@@ -678,6 +679,78 @@ hs_status Plan::bind(void* p, size_t bytes, std::string& err) {
   return HS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// per-stage event timing
+// ---------------------------------------------------------------------------
+hs_status Plan::profile_enable(bool on, std::string& err) {
+  if (on && ev_pool.empty()) {
+    if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+    ev_pool.resize(8192);
+    for (auto& e : ev_pool)
+      if (hipEventCreate(&e) != hipSuccess) { err = "hipEventCreate failed"; return HS_ERR_DEVICE; }
+  }
+  prof_on = on;
+  return HS_OK;
+}
+
+void Plan::stage_begin(const char* name, double bytes, double flops, hipStream_t st) {
+  if (!prof_on) return;
+  int id = -1;
+  for (size_t i = 0; i < prof.size(); ++i)
+    if (prof[i].name == name) { id = int(i); break; }
+  if (id < 0) {
+    StageProf p;
+    p.name = name;
+    prof.push_back(p);
+    id = int(prof.size()) - 1;
+  }
+  prof[id].bytes = bytes;
+  prof[id].flops = flops;
+  if (ev_next + 2 > ev_pool.size()) { cur_stage = -1; return; }
+  hipEvent_t a = ev_pool[ev_next++], b = ev_pool[ev_next++];
+  (void)hipEventRecord(a, st);
+  ev_pending.push_back({id, {a, b}});
+  cur_stage = id;
+  cur_stream = st;
+}
+
+void Plan::stage_end() {
+  if (!prof_on || cur_stage < 0) return;
+  (void)hipEventRecord(ev_pending.back().second.second, cur_stream);
+  cur_stage = -1;
+}
+
+hs_status Plan::profile_read(hs_stage_time* out, int max_out, int* n_out, std::string& err) {
+  for (auto& pe : ev_pending) {
+    float ms = 0;
+    if (hipEventSynchronize(pe.second.second) != hipSuccess ||
+        hipEventElapsedTime(&ms, pe.second.first, pe.second.second) != hipSuccess) {
+      err = "event timing failed";
+      return HS_ERR_DEVICE;
+    }
+    prof[pe.first].ms += ms;
+    prof[pe.first].launches += 1;
+  }
+  ev_pending.clear();
+  ev_next = 0;
+  int n = 0;
+  for (auto& p : prof) {
+    if (p.launches == 0) continue;
+    if (out && n < max_out) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, p.name.c_str(), sizeof(out[n].name) - 1);
+      out[n].ms = p.ms;
+      out[n].launches = p.launches;
+      out[n].bytes_per_launch = p.bytes;
+      out[n].flops_per_launch = p.flops;
+    }
+    ++n;
+  }
+  if (n_out) *n_out = n;
+  for (auto& p : prof) { p.ms = 0; p.launches = 0; }
+  return HS_OK;
+}
+
 void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st) {
   const void* T = tab();
   void* W = ws;
@@ -697,38 +770,92 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     for (auto& d : v) m = std::max(m, d.tiles_a * d.tiles_b);
     return m;
   };
+  // algorithmic work of the stages (per call, all right-hand sides)
+  const double R = nrhs;
+  const double esz = prec == 0 ? 16.0 : 8.0;
+  const double esz_in = in64 ? 16.0 : 8.0;
+  double nblk = 0, fx = 0, fy = 0, nface = 0;
+  for (auto& B : blocks) {
+    const double nbv = double(NZ) * B.nbx * B.nby;
+    nblk += nbv;
+    fx += nbv * 8.0 * B.nbx;
+    fy += nbv * 8.0 * B.nby;
+    nface += double(NZ) * 2.0 * (B.nbx + B.nby);
+  }
+  const double thomas = 44.0;   // flops per node of one z solve
   const int out64 = 1;
-  // steps 1: forward transforms of every block
+  // step 1: forward transforms of every block
+  stage_begin("xform_x_fwd", R * nblk * (esz_in + esz), R * fx, st);
   xform_lines(prec, in64, 0, 0, p_fwdx, nb, tiles_lines(d_fwdx), T, f, W, nrhs, st);
+  stage_end();
+  stage_begin("xform_y_fwd", R * nblk * 2 * esz, R * fy, st);
   xform_y(prec, p_fwdy, nb, max_block_n, tiles_y(d_fwdy, 16), tiles_y(d_fwdy, 8), T, W, nrhs, st);
+  stage_end();
   if (!decomposed) {
+    stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweep, nb, tiles_sw(d_sweep), T, W, nrhs, st);
+    stage_end();
   } else {
+    const double nsx = double(sepx.size()), nsy = double(sepy.size());
+    const double nsig = double(NZ) * (nsx * NY + nsy * NX);
+    const double nglob = double(NX) * NY * NZ;
     // steps 2-3: block sweeps, v on the lines next to the separators
+    stage_begin("zsweep_blocks_v", R * (nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepB, nb, tiles_sw(d_sweepB), T, W, nrhs, st);
+    stage_end();
+    stage_begin("face_reduce", R * nface * 2 * esz, 0, st);
     reduce_partials(prec, p_redB, int(d_redB.size()), redB_max, W, nrhs, st);
+    stage_end();
+    double ffl = 0;
+    for (auto& B : blocks) ffl += double(NZ) * 2.0 * (double(B.nby) * B.nby + double(B.nbx) * B.nbx) * 8.0;
+    stage_begin("face_xform", R * nface * 2 * esz, R * ffl, st);
     xform_lines(prec, 0, 0, 0, p_vface, int(d_vface.size()), tiles_lines(d_vface), T, W, W, nrhs, st);
+    stage_end();
     // step 4: residual on the separators
     SigmaGeom g = sg;
     g.coef = T;
+    stage_begin("sigma_resid", R * nsig * (esz_in + 3 * esz), R * nsig * 16, st);
     sigma_resid(prec, in64, g, f, W, nrhs, st);
+    stage_end();
     // step 5: global interface solve, evaluated on the separators
+    const double gfl = double(NZ) * (nsx * double(NY) * NY + nsy * double(NX) * NX) * 8.0;
+    stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
     xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
+    stage_end();
+    stage_begin("zsweep_global", R * nsig * 2 * esz, R * nglob * (thomas + 16 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, tiles_sw(d_sweepG), T, W, nrhs, st);
+    stage_end();
+    stage_begin("sigma_reduce", R * nsig * 2 * esz, 0, st);
     reduce_partials(prec, p_redG, int(d_redG.size()), redG_max, W, nrhs, st);
+    stage_end();
+    stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
     xform_lines(prec, 0, 0, 0, p_glob_out, int(d_glob_out.size()), tiles_lines(d_glob_out), T, W, W, nrhs, st);
+    stage_end();
     // step 6: lift the separator values into the blocks and sweep again
+    stage_begin("lift", R * nface * 2 * esz, R * nface * 6, st);
     lift(prec, g, p_lift, nb, W, nrhs, st);
+    stage_end();
+    stage_begin("lift_xform", R * nface * 2 * esz, R * ffl, st);
     xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
+    stage_end();
+    stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, tiles_sw(d_sweepC), T, W, nrhs, st);
+    stage_end();
   }
   // step 7: inverse transforms into u
+  stage_begin("xform_y_inv", R * nblk * 2 * esz, R * fy, st);
   xform_y(prec, p_invy, nb, max_block_n, tiles_y(d_invy, 16), tiles_y(d_invy, 8), T, W, nrhs, st);
+  stage_end();
+  stage_begin("xform_x_inv", R * nblk * (esz + 16 + (acc ? 16 : 0)), R * fx, st);
   xform_lines(prec, 0, out64, acc, p_invx, nb, tiles_lines(d_invx), T, W, u, nrhs, st);
+  stage_end();
   if (decomposed) {
     SigmaGeom g = sg;
     g.coef = T;
+    const double nsig = double(NZ) * (double(sepx.size()) * NY + double(sepy.size()) * NX);
+    stage_begin("sigma_scatter", R * nsig * (esz + 16 + (acc ? 16 : 0)), 0, st);
     sigma_scatter(prec, acc, g, W, u, nrhs, st);
+    stage_end();
   }
 }
 
@@ -747,8 +874,11 @@ hs_status Plan::solve(const void* f, void* u, int nrhs, hipStream_t st, std::str
       return HS_ERR_ARG;
     }
     solve_pass(f, 1, u, 0, nrhs, st);
+    const double N = double(NX) * NY * NZ;
     for (int it = 0; it < refine_steps; ++it) {
+      stage_begin("residual_fp64", double(nrhs) * N * 40.0, double(nrhs) * N * 62.0, st);
       hs::residual(sten, f, u, rbuf, 0, 0, nrhs, st);
+      stage_end();
       solve_pass(rbuf, 0, u, 1, nrhs, st);
     }
   }
@@ -763,10 +893,15 @@ hs_status Plan::solve_adjoint(const void* g, void* a, int nrhs, hipStream_t st, 
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
   // A^{-H} g = conj(M A^{-1} M^{-1} conj(g)) from the symmetry of M A (eq. (3))
   void* tmp = (unsigned char*)ws + off_d64;
+  const double N = double(NX) * NY * NZ;
+  stage_begin("adjoint_pre", double(nrhs) * N * 32.0, double(nrhs) * N * 16.0, st);
   conj_mass(sten, g, tmp, 1, nrhs, st);
+  stage_end();
   hs_status s = solve(tmp, a, nrhs, st, err);
   if (s != HS_OK) return s;
+  stage_begin("adjoint_post", double(nrhs) * N * 32.0, double(nrhs) * N * 16.0, st);
   conj_mass(sten, a, a, 0, nrhs, st);
+  stage_end();
   if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
   return HS_OK;
 }

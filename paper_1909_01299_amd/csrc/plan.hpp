@@ -39,6 +39,13 @@ struct DevArray {
   int n = 0;
 };
 
+struct StageProf {
+  std::string name;
+  double ms = 0;
+  int64_t launches = 0;
+  double bytes = 0, flops = 0;   // per launch, algorithmic
+};
+
 struct Plan {
   // ---------------- grid
   int NX = 0, NY = 0, NZ = 0, nlayers = 0;
@@ -101,6 +108,19 @@ struct Plan {
   SigmaGeom sg{};
   int64_t redB_max = 0, redG_max = 0;
   int max_block_n = 0;
+
+  // ---------------- per-stage event timing
+  bool prof_on = false;
+  std::vector<StageProf> prof;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+  size_t ev_next = 0;
+  int cur_stage = -1;
+  hipStream_t cur_stream = nullptr;
+  hs_status profile_enable(bool on, std::string& err);
+  hs_status profile_read(hs_stage_time* out, int max_out, int* n_out, std::string& err);
+  void stage_begin(const char* name, double bytes, double flops, hipStream_t st);
+  void stage_end();
 
   ~Plan();
   hs_status build(const hs_grid* g, const hs_blocks* b, const hs_options* o, std::string& err);
