@@ -91,6 +91,16 @@ struct XformYDesc {
   int64_t data, s_r, s_p, s_k;
 };
 
+// Orthonormal sine transform (DST-I, n = N - 1 points, N a power of two) of
+// lines (p, q) of one RHS r; element i of a line sits at
+//   base + r*_r + p*_p + q*_q + i*_i      (for src and dst separately).
+// Used on uniform axes in place of the dense table (same matrix).
+struct DstDesc {
+  int32_t n, P, Q, pad_;
+  int64_t src, src_r, src_p, src_q, src_i;
+  int64_t dst, dst_r, dst_p, dst_q, dst_i;
+};
+
 // One batched z sweep over the (a, b) modes of a block.
 //  rhs(a,b,z,r) = [dense ? data(r,z,b,a) : 0]
 //               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)

@@ -123,6 +123,183 @@ __global__ __launch_bounds__(256) void k_xform_y(const XformYDesc* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Orthonormal DST-I of length n = N - 1 (N = 8 V a power of two) through the
+// complex FFT of the odd extension y (y_0 = y_N = 0, y_j = x_j, y_{2N-j} = -x_j):
+// Y_m = -2i sum_j x_j sin(pi j m / N), so X_m = sqrt(2/N) (i/2) Y_m.
+// The length L = 2N = 16 V FFT is split 16 x V: each of 16 lanes per line
+// runs a V-point FFT in registers over y[t + 16 v], applies the twiddles
+// W_L^{t k2}, exchanges through a padded LDS row, and finishes with 16-point
+// FFTs over t.  A workgroup stages whole lines in LDS, so the same kernel
+// serves contiguous x lines and strided y lines (and runs in place).
+// ---------------------------------------------------------------------------
+constexpr int TW_N = 512;   // tw[k] = exp(-2 pi i k / 512)
+
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+__host__ __device__ constexpr int bitrevc(int i, int lg) {
+  int r = 0;
+  for (int b = 0; b < lg; ++b) r |= ((i >> b) & 1) << (lg - 1 - b);
+  return r;
+}
+
+// In-place radix-2 decimation-in-time FFT of V register values (natural order in and out).
+template <typename C, int V>
+__device__ __forceinline__ void fft_reg(C (&a)[V], const C* __restrict__ tw) {
+  constexpr int LG = ilog2c(V);
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int j = bitrevc(i, LG);
+    if (j > i) {
+      C t = a[i];
+      a[i] = a[j];
+      a[j] = t;
+    }
+  }
+#pragma unroll
+  for (int len = 2; len <= V; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < V; i += len) {
+#pragma unroll
+      for (int k = 0; k < len / 2; ++k) {
+        const C u = a[i + k];
+        const C v = a[i + k + len / 2];
+        C t;
+        if (k == 0) {
+          t = v;
+        } else if (4 * k == len) {  // multiply by -i
+          t.x = v.y;
+          t.y = -v.x;
+        } else {
+          t = cmul(v, tw[k * (TW_N / len)]);
+        }
+        a[i + k] = cadd(u, t);
+        a[i + k + len / 2] = csub(u, t);
+      }
+    }
+  }
+}
+
+template <typename R, typename CI, typename CO, bool ACC, int V>
+__global__ __launch_bounds__(256) void k_dst(const DstDesc* __restrict__ descs, const cplx<R>* __restrict__ tw,
+                                             const CI* __restrict__ src, CO* __restrict__ dst, int lt) {
+  using C = cplx<R>;
+  constexpr int L = 16 * V;
+  constexpr int N = L / 2;
+  constexpr int n = N - 1;
+  constexpr int XS = L + L / 16;   // LDS row: 17 slots per 16 values
+  extern __shared__ unsigned char smem_raw[];
+  C* buf = reinterpret_cast<C*>(smem_raw);
+  const DstDesc d = descs[blockIdx.y];
+  const int lines = d.P * d.Q;
+  const int l0 = blockIdx.x * lt;
+  if (l0 >= lines) return;
+  const int r = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int nthr = lt * 16;
+  const int li = tid >> 4, t = tid & 15;
+  const CI* sb = src + d.src + (int64_t)r * d.src_r;
+  // stage the input lines: buf[l * XS + i]
+  if (d.src_i == 1) {
+    for (int e = tid; e < lt * n; e += nthr) {
+      const int l = e / n, i = e % n, g = l0 + l;
+      if (g < lines) {
+        const int p = g / d.Q, q = g % d.Q;
+        buf[l * XS + i] = cvt<C>(sb[(int64_t)p * d.src_p + (int64_t)q * d.src_q + i]);
+      }
+    }
+  } else {
+    for (int e = tid; e < lt * n; e += nthr) {
+      const int i = e / lt, l = e % lt, g = l0 + l;
+      if (g < lines) {
+        const int p = g / d.Q, q = g % d.Q;
+        buf[l * XS + i] = cvt<C>(sb[(int64_t)p * d.src_p + (int64_t)q * d.src_q + (int64_t)i * d.src_i]);
+      }
+    }
+  }
+  __syncthreads();
+  const C* row = buf + li * XS;
+  C a[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int j = t + 16 * v;
+    C val = mk<R>(0, 0);
+    if (j > 0 && j < N) {
+      val = row[j - 1];
+    } else if (j > N) {
+      val = row[2 * N - j - 1];
+      val.x = -val.x;
+      val.y = -val.y;
+    }
+    a[v] = val;
+  }
+  fft_reg<C, V>(a, tw);
+#pragma unroll
+  for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % L) * (TW_N / L)]);
+  __syncthreads();
+  C* wrow = buf + li * XS;
+#pragma unroll
+  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2];
+  __syncthreads();
+  constexpr int G = V >= 16 ? V / 16 : 1;
+  C b[G][16];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int k2 = t + 16 * g;
+    if (k2 < V) {
+#pragma unroll
+      for (int tt = 0; tt < 16; ++tt) b[g][tt] = wrow[k2 * 17 + tt];
+      fft_reg<C, 16>(b[g], tw);
+    }
+  }
+  __syncthreads();
+  const R sc = R(0.5) * R(sqrt(2.0 / double(N)));
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int k2 = t + 16 * g;
+    if (k2 < V) {
+#pragma unroll
+      for (int k1 = 0; k1 < 16; ++k1) {
+        const int m = k2 + V * k1;
+        if (m >= 1 && m <= n) {
+          C o;
+          o.x = -sc * b[g][k1].y;
+          o.y = sc * b[g][k1].x;
+          wrow[m - 1] = o;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  CO* db = dst + d.dst + (int64_t)r * d.dst_r;
+  auto put = [&](CO* ptr, const C& v) {
+    if (ACC) {
+      CO pv = *ptr;
+      pv.x += v.x;
+      pv.y += v.y;
+      *ptr = pv;
+    } else {
+      *ptr = cvt<CO>(v);
+    }
+  };
+  if (d.dst_i == 1) {
+    for (int e = tid; e < lt * n; e += nthr) {
+      const int l = e / n, i = e % n, g = l0 + l;
+      if (g < lines) {
+        const int p = g / d.Q, q = g % d.Q;
+        put(db + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + i, buf[l * XS + i]);
+      }
+    }
+  } else {
+    for (int e = tid; e < lt * n; e += nthr) {
+      const int i = e / lt, l = e % lt, g = l0 + l;
+      if (g < lines) {
+        const int p = g / d.Q, q = g % d.Q;
+        put(db + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + (int64_t)i * d.dst_i, buf[l * XS + i]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Batched z sweep (Thomas without pivoting) over the modes of a block, one
 // mode per lane; a 16 x 16 tile of (a, b) modes per workgroup.  The forward
 // elimination stores the swept right-hand side; the pivot recurrence is
@@ -169,28 +346,43 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepDesc* __restrict__ des
   const C* zdg = tab + d.zdiag;
   const C* zup = tab + d.zup;
 
-  // forward elimination
+  // forward elimination; each segment's right-hand sides are loaded before
+  // the recurrence runs over them so the loads overlap
   C cprev = mk<R>(0, 0), dprev = mk<R>(0, 0);
   for (int seg = 0; seg < nseg; ++seg) {
     if (act) ck[seg * plane + m] = cprev;
+    const int k0 = seg * SEG;
+    C rb[SEG];
+#pragma unroll
     for (int kk = 0; kk < SEG; ++kk) {
-      const int k = seg * SEG + kk;
-      if (k >= nz) break;
-      const C lo = zlo[k];
-      const C piv = cfms(lo, cprev, cadd(zdg[k], s));
-      const C ip = crcp(piv);
-      C rhs = mk<R>(0, 0);
-      if (act) {
-        if (d.dense_in) rhs = data[k * plane + m];
-        for (int i = 0; i < nxt; ++i)
-          rhs = cfma(cx[i], ws[d.gx[i] + (int64_t)r * d.gx_r + (int64_t)k * d.gx_z + b], rhs);
-        for (int j = 0; j < nyt; ++j)
-          rhs = cfma(cy[j], ws[d.gy[j] + (int64_t)r * d.gy_r + (int64_t)k * d.gy_z + a], rhs);
+      const int k = k0 + kk;
+      rb[kk] = (act && d.dense_in && k < nz) ? data[k * plane + m] : mk<R>(0, 0);
+    }
+    if (act) {
+      for (int i = 0; i < nxt; ++i) {
+        const C* g = ws + d.gx[i] + (int64_t)r * d.gx_r + b;
+#pragma unroll
+        for (int kk = 0; kk < SEG; ++kk)
+          if (k0 + kk < nz) rb[kk] = cfma(cx[i], g[(int64_t)(k0 + kk) * d.gx_z], rb[kk]);
       }
-      const C dd = cmul(cfms(lo, dprev, rhs), ip);
-      if (act) fwd[k * plane + m] = dd;
-      cprev = cmul(zup[k], ip);
-      dprev = dd;
+      for (int j = 0; j < nyt; ++j) {
+        const C* g = ws + d.gy[j] + (int64_t)r * d.gy_r + a;
+#pragma unroll
+        for (int kk = 0; kk < SEG; ++kk)
+          if (k0 + kk < nz) rb[kk] = cfma(cy[j], g[(int64_t)(k0 + kk) * d.gy_z], rb[kk]);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < SEG; ++kk) {
+      const int k = k0 + kk;
+      if (k < nz) {
+        const C lo = zlo[k];
+        const C ip = crcp(cfms(lo, cprev, cadd(zdg[k], s)));
+        const C dd = cmul(cfms(lo, dprev, rb[kk]), ip);
+        if (act) fwd[k * plane + m] = dd;
+        cprev = cmul(zup[k], ip);
+        dprev = dd;
+      }
     }
   }
 
@@ -199,11 +391,17 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepDesc* __restrict__ des
   const int nred = nxr + nyr;
   C xn = mk<R>(0, 0);
   for (int seg = nseg - 1; seg >= 0; --seg) {
-    C cseg[SEG];
+    const int k0 = seg * SEG;
+    C dseg[SEG], cseg[SEG];
+#pragma unroll
+    for (int kk = 0; kk < SEG; ++kk) {
+      const int k = k0 + kk;
+      dseg[kk] = (act && k < nz) ? fwd[k * plane + m] : mk<R>(0, 0);
+    }
     C cp = act ? ck[seg * plane + m] : mk<R>(0, 0);
 #pragma unroll
     for (int kk = 0; kk < SEG; ++kk) {
-      const int k = seg * SEG + kk;
+      const int k = k0 + kk;
       if (k < nz) {
         const C piv = cfms(zlo[k], cp, cadd(zdg[k], s));
         cseg[kk] = cmul(zup[k], crcp(piv));
@@ -214,10 +412,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepDesc* __restrict__ des
     }
 #pragma unroll
     for (int kk = SEG - 1; kk >= 0; --kk) {
-      const int k = seg * SEG + kk;
+      const int k = k0 + kk;
       if (k >= nz) continue;
-      const C dd = act ? fwd[k * plane + m] : mk<R>(0, 0);
-      const C x = cfms(cseg[kk], xn, dd);
+      const C x = cfms(cseg[kk], xn, dseg[kk]);
       xn = x;
       if (act && d.dense_out) data[k * plane + m] = x;
       if (nred > 0) {
@@ -506,6 +703,62 @@ void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int
       launch_lines_t<float, float2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
   } else {
     launch_lines_t<float, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  }
+}
+
+
+// ---------------------------------------------------------------- sine transform
+int dst_lines_per_wg(int prec, int V) {
+  const int L = 16 * V;
+  const int xs = L + L / 16;
+  const int esz = prec == 0 ? 16 : 8;
+  int lt = 65536 / (xs * esz);
+  if (lt > 16) lt = 16;
+  if (lt < 1) lt = 1;
+  return lt;
+}
+
+template <typename R, typename CI, typename CO, bool ACC>
+static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, const void* tw, const void* src,
+                         void* dst, int nrhs, hipStream_t st) {
+  const int prec = sizeof(R) == 8 ? 0 : 1;
+  const int lt = dst_lines_per_wg(prec, V);
+  const size_t lds = size_t(lt) * (16 * V + V) * sizeof(cplx<R>);
+  const dim3 grid((max_lines + lt - 1) / lt, ndesc, nrhs);
+  const dim3 block(16 * lt);
+  const cplx<R>* T = (const cplx<R>*)tw;
+  switch (V) {
+#define HS_DST_CASE(VV)                                                                                  \
+  case VV:                                                                                               \
+    hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV>), grid, block, lds, st, d, T, (const CI*)src, (CO*)dst, lt); \
+    break;
+    HS_DST_CASE(2)
+    HS_DST_CASE(4)
+    HS_DST_CASE(8)
+    HS_DST_CASE(16)
+    HS_DST_CASE(32)
+#undef HS_DST_CASE
+    default:
+      break;
+  }
+}
+
+void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
+               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st) {
+  if (ndesc == 0 || max_lines == 0 || nrhs == 0) return;
+  if (prec == 0) {
+    launch_dst_t<double, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+  } else if (!in64 && !out64) {
+    launch_dst_t<float, float2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+  } else if (in64 && !out64) {
+    launch_dst_t<float, double2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+  } else if (!in64 && out64) {
+    if (acc)
+      launch_dst_t<float, float2, double2, true>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+    else
+      launch_dst_t<float, float2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+  } else {
+    launch_dst_t<float, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
   }
 }
 

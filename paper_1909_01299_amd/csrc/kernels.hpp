@@ -47,6 +47,12 @@ void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int
                  const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
 int xform_lines_tiles(const XformDesc& d);
 
+// Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
+constexpr int kTwiddleN = 512;
+void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
+               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st);
+int dst_lines_per_wg(int prec, int V);
+
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st);
 int xform_y_tiles(const XformYDesc& d, int ct);

@@ -20,6 +20,7 @@ namespace hs {
 namespace {
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+int ilog2i(int v) { int r = 0; while (v > 1) { v >>= 1; ++r; } return r; }
 
 // Maximal runs of interior nodes between separators (inclusive lo, hi).
 std::vector<std::pair<int, int>> runs(int n, const std::vector<int32_t>& seps) {
@@ -143,6 +144,8 @@ hs_status Plan::build_tables(std::string& err) {
     Axis a;
     a.n = n;
     a.sine = axis_is_uniform(n, h) && !(flags & 1);
+    const int N = n + 1;
+    if (a.sine && N >= 16 && N <= 256 && (N & (N - 1)) == 0) a.dstV = N / 8;
     if (axis_is_uniform(n, h)) {
       axis_eig_uniform(n, h[0], a.e);
     } else {
@@ -196,6 +199,15 @@ hs_status Plan::build_tables(std::string& err) {
     a.fwd = push(a.e.Winv);
     a.inv = push(a.e.W);
     a.lam = push(a.e.lam);
+  }
+  {
+    std::vector<cd> tw(kTwiddleN);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 0; k < kTwiddleN; ++k) {
+      const long double ang = -2.0L * pi * (long double)k / (long double)kTwiddleN;
+      tw[k] = cd(double(cosl(ang)), double(sinl(ang)));
+    }
+    twid = push(tw);
   }
   zlo = push(std::vector<cd>(NZ));
   zdiag = push(std::vector<cd>(NZ));
@@ -356,7 +368,8 @@ void Plan::layout_workspace() {
 void Plan::build_descriptors() {
   const int64_t R = max_rhs;
   (void)R;
-  d_fwdx.clear(); d_invx.clear(); d_fwdy.clear(); d_invy.clear(); d_sweep.clear();
+  s_fwdx = {}; s_invx = {}; s_fwdy = {}; s_invy = {};
+  d_sweep.clear();
   d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear(); d_redB.clear(); d_redG.clear();
   d_vface.clear(); d_gface.clear(); d_glob_in.clear(); d_glob_out.clear(); d_lift.clear();
   const int64_t gplane = (int64_t)NX * NY;
@@ -368,24 +381,46 @@ void Plan::build_descriptors() {
     const Axis& AY = axes[B.ay];
     const int64_t plane = (int64_t)B.nbx * B.nby;
     const int64_t spec_r = plane * NZ;
-    XformDesc fx{};
-    fx.tab = AX.fwd; fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
-    fx.src = (int64_t)B.y0 * NX + B.x0; fx.src_r = f_r; fx.src_p = gplane; fx.src_q = NX;
-    fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.nbx;
-    fx.sine = AX.sine;
-    d_fwdx.push_back(fx);
-    XformDesc ix = fx;
-    ix.tab = AX.inv;
-    ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
-    ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
-    d_invx.push_back(ix);
-    XformYDesc fy{};
-    fy.tab = AY.fwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
-    fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.nbx;
-    d_fwdy.push_back(fy);
-    XformYDesc iy = fy;
-    iy.tab = AY.inv;
-    d_invy.push_back(iy);
+    auto vidx = [](int V) { return ilog2i(V) - 1; };
+    if (AX.dstV) {
+      DstDesc dx{};
+      dx.n = B.nbx; dx.P = NZ; dx.Q = B.nby;
+      dx.src = (int64_t)B.y0 * NX + B.x0; dx.src_r = f_r; dx.src_p = gplane; dx.src_q = NX; dx.src_i = 1;
+      dx.dst = B.spec; dx.dst_r = spec_r; dx.dst_p = plane; dx.dst_q = B.nbx; dx.dst_i = 1;
+      s_fwdx.dst[vidx(AX.dstV)].push_back(dx);
+      DstDesc ix = dx;
+      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
+      ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
+      s_invx.dst[vidx(AX.dstV)].push_back(ix);
+    } else {
+      XformDesc fx{};
+      fx.tab = AX.fwd; fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
+      fx.src = (int64_t)B.y0 * NX + B.x0; fx.src_r = f_r; fx.src_p = gplane; fx.src_q = NX;
+      fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.nbx;
+      fx.sine = AX.sine;
+      s_fwdx.dense.push_back(fx);
+      XformDesc ix = fx;
+      ix.tab = AX.inv;
+      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
+      ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
+      s_invx.dense.push_back(ix);
+    }
+    if (AY.dstV) {
+      DstDesc dy{};
+      dy.n = B.nby; dy.P = NZ; dy.Q = B.nbx;
+      dy.src = B.spec; dy.src_r = spec_r; dy.src_p = plane; dy.src_q = 1; dy.src_i = B.nbx;
+      dy.dst = B.spec; dy.dst_r = spec_r; dy.dst_p = plane; dy.dst_q = 1; dy.dst_i = B.nbx;
+      s_fwdy.dst[vidx(AY.dstV)].push_back(dy);
+      s_invy.dst[vidx(AY.dstV)].push_back(dy);
+    } else {
+      XformYDesc fy{};
+      fy.tab = AY.fwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
+      fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.nbx;
+      s_fwdy.dense.push_back(fy);
+      XformYDesc iy = fy;
+      iy.tab = AY.inv;
+      s_invy.dense.push_back(iy);
+    }
 
     SweepDesc s{};
     s.na = B.nbx; s.nb = B.nby; s.nz = NZ;
@@ -612,9 +647,18 @@ hs_status Plan::upload(std::string& err) {
     size_t o = dpush(v.data(), v.size() * sizeof(v[0]));
     fx.push_back({o, (const void**)out});
   };
-  reg(d_fwdx, &p_fwdx); reg(d_invx, &p_invx); reg(d_vface, &p_vface); reg(d_gface, &p_gface);
+  auto reg_stage = [&](auto& sl) {
+    reg(sl.dense, &sl.p_dense);
+    for (int v = 0; v < kNumV; ++v) {
+      reg(sl.dst[v], &sl.p_dst[v]);
+      int m = 0;
+      for (auto& d : sl.dst[v]) m = std::max(m, d.P * d.Q);
+      sl.max_lines[v] = m;
+    }
+  };
+  reg_stage(s_fwdx); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
+  reg(d_vface, &p_vface); reg(d_gface, &p_gface);
   reg(d_glob_in, &p_glob_in); reg(d_glob_out, &p_glob_out);
-  reg(d_fwdy, &p_fwdy); reg(d_invy, &p_invy);
   reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
   reg(d_redB, &p_redB); reg(d_redG, &p_redG); reg(d_lift, &p_lift);
   if (hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
@@ -751,6 +795,41 @@ hs_status Plan::profile_read(hs_stage_time* out, int max_out, int* n_out, std::s
   return HS_OK;
 }
 
+void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, const void* src, void* dst,
+                 int nrhs, hipStream_t st) {
+  const void* T = tab();
+  if (!sl.dense.empty()) {
+    int m = 0;
+    for (auto& d : sl.dense) m = std::max(m, xform_lines_tiles(d));
+    xform_lines(prec, in64, out64, acc, sl.p_dense, int(sl.dense.size()), m, T, src, dst, nrhs, st);
+  }
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const void* tw = (const unsigned char*)T + size_t(twid) * esz;
+  for (int v = 0; v < kNumV; ++v)
+    if (!sl.dst[v].empty())
+      dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
+                dst, nrhs, st);
+}
+
+void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
+  const void* T = tab();
+  if (!sl.dense.empty()) {
+    int m16 = 0, m8 = 0, mn = 0;
+    for (auto& d : sl.dense) {
+      m16 = std::max(m16, xform_y_tiles(d, 16));
+      m8 = std::max(m8, xform_y_tiles(d, 8));
+      mn = std::max(mn, d.n);
+    }
+    xform_y(prec, sl.p_dense, int(sl.dense.size()), mn, m16, m8, T, ws, nrhs, st);
+  }
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const void* tw = (const unsigned char*)T + size_t(twid) * esz;
+  for (int v = 0; v < kNumV; ++v)
+    if (!sl.dst[v].empty())
+      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, nrhs,
+                st);
+}
+
 void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st) {
   const void* T = tab();
   void* W = ws;
@@ -758,11 +837,6 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   auto tiles_lines = [](const std::vector<XformDesc>& v) {
     int m = 0;
     for (auto& d : v) m = std::max(m, xform_lines_tiles(d));
-    return m;
-  };
-  auto tiles_y = [](const std::vector<XformYDesc>& v, int ct) {
-    int m = 0;
-    for (auto& d : v) m = std::max(m, xform_y_tiles(d, ct));
     return m;
   };
   auto tiles_sw = [](const std::vector<SweepDesc>& v) {
@@ -774,22 +848,30 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   const double R = nrhs;
   const double esz = prec == 0 ? 16.0 : 8.0;
   const double esz_in = in64 ? 16.0 : 8.0;
+  // dense pass: 8 n flops per complex output; sine FFT pass: 5 L log2(L) / n per output
+  auto pass_flops = [](const Axis& a) {
+    if (a.dstV) {
+      const double L = 2.0 * (a.n + 1);
+      return 5.0 * L * std::log2(L) / a.n;
+    }
+    return 8.0 * a.n;
+  };
   double nblk = 0, fx = 0, fy = 0, nface = 0;
   for (auto& B : blocks) {
     const double nbv = double(NZ) * B.nbx * B.nby;
     nblk += nbv;
-    fx += nbv * 8.0 * B.nbx;
-    fy += nbv * 8.0 * B.nby;
+    fx += nbv * pass_flops(axes[B.ax]);
+    fy += nbv * pass_flops(axes[B.ay]);
     nface += double(NZ) * 2.0 * (B.nbx + B.nby);
   }
   const double thomas = 44.0;   // flops per node of one z solve
   const int out64 = 1;
   // step 1: forward transforms of every block
   stage_begin("xform_x_fwd", R * nblk * (esz_in + esz), R * fx, st);
-  xform_lines(prec, in64, 0, 0, p_fwdx, nb, tiles_lines(d_fwdx), T, f, W, nrhs, st);
+  run_x(s_fwdx, in64, 0, 0, f, W, nrhs, st);
   stage_end();
   stage_begin("xform_y_fwd", R * nblk * 2 * esz, R * fy, st);
-  xform_y(prec, p_fwdy, nb, max_block_n, tiles_y(d_fwdy, 16), tiles_y(d_fwdy, 8), T, W, nrhs, st);
+  run_y(s_fwdy, nrhs, st);
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
@@ -844,10 +926,10 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   }
   // step 7: inverse transforms into u
   stage_begin("xform_y_inv", R * nblk * 2 * esz, R * fy, st);
-  xform_y(prec, p_invy, nb, max_block_n, tiles_y(d_invy, 16), tiles_y(d_invy, 8), T, W, nrhs, st);
+  run_y(s_invy, nrhs, st);
   stage_end();
   stage_begin("xform_x_inv", R * nblk * (esz + 16 + (acc ? 16 : 0)), R * fx, st);
-  xform_lines(prec, 0, out64, acc, p_invx, nb, tiles_lines(d_invx), T, W, u, nrhs, st);
+  run_x(s_invx, 0, out64, acc, W, u, nrhs, st);
   stage_end();
   if (decomposed) {
     SigmaGeom g = sg;

@@ -18,6 +18,7 @@ namespace hs {
 struct Axis {
   int n = 0;
   bool sine = false;
+  int dstV = 0;                        // > 0: sine transform by FFT with V = (n + 1) / 8
   AxisEig e;
   int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
 };
@@ -33,10 +34,15 @@ struct Block {
   int64_t partx = 0, party = 0;  // tile partials of its face reductions
 };
 
-template <typename T>
-struct DevArray {
-  T* d = nullptr;
-  int n = 0;
+// One transform stage: dense-table descriptors plus sine-FFT descriptors per V.
+constexpr int kNumV = 5;   // V = 2, 4, 8, 16, 32
+template <typename DenseDesc>
+struct StageList {
+  std::vector<DenseDesc> dense;
+  std::vector<DstDesc> dst[kNumV];
+  const DenseDesc* p_dense = nullptr;
+  const DstDesc* p_dst[kNumV] = {};
+  int max_lines[kNumV] = {};
 };
 
 struct StageProf {
@@ -93,15 +99,15 @@ struct Plan {
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;
-  std::vector<XformDesc> d_fwdx, d_invx, d_vface, d_gface, d_glob_in, d_glob_out;
-  std::vector<XformYDesc> d_fwdy, d_invy;
+  StageList<XformDesc> s_fwdx, s_invx;
+  StageList<XformYDesc> s_fwdy, s_invy;
+  std::vector<XformDesc> d_vface, d_gface, d_glob_in, d_glob_out;
+  int64_t twid = 0;                  // twiddle table offset
   std::vector<SweepDesc> d_sweep, d_sweepB, d_sweepC, d_sweepG;
   std::vector<ReduceDesc> d_redB, d_redG;
   std::vector<LiftBlock> d_lift;
   // device pointers of each list
-  const XformDesc *p_fwdx = nullptr, *p_invx = nullptr, *p_vface = nullptr, *p_gface = nullptr,
-                  *p_glob_in = nullptr, *p_glob_out = nullptr;
-  const XformYDesc *p_fwdy = nullptr, *p_invy = nullptr;
+  const XformDesc *p_vface = nullptr, *p_gface = nullptr, *p_glob_in = nullptr, *p_glob_out = nullptr;
   const SweepDesc *p_sweep = nullptr, *p_sweepB = nullptr, *p_sweepC = nullptr, *p_sweepG = nullptr;
   const ReduceDesc *p_redB = nullptr, *p_redG = nullptr;
   const LiftBlock* p_lift = nullptr;
@@ -145,6 +151,9 @@ struct Plan {
   hs_status upload(std::string& err);
   hs_status scan_pivots(std::string& err);
   const void* tab() const { return prec == 0 ? dtab64 : dtab32; }
+  void run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, const void* src, void* dst, int nrhs,
+             hipStream_t st);
+  void run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st);
 };
 
 }  // namespace hs

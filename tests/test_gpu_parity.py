@@ -69,6 +69,23 @@ def test_dense_path_on_uniform_axes_matches_sine_path(hs):
     assert per_rhs_err(u1, u2) < TOL128
 
 
+@pytest.mark.parametrize("shape", [(15, 31, 12), (63, 127, 9), (255, 15, 6), (127, 127, 20)])
+def test_sine_fft_path_vs_oracle_and_dense(hs, shape):
+    """Uniform axes with n + 1 a power of two take the FFT sine transform."""
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx + 7 * ny)
+    p = W.uniform_problem(nx, ny, nz, 3, rng)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, "c128", max_rhs=2)
+    assert plan.info()["n_sine_axes"] >= 1
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+    u2 = hs.Plan(p, "c128", max_rhs=2, force_dense=True).solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, u2) < TOL128
+    um = hs.Plan(p, "mixed", max_rhs=2).solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(um, u) < TOL64R
+
+
 def test_manufactured_solution_and_stencil(hs):
     rng = np.random.default_rng(11)
     p = W.random_problem(30, 26, 22, 3, rng, pml_x=4, pml_y=3)
