@@ -102,38 +102,35 @@ struct DstDesc {
 };
 
 // One batched z sweep over the (a, b) modes of a block.
-//  rhs(a,b,z,r) = [dense ? data(r,z,b,a) : 0]
+//  rhs(a,b,z,r) = [dense_in ? data(r,z,b,a) : 0]
 //               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)
-//  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) I) x = rhs
-//  dense_out: data(r,z,b,a) = x
-//  reductions: redx_i(tile_a, r, z, b) = sum_{a in tile} ex_i[a] x ;
-//              redy_j(tile_b, r, z, a) = sum_{b in tile} ey_j[b] x
+//  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) I) x = rhs,   out(r,z,b,a) = x
+// element (r,z,b,a) of data / out sits at base + r*_r + (z*nb + b)*na + a.
 constexpr int kMaxTerms = 4;
 struct SweepDesc {
   int32_t na, nb, nz, dense_in;
-  int32_t dense_out, nxt, nyt, nxr;
-  int32_t nyr, tiles_a, tiles_b, pad_;
-  int64_t lam_x, lam_y;         // table offsets (complex, length na / nb)
-  int64_t zlo, zdiag, zup;      // table offsets (complex, length nz)
-  int64_t data, data_r;         // workspace offsets; element (r,z,b,a) = data + r*data_r + (z*nb + b)*na + a
-  int64_t dbuf, dbuf_r;         // scratch for forward-swept rhs when !dense_in || !dense_out
-  int64_t ckpt;                 // workspace offset of checkpoints [r? no][seg][tile thread]
+  int32_t nxt, nyt, pad0_, pad1_;
+  int64_t lam_x, lam_y;           // table offsets (complex, length na / nb)
+  int64_t zlo, zdiag, zup;        // table offsets (complex, length nz)
+  int64_t data, data_r;           // workspace offsets
+  int64_t out, out_r;
   int64_t colx[kMaxTerms]; int32_t colx_stride[kMaxTerms];   // table offsets
-  int64_t gx[kMaxTerms];        // workspace offsets
+  int64_t gx[kMaxTerms];          // workspace offsets
   int64_t coly[kMaxTerms]; int32_t coly_stride[kMaxTerms];
   int64_t gy[kMaxTerms];
   int64_t gx_r, gy_r, gx_z, gy_z;   // gx(r,z,b) = gx + r*gx_r + z*gx_z + b
-  int64_t ex[kMaxTerms]; int32_t ex_stride[kMaxTerms];       // table offsets
-  int64_t ey[kMaxTerms]; int32_t ey_stride[kMaxTerms];
-  int64_t redx, redx_term, redx_tile, redx_r;  // redx_i(tile, r, z, b) = redx + i*term + tile*tile_s + r*r_s + z*nb + b
-  int64_t redy, redy_term, redy_tile, redy_r;
 };
 
-// Sum of tile partials: out(t, r, z, i) = sum_{tile} in(t, tile, r, z, i)
-struct ReduceDesc {
-  int64_t src, src_term, src_tile, src_r;   // src(t, tile, r, z, i) = src + ... + z*n + i
-  int64_t dst, dst_term, dst_r, dst_z;      // dst(t, r, z, i) = dst + ... + z*dst_z + i
-  int32_t nterms, ntiles, nz, n;
+// Contraction of a spectral array X(r,z,b,a) = src + r*src_r + (z*nb + b)*na + a
+// with up to kMaxTerms coefficient vectors:
+//   axis 0: out_t(r,z,b) = sum_a c_t[a] X(r,z,b,a)
+//   axis 1: out_t(r,z,a) = sum_b c_t[b] X(r,z,b,a)
+// out_t(r,z,i) = dst + t*dst_t + r*dst_r + z*dst_z + i.
+struct ContractDesc {
+  int32_t na, nb, nz, nterms;
+  int64_t src, src_r;
+  int64_t coef[kMaxTerms]; int32_t coef_stride[kMaxTerms];   // table offsets
+  int64_t dst, dst_t, dst_r, dst_z;
 };
 
 }  // namespace hs

@@ -300,168 +300,339 @@ __global__ __launch_bounds__(256) void k_dst(const DstDesc* __restrict__ descs, 
 }
 
 // ---------------------------------------------------------------------------
-// Batched z sweep (Thomas without pivoting) over the modes of a block, one
-// mode per lane; a 16 x 16 tile of (a, b) modes per workgroup.  The forward
-// elimination stores the swept right-hand side; the pivot recurrence is
-// checkpointed every SEG rows and recomputed segment-wise on the way back so
-// the backward pass keeps its multipliers in registers.
+// Batched z solves: for every (a, b) mode of a block one tridiagonal system
+// (Dz - diag k^2 + (lam_a + mu_b) I) x = rhs in z (eq. (5)), solved by
+// Gaussian elimination without pivoting.
+//
+// Partitioned form, everything in registers: a workgroup takes MW modes and
+// splits each mode's z line into P chunks, one lane per (mode, chunk).
+//  1. Each chunk eliminates its own rows top-down and bottom-up, which gives
+//     the chunk's response at its first and last row to its right-hand side
+//     (y) and to unit values of the neighbouring unknowns above (v) and
+//     below (w):  x_k = y_k - lo_{k0} v_k x_{k0-1} - up_{k1} w_k x_{k1+1}.
+//  2. One lane per mode solves the reduced system on the chunk ends
+//     (first F_j, last L_j), a block recurrence of 2 x 2 structure.
+//  3. Each chunk re-solves its rows with the now known x_{k0-1}, x_{k1+1}.
+// Reads the right-hand side once and writes the solution once.
 // ---------------------------------------------------------------------------
-constexpr int SEG = 16;
+template <typename R> struct quad_of;
+template <> struct quad_of<double> { using type = double4; };
+template <> struct quad_of<float> { using type = float4; };
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_sweep(const SweepDesc* __restrict__ descs,
-                                               const cplx<R>* __restrict__ tab,
-                                               cplx<R>* __restrict__ ws) {
+template <typename C>
+__device__ __forceinline__ C shfl_xor_c(C v, int mask, int width) {
+  C o;
+  o.x = __shfl_xor(v.x, mask, width);
+  o.y = __shfl_xor(v.y, mask, width);
+  return o;
+}
+
+// 1/z for pivots (|z| bounded away from 0 and infinity by the plan's pivot
+// scan): hardware reciprocal of |z|^2 refined by Newton steps.
+__device__ __forceinline__ double rcp_refined(double n) {
+  double r = __builtin_amdgcn_rcp(n);
+  double e = fma(-n, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-n, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_refined(float n) {
+  float r = __builtin_amdgcn_rcpf(n);
+  const float e = fmaf(-n, r, 1.0f);
+  return fmaf(r, e, r);
+}
+template <typename C>
+__device__ __forceinline__ C crcp_fast(C z) {
+  const auto inv = rcp_refined(z.x * z.x + z.y * z.y);
+  C r;
+  r.x = z.x * inv;
+  r.y = -z.y * inv;
+  return r;
+}
+
+constexpr int PS_LMAX = 16;   // rows per chunk held in registers
+
+template <typename R, int P, int MW>
+__global__ __launch_bounds__(512) void k_psweep(const SweepDesc* __restrict__ descs,
+                                                const cplx<R>* __restrict__ tab,
+                                                cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
-  const SweepDesc& d = descs[blockIdx.y];
-  const int tiles_a = d.tiles_a;
-  const int tile = blockIdx.x;
-  if (tile >= tiles_a * d.tiles_b) return;
-  const int ta = tile % tiles_a, tb = tile / tiles_a;
-  const int al = threadIdx.x & 15, bl = threadIdx.x >> 4;
+  using Q = typename quad_of<R>::type;
+  static_assert(P * MW == 512, "512 lanes per workgroup");
+  extern __shared__ unsigned char smem_raw[];
+  const SweepDesc d = descs[blockIdx.y];
   const int na = d.na, nb = d.nb, nz = d.nz;
-  const int a = ta * 16 + al, b = tb * 16 + bl;
-  const bool act = (a < na) && (b < nb);
-  const int r = blockIdx.z;
   const int64_t plane = (int64_t)na * nb;
-  const int64_t m = (int64_t)b * na + a;
-  const int nxt = d.nxt, nyt = d.nyt, nxr = d.nxr, nyr = d.nyr;
-
-  const C s = act ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
-  C cx[kMaxTerms], cy[kMaxTerms], ex[kMaxTerms], ey[kMaxTerms];
-#pragma unroll
-  for (int i = 0; i < kMaxTerms; ++i) {
-    cx[i] = (act && i < nxt) ? tab[d.colx[i] + (int64_t)a * d.colx_stride[i]] : mk<R>(0, 0);
-    cy[i] = (act && i < nyt) ? tab[d.coly[i] + (int64_t)b * d.coly_stride[i]] : mk<R>(0, 0);
-    ex[i] = (act && i < nxr) ? tab[d.ex[i] + (int64_t)a * d.ex_stride[i]] : mk<R>(0, 0);
-    ey[i] = (act && i < nyr) ? tab[d.ey[i] + (int64_t)b * d.ey_stride[i]] : mk<R>(0, 0);
+  const int64_t m0 = (int64_t)blockIdx.x * MW;
+  if (m0 >= plane) return;
+  Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z
+  C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nz) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
+  for (int k = threadIdx.x; k < nz; k += 512) {
+    const C dg = tab[d.zdiag + k];
+    Q q;
+    q.x = dg.x;
+    q.y = dg.y;
+    q.z = tab[d.zlo + k].x;
+    q.w = tab[d.zup + k].x;
+    zt[k] = q;
   }
-  C* data = ws + d.data + (int64_t)r * d.data_r;
-  C* fwd = (d.dense_in && d.dense_out) ? data
-           : (!d.dense_in && d.dense_out) ? data
-                                          : ws + d.dbuf + (int64_t)r * d.dbuf_r;
-  const int nseg = (nz + SEG - 1) / SEG;
-  C* ck = ws + d.ckpt + (int64_t)r * nseg * plane;
-  const C* zlo = tab + d.zlo;
-  const C* zdg = tab + d.zdiag;
-  const C* zup = tab + d.zup;
+  const int ml = threadIdx.x % MW, j = threadIdx.x / MW;
+  const int64_t m = m0 + ml;
+  const bool mact = m < plane;
+  const int np = nz >= 2 * P ? P : (nz / 2 > 0 ? nz / 2 : 1);   // chunks in use (each >= 2 rows)
+  const bool cact = j < np;
+  const bool act = mact && cact;
+  const int k0 = (j * nz) / np;
+  const int len = cact ? ((j + 1) * nz) / np - k0 : 0;
+  const int a = mact ? int(m % na) : 0, b = mact ? int(m / na) : 0;
+  const int r = blockIdx.z;
+  const C s = mact ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
+  auto X = [&](int f, int jj) -> C& { return xch[(jj * 6 + f) * MW + ml]; };
 
-  // forward elimination; each segment's right-hand sides are loaded before
-  // the recurrence runs over them so the loads overlap
-  C cprev = mk<R>(0, 0), dprev = mk<R>(0, 0);
-  for (int seg = 0; seg < nseg; ++seg) {
-    if (act) ck[seg * plane + m] = cprev;
-    const int k0 = seg * SEG;
-    C rb[SEG];
+  // right-hand side of the chunk
+  C rb[PS_LMAX];
+  const C* src = ws + d.data + (int64_t)r * d.data_r + m;
 #pragma unroll
-    for (int kk = 0; kk < SEG; ++kk) {
-      const int k = k0 + kk;
-      rb[kk] = (act && d.dense_in && k < nz) ? data[k * plane + m] : mk<R>(0, 0);
-    }
-    if (act) {
-      for (int i = 0; i < nxt; ++i) {
-        const C* g = ws + d.gx[i] + (int64_t)r * d.gx_r + b;
+  for (int kk = 0; kk < PS_LMAX; ++kk)
+    rb[kk] = (act && d.dense_in && kk < len) ? src[(int64_t)(k0 + kk) * plane] : mk<R>(0, 0);
+  // low-rank terms: a chunk's values are loaded together (row index clamped
+  // into the chunk so every load is valid), then accumulated
+  const int lastk = k0 + (len > 0 ? len - 1 : 0);
 #pragma unroll
-        for (int kk = 0; kk < SEG; ++kk)
-          if (k0 + kk < nz) rb[kk] = cfma(cx[i], g[(int64_t)(k0 + kk) * d.gx_z], rb[kk]);
-      }
-      for (int j = 0; j < nyt; ++j) {
-        const C* g = ws + d.gy[j] + (int64_t)r * d.gy_r + a;
+  for (int i = 0; i < 2 * kMaxTerms; ++i) {
+    const bool isx = i < kMaxTerms;
+    const int t = isx ? i : i - kMaxTerms;
+    if (act && t < (isx ? d.nxt : d.nyt)) {
+      const C c = isx ? tab[d.colx[t] + (int64_t)a * d.colx_stride[t]]
+                      : tab[d.coly[t] + (int64_t)b * d.coly_stride[t]];
+      const C* g = isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a;
+      const int64_t gz = isx ? d.gx_z : d.gy_z;
+      C gv[PS_LMAX];
 #pragma unroll
-        for (int kk = 0; kk < SEG; ++kk)
-          if (k0 + kk < nz) rb[kk] = cfma(cy[j], g[(int64_t)(k0 + kk) * d.gy_z], rb[kk]);
-      }
-    }
+      for (int kk = 0; kk < PS_LMAX; ++kk) gv[kk] = g[(int64_t)min(k0 + kk, lastk) * gz];
 #pragma unroll
-    for (int kk = 0; kk < SEG; ++kk) {
-      const int k = k0 + kk;
-      if (k < nz) {
-        const C lo = zlo[k];
-        const C ip = crcp(cfms(lo, cprev, cadd(zdg[k], s)));
-        const C dd = cmul(cfms(lo, dprev, rb[kk]), ip);
-        if (act) fwd[k * plane + m] = dd;
-        cprev = cmul(zup[k], ip);
-        dprev = dd;
-      }
+      for (int kk = 0; kk < PS_LMAX; ++kk)
+        if (kk < len) rb[kk] = cfma(c, gv[kk], rb[kk]);
     }
   }
+  __syncthreads();
 
-  // backward substitution
-  __shared__ C sh[2 * kMaxTerms][16][17];
-  const int nred = nxr + nyr;
-  C xn = mk<R>(0, 0);
-  for (int seg = nseg - 1; seg >= 0; --seg) {
-    const int k0 = seg * SEG;
-    C dseg[SEG], cseg[SEG];
+  // 1. local eliminations: top-down gives the last row, bottom-up the first row
+  if (act) {
+    C cp = mk<R>(0, 0), yb = mk<R>(0, 0), yv = mk<R>(0, 0), ipl = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = 0; kk < SEG; ++kk) {
-      const int k = k0 + kk;
-      dseg[kk] = (act && k < nz) ? fwd[k * plane + m] : mk<R>(0, 0);
-    }
-    C cp = act ? ck[seg * plane + m] : mk<R>(0, 0);
-#pragma unroll
-    for (int kk = 0; kk < SEG; ++kk) {
-      const int k = k0 + kk;
-      if (k < nz) {
-        const C piv = cfms(zlo[k], cp, cadd(zdg[k], s));
-        cseg[kk] = cmul(zup[k], crcp(piv));
-        cp = cseg[kk];
-      } else {
-        cseg[kk] = mk<R>(0, 0);
+    for (int kk = 0; kk < PS_LMAX; ++kk) {
+      if (kk < len) {
+        const Q q = zt[k0 + kk];
+        const R lo = kk > 0 ? q.z : R(0);
+        C piv;
+        piv.x = q.x + s.x - lo * cp.x;
+        piv.y = q.y + s.y - lo * cp.y;
+        const C ip = crcp_fast(piv);
+        C t;
+        t.x = rb[kk].x - lo * yb.x;
+        t.y = rb[kk].y - lo * yb.y;
+        yb = cmul(t, ip);
+        t.x = (kk == 0 ? R(1) : R(0)) - lo * yv.x;
+        t.y = -lo * yv.y;
+        yv = cmul(t, ip);
+        cp.x = q.w * ip.x;
+        cp.y = q.w * ip.y;
+        ipl = ip;
       }
     }
+    C cn = mk<R>(0, 0), zb = mk<R>(0, 0), zw = mk<R>(0, 0), ipf = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = SEG - 1; kk >= 0; --kk) {
-      const int k = k0 + kk;
-      if (k >= nz) continue;
-      const C x = cfms(cseg[kk], xn, dseg[kk]);
-      xn = x;
-      if (act && d.dense_out) data[k * plane + m] = x;
-      if (nred > 0) {
-        for (int i = 0; i < nxr; ++i) sh[i][bl][al] = act ? cmul(ex[i], x) : mk<R>(0, 0);
-        for (int j = 0; j < nyr; ++j) sh[nxr + j][bl][al] = act ? cmul(ey[j], x) : mk<R>(0, 0);
-        __syncthreads();
-        const int t = threadIdx.x;
-        if (t < 16 * nred) {
-          const int term = t >> 4, idx = t & 15;
-          C acc = mk<R>(0, 0);
-          if (term < nxr) {
-            for (int q = 0; q < 16; ++q) acc = cadd(acc, sh[term][idx][q]);
-            const int bg = tb * 16 + idx;
-            if (bg < nb)
-              ws[d.redx + term * d.redx_term + ta * d.redx_tile + (int64_t)r * d.redx_r +
-                 (int64_t)k * nb + bg] = acc;
-          } else {
-            for (int q = 0; q < 16; ++q) acc = cadd(acc, sh[term][q][idx]);
-            const int ag = ta * 16 + idx;
-            if (ag < na)
-              ws[d.redy + (term - nxr) * d.redy_term + tb * d.redy_tile + (int64_t)r * d.redy_r +
-                 (int64_t)k * na + ag] = acc;
-          }
-        }
-        __syncthreads();
+    for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
+      if (kk < len) {
+        const Q q = zt[k0 + kk];
+        const R up = kk < len - 1 ? q.w : R(0);
+        C piv;
+        piv.x = q.x + s.x - up * cn.x;
+        piv.y = q.y + s.y - up * cn.y;
+        const C ip = crcp_fast(piv);
+        C t;
+        t.x = rb[kk].x - up * zb.x;
+        t.y = rb[kk].y - up * zb.y;
+        zb = cmul(t, ip);
+        t.x = (kk == len - 1 ? R(1) : R(0)) - up * zw.x;
+        t.y = -up * zw.y;
+        zw = cmul(t, ip);
+        cn.x = q.z * ip.x;
+        cn.y = q.z * ip.y;
+        ipf = ip;
+      }
+    }
+    X(0, j) = zb;    // y first
+    X(1, j) = yb;    // y last
+    X(2, j) = ipf;   // v first
+    X(3, j) = yv;    // v last
+    X(4, j) = zw;    // w first
+    X(5, j) = ipl;   // w last
+  }
+  __syncthreads();
+
+  // 2. reduced system on the chunk ends (one lane per mode)
+  if (j == 0 && mact) {
+    C p = mk<R>(0, 0), qv = mk<R>(0, 0);
+    for (int jj = 0; jj < np; ++jj) {
+      const int c0 = (jj * nz) / np, c1 = ((jj + 1) * nz) / np - 1;
+      const R al = zt[c0].z, be = zt[c1].w;
+      const C yf = X(0, jj), yl = X(1, jj), vf = X(2, jj), vl = X(3, jj), wf = X(4, jj), wl = X(5, jj);
+      // D = 1 + al vf q
+      C D = cmul(vf, qv);
+      D.x = R(1) + al * D.x;
+      D.y = al * D.y;
+      const C iD = crcp_fast(D);
+      C t = cmul(vf, p);
+      t.x = yf.x - al * t.x;
+      t.y = yf.y - al * t.y;
+      const C g = cmul(t, iD);
+      C h = cmul(wf, iD);
+      h.x = -be * h.x;
+      h.y = -be * h.y;
+      // p' = yl - al vl (p + q g) ;  q' = -al vl q h - be wl
+      const C pq = cfma(qv, g, p);
+      C vlpq = cmul(vl, pq);
+      C pn;
+      pn.x = yl.x - al * vlpq.x;
+      pn.y = yl.y - al * vlpq.y;
+      C vlqh = cmul(vl, cmul(qv, h));
+      C qn;
+      qn.x = -al * vlqh.x - be * wl.x;
+      qn.y = -al * vlqh.y - be * wl.y;
+      p = pn;
+      qv = qn;
+      X(0, jj) = g;
+      X(1, jj) = h;
+      X(2, jj) = p;
+      X(3, jj) = qv;
+    }
+    C Fn = mk<R>(0, 0);
+    for (int jj = np - 1; jj >= 0; --jj) {
+      const C F = cfma(X(1, jj), Fn, X(0, jj));
+      const C L = cfma(X(3, jj), Fn, X(2, jj));
+      X(0, jj) = F;
+      X(1, jj) = L;
+      Fn = F;
+    }
+  }
+  __syncthreads();
+
+  // 3. re-solve each chunk with its neighbours' end values
+  if (act) {
+    const C XL = j > 0 ? X(1, j - 1) : mk<R>(0, 0);
+    const C XR = j + 1 < np ? X(0, j + 1) : mk<R>(0, 0);
+    C cr[PS_LMAX];
+    C cp = mk<R>(0, 0), dp = mk<R>(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < PS_LMAX; ++kk) {
+      if (kk < len) {
+        const Q q = zt[k0 + kk];
+        C rhs = rb[kk];
+        if (kk == 0) rhs = cfms(mk<R>(q.z, 0), XL, rhs);
+        if (kk == len - 1) rhs = cfms(mk<R>(q.w, 0), XR, rhs);
+        const R lo = kk > 0 ? q.z : R(0);
+        C piv;
+        piv.x = q.x + s.x - lo * cp.x;
+        piv.y = q.y + s.y - lo * cp.y;
+        const C ip = crcp_fast(piv);
+        C t;
+        t.x = rhs.x - lo * dp.x;
+        t.y = rhs.y - lo * dp.y;
+        dp = cmul(t, ip);
+        rb[kk] = dp;
+        cp.x = q.w * ip.x;
+        cp.y = q.w * ip.y;
+        cr[kk] = cp;
+      }
+    }
+    C xn = mk<R>(0, 0);
+#pragma unroll
+    for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
+      if (kk < len) {
+        if (kk < len - 1) rb[kk] = cfms(cr[kk], xn, rb[kk]);
+        xn = rb[kk];
+      }
+    }
+    C* dst = ws + d.out + (int64_t)r * d.out_r + m;
+#pragma unroll
+    for (int kk = 0; kk < PS_LMAX; ++kk)
+      if (kk < len) dst[(int64_t)(k0 + kk) * plane] = rb[kk];
+  }
+}
+
+// Contraction over a (contiguous): out_t(r,z,b) = sum_a c_t[a] X(r,z,b,a).
+// 16 lines (z, b) per workgroup, 16 lanes stride over a, then a 16-lane sum.
+template <typename R>
+__global__ __launch_bounds__(256) void k_contract_x(const ContractDesc* __restrict__ descs,
+                                                    const cplx<R>* __restrict__ tab,
+                                                    cplx<R>* __restrict__ ws) {
+  using C = cplx<R>;
+  const ContractDesc d = descs[blockIdx.y];
+  const int64_t lines = (int64_t)d.nz * d.nb;
+  const int64_t line = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  if ((int64_t)blockIdx.x * 16 >= lines) return;
+  const int lane = threadIdx.x & 15;
+  const int r = blockIdx.z;
+  const bool ok = line < lines;
+  C acc[kMaxTerms];
+#pragma unroll
+  for (int t = 0; t < kMaxTerms; ++t) acc[t] = mk<R>(0, 0);
+  if (ok) {
+    const C* x = ws + d.src + (int64_t)r * d.src_r + line * d.na;
+#pragma unroll 4
+    for (int a = lane; a < d.na; a += 16) {
+      const C v = x[a];
+#pragma unroll
+      for (int t = 0; t < kMaxTerms; ++t)
+        if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)a * d.coef_stride[t]], v, acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kMaxTerms; ++t) {
+    if (t < d.nterms) {
+      C v = acc[t];
+      v = cadd(v, shfl_xor_c(v, 8, 16));
+      v = cadd(v, shfl_xor_c(v, 4, 16));
+      v = cadd(v, shfl_xor_c(v, 2, 16));
+      v = cadd(v, shfl_xor_c(v, 1, 16));
+      if (ok && lane == 0) {
+        const int z = int(line / d.nb), bq = int(line % d.nb);
+        ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + bq] = v;
       }
     }
   }
 }
 
+// Contraction over b (strided): out_t(r,z,a) = sum_b c_t[b] X(r,z,b,a).
+// One lane per column a of a z plane.
 template <typename R>
-__global__ __launch_bounds__(256) void k_reduce(const ReduceDesc* __restrict__ descs,
-                                                cplx<R>* __restrict__ ws) {
+__global__ __launch_bounds__(256) void k_contract_y(const ContractDesc* __restrict__ descs,
+                                                    const cplx<R>* __restrict__ tab,
+                                                    cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
-  const ReduceDesc d = descs[blockIdx.y];
+  const ContractDesc d = descs[blockIdx.y];
+  const int ncol = (d.na + 255) / 256;
+  if ((int)blockIdx.x >= ncol * d.nz) return;
+  const int z = blockIdx.x / ncol;
+  const int a = (blockIdx.x % ncol) * 256 + threadIdx.x;
+  if (a >= d.na) return;
   const int r = blockIdx.z;
-  const int64_t per_term = (int64_t)d.nz * d.n;
-  const int64_t total = per_term * d.nterms;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int t = int(e / per_term);
-    const int64_t rest = e % per_term;
-    const int z = int(rest / d.n), i = int(rest % d.n);
-    const C* s = ws + d.src + t * d.src_term + (int64_t)r * d.src_r + rest;
-    C acc = mk<R>(0, 0);
-    for (int q = 0; q < d.ntiles; ++q) acc = cadd(acc, s[q * d.src_tile]);
-    ws[d.dst + t * d.dst_term + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + i] = acc;
+  const C* x = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.nb * d.na + a;
+  C acc[kMaxTerms];
+#pragma unroll
+  for (int t = 0; t < kMaxTerms; ++t) acc[t] = mk<R>(0, 0);
+#pragma unroll 8
+  for (int b = 0; b < d.nb; ++b) {
+    const C v = x[(int64_t)b * d.na];
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t)
+      if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)b * d.coef_stride[t]], v, acc[t]);
   }
+#pragma unroll
+  for (int t = 0; t < kMaxTerms; ++t)
+    if (t < d.nterms) ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + a] = acc[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -794,28 +965,48 @@ void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles1
 
 int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct) * d.P; }
 
-void sweep(int prec, const SweepDesc* d, int ndesc, int max_tiles, const void* tab, void* ws, int nrhs,
-           hipStream_t st) {
-  if (ndesc == 0 || nrhs == 0) return;
-  if (prec == 0)
-    hipLaunchKernelGGL((k_sweep<double>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
-                       (const double2*)tab, (double2*)ws);
-  else
-    hipLaunchKernelGGL((k_sweep<float>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
-                       (const float2*)tab, (float2*)ws);
+size_t sweep_lds_bytes(int prec, int nz) {
+  const size_t q = prec == 0 ? sizeof(double4) : sizeof(float4);
+  const size_t c = prec == 0 ? sizeof(double2) : sizeof(float2);
+  return (size_t(nz) * q + 255) / 256 * 256 + 6 * 512 * c;
 }
 
-int sweep_segments(int nz) { return (nz + SEG - 1) / SEG; }
+void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab, void* ws,
+           int nrhs, hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
+  const size_t lds = sweep_lds_bytes(prec, max_nz);
+  const bool deep = max_nz > 16 * PS_LMAX;   // up to 32 chunks of 16 rows
+  const int mw = deep ? 16 : 32;
+  const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
+  if (prec == 0) {
+    if (deep)
+      hipLaunchKernelGGL((k_psweep<double, 32, 16>), grid, dim3(512), lds, st, d, (const double2*)tab, (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_psweep<double, 16, 32>), grid, dim3(512), lds, st, d, (const double2*)tab, (double2*)ws);
+  } else {
+    if (deep)
+      hipLaunchKernelGGL((k_psweep<float, 32, 16>), grid, dim3(512), lds, st, d, (const float2*)tab, (float2*)ws);
+    else
+      hipLaunchKernelGGL((k_psweep<float, 16, 32>), grid, dim3(512), lds, st, d, (const float2*)tab, (float2*)ws);
+  }
+}
 
-void reduce_partials(int prec, const ReduceDesc* d, int ndesc, int64_t max_elems, void* ws, int nrhs,
-                     hipStream_t st) {
-  if (ndesc == 0 || nrhs == 0) return;
-  unsigned gx = unsigned(std::min<int64_t>((max_elems + 255) / 256, 4096));
-  if (gx == 0) return;
-  if (prec == 0)
-    hipLaunchKernelGGL((k_reduce<double>), dim3(gx, ndesc, nrhs), dim3(256), 0, st, d, (double2*)ws);
-  else
-    hipLaunchKernelGGL((k_reduce<float>), dim3(gx, ndesc, nrhs), dim3(256), 0, st, d, (float2*)ws);
+void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,
+              int nrhs, hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0 || max_units == 0) return;
+  if (axis == 0) {
+    const dim3 grid(unsigned((max_units + 15) / 16), ndesc, nrhs);
+    if (prec == 0)
+      hipLaunchKernelGGL((k_contract_x<double>), grid, dim3(256), 0, st, d, (const double2*)tab, (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_contract_x<float>), grid, dim3(256), 0, st, d, (const float2*)tab, (float2*)ws);
+  } else {
+    const dim3 grid(unsigned(max_units), ndesc, nrhs);
+    if (prec == 0)
+      hipLaunchKernelGGL((k_contract_y<double>), grid, dim3(256), 0, st, d, (const double2*)tab, (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_contract_y<float>), grid, dim3(256), 0, st, d, (const float2*)tab, (float2*)ws);
+  }
 }
 
 void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st) {

@@ -57,12 +57,17 @@ void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles1
              const void* tab, void* ws, int nrhs, hipStream_t st);
 int xform_y_tiles(const XformYDesc& d, int ct);
 
-void sweep(int prec, const SweepDesc* d, int ndesc, int max_tiles, const void* tab, void* ws, int nrhs,
-           hipStream_t st);
-int sweep_segments(int nz);
+// z solves: LDS of one workgroup (z tables + chunk-end exchange), and the
+// batched launch over descriptors (max_modes = largest na * nb).
+size_t sweep_lds_bytes(int prec, int nz);
+constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
+void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab, void* ws,
+           int nrhs, hipStream_t st);
 
-void reduce_partials(int prec, const ReduceDesc* d, int ndesc, int64_t max_elems, void* ws, int nrhs,
-                     hipStream_t st);
+// Face / interface contractions (axis 0: over a, max_units = nz * nb lines;
+// axis 1: over b, max_units = nz * ceil(na / 256) column groups).
+void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,
+              int nrhs, hipStream_t st);
 
 void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st);
 void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,

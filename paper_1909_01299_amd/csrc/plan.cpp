@@ -112,7 +112,7 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   for (auto& rx : runs(NX, sepx)) max_block_n = std::max(max_block_n, rx.second - rx.first + 1);
   for (auto& ry : runs(NY, sepy)) max_block_n = std::max(max_block_n, ry.second - ry.first + 1);
   if (max_block_n > 512) { err = "block side > 512 is not supported; add separators"; return HS_ERR_ARG; }
-  if (NZ > 4096) { err = "nz > 4096 is not supported"; return HS_ERR_ARG; }
+  if (NZ > kMaxNz) { err = "nz > " + std::to_string(kMaxNz) + " is not supported"; return HS_ERR_ARG; }
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -320,25 +320,9 @@ void Plan::layout_workspace() {
   };
   NF = 0;
   for (auto& B : blocks) NF = std::max(NF, std::max(B.nbx, B.nby));
-  const int nseg = sweep_segments(NZ);
   for (auto& B : blocks) B.spec = take(R * NZ * B.nbx * B.nby);
-  for (auto& B : blocks) B.ckpt = take(R * nseg * (int64_t)B.nbx * B.nby);
   if (decomposed) {
-    // forward-sweep scratch shared by the block sweeps and the global sweep
-    int64_t glob = R * NZ * (int64_t)NX * NY;
-    int64_t sum = 0;
-    for (auto& B : blocks) sum = align_up(sum + R * NZ * B.nbx * B.nby, 64);
-    w_gdbuf = take(std::max(glob, sum));
-    int64_t acc = w_gdbuf;
-    for (auto& B : blocks) {
-      B.dbuf = acc;
-      acc = align_up(acc + R * NZ * B.nbx * B.nby, 64);
-    }
-    for (auto& B : blocks) {
-      const int ta = (B.nbx + 15) / 16, tb = (B.nby + 15) / 16;
-      B.partx = take(2LL * ta * R * NZ * B.nby);
-      B.party = take(2LL * tb * R * NZ * B.nbx);
-    }
+    for (auto& B : blocks) B.vt = take(R * NZ * B.nbx * B.nby);
     const int64_t faces = (int64_t)blocks.size() * R * 4 * NZ * NF;
     w_face = take(faces);
     w_vface = take(faces);
@@ -348,10 +332,7 @@ void Plan::layout_workspace() {
     const int64_t lx = R * nsx * NZ * (int64_t)NY, ly = R * nsy * NZ * (int64_t)NX;
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
-    const int gta = (NX + 15) / 16, gtb = (NY + 15) / 16;
-    w_gpartx = take((int64_t)nsx * gta * R * NZ * NY);
-    w_gparty = take((int64_t)nsy * gtb * R * NZ * NX);
-    w_gckpt = take(R * nseg * (int64_t)NX * NY);
+    w_gspec = take(R * NZ * (int64_t)NX * NY);
   }
   ws_elems = size_t(off);
   const size_t esz = prec == 0 ? 16 : 8;
@@ -370,7 +351,8 @@ void Plan::build_descriptors() {
   (void)R;
   s_fwdx = {}; s_invx = {}; s_fwdy = {}; s_invy = {};
   d_sweep.clear();
-  d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear(); d_redB.clear(); d_redG.clear();
+  d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear();
+  d_facex.clear(); d_facey.clear(); d_sigx.clear(); d_sigy.clear();
   d_vface.clear(); d_gface.clear(); d_glob_in.clear(); d_glob_out.clear(); d_lift.clear();
   const int64_t gplane = (int64_t)NX * NY;
   const int64_t f_r = gplane * NZ;
@@ -424,41 +406,32 @@ void Plan::build_descriptors() {
 
     SweepDesc s{};
     s.na = B.nbx; s.nb = B.nby; s.nz = NZ;
-    s.tiles_a = (B.nbx + 15) / 16; s.tiles_b = (B.nby + 15) / 16;
     s.lam_x = AX.lam; s.lam_y = AY.lam;
     s.zlo = zlo; s.zdiag = zdiag; s.zup = zup;
     s.data = B.spec; s.data_r = spec_r;
-    s.ckpt = B.ckpt;
+    s.out = B.spec; s.out_r = spec_r;
+    s.dense_in = 1;
     if (!decomposed) {
-      s.dense_in = 1; s.dense_out = 1;
       d_sweep.push_back(s);
       continue;
     }
-    // steps 1-3: block sweep, v on the first / last interior lines via reductions
+    // steps 2-3: block solve v~ = T^{-1} f^, then v on the first / last interior lines
     SweepDesc sb = s;
-    sb.dense_in = 1; sb.dense_out = 0;
-    sb.dbuf = B.dbuf; sb.dbuf_r = spec_r;
-    sb.nxr = 2; sb.nyr = 2;
-    sb.ex[0] = AX.inv; sb.ex_stride[0] = 1;                              // W_x[0][a]
-    sb.ex[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; sb.ex_stride[1] = 1;  // W_x[n-1][a]
-    sb.ey[0] = AY.inv; sb.ey_stride[0] = 1;
-    sb.ey[1] = AY.inv + (int64_t)(B.nby - 1) * B.nby; sb.ey_stride[1] = 1;
-    sb.redx = B.partx; sb.redx_term = (int64_t)s.tiles_a * R * NZ * B.nby;
-    sb.redx_tile = R * NZ * B.nby; sb.redx_r = (int64_t)NZ * B.nby;
-    sb.redy = B.party; sb.redy_term = (int64_t)s.tiles_b * R * NZ * B.nbx;
-    sb.redy_tile = R * NZ * B.nbx; sb.redy_r = (int64_t)NZ * B.nbx;
+    sb.out = B.vt;
     d_sweepB.push_back(sb);
     const int64_t fbase = w_face + (int64_t)bi * R * 4 * face_f;
-    ReduceDesc rx{};
-    rx.src = B.partx; rx.src_term = sb.redx_term; rx.src_tile = sb.redx_tile; rx.src_r = sb.redx_r;
-    rx.dst = fbase; rx.dst_term = face_f; rx.dst_r = 4 * face_f; rx.dst_z = NF;
-    rx.nterms = 2; rx.ntiles = s.tiles_a; rx.nz = NZ; rx.n = B.nby;
-    d_redB.push_back(rx);
-    ReduceDesc ry{};
-    ry.src = B.party; ry.src_term = sb.redy_term; ry.src_tile = sb.redy_tile; ry.src_r = sb.redy_r;
-    ry.dst = fbase + 2 * face_f; ry.dst_term = face_f; ry.dst_r = 4 * face_f; ry.dst_z = NF;
-    ry.nterms = 2; ry.ntiles = s.tiles_b; ry.nz = NZ; ry.n = B.nbx;
-    d_redB.push_back(ry);
+    ContractDesc cx{};
+    cx.na = B.nbx; cx.nb = B.nby; cx.nz = NZ; cx.nterms = 2;
+    cx.src = B.vt; cx.src_r = spec_r;
+    cx.coef[0] = AX.inv; cx.coef_stride[0] = 1;                                // W_x[0][a]
+    cx.coef[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; cx.coef_stride[1] = 1;  // W_x[n-1][a]
+    cx.dst = fbase; cx.dst_t = face_f; cx.dst_r = 4 * face_f; cx.dst_z = NF;
+    d_facex.push_back(cx);
+    ContractDesc cy = cx;
+    cy.coef[0] = AY.inv; cy.coef_stride[0] = 1;
+    cy.coef[1] = AY.inv + (int64_t)(B.nby - 1) * B.nby; cy.coef_stride[1] = 1;
+    cy.dst = fbase + 2 * face_f;
+    d_facey.push_back(cy);
     // face values v(y) = sum_b W_y[y][b] e(b) (faces 0, 1) and v(x) = sum_a W_x[x][a] e(a) (faces 2, 3)
     XformDesc vf{};
     vf.tab = AY.inv; vf.n_in = vf.n_out = B.nby; vf.P = 2 * NZ; vf.Q = 1;
@@ -484,9 +457,8 @@ void Plan::build_descriptors() {
     XformDesc gf2 = vf2;
     gf2.tab = AX.fwd; gf2.src = gbase + 2 * face_f; gf2.dst = Gbase + 2 * face_f;
     d_gface.push_back(gf2);
-    // steps 6-7: block sweep of f^ + g^ (g^ generated from the four faces)
+    // steps 6-7: block solve of f^ + g^ (g^ generated from the four faces), in place
     SweepDesc sc = s;
-    sc.dense_in = 1; sc.dense_out = 1;
     sc.nxt = 2; sc.nyt = 2;
     sc.colx[0] = AX.fwd; sc.colx_stride[0] = B.nbx;                       // W_x^{-1}[a][0]
     sc.colx[1] = AX.fwd + (B.nbx - 1); sc.colx_stride[1] = B.nbx;         // W_x^{-1}[a][n-1]
@@ -529,48 +501,39 @@ void Plan::build_descriptors() {
     }
     SweepDesc g{};
     g.na = NX; g.nb = NY; g.nz = NZ;
-    g.tiles_a = (NX + 15) / 16; g.tiles_b = (NY + 15) / 16;
     g.lam_x = GX.lam; g.lam_y = GY.lam;
     g.zlo = zlo; g.zdiag = zdiag; g.zup = zup;
-    g.dense_in = 0; g.dense_out = 0;
-    g.dbuf = w_gdbuf; g.dbuf_r = (int64_t)NX * NY * NZ;
-    g.ckpt = w_gckpt;
-    g.nxt = nsx; g.nyt = nsy; g.nxr = nsx; g.nyr = nsy;
+    g.dense_in = 0;
+    g.out = w_gspec; g.out_r = (int64_t)NX * NY * NZ;
+    g.nxt = nsx; g.nyt = nsy;
     for (int i = 0; i < nsx; ++i) {
       g.colx[i] = GX.fwd + sepx[i]; g.colx_stride[i] = NX;        // W_x^{-1}[a][s_i]
       g.gx[i] = w_Rx + (int64_t)i * NZ * NY;
-      g.ex[i] = GX.inv + (int64_t)sepx[i] * NX; g.ex_stride[i] = 1;  // W_x[s_i][a]
     }
     for (int j = 0; j < nsy; ++j) {
       g.coly[j] = GY.fwd + sepy[j]; g.coly_stride[j] = NY;
       g.gy[j] = w_Ry + (int64_t)j * NZ * NX;
-      g.ey[j] = GY.inv + (int64_t)sepy[j] * NY; g.ey_stride[j] = 1;
     }
     g.gx_r = (int64_t)nsx * NZ * NY; g.gy_r = (int64_t)nsy * NZ * NX;
     g.gx_z = NY; g.gy_z = NX;
-    g.redx = w_gpartx; g.redx_tile = R * NZ * NY; g.redx_term = (int64_t)g.tiles_a * g.redx_tile;
-    g.redx_r = (int64_t)NZ * NY;
-    g.redy = w_gparty; g.redy_tile = R * NZ * NX; g.redy_term = (int64_t)g.tiles_b * g.redy_tile;
-    g.redy_r = (int64_t)NZ * NX;
     d_sweepG.push_back(g);
+    // w~ contracted with the rows of W at the separators: Q_x[s](b) = sum_a W_x[s][a] w~(a,b)
     if (nsx > 0) {
-      ReduceDesc rq{};
-      rq.src = w_gpartx; rq.src_term = g.redx_term; rq.src_tile = g.redx_tile; rq.src_r = g.redx_r;
-      rq.dst = w_Qx; rq.dst_term = (int64_t)NZ * NY; rq.dst_r = (int64_t)nsx * NZ * NY; rq.dst_z = NY;
-      rq.nterms = nsx; rq.ntiles = g.tiles_a; rq.nz = NZ; rq.n = NY;
-      d_redG.push_back(rq);
+      ContractDesc c{};
+      c.na = NX; c.nb = NY; c.nz = NZ; c.nterms = nsx;
+      c.src = w_gspec; c.src_r = g.out_r;
+      for (int i = 0; i < nsx; ++i) { c.coef[i] = GX.inv + (int64_t)sepx[i] * NX; c.coef_stride[i] = 1; }
+      c.dst = w_Qx; c.dst_t = (int64_t)NZ * NY; c.dst_r = (int64_t)nsx * NZ * NY; c.dst_z = NY;
+      d_sigx.push_back(c);
     }
     if (nsy > 0) {
-      ReduceDesc rq{};
-      rq.src = w_gparty; rq.src_term = g.redy_term; rq.src_tile = g.redy_tile; rq.src_r = g.redy_r;
-      rq.dst = w_Qy; rq.dst_term = (int64_t)NZ * NX; rq.dst_r = (int64_t)nsy * NZ * NX; rq.dst_z = NX;
-      rq.nterms = nsy; rq.ntiles = g.tiles_b; rq.nz = NZ; rq.n = NX;
-      d_redG.push_back(rq);
+      ContractDesc c{};
+      c.na = NX; c.nb = NY; c.nz = NZ; c.nterms = nsy;
+      c.src = w_gspec; c.src_r = g.out_r;
+      for (int j = 0; j < nsy; ++j) { c.coef[j] = GY.inv + (int64_t)sepy[j] * NY; c.coef_stride[j] = 1; }
+      c.dst = w_Qy; c.dst_t = (int64_t)NZ * NX; c.dst_r = (int64_t)nsy * NZ * NX; c.dst_z = NX;
+      d_sigy.push_back(c);
     }
-    redB_max = 0;
-    for (auto& d : d_redB) redB_max = std::max<int64_t>(redB_max, (int64_t)d.nterms * d.nz * d.n);
-    redG_max = 0;
-    for (auto& d : d_redG) redG_max = std::max<int64_t>(redG_max, (int64_t)d.nterms * d.nz * d.n);
     sg.NX = NX; sg.NY = NY; sg.nz = NZ; sg.nsx = nsx; sg.nsy = nsy; sg.NF = NF;
     sg.rmax = max_rhs; sg.nbx_blocks = nbx_blocks;
     sg.f_r = f_r; sg.face = w_vface; sg.face_f = face_f; sg.gface = w_gface;
@@ -660,7 +623,8 @@ hs_status Plan::upload(std::string& err) {
   reg(d_vface, &p_vface); reg(d_gface, &p_gface);
   reg(d_glob_in, &p_glob_in); reg(d_glob_out, &p_glob_out);
   reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
-  reg(d_redB, &p_redB); reg(d_redG, &p_redG); reg(d_lift, &p_lift);
+  reg(d_facex, &p_facex); reg(d_facey, &p_facey); reg(d_sigx, &p_sigx); reg(d_sigy, &p_sigy);
+  reg(d_lift, &p_lift);
   if (hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
   if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail("descriptors");
   for (auto& f : fx) *f.dst = (const unsigned char*)ddesc + f.off;
@@ -839,9 +803,19 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     for (auto& d : v) m = std::max(m, xform_lines_tiles(d));
     return m;
   };
-  auto tiles_sw = [](const std::vector<SweepDesc>& v) {
-    int m = 0;
-    for (auto& d : v) m = std::max(m, d.tiles_a * d.tiles_b);
+  auto modes = [](const std::vector<SweepDesc>& v) {
+    int64_t m = 0;
+    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.na * d.nb);
+    return m;
+  };
+  auto lines_x = [](const std::vector<ContractDesc>& v) {
+    int64_t m = 0;
+    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * d.nb);
+    return m;
+  };
+  auto cols_y = [](const std::vector<ContractDesc>& v) {
+    int64_t m = 0;
+    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * ((d.na + 255) / 256));
     return m;
   };
   // algorithmic work of the stages (per call, all right-hand sides)
@@ -875,18 +849,19 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweep, nb, tiles_sw(d_sweep), T, W, nrhs, st);
+    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, T, W, nrhs, st);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
     const double nsig = double(NZ) * (nsx * NY + nsy * NX);
     const double nglob = double(NX) * NY * NZ;
     // steps 2-3: block sweeps, v on the lines next to the separators
-    stage_begin("zsweep_blocks_v", R * (nblk + nface) * esz, R * nblk * (thomas + 32), st);
-    sweep(prec, p_sweepB, nb, tiles_sw(d_sweepB), T, W, nrhs, st);
+    stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
+    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, W, nrhs, st);
     stage_end();
-    stage_begin("face_reduce", R * nface * 2 * esz, 0, st);
-    reduce_partials(prec, p_redB, int(d_redB.size()), redB_max, W, nrhs, st);
+    stage_begin("face_contract", R * nblk * 2 * esz, R * nblk * 2 * 2 * 8, st);
+    contract(prec, 0, p_facex, int(d_facex.size()), lines_x(d_facex), T, W, nrhs, st);
+    contract(prec, 1, p_facey, int(d_facey.size()), cols_y(d_facey), T, W, nrhs, st);
     stage_end();
     double ffl = 0;
     for (auto& B : blocks) ffl += double(NZ) * 2.0 * (double(B.nby) * B.nby + double(B.nbx) * B.nbx) * 8.0;
@@ -904,11 +879,12 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
     xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
     stage_end();
-    stage_begin("zsweep_global", R * nsig * 2 * esz, R * nglob * (thomas + 16 * (nsx + nsy)), st);
-    sweep(prec, p_sweepG, 1, tiles_sw(d_sweepG), T, W, nrhs, st);
+    stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
+    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, W, nrhs, st);
     stage_end();
-    stage_begin("sigma_reduce", R * nsig * 2 * esz, 0, st);
-    reduce_partials(prec, p_redG, int(d_redG.size()), redG_max, W, nrhs, st);
+    stage_begin("sigma_contract", R * nglob * 2 * esz, R * nglob * (nsx + nsy) * 8, st);
+    contract(prec, 0, p_sigx, int(d_sigx.size()), lines_x(d_sigx), T, W, nrhs, st);
+    contract(prec, 1, p_sigy, int(d_sigy.size()), cols_y(d_sigy), T, W, nrhs, st);
     stage_end();
     stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
     xform_lines(prec, 0, 0, 0, p_glob_out, int(d_glob_out.size()), tiles_lines(d_glob_out), T, W, W, nrhs, st);
@@ -921,7 +897,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
-    sweep(prec, p_sweepC, nb, tiles_sw(d_sweepC), T, W, nrhs, st);
+    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, T, W, nrhs, st);
     stage_end();
   }
   // step 7: inverse transforms into u

@@ -29,9 +29,7 @@ struct Block {
   int ax = -1, ay = -1;          // axis table indices
   int sep_lo_x = -1, sep_hi_x = -1, sep_lo_y = -1, sep_hi_y = -1;
   int64_t spec = 0;              // workspace offset of the block spectral array
-  int64_t dbuf = 0;              // workspace offset of its forward-sweep scratch
-  int64_t ckpt = 0, ckptC = 0;   // checkpoint regions of its sweeps
-  int64_t partx = 0, party = 0;  // tile partials of its face reductions
+  int64_t vt = 0;                // workspace offset of its spectral block solution v~ (steps 2-3)
 };
 
 // One transform stage: dense-table descriptors plus sine-FFT descriptors per V.
@@ -95,7 +93,7 @@ struct Plan {
   int NF = 0;
   int64_t w_face = 0, w_vface = 0, w_gface = 0, w_Gface = 0;
   int64_t w_rx = 0, w_ry = 0, w_Rx = 0, w_Ry = 0, w_Qx = 0, w_Qy = 0, w_wx = 0, w_wy = 0;
-  int64_t w_gpartx = 0, w_gparty = 0, w_gckpt = 0, w_gdbuf = 0;
+  int64_t w_gspec = 0;           // global spectral solution w~ of the interface solve
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;
@@ -104,15 +102,15 @@ struct Plan {
   std::vector<XformDesc> d_vface, d_gface, d_glob_in, d_glob_out;
   int64_t twid = 0;                  // twiddle table offset
   std::vector<SweepDesc> d_sweep, d_sweepB, d_sweepC, d_sweepG;
-  std::vector<ReduceDesc> d_redB, d_redG;
+  std::vector<ContractDesc> d_facex, d_facey, d_sigx, d_sigy;
   std::vector<LiftBlock> d_lift;
   // device pointers of each list
   const XformDesc *p_vface = nullptr, *p_gface = nullptr, *p_glob_in = nullptr, *p_glob_out = nullptr;
   const SweepDesc *p_sweep = nullptr, *p_sweepB = nullptr, *p_sweepC = nullptr, *p_sweepG = nullptr;
-  const ReduceDesc *p_redB = nullptr, *p_redG = nullptr;
+  const ContractDesc *p_facex = nullptr, *p_facey = nullptr, *p_sigx = nullptr, *p_sigy = nullptr;
   const LiftBlock* p_lift = nullptr;
   SigmaGeom sg{};
-  int64_t redB_max = 0, redG_max = 0;
+  int64_t max_modes_blk = 0;
   int max_block_n = 0;
 
   // ---------------- per-stage event timing

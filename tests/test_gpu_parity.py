@@ -86,6 +86,27 @@ def test_sine_fft_path_vs_oracle_and_dense(hs, shape):
     assert per_rhs_err(um, u) < TOL64R
 
 
+@pytest.mark.parametrize("nz", [2, 3, 31, 32, 33, 255, 256, 257, 300, 512])
+def test_z_line_lengths_vs_oracle(hs, nz):
+    """z solves split each line into up to 16 (32 beyond 256 rows) chunks;
+    cover short lines, chunk-count boundaries and ragged chunks."""
+    rng = np.random.default_rng(nz)
+    p = W.random_problem(9, 7, nz, min(5, nz), rng, pml_x=2)
+    f = W.complex_normal(rng, (1,) + p.shape)
+    u = hs.Plan(p, "c128").solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+    um = hs.Plan(p, "mixed").solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(um, u) < TOL64R
+
+
+def test_nz_limit_is_an_argument_error(hs):
+    rng = np.random.default_rng(0)
+    p = W.uniform_problem(4, 4, 513, 1, rng)
+    with pytest.raises(hs.HSError) as e:
+        hs.Plan(p, "c128")
+    assert e.value.status == hs.HS_ERR_ARG
+
+
 def test_manufactured_solution_and_stencil(hs):
     rng = np.random.default_rng(11)
     p = W.random_problem(30, 26, 22, 3, rng, pml_x=4, pml_y=3)
