@@ -178,122 +178,99 @@ __device__ __forceinline__ void fft_reg(C (&a)[V], const C* __restrict__ tw) {
   }
 }
 
-template <typename R, typename CI, typename CO, bool ACC, int V>
-__global__ __launch_bounds__(256) void k_dst(const DstDesc* __restrict__ descs, const cplx<R>* __restrict__ tw,
-                                             const CI* __restrict__ src, CO* __restrict__ dst, int lt) {
+template <typename R, typename CI, typename CO, bool ACC, int V, int LT>
+__global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ descs, const cplx<R>* __restrict__ tw,
+                                                 const CI* __restrict__ src, CO* __restrict__ dst) {
   using C = cplx<R>;
   constexpr int L = 16 * V;
   constexpr int N = L / 2;
   constexpr int n = N - 1;
-  constexpr int XS = L + L / 16;   // LDS row: 17 slots per 16 values
-  extern __shared__ unsigned char smem_raw[];
-  C* buf = reinterpret_cast<C*>(smem_raw);
+  constexpr int XS = 17 * V + 1;   // LDS row of one line: 17 slots per 16 values, odd pad
+  __shared__ R xbuf[LT * XS];      // real and imaginary parts exchanged in turn
   const DstDesc d = descs[blockIdx.y];
   const int lines = d.P * d.Q;
-  const int l0 = blockIdx.x * lt;
+  const int l0 = blockIdx.x * LT;
   if (l0 >= lines) return;
   const int r = blockIdx.z;
-  const int tid = threadIdx.x;
-  const int nthr = lt * 16;
-  const int li = tid >> 4, t = tid & 15;
-  const CI* sb = src + d.src + (int64_t)r * d.src_r;
-  // stage the input lines: buf[l * XS + i]
-  if (d.src_i == 1) {
-    for (int e = tid; e < lt * n; e += nthr) {
-      const int l = e / n, i = e % n, g = l0 + l;
-      if (g < lines) {
-        const int p = g / d.Q, q = g % d.Q;
-        buf[l * XS + i] = cvt<C>(sb[(int64_t)p * d.src_p + (int64_t)q * d.src_q + i]);
-      }
-    }
-  } else {
-    for (int e = tid; e < lt * n; e += nthr) {
-      const int i = e / lt, l = e % lt, g = l0 + l;
-      if (g < lines) {
-        const int p = g / d.Q, q = g % d.Q;
-        buf[l * XS + i] = cvt<C>(sb[(int64_t)p * d.src_p + (int64_t)q * d.src_q + (int64_t)i * d.src_i]);
-      }
-    }
-  }
-  __syncthreads();
-  const C* row = buf + li * XS;
+  // lanes run along a line for contiguous lines (x) and across lines for
+  // strided ones (y), so that each 16-lane group touches consecutive addresses
+  const bool along = d.src_i == 1;
+  const int li = along ? int(threadIdx.x >> 4) : int(threadIdx.x % LT);
+  const int t = along ? int(threadIdx.x & 15) : int(threadIdx.x / LT);
+  const int g = l0 + li;
+  const bool ok = g < lines;
+  const int p = ok ? g / d.Q : 0, q = ok ? g % d.Q : 0;
+  const CI* sl = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
+  // odd extension y_j, j = t + 16 v: y_j = x_{j-1} (0 < j < N), -x_{2N-j-1} (j > N), 0 else
   C a[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int j = t + 16 * v;
     C val = mk<R>(0, 0);
-    if (j > 0 && j < N) {
-      val = row[j - 1];
-    } else if (j > N) {
-      val = row[2 * N - j - 1];
-      val.x = -val.x;
-      val.y = -val.y;
+    if (ok && j != 0 && j != N) {
+      const int e = j < N ? j - 1 : 2 * N - j - 1;
+      val = cvt<C>(sl[(int64_t)e * d.src_i]);
+      if (j > N) {
+        val.x = -val.x;
+        val.y = -val.y;
+      }
     }
     a[v] = val;
   }
   fft_reg<C, V>(a, tw);
 #pragma unroll
   for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % L) * (TW_N / L)]);
-  __syncthreads();
-  C* wrow = buf + li * XS;
-#pragma unroll
-  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2];
-  __syncthreads();
+  R* wrow = xbuf + li * XS;
   constexpr int G = V >= 16 ? V / 16 : 1;
   C b[G][16];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int k2 = t + 16 * g;
+  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2].x;
+  __syncthreads();
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) {
+    const int k2 = t + 16 * gg;
     if (k2 < V) {
 #pragma unroll
-      for (int tt = 0; tt < 16; ++tt) b[g][tt] = wrow[k2 * 17 + tt];
-      fft_reg<C, 16>(b[g], tw);
+      for (int tt = 0; tt < 16; ++tt) b[gg][tt].x = wrow[k2 * 17 + tt];
     }
   }
   __syncthreads();
-  const R sc = R(0.5) * R(sqrt(2.0 / double(N)));
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int k2 = t + 16 * g;
+  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2].y;
+  __syncthreads();
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) {
+    const int k2 = t + 16 * gg;
+    if (k2 < V) {
+#pragma unroll
+      for (int tt = 0; tt < 16; ++tt) b[gg][tt].y = wrow[k2 * 17 + tt];
+      fft_reg<C, 16>(b[gg], tw);
+    }
+  }
+  if (!ok) return;
+  const R sc = R(0.5) * R(sqrt(2.0 / double(N)));
+  CO* dl = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q;
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) {
+    const int k2 = t + 16 * gg;
     if (k2 < V) {
 #pragma unroll
       for (int k1 = 0; k1 < 16; ++k1) {
         const int m = k2 + V * k1;
         if (m >= 1 && m <= n) {
           C o;
-          o.x = -sc * b[g][k1].y;
-          o.y = sc * b[g][k1].x;
-          wrow[m - 1] = o;
+          o.x = -sc * b[gg][k1].y;
+          o.y = sc * b[gg][k1].x;
+          CO* ptr = dl + (int64_t)(m - 1) * d.dst_i;
+          if (ACC) {
+            CO pv = *ptr;
+            pv.x += o.x;
+            pv.y += o.y;
+            *ptr = pv;
+          } else {
+            *ptr = cvt<CO>(o);
+          }
         }
-      }
-    }
-  }
-  __syncthreads();
-  CO* db = dst + d.dst + (int64_t)r * d.dst_r;
-  auto put = [&](CO* ptr, const C& v) {
-    if (ACC) {
-      CO pv = *ptr;
-      pv.x += v.x;
-      pv.y += v.y;
-      *ptr = pv;
-    } else {
-      *ptr = cvt<CO>(v);
-    }
-  };
-  if (d.dst_i == 1) {
-    for (int e = tid; e < lt * n; e += nthr) {
-      const int l = e / n, i = e % n, g = l0 + l;
-      if (g < lines) {
-        const int p = g / d.Q, q = g % d.Q;
-        put(db + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + i, buf[l * XS + i]);
-      }
-    }
-  } else {
-    for (int e = tid; e < lt * n; e += nthr) {
-      const int i = e / lt, l = e % lt, g = l0 + l;
-      if (g < lines) {
-        const int p = g / d.Q, q = g % d.Q;
-        put(db + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + (int64_t)i * d.dst_i, buf[l * XS + i]);
       }
     }
   }
@@ -353,12 +330,12 @@ __device__ __forceinline__ C crcp_fast(C z) {
 constexpr int PS_LMAX = 16;   // rows per chunk held in registers
 
 template <typename R, int P, int MW>
-__global__ __launch_bounds__(512) void k_psweep(const SweepDesc* __restrict__ descs,
+__global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
   using Q = typename quad_of<R>::type;
-  static_assert(P * MW == 512, "512 lanes per workgroup");
+  static_assert(P * MW == 256, "256 lanes per workgroup");
   extern __shared__ unsigned char smem_raw[];
   const SweepDesc d = descs[blockIdx.y];
   const int na = d.na, nb = d.nb, nz = d.nz;
@@ -367,7 +344,7 @@ __global__ __launch_bounds__(512) void k_psweep(const SweepDesc* __restrict__ de
   if (m0 >= plane) return;
   Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z
   C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nz) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
-  for (int k = threadIdx.x; k < nz; k += 512) {
+  for (int k = threadIdx.x; k < nz; k += 256) {
     const C dg = tab[d.zdiag + k];
     Q q;
     q.x = dg.x;
@@ -606,33 +583,48 @@ __global__ __launch_bounds__(256) void k_contract_x(const ContractDesc* __restri
 }
 
 // Contraction over b (strided): out_t(r,z,a) = sum_b c_t[b] X(r,z,b,a).
-// One lane per column a of a z plane.
+// 64 columns a x 4 row groups per workgroup; the groups meet in LDS.
 template <typename R>
 __global__ __launch_bounds__(256) void k_contract_y(const ContractDesc* __restrict__ descs,
                                                     const cplx<R>* __restrict__ tab,
                                                     cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
+  __shared__ C part[3][kMaxTerms][64];
   const ContractDesc d = descs[blockIdx.y];
-  const int ncol = (d.na + 255) / 256;
+  const int ncol = (d.na + 63) / 64;
   if ((int)blockIdx.x >= ncol * d.nz) return;
   const int z = blockIdx.x / ncol;
-  const int a = (blockIdx.x % ncol) * 256 + threadIdx.x;
-  if (a >= d.na) return;
+  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int a = (blockIdx.x % ncol) * 64 + c;
+  const bool ok = a < d.na;
   const int r = blockIdx.z;
-  const C* x = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.nb * d.na + a;
+  const C* x = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.nb * d.na + (ok ? a : 0);
   C acc[kMaxTerms];
 #pragma unroll
   for (int t = 0; t < kMaxTerms; ++t) acc[t] = mk<R>(0, 0);
-#pragma unroll 8
-  for (int b = 0; b < d.nb; ++b) {
-    const C v = x[(int64_t)b * d.na];
+  if (ok) {
+#pragma unroll 4
+    for (int b = grp; b < d.nb; b += 4) {
+      const C v = x[(int64_t)b * d.na];
 #pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t)
-      if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)b * d.coef_stride[t]], v, acc[t]);
+      for (int t = 0; t < kMaxTerms; ++t)
+        if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)b * d.coef_stride[t]], v, acc[t]);
+    }
   }
+  if (grp > 0) {
 #pragma unroll
-  for (int t = 0; t < kMaxTerms; ++t)
-    if (t < d.nterms) ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + a] = acc[t];
+    for (int t = 0; t < kMaxTerms; ++t) part[grp - 1][t][c] = acc[t];
+  }
+  __syncthreads();
+  if (grp == 0 && ok) {
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < d.nterms) {
+        C v = cadd(cadd(acc[t], part[0][t][c]), cadd(part[1][t][c], part[2][t][c]));
+        ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + a] = v;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -880,12 +872,10 @@ void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int
 
 // ---------------------------------------------------------------- sine transform
 int dst_lines_per_wg(int prec, int V) {
-  const int L = 16 * V;
-  const int xs = L + L / 16;
-  const int esz = prec == 0 ? 16 : 8;
-  int lt = 65536 / (xs * esz);
-  if (lt > 16) lt = 16;
-  if (lt < 1) lt = 1;
+  // exchange rows of 17 V + 1 real values, at most 40 KB of LDS per workgroup
+  const int rsz = prec == 0 ? 8 : 4;
+  int lt = 16;
+  while (lt > 4 && (17 * V + 1) * rsz * lt > 40960) lt /= 2;
   return lt;
 }
 
@@ -894,24 +884,23 @@ static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, cons
                          void* dst, int nrhs, hipStream_t st) {
   const int prec = sizeof(R) == 8 ? 0 : 1;
   const int lt = dst_lines_per_wg(prec, V);
-  const size_t lds = size_t(lt) * (16 * V + V) * sizeof(cplx<R>);
   const dim3 grid((max_lines + lt - 1) / lt, ndesc, nrhs);
-  const dim3 block(16 * lt);
   const cplx<R>* T = (const cplx<R>*)tw;
-  switch (V) {
-#define HS_DST_CASE(VV)                                                                                  \
-  case VV:                                                                                               \
-    hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV>), grid, block, lds, st, d, T, (const CI*)src, (CO*)dst, lt); \
-    break;
-    HS_DST_CASE(2)
-    HS_DST_CASE(4)
-    HS_DST_CASE(8)
-    HS_DST_CASE(16)
-    HS_DST_CASE(32)
-#undef HS_DST_CASE
-    default:
-      break;
+#define HS_DST_CASE(VV, LL)                                                                                    \
+  if (V == VV && lt == LL) {                                                                                   \
+    hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV, LL>), grid, dim3(16 * LL), 0, st, d, T, (const CI*)src,       \
+                       (CO*)dst);                                                                              \
+    return;                                                                                                    \
   }
+  HS_DST_CASE(2, 16)
+  HS_DST_CASE(4, 16)
+  HS_DST_CASE(8, 16)
+  HS_DST_CASE(16, 16)
+  HS_DST_CASE(16, 8)
+  HS_DST_CASE(32, 16)
+  HS_DST_CASE(32, 8)
+  HS_DST_CASE(32, 4)
+#undef HS_DST_CASE
 }
 
 void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
@@ -968,7 +957,7 @@ int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct
 size_t sweep_lds_bytes(int prec, int nz) {
   const size_t q = prec == 0 ? sizeof(double4) : sizeof(float4);
   const size_t c = prec == 0 ? sizeof(double2) : sizeof(float2);
-  return (size_t(nz) * q + 255) / 256 * 256 + 6 * 512 * c;
+  return (size_t(nz) * q + 255) / 256 * 256 + 6 * 256 * c;
 }
 
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab, void* ws,
@@ -976,18 +965,18 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   const size_t lds = sweep_lds_bytes(prec, max_nz);
   const bool deep = max_nz > 16 * PS_LMAX;   // up to 32 chunks of 16 rows
-  const int mw = deep ? 16 : 32;
+  const int mw = deep ? 8 : 16;
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
   if (prec == 0) {
     if (deep)
-      hipLaunchKernelGGL((k_psweep<double, 32, 16>), grid, dim3(512), lds, st, d, (const double2*)tab, (double2*)ws);
+      hipLaunchKernelGGL((k_psweep<double, 32, 8>), grid, dim3(256), lds, st, d, (const double2*)tab, (double2*)ws);
     else
-      hipLaunchKernelGGL((k_psweep<double, 16, 32>), grid, dim3(512), lds, st, d, (const double2*)tab, (double2*)ws);
+      hipLaunchKernelGGL((k_psweep<double, 16, 16>), grid, dim3(256), lds, st, d, (const double2*)tab, (double2*)ws);
   } else {
     if (deep)
-      hipLaunchKernelGGL((k_psweep<float, 32, 16>), grid, dim3(512), lds, st, d, (const float2*)tab, (float2*)ws);
+      hipLaunchKernelGGL((k_psweep<float, 32, 8>), grid, dim3(256), lds, st, d, (const float2*)tab, (float2*)ws);
     else
-      hipLaunchKernelGGL((k_psweep<float, 16, 32>), grid, dim3(512), lds, st, d, (const float2*)tab, (float2*)ws);
+      hipLaunchKernelGGL((k_psweep<float, 16, 16>), grid, dim3(256), lds, st, d, (const float2*)tab, (float2*)ws);
   }
 }
 

@@ -65,7 +65,7 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
            int nrhs, hipStream_t st);
 
 // Face / interface contractions (axis 0: over a, max_units = nz * nb lines;
-// axis 1: over b, max_units = nz * ceil(na / 256) column groups).
+// axis 1: over b, max_units = nz * ceil(na / 64) column groups).
 void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,
               int nrhs, hipStream_t st);
 

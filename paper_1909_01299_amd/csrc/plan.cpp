@@ -815,7 +815,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   };
   auto cols_y = [](const std::vector<ContractDesc>& v) {
     int64_t m = 0;
-    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * ((d.na + 255) / 256));
+    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * ((d.na + 63) / 64));
     return m;
   };
   // algorithmic work of the stages (per call, all right-hand sides)
