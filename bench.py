@@ -131,6 +131,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--mixed-only", action="store_true", help="time only the mixed-precision solve (profiling)")
     ap.add_argument("--core", type=int, default=256, help="uniform core cells per axis")
     ap.add_argument("--pml", type=int, default=16)
     ap.add_argument("--nz", type=int, default=200)
@@ -153,6 +154,12 @@ def main():
     f = hs.to_device(f_np)
     u = torch.empty_like(f)
 
+    if args.mixed_only:
+        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs)
+        um = torch.empty_like(f)
+        dtm, _ = time_solves(plan_m, f, um, args.steps, args.warmup, profile=False)
+        print(json.dumps({"mixed_ms_per_step": dtm / args.steps * 1e3}), flush=True)
+        return
     plan = hs.Plan(p, "c128", max_rhs=nrhs)
     info = plan.info()
     dt, stages = time_solves(plan, f, u, args.steps, args.warmup)
