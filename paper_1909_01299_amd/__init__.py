@@ -266,6 +266,52 @@ class Plan:
         return out
 
 
+class Batch:
+    """Many independent single-block plans solved together: every stage is one
+    batched launch over all (plan, right-hand side) pairs, enqueued as one
+    captured HIP graph (re-captured only when the array pointers change)."""
+
+    def __init__(self, plans: Sequence[Plan], nrhs: Sequence[int]):
+        import torch
+        self.plans = list(plans)
+        self.nrhs = [int(r) for r in nrhs]
+        if len(self.plans) != len(self.nrhs) or not self.plans:
+            raise ValueError("one nrhs per plan")
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        rs = (ctypes.c_int32 * len(self.plans))(*self.nrhs)
+        h = ctypes.c_void_p()
+        _check(lib().hs_batch_create(arr, len(self.plans), rs, ctypes.byref(h)))
+        self._h = h
+        nbytes = lib().hs_batch_workspace_bytes(self._h)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.plans[0].device)
+        _check(lib().hs_batch_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().hs_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def solve(self, fs, us=None, stream=None):
+        import torch
+        if len(fs) != len(self.plans):
+            raise ValueError("one f per plan")
+        if us is None:
+            us = [torch.empty_like(f) for f in fs]
+        for p, r, f, u in zip(self.plans, self.nrhs, fs, us):
+            _check_array(f, p.shape, "f")
+            _check_array(u, p.shape, "u")
+            if p._nrhs(f) != r or p._nrhs(u) != r:
+                raise ValueError("right-hand side count differs from the batch's")
+        fa = (ctypes.c_void_p * len(fs))(*[_ptr(f) for f in fs])
+        ua = (ctypes.c_void_p * len(us))(*[_ptr(u) for u in us])
+        _check(lib().hs_batch_solve(self._h, fa, ua, _stream(stream)))
+        return us
+
+
 def _make_autograd():
     import torch
 

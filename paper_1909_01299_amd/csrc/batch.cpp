@@ -1,0 +1,321 @@
+// Batched solve of many independent single-block plans (see batch.hpp).
+//
+// The plans' FP64 table images are concatenated into one device table buffer;
+// every (plan, right-hand side) pair becomes one descriptor per stage, so a
+// stage of the whole batch is one kernel launch (blocks of different sizes and
+// z lengths side by side).  The sequence of launches (and, for the mixed path,
+// the fixed number of refinement steps with one FP64 residual per plan) is
+// captured once into a HIP graph and replayed; it is re-captured only when the
+// caller passes different array pointers.
+#include "batch.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+namespace hs {
+
+namespace {
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+int ilog2i(int v) {
+  int r = 0;
+  while (v > 1) { v >>= 1; ++r; }
+  return r;
+}
+}  // namespace
+
+Batch::~Batch() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (dtab64) (void)hipFree(dtab64);
+  if (dtab32) (void)hipFree(dtab32);
+  if (ddesc) (void)hipFree(ddesc);
+}
+
+hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int>& rs, std::string& err) {
+  plans = ps;
+  nrhs = rs;
+  prec = plans[0]->prec;
+  refine_steps = plans[0]->refine_steps;
+  device = plans[0]->device;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    if (p->decomposed) { err = "batched plans must be single blocks (no separators)"; return HS_ERR_ARG; }
+    if (p->prec != prec || p->refine_steps != refine_steps) { err = "batched plans must share one precision"; return HS_ERR_ARG; }
+    if (p->device != device) { err = "batched plans must live on one device"; return HS_ERR_ARG; }
+    if (rs[i] < 1 || rs[i] > 4096) { err = "nrhs out of range"; return HS_ERR_ARG; }
+  }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  // tables
+  std::vector<cd> img;
+  for (const Plan* p : plans) {
+    tab_off.push_back(int64_t(img.size()));
+    img.insert(img.end(), p->htab.begin(), p->htab.end());
+    img.resize(align_up(int64_t(img.size()), 32));
+  }
+  tab_elems = img.size();
+  std::vector<double2> t64(tab_elems);
+  for (size_t i = 0; i < tab_elems; ++i) t64[i] = make_double2(img[i].real(), img[i].imag());
+  if (hipMalloc(&dtab64, tab_elems * sizeof(double2)) != hipSuccess ||
+      hipMemcpy(dtab64, t64.data(), tab_elems * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    err = "table upload failed";
+    return HS_ERR_ALLOC;
+  }
+  if (prec == 1) {
+    std::vector<float2> t32(tab_elems);
+    for (size_t i = 0; i < tab_elems; ++i) t32[i] = make_float2(float(img[i].real()), float(img[i].imag()));
+    if (hipMalloc(&dtab32, tab_elems * sizeof(float2)) != hipSuccess ||
+        hipMemcpy(dtab32, t32.data(), tab_elems * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipGetLastError();
+      err = "table upload failed";
+      return HS_ERR_ALLOC;
+    }
+  }
+  // workspace: spectral arrays of every (plan, rhs), then the complex64 residuals
+  int64_t off = 0;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    spec_off.push_back(off);
+    off = align_up(off + int64_t(nrhs[i]) * p->NX * p->NY * p->NZ, 64);
+    max_nz = std::max(max_nz, p->NZ);
+    max_modes = std::max<int64_t>(max_modes, (int64_t)p->NX * p->NY);
+  }
+  ws_elems = size_t(off);
+  const size_t esz = prec == 0 ? 16 : 8;
+  size_t bytes = align_up(int64_t(ws_elems * esz), 256);
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    res_off.push_back(bytes);
+    if (prec == 1) bytes += align_up(int64_t(nrhs[i]) * p->NX * p->NY * p->NZ * 8, 256);
+  }
+  ws_bytes = bytes;
+  if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    err = "stream creation failed";
+    return HS_ERR_DEVICE;
+  }
+  return HS_OK;
+}
+
+hs_status Batch::bind(void* p, size_t bytes, std::string& err) {
+  if (!p) { err = "workspace pointer is NULL"; return HS_ERR_ARG; }
+  if (bytes < ws_bytes) { err = "workspace too small"; return HS_ERR_ARG; }
+  if ((uintptr_t)p % 256 != 0) { err = "workspace must be 256-byte aligned"; return HS_ERR_ARG; }
+  if (p != ws) {
+    ws = p;
+    last_f.clear();   // forces a new capture
+  }
+  return HS_OK;
+}
+
+hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err) {
+  s_fwdx = {}; s_fwdx_res = {}; s_invx = {}; s_fwdy = {}; s_invy = {};
+  d_sweep.clear();
+  const char* f0 = (const char*)f[0];
+  const char* u0 = (const char*)u[0];
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    const int64_t df = (const char*)f[i] - f0, du = (const char*)u[i] - u0;
+    if (df % 16 || du % 16) { err = "f and u arrays must be 16-byte aligned"; return HS_ERR_ARG; }
+    const Block& B = p->blocks[0];
+    const Axis& AX = p->axes[B.ax];
+    const Axis& AY = p->axes[B.ay];
+    const int64_t T0 = tab_off[i];
+    const int64_t plane = (int64_t)B.nbx * B.nby;
+    const int64_t N = plane * p->NZ;
+    for (int r = 0; r < nrhs[i]; ++r) {
+      const int64_t spec = spec_off[i] + r * N;
+      const int64_t fo = df / 16 + r * N, uo = du / 16 + r * N;
+      const int64_t ro = int64_t(res_off[i] / 8) + r * N;   // complex64 elements from the workspace base
+      if (AX.dstV) {
+        DstDesc dx{};
+        dx.n = B.nbx; dx.P = p->NZ; dx.Q = B.nby;
+        dx.src = fo; dx.src_p = plane; dx.src_q = B.nbx; dx.src_i = 1;
+        dx.dst = spec; dx.dst_p = plane; dx.dst_q = B.nbx; dx.dst_i = 1;
+        const int v = ilog2i(AX.dstV) - 1;
+        s_fwdx.dst[v].push_back(dx);
+        DstDesc dr = dx;
+        dr.src = ro;
+        s_fwdx_res.dst[v].push_back(dr);
+        DstDesc ix = dx;
+        ix.src = spec; ix.dst = uo;
+        s_invx.dst[v].push_back(ix);
+      } else {
+        XformDesc fx{};
+        fx.tab = T0 + AX.fwd; fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
+        fx.src = fo; fx.src_p = plane; fx.src_q = B.nbx;
+        fx.dst = spec; fx.dst_p = plane; fx.dst_q = B.nbx;
+        s_fwdx.dense.push_back(fx);
+        XformDesc fr = fx;
+        fr.src = ro;
+        s_fwdx_res.dense.push_back(fr);
+        XformDesc ix = fx;
+        ix.tab = T0 + AX.inv; ix.src = spec; ix.dst = uo;
+        s_invx.dense.push_back(ix);
+      }
+      if (AY.dstV) {
+        DstDesc dy{};
+        dy.n = B.nby; dy.P = p->NZ; dy.Q = B.nbx;
+        dy.src = spec; dy.src_p = plane; dy.src_q = 1; dy.src_i = B.nbx;
+        dy.dst = spec; dy.dst_p = plane; dy.dst_q = 1; dy.dst_i = B.nbx;
+        const int v = ilog2i(AY.dstV) - 1;
+        s_fwdy.dst[v].push_back(dy);
+        s_invy.dst[v].push_back(dy);
+      } else {
+        XformYDesc fy{};
+        fy.tab = T0 + AY.fwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
+        fy.data = spec; fy.s_p = plane; fy.s_k = B.nbx;
+        s_fwdy.dense.push_back(fy);
+        XformYDesc iy = fy;
+        iy.tab = T0 + AY.inv;
+        s_invy.dense.push_back(iy);
+      }
+      SweepDesc s{};
+      s.na = B.nbx; s.nb = B.nby; s.nz = p->NZ; s.dense_in = 1;
+      s.lam_x = T0 + AX.lam; s.lam_y = T0 + AY.lam;
+      s.zlo = T0 + p->zlo; s.zdiag = T0 + p->zdiag; s.zup = T0 + p->zup;
+      s.data = spec; s.out = spec;
+      d_sweep.push_back(s);
+    }
+  }
+  // upload the descriptor tables
+  std::vector<unsigned char> blob;
+  struct Fix { size_t off; const void** dst; };
+  std::vector<Fix> fx;
+  auto reg = [&](const auto& v, auto** out) {
+    size_t o = align_up(int64_t(blob.size()), 256);
+    const size_t n = v.size() * sizeof(v[0]);
+    blob.resize(o + n);
+    if (n) std::memcpy(blob.data() + o, v.data(), n);
+    fx.push_back({o, (const void**)out});
+  };
+  auto reg_stage = [&](auto& sl) {
+    reg(sl.dense, &sl.p_dense);
+    for (int v = 0; v < kNumV; ++v) {
+      reg(sl.dst[v], &sl.p_dst[v]);
+      int m = 0;
+      for (auto& d : sl.dst[v]) m = std::max(m, d.P * d.Q);
+      sl.max_lines[v] = m;
+    }
+  };
+  reg_stage(s_fwdx); reg_stage(s_fwdx_res); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
+  reg(d_sweep, &p_sweep);
+  if (blob.size() > ddesc_bytes) {
+    if (ddesc) (void)hipFree(ddesc);
+    ddesc = nullptr;
+    if (hipMalloc(&ddesc, blob.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      ddesc_bytes = 0;
+      err = "descriptor allocation failed";
+      return HS_ERR_ALLOC;
+    }
+    ddesc_bytes = blob.size();
+  }
+  if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    err = "descriptor upload failed";
+    return HS_ERR_DEVICE;
+  }
+  for (auto& f2 : fx) *f2.dst = (const unsigned char*)ddesc + f2.off;
+  return HS_OK;
+}
+
+void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, const void* src, void* dst,
+                  hipStream_t st) {
+  const void* T = tab();
+  if (!sl.dense.empty()) {
+    int m = 0;
+    for (auto& d : sl.dense) m = std::max(m, xform_lines_tiles(d));
+    xform_lines(prec, in64, out64, acc, sl.p_dense, int(sl.dense.size()), m, T, src, dst, 1, st);
+  }
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
+  for (int v = 0; v < kNumV; ++v)
+    if (!sl.dst[v].empty())
+      dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
+                dst, 1, st);
+}
+
+void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
+  const void* T = tab();
+  if (!sl.dense.empty()) {
+    int m16 = 0, m8 = 0, mn = 0;
+    for (auto& d : sl.dense) {
+      m16 = std::max(m16, xform_y_tiles(d, 16));
+      m8 = std::max(m8, xform_y_tiles(d, 8));
+      mn = std::max(mn, d.n);
+    }
+    xform_y(prec, sl.p_dense, int(sl.dense.size()), mn, m16, m8, T, ws, 1, st);
+  }
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
+  for (int v = 0; v < kNumV; ++v)
+    if (!sl.dst[v].empty())
+      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st);
+}
+
+void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
+  auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
+    run_x(fwd, in64, 0, 0, src, ws, st);
+    run_y(s_fwdy, st);
+    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, tab(), ws, 1, st);
+    run_y(s_invy, st);
+    run_x(s_invx, 0, 1, acc, ws, u0, st);
+  };
+  pass(s_fwdx, f0, 1, 0);
+  for (int it = 0; it < refine_steps; ++it) {
+    for (size_t i = 0; i < plans.size(); ++i) {
+      const Plan* p = plans[i];
+      // r = f - A u of plan i (FP64 stencil, complex64 output); f, u of plan i are
+      // recovered from the offsets relative to f0 / u0 recorded at capture
+      hs::residual(p->sten, (const char*)f0 + foff[i], (char*)u0 + uoff[i], (char*)ws + res_off[i], 0, 0,
+                   nrhs[i], st);
+    }
+    pass(s_fwdx_res, ws, 0, 1);
+  }
+}
+
+hs_status Batch::solve(const void* const* f, void* const* u, hipStream_t st, std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (!f || !u) { err = "f and u must be non-NULL"; return HS_ERR_ARG; }
+  for (size_t i = 0; i < plans.size(); ++i)
+    if (!f[i] || !u[i]) { err = "NULL array in f or u"; return HS_ERR_ARG; }
+  if (prec == 1)
+    for (size_t i = 0; i < plans.size(); ++i)
+      if (f[i] == (const void*)u[i]) { err = "the mixed-precision solve needs u distinct from f"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  bool same = last_f.size() == plans.size();
+  for (size_t i = 0; same && i < plans.size(); ++i) same = last_f[i] == f[i] && last_u[i] == u[i];
+  if (!same) {
+    hs_status s = rebuild(f, u, err);
+    if (s != HS_OK) return s;
+    foff.assign(plans.size(), 0);
+    uoff.assign(plans.size(), 0);
+    for (size_t i = 0; i < plans.size(); ++i) {
+      foff[i] = (const char*)f[i] - (const char*)f[0];
+      uoff[i] = (const char*)u[i] - (const char*)u[0];
+    }
+    if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+    if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      err = "graph capture failed to start";
+      return HS_ERR_DEVICE;
+    }
+    enqueue(f[0], u[0], cap_stream);
+    if (hipStreamEndCapture(cap_stream, &graph) != hipSuccess ||
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      err = "graph capture failed";
+      return HS_ERR_DEVICE;
+    }
+    last_f.assign(f, f + plans.size());
+    last_u.assign(u, u + plans.size());
+  }
+  if (hipGraphLaunch(exec, st) != hipSuccess) {
+    (void)hipGetLastError();
+    err = "graph launch failed";
+    return HS_ERR_DEVICE;
+  }
+  return HS_OK;
+}
+
+}  // namespace hs

@@ -1,0 +1,62 @@
+// Batched solve of many independent single-block plans (uneven sizes, several
+// right-hand sides each) as one captured HIP graph: every stage is one batched
+// launch over all (plan, right-hand side) pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace hs {
+
+struct Batch {
+  std::vector<const Plan*> plans;
+  std::vector<int> nrhs;
+  int prec = 0;
+  int refine_steps = 0;
+  int device = 0;
+  // combined tables
+  std::vector<int64_t> tab_off;   // per plan, element offset of its tables
+  void* dtab64 = nullptr;
+  void* dtab32 = nullptr;
+  size_t tab_elems = 0;
+  // workspace layout: per (plan, rhs) spectral array; complex64 residual per plan
+  std::vector<int64_t> spec_off;  // per plan, first rhs (elements of the compute precision)
+  std::vector<size_t> res_off;    // per plan, byte offset of its residual
+  size_t ws_elems = 0, ws_bytes = 0;
+  void* ws = nullptr;
+  int max_nz = 0;
+  int64_t max_modes = 0;
+  // descriptors rebuilt when the caller's pointers change
+  std::vector<const void*> last_f;
+  std::vector<void*> last_u;
+  std::vector<int64_t> foff, uoff;   // byte offsets of each plan's f / u from the first plan's
+  StageList<XformDesc> s_fwdx, s_fwdx_res, s_invx;
+  StageList<XformYDesc> s_fwdy, s_invy;
+  std::vector<SweepDesc> d_sweep;
+  const SweepDesc* p_sweep = nullptr;
+  void* ddesc = nullptr;
+  size_t ddesc_bytes = 0;
+  // graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~Batch();
+  hs_status build(const std::vector<const Plan*>& ps, const std::vector<int>& rs, std::string& err);
+  hs_status bind(void* p, size_t bytes, std::string& err);
+  hs_status solve(const void* const* f, void* const* u, hipStream_t st, std::string& err);
+
+ private:
+  hs_status rebuild(const void* const* f, void* const* u, std::string& err);
+  void enqueue(const void* f0, void* u0, hipStream_t st);
+  void run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, const void* src, void* dst,
+             hipStream_t st);
+  void run_y(const StageList<XformYDesc>& sl, hipStream_t st);
+  const void* tab() const { return prec == 0 ? dtab64 : dtab32; }
+};
+
+}  // namespace hs

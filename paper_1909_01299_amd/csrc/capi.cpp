@@ -8,10 +8,15 @@
 #include <string>
 
 #include "../../include/helmsep.h"
+#include "batch.hpp"
 #include "plan.hpp"
 
 struct hs_plan_s {
   hs::Plan p;
+};
+
+struct hs_batch_s {
+  hs::Batch b;
 };
 
 namespace {
@@ -170,17 +175,49 @@ hs_status hs_axis_eig(int32_t n, const double* h, double* lam, double* W, double
 
 // ---------------------------------------------------------------- batch
 
-struct hs_batch_s {
-  size_t ws_bytes = 0;
-};
-
-hs_status hs_batch_create(const hs_plan*, int32_t, const int32_t*, hs_batch* out) {
-  if (out) *out = nullptr;
-  return ret(HS_ERR_STATE, "batched solve not available in this build");
+hs_status hs_batch_create(const hs_plan* plans, int32_t nplans, const int32_t* nrhs, hs_batch* out) {
+  if (!out) return ret(HS_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!plans || nplans < 1 || !nrhs) return ret(HS_ERR_ARG, "invalid plan list");
+  std::vector<const hs::Plan*> ps(nplans);
+  std::vector<int> rs(nplans);
+  for (int i = 0; i < nplans; ++i) {
+    if (!plans[i]) return ret(HS_ERR_ARG, "NULL plan in list");
+    ps[i] = &plans[i]->p;
+    rs[i] = nrhs[i];
+  }
+  auto* b = new (std::nothrow) hs_batch_s;
+  if (!b) return ret(HS_ERR_ALLOC, "host allocation failed");
+  std::string err;
+  hs_status s;
+  try {
+    s = b->b.build(ps, rs, err);
+  } catch (const std::exception& e) {
+    s = HS_ERR_ALLOC;
+    err = e.what();
+  }
+  if (s != HS_OK) {
+    delete b;
+    return ret(s, err);
+  }
+  *out = b;
+  return ret(HS_OK, "");
 }
-size_t hs_batch_workspace_bytes(hs_batch) { return 0; }
-hs_status hs_batch_bind_workspace(hs_batch, void*, size_t) { return ret(HS_ERR_STATE, "no batch"); }
-hs_status hs_batch_solve(hs_batch, const void* const*, void* const*, void*) { return ret(HS_ERR_STATE, "no batch"); }
-void hs_batch_destroy(hs_batch b) { delete b; }
+
+size_t hs_batch_workspace_bytes(hs_batch batch) { return batch ? batch->b.ws_bytes : 0; }
+
+hs_status hs_batch_bind_workspace(hs_batch batch, void* dev_ptr, size_t bytes) {
+  if (!batch) return ret(HS_ERR_ARG, "batch is NULL");
+  std::string err;
+  return ret(batch->b.bind(dev_ptr, bytes, err), err);
+}
+
+hs_status hs_batch_solve(hs_batch batch, const void* const* f, void* const* u, void* stream) {
+  if (!batch) return ret(HS_ERR_ARG, "batch is NULL");
+  std::string err;
+  return ret(batch->b.solve(f, u, (hipStream_t)stream, err), err);
+}
+
+void hs_batch_destroy(hs_batch batch) { delete batch; }
 
 }  // extern "C"
