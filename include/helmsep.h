@@ -107,6 +107,9 @@ typedef struct {
   double min_pivot;         /* smallest |z pivot| over all modes (FP64 scan)    */
   double plan_seconds;      /* host time spent building the plan               */
   size_t table_bytes;       /* device bytes held by the plan                   */
+  int64_t n_fp64_modes;     /* HS_C64_REFINE: modes near resonance (Re(lam_x +
+                               lam_y) <= 1.25 max Re k^2) whose z solves run in
+                               FP64 with the workgroup that holds them        */
 } hs_info;
 
 /* Build a plan: validates the grid and blocks (HS_ERR_ARG), computes the 1D

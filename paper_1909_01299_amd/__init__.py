@@ -53,7 +53,8 @@ class Info(ctypes.Structure):
                 ("n_dense_axes", ctypes.c_int32), ("n_sine_axes", ctypes.c_int32),
                 ("kappa_max", ctypes.c_double), ("eig_resid_max", ctypes.c_double),
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t)]
+                ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
+                ("n_fp64_modes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -175,6 +175,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
       s.lam_x = T0 + AX.lam; s.lam_y = T0 + AY.lam;
       s.zlo = T0 + p->zlo; s.zdiag = T0 + p->zdiag; s.zup = T0 + p->zup;
       s.data = spec; s.out = spec;
+      s.fp64_below = p->fp64_below;
       d_sweep.push_back(s);
     }
   }
@@ -257,7 +258,7 @@ void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
   auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
-    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, tab(), ws, 1, st);
+    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, tab(), dtab64, ws, 1, st);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

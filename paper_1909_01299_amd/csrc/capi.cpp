@@ -130,6 +130,7 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   info->min_pivot = p.min_pivot;
   info->plan_seconds = p.plan_seconds;
   info->table_bytes = p.tab_elems * (p.prec == 0 ? 16 : 24);
+  info->n_fp64_modes = p.n_fp64_modes;
   return ret(HS_OK, "");
 }
 

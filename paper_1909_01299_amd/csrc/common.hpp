@@ -110,6 +110,7 @@ constexpr int kMaxTerms = 4;
 struct SweepDesc {
   int32_t na, nb, nz, dense_in;
   int32_t nxt, nyt, pad0_, pad1_;
+  double fp64_below;              // complex64 path: modes with Re(lam_x + lam_y) <= this solve in FP64
   int64_t lam_x, lam_y;           // table offsets (complex, length na / nb)
   int64_t zlo, zdiag, zup;        // table offsets (complex, length nz)
   int64_t data, data_r;           // workspace offsets

@@ -329,19 +329,17 @@ __device__ __forceinline__ C crcp_fast(C z) {
 
 constexpr int PS_LMAX = 16;   // rows per chunk held in registers
 
-template <typename R, int P, int MW>
-__global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
-                                                const cplx<R>* __restrict__ tab,
-                                                cplx<R>* __restrict__ ws) {
+// RS: storage precision of the workspace arrays; R: arithmetic precision and
+// precision of the tables `tab`.
+template <typename RS, typename R, int P, int MW>
+__device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* __restrict__ tab,
+                                            cplx<RS>* __restrict__ ws, unsigned char* smem_raw) {
   using C = cplx<R>;
+  using CS = cplx<RS>;
   using Q = typename quad_of<R>::type;
-  static_assert(P * MW == 256, "256 lanes per workgroup");
-  extern __shared__ unsigned char smem_raw[];
-  const SweepDesc d = descs[blockIdx.y];
   const int na = d.na, nb = d.nb, nz = d.nz;
   const int64_t plane = (int64_t)na * nb;
   const int64_t m0 = (int64_t)blockIdx.x * MW;
-  if (m0 >= plane) return;
   Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z
   C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nz) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
   for (int k = threadIdx.x; k < nz; k += 256) {
@@ -368,10 +366,10 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 
   // right-hand side of the chunk
   C rb[PS_LMAX];
-  const C* src = ws + d.data + (int64_t)r * d.data_r + m;
+  const CS* src = ws + d.data + (int64_t)r * d.data_r + m;
 #pragma unroll
   for (int kk = 0; kk < PS_LMAX; ++kk)
-    rb[kk] = (act && d.dense_in && kk < len) ? src[(int64_t)(k0 + kk) * plane] : mk<R>(0, 0);
+    rb[kk] = (act && d.dense_in && kk < len) ? cvt<C>(src[(int64_t)(k0 + kk) * plane]) : mk<R>(0, 0);
   // low-rank terms: a chunk's values are loaded together (row index clamped
   // into the chunk so every load is valid), then accumulated
   const int lastk = k0 + (len > 0 ? len - 1 : 0);
@@ -382,11 +380,11 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
     if (act && t < (isx ? d.nxt : d.nyt)) {
       const C c = isx ? tab[d.colx[t] + (int64_t)a * d.colx_stride[t]]
                       : tab[d.coly[t] + (int64_t)b * d.coly_stride[t]];
-      const C* g = isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a;
+      const CS* g = isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a;
       const int64_t gz = isx ? d.gx_z : d.gy_z;
       C gv[PS_LMAX];
 #pragma unroll
-      for (int kk = 0; kk < PS_LMAX; ++kk) gv[kk] = g[(int64_t)min(k0 + kk, lastk) * gz];
+      for (int kk = 0; kk < PS_LMAX; ++kk) gv[kk] = cvt<C>(g[(int64_t)min(k0 + kk, lastk) * gz]);
 #pragma unroll
       for (int kk = 0; kk < PS_LMAX; ++kk)
         if (kk < len) rb[kk] = cfma(c, gv[kk], rb[kk]);
@@ -532,12 +530,41 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
         xn = rb[kk];
       }
     }
-    C* dst = ws + d.out + (int64_t)r * d.out_r + m;
+    CS* dst = ws + d.out + (int64_t)r * d.out_r + m;
 #pragma unroll
     for (int kk = 0; kk < PS_LMAX; ++kk)
-      if (kk < len) dst[(int64_t)(k0 + kk) * plane] = rb[kk];
+      if (kk < len) dst[(int64_t)(k0 + kk) * plane] = cvt<CS>(rb[kk]);
   }
 }
+
+template <typename R, int P, int MW>
+__global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
+                                                const cplx<R>* __restrict__ tab,
+                                                const double2* __restrict__ tab64,
+                                                cplx<R>* __restrict__ ws) {
+  static_assert(P * MW == 256, "256 lanes per workgroup");
+  extern __shared__ unsigned char smem_raw[];
+  const SweepDesc d = descs[blockIdx.y];
+  const int64_t plane = (int64_t)d.na * d.nb;
+  if ((int64_t)blockIdx.x * MW >= plane) return;
+  if constexpr (sizeof(R) == 8) {
+    psweep_body<R, R, P, MW>(d, tab, ws, smem_raw);
+  } else {
+    // complex64 storage: a workgroup holding a mode near resonance (small
+    // Re(lam_x + lam_y)) runs its z solves in FP64 from the FP64 tables
+    const int64_t m = (int64_t)blockIdx.x * MW + threadIdx.x % MW;
+    bool low = false;
+    if (m < plane) {
+      const int a = int(m % d.na), b = int(m / d.na);
+      low = tab64[d.lam_x + a].x + tab64[d.lam_y + b].x <= d.fp64_below;
+    }
+    if (__syncthreads_or(low))
+      psweep_body<R, double, P, MW>(d, tab64, ws, smem_raw);
+    else
+      psweep_body<R, R, P, MW>(d, tab, ws, smem_raw);
+  }
+}
+
 
 // Contraction over a (contiguous): out_t(r,z,b) = sum_a c_t[a] X(r,z,b,a).
 // 16 lines (z, b) per workgroup, 16 lanes stride over a, then a 16-lane sum.
@@ -955,13 +982,13 @@ void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles1
 int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct) * d.P; }
 
 size_t sweep_lds_bytes(int prec, int nz) {
-  const size_t q = prec == 0 ? sizeof(double4) : sizeof(float4);
-  const size_t c = prec == 0 ? sizeof(double2) : sizeof(float2);
-  return (size_t(nz) * q + 255) / 256 * 256 + 6 * 256 * c;
+  // sized for FP64 arithmetic, which the complex64 kernel may switch to
+  (void)prec;
+  return (size_t(nz) * sizeof(double4) + 255) / 256 * 256 + 6 * 256 * sizeof(double2);
 }
 
-void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab, void* ws,
-           int nrhs, hipStream_t st) {
+void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab,
+           const void* tab64, void* ws, int nrhs, hipStream_t st) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   const size_t lds = sweep_lds_bytes(prec, max_nz);
   const bool deep = max_nz > 16 * PS_LMAX;   // up to 32 chunks of 16 rows
@@ -969,14 +996,18 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
   if (prec == 0) {
     if (deep)
-      hipLaunchKernelGGL((k_psweep<double, 32, 8>), grid, dim3(256), lds, st, d, (const double2*)tab, (double2*)ws);
+      hipLaunchKernelGGL((k_psweep<double, 32, 8>), grid, dim3(256), lds, st, d, (const double2*)tab,
+                         (const double2*)tab64, (double2*)ws);
     else
-      hipLaunchKernelGGL((k_psweep<double, 16, 16>), grid, dim3(256), lds, st, d, (const double2*)tab, (double2*)ws);
+      hipLaunchKernelGGL((k_psweep<double, 16, 16>), grid, dim3(256), lds, st, d, (const double2*)tab,
+                         (const double2*)tab64, (double2*)ws);
   } else {
     if (deep)
-      hipLaunchKernelGGL((k_psweep<float, 32, 8>), grid, dim3(256), lds, st, d, (const float2*)tab, (float2*)ws);
+      hipLaunchKernelGGL((k_psweep<float, 32, 8>), grid, dim3(256), lds, st, d, (const float2*)tab,
+                         (const double2*)tab64, (float2*)ws);
     else
-      hipLaunchKernelGGL((k_psweep<float, 16, 16>), grid, dim3(256), lds, st, d, (const float2*)tab, (float2*)ws);
+      hipLaunchKernelGGL((k_psweep<float, 16, 16>), grid, dim3(256), lds, st, d, (const float2*)tab,
+                         (const double2*)tab64, (float2*)ws);
   }
 }
 

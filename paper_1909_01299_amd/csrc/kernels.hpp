@@ -61,8 +61,8 @@ int xform_y_tiles(const XformYDesc& d, int ct);
 // batched launch over descriptors (max_modes = largest na * nb).
 size_t sweep_lds_bytes(int prec, int nz);
 constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
-void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab, void* ws,
-           int nrhs, hipStream_t st);
+void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab,
+           const void* tab64, void* ws, int nrhs, hipStream_t st);
 
 // Face / interface contractions (axis 0: over a, max_units = nz * nb lines;
 // axis 1: over b, max_units = nz * ceil(na / 64) column groups).

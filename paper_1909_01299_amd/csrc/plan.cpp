@@ -128,6 +128,7 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   if (st != HS_OK) return st;
   layout_workspace();
   build_descriptors();
+  set_fp64_threshold();
   st = upload(err);
   plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
@@ -277,6 +278,19 @@ void Plan::build_stencil_host(std::vector<double2>& out) {
   for (int k = 0; k < NZ; ++k) put(cd(0.5 * (hz[k] + hz[k + 1])));
 }
 
+// Near resonance a mode's z pivots lose digits to cancellation; in the
+// complex64 path every workgroup holding a mode with
+// Re(lam_x + lam_y) <= 1.25 max_z Re k^2(z) solves its z systems in FP64.
+void Plan::set_fp64_threshold() {
+  double kmax = -1e300;
+  for (int k = 0; k < NZ; ++k) kmax = std::max(kmax, k2[layer[k]].real());
+  fp64_below = prec == 1 ? 1.25 * kmax : -1e300;
+  auto patch = [&](std::vector<SweepDesc>& v) {
+    for (auto& d : v) d.fp64_below = fp64_below;
+  };
+  patch(d_sweep); patch(d_sweepB); patch(d_sweepC); patch(d_sweepG);
+}
+
 hs_status Plan::scan_pivots(std::string& err) {
   // FP64 scan of the no-pivoting Thomas pivots of every mode of every block
   // (and of the global axes): the z solve needs them bounded away from zero.
@@ -302,6 +316,19 @@ hs_status Plan::scan_pivots(std::string& err) {
     scan(axes[B.ax], axes[B.ay]);
   }
   if (decomposed) scan(axes[gax], axes[gay]);
+  set_fp64_threshold();
+  n_fp64_modes = 0;
+  if (prec == 1) {
+    auto count = [&](const Axis& ax, const Axis& ay) {
+      int64_t c = 0;
+      for (int b = 0; b < ay.n; ++b)
+        for (int a = 0; a < ax.n; ++a)
+          if ((ax.e.lam[a] + ay.e.lam[b]).real() <= fp64_below) ++c;
+      return c;
+    };
+    for (auto& B : blocks) n_fp64_modes += count(axes[B.ax], axes[B.ay]);
+    if (decomposed) n_fp64_modes += count(axes[gax], axes[gay]);
+  }
   min_pivot = mn;
   if (!(mn > 1e-12 * std::max(scale, 1.0))) {
     err = "z pivot too small (" + std::to_string(mn) + "): the layered operator is numerically singular";
@@ -596,6 +623,15 @@ hs_status Plan::upload(std::string& err) {
   sten.yd = p; p += NY; sten.yl = p; p += NY; sten.yu = p; p += NY;
   sten.zd = p; p += NZ; sten.zl = p; p += NZ; sten.zu = p; p += NZ;
   sten.mx = p; p += NX; sten.my = p; p += NY; sten.mz = p; p += NZ;
+  return upload_descs(err);
+}
+
+hs_status Plan::upload_descs(std::string& err) {
+  auto fail = [&](const char* what) {
+    (void)hipGetLastError();
+    err = std::string("device allocation/copy failed: ") + what;
+    return HS_ERR_ALLOC;
+  };
   // descriptors
   std::vector<unsigned char> blob;
   auto dpush = [&](const void* src, size_t bytes) {
@@ -625,7 +661,7 @@ hs_status Plan::upload(std::string& err) {
   reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
   reg(d_facex, &p_facex); reg(d_facey, &p_facey); reg(d_sigx, &p_sigx); reg(d_sigy, &p_sigy);
   reg(d_lift, &p_lift);
-  if (hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
+  if (!ddesc && hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
   if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail("descriptors");
   for (auto& f : fx) *f.dst = (const unsigned char*)ddesc + f.off;
   return HS_OK;
@@ -676,7 +712,7 @@ hs_status Plan::set_k2(const double* k2v, std::string& err) {
     err = "hipMemcpy failed";
     return HS_ERR_DEVICE;
   }
-  return HS_OK;
+  return upload_descs(err);   // the FP64 threshold of the sweeps depends on k^2
 }
 
 hs_status Plan::bind(void* p, size_t bytes, std::string& err) {
@@ -849,7 +885,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, T, W, nrhs, st);
+    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, T, dtab64, W, nrhs, st);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -857,7 +893,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     const double nglob = double(NX) * NY * NZ;
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, W, nrhs, st);
+    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, dtab64, W, nrhs, st);
     stage_end();
     stage_begin("face_contract", R * nblk * 2 * esz, R * nblk * 2 * 2 * 8, st);
     contract(prec, 0, p_facex, int(d_facex.size()), lines_x(d_facex), T, W, nrhs, st);
@@ -880,7 +916,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
-    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, W, nrhs, st);
+    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, dtab64, W, nrhs, st);
     stage_end();
     stage_begin("sigma_contract", R * nglob * 2 * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, 0, p_sigx, int(d_sigx.size()), lines_x(d_sigx), T, W, nrhs, st);
@@ -897,7 +933,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
-    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, T, W, nrhs, st);
+    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, T, dtab64, W, nrhs, st);
     stage_end();
   }
   // step 7: inverse transforms into u

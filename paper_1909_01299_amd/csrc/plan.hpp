@@ -83,6 +83,8 @@ struct Plan {
   double2* dsten = nullptr;      // FP64 stencil arrays
   StencilGeom sten{};
   double min_pivot = 0;
+  double fp64_below = -1e300;    // complex64 path: z solves of modes with Re(lam_x + lam_y) <= this in FP64
+  int64_t n_fp64_modes = 0;
 
   // ---------------- workspace (layout for max_rhs)
   size_t ws_elems = 0;           // compute-precision complex elements
@@ -147,6 +149,8 @@ struct Plan {
   void layout_workspace();
   void build_descriptors();
   hs_status upload(std::string& err);
+  hs_status upload_descs(std::string& err);
+  void set_fp64_threshold();
   hs_status scan_pivots(std::string& err);
   const void* tab() const { return prec == 0 ? dtab64 : dtab32; }
   void run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, const void* src, void* dst, int nrhs,

@@ -244,6 +244,20 @@ def test_mixed_precision_single_block(hs):
     assert per_rhs_err(u, separable.solve(p, f)) < TOL64R
 
 
+def test_mixed_precision_near_resonance_modes_run_fp64(hs):
+    """Large Re k^2 puts many low modes near resonance; their z solves switch
+    to FP64 and the refined result still meets the mixed-precision bar."""
+    rng = np.random.default_rng(14)
+    p = W.uniform_problem(63, 47, 64, 4, rng)
+    p = p.with_k2(np.array([1.5 + 0.002j, 2.0 + 0.001j, 1.2 + 0.004j, 1.8 + 0.003j]))
+    f = W.complex_normal(rng, (1,) + p.shape)
+    plan = hs.Plan(p, "mixed")
+    assert plan.info()["n_fp64_modes"] > 0
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL64R
+    assert hs.Plan(p, "c128").info()["n_fp64_modes"] == 0
+
+
 def test_mixed_precision_decomposed(hs):
     p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=40, nlayers=6)
     rng = np.random.default_rng(13)
