@@ -161,6 +161,7 @@ def main():
         print(json.dumps({"mixed_ms_per_step": dtm / args.steps * 1e3}), flush=True)
         return
     plan = hs.Plan(p, "c128", max_rhs=nrhs)
+    tuned = plan.tune(nrhs)
     info = plan.info()
     dt, stages = time_solves(plan, f, u, args.steps, args.warmup)
     ms = dt / args.steps * 1e3
@@ -170,6 +171,7 @@ def main():
     mixed = None
     if not args.no_mixed:
         plan_m = hs.Plan(p, "mixed", max_rhs=nrhs)
+        plan_m.tune(nrhs)
         um = torch.empty_like(f)
         dtm, stages_m = time_solves(plan_m, f, um, args.steps, args.warmup)
         mixed = {"value": p.unknowns * nrhs / (dtm / args.steps), "ms_per_step": dtm / args.steps * 1e3,
@@ -213,6 +215,7 @@ def main():
             "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"]},
         "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
         "plan_seconds": info["plan_seconds"],
+        "tuned": tuned,
     }
     print(json.dumps(line), flush=True)
 

@@ -93,7 +93,9 @@ typedef struct {
   hs_precision prec;
   int32_t refine_steps;   /* HS_C64_REFINE: correction steps (default 2 when <= 0) */
   int32_t max_rhs;        /* largest nrhs a solve will be called with (>= 1)       */
-  int32_t flags;          /* bit 0: force the dense transform on uniform axes      */
+  int32_t flags;          /* bit 0: force the dense transform on uniform axes;
+                             bits 1-2: z-line chunks per mode (0 auto, 1: 8, 2: 16,
+                             3: 32; must hold nz within 16 rows per chunk)        */
 } hs_options;
 
 typedef struct {
@@ -110,6 +112,8 @@ typedef struct {
   int64_t n_fp64_modes;     /* HS_C64_REFINE: modes near resonance (Re(lam_x +
                                lam_y) <= 1.25 max Re k^2) whose z solves run in
                                FP64 with the workgroup that holds them        */
+  int32_t z_chunks;         /* z-line chunks per mode in use (hs_plan_tune)   */
+  int32_t sine_lines;       /* sine-transform lines per workgroup (0 = default) */
 } hs_info;
 
 /* Build a plan: validates the grid and blocks (HS_ERR_ARG), computes the 1D
@@ -154,6 +158,15 @@ hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r,
 hs_status hs_apply(hs_plan plan, const void* u, void* out, int32_t nrhs, void* stream);
 
 hs_status hs_get_info(hs_plan plan, hs_info* info);
+
+/* Autotune the plan's launch shapes for nrhs right-hand sides: every usable
+ * pair of (z-line chunks per mode in {8, 16, 32}, sine-transform lines per
+ * workgroup in {4, 8, 16}) is timed with hipEvents on `stream` over 3 solves
+ * of scratch data and the fastest is kept in the plan.  cache_path (may be
+ * NULL) names a JSON-lines file keyed by device architecture and plan shape:
+ * a hit skips the timing, a miss appends the result.  Needs a bound workspace;
+ * allocates and frees two scratch arrays; synchronizes the stream. */
+hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void* stream);
 
 /* Per-stage timing.  While enabled, every stage of a solve is bracketed by
  * hipEvents recorded on the solve's stream (events come from a pool created

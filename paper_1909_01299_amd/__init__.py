@@ -54,7 +54,7 @@ class Info(ctypes.Structure):
                 ("kappa_max", ctypes.c_double), ("eig_resid_max", ctypes.c_double),
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
-                ("n_fp64_modes", ctypes.c_int64)]
+                ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +82,7 @@ EXPORTS = {
     "hs_batch_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
+    "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "hs_axis_eig": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5),
@@ -154,7 +155,7 @@ class Plan:
     layer_of_z, k2 and optional sep_x, sep_y (numpy arrays)."""
 
     def __init__(self, problem, precision: str = "c128", max_rhs: int = 1, refine_steps: int = 0,
-                 force_dense: bool = False, device=None):
+                 force_dense: bool = False, z_chunks: int = 0, device=None):
         import torch
         self.problem = problem
         self.nx = len(problem.hx) - 1
@@ -176,7 +177,8 @@ class Plan:
                      self.nlayers, lz.ctypes.data, k2.ctypes.data)
         blocks = _Blocks(len(sx), sx.ctypes.data if len(sx) else None, len(sy), sy.ctypes.data if len(sy) else None)
         prec = {"c128": HS_C128, "c64": HS_C64_REFINE, "mixed": HS_C64_REFINE}[precision]
-        opts = _Options(prec, int(refine_steps), self.max_rhs, 1 if force_dense else 0)
+        chunk_bits = {0: 0, 8: 1, 16: 2, 32: 3}[int(z_chunks)] << 1
+        opts = _Options(prec, int(refine_steps), self.max_rhs, (1 if force_dense else 0) | chunk_bits)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().hs_plan_create(ctypes.byref(grid), ctypes.byref(blocks), ctypes.byref(opts),
@@ -203,6 +205,12 @@ class Plan:
         inf = Info()
         _check(lib().hs_get_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def tune(self, nrhs: int = 1, cache: Optional[str] = None, stream=None):
+        """Autotune launch shapes (z chunking, sine lines per workgroup) on this plan."""
+        _check(lib().hs_plan_tune(self._h, int(nrhs), cache.encode() if cache else None, _stream(stream)))
+        inf = self.info()
+        return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"]}
 
     def profile(self, on: bool = True):
         """Record hipEvents around every stage of subsequent solves."""

@@ -233,7 +233,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
       dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
-                dst, 1, st);
+                dst, 1, st, plans[0]->tune_lt);
 }
 
 void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
@@ -251,14 +251,15 @@ void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
-      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st);
+      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st,
+                plans[0]->tune_lt);
 }
 
 void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
   auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
-    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, tab(), dtab64, ws, 1, st);
+    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

@@ -131,7 +131,15 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   info->plan_seconds = p.plan_seconds;
   info->table_bytes = p.tab_elems * (p.prec == 0 ? 16 : 24);
   info->n_fp64_modes = p.n_fp64_modes;
+  info->z_chunks = hs::sweep_chunks_ok(p.tune_chunks, p.NZ) ? p.tune_chunks : hs::sweep_default_chunks(p.NZ);
+  info->sine_lines = p.tune_lt;
   return ret(HS_OK, "");
+}
+
+hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.tune(nrhs, cache_path, (hipStream_t)stream, err), err);
 }
 
 hs_status hs_profile_enable(hs_plan plan, int32_t on) {

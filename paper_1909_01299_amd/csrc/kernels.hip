@@ -906,11 +906,16 @@ int dst_lines_per_wg(int prec, int V) {
   return lt;
 }
 
+bool dst_lt_ok(int prec, int V, int lt) {
+  const int rsz = prec == 0 ? 8 : 4;
+  return (lt == 4 || lt == 8 || lt == 16) && (17 * V + 1) * rsz * lt <= 65536;
+}
+
 template <typename R, typename CI, typename CO, bool ACC>
 static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, const void* tw, const void* src,
-                         void* dst, int nrhs, hipStream_t st) {
+                         void* dst, int nrhs, hipStream_t st, int lt) {
   const int prec = sizeof(R) == 8 ? 0 : 1;
-  const int lt = dst_lines_per_wg(prec, V);
+  if (!dst_lt_ok(prec, V, lt)) lt = dst_lines_per_wg(prec, V);
   const dim3 grid((max_lines + lt - 1) / lt, ndesc, nrhs);
   const cplx<R>* T = (const cplx<R>*)tw;
 #define HS_DST_CASE(VV, LL)                                                                                    \
@@ -920,10 +925,17 @@ static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, cons
     return;                                                                                                    \
   }
   HS_DST_CASE(2, 16)
+  HS_DST_CASE(2, 8)
+  HS_DST_CASE(2, 4)
   HS_DST_CASE(4, 16)
+  HS_DST_CASE(4, 8)
+  HS_DST_CASE(4, 4)
   HS_DST_CASE(8, 16)
+  HS_DST_CASE(8, 8)
+  HS_DST_CASE(8, 4)
   HS_DST_CASE(16, 16)
   HS_DST_CASE(16, 8)
+  HS_DST_CASE(16, 4)
   HS_DST_CASE(32, 16)
   HS_DST_CASE(32, 8)
   HS_DST_CASE(32, 4)
@@ -931,21 +943,21 @@ static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, cons
 }
 
 void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
-               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st) {
+               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st, int lt) {
   if (ndesc == 0 || max_lines == 0 || nrhs == 0) return;
   if (prec == 0) {
-    launch_dst_t<double, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+    launch_dst_t<double, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
   } else if (!in64 && !out64) {
-    launch_dst_t<float, float2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+    launch_dst_t<float, float2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
   } else if (in64 && !out64) {
-    launch_dst_t<float, double2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+    launch_dst_t<float, double2, float2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
   } else if (!in64 && out64) {
     if (acc)
-      launch_dst_t<float, float2, double2, true>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+      launch_dst_t<float, float2, double2, true>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
     else
-      launch_dst_t<float, float2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+      launch_dst_t<float, float2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
   } else {
-    launch_dst_t<float, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st);
+    launch_dst_t<float, double2, double2, false>(V, d, ndesc, max_lines, tw, src, dst, nrhs, st, lt);
   }
 }
 
@@ -987,28 +999,32 @@ size_t sweep_lds_bytes(int prec, int nz) {
   return (size_t(nz) * sizeof(double4) + 255) / 256 * 256 + 6 * 256 * sizeof(double2);
 }
 
+int sweep_default_chunks(int nz) { return nz > 16 * PS_LMAX ? 32 : 16; }
+
+bool sweep_chunks_ok(int chunks, int nz) {
+  return (chunks == 8 || chunks == 16 || chunks == 32) && nz <= chunks * PS_LMAX;
+}
+
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st) {
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
+  if (!sweep_chunks_ok(chunks, max_nz)) chunks = sweep_default_chunks(max_nz);
   const size_t lds = sweep_lds_bytes(prec, max_nz);
-  const bool deep = max_nz > 16 * PS_LMAX;   // up to 32 chunks of 16 rows
-  const int mw = deep ? 8 : 16;
+  const int mw = 256 / chunks;
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
+#define HS_PSWEEP(RR, CC, PP, MM)                                                                        \
+  hipLaunchKernelGGL((k_psweep<RR, PP, MM>), grid, dim3(256), lds, st, d, (const CC*)tab, (const double2*)tab64, \
+                     (CC*)ws)
   if (prec == 0) {
-    if (deep)
-      hipLaunchKernelGGL((k_psweep<double, 32, 8>), grid, dim3(256), lds, st, d, (const double2*)tab,
-                         (const double2*)tab64, (double2*)ws);
-    else
-      hipLaunchKernelGGL((k_psweep<double, 16, 16>), grid, dim3(256), lds, st, d, (const double2*)tab,
-                         (const double2*)tab64, (double2*)ws);
+    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8);
+    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16);
+    else HS_PSWEEP(double, double2, 8, 32);
   } else {
-    if (deep)
-      hipLaunchKernelGGL((k_psweep<float, 32, 8>), grid, dim3(256), lds, st, d, (const float2*)tab,
-                         (const double2*)tab64, (float2*)ws);
-    else
-      hipLaunchKernelGGL((k_psweep<float, 16, 16>), grid, dim3(256), lds, st, d, (const float2*)tab,
-                         (const double2*)tab64, (float2*)ws);
+    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8);
+    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16);
+    else HS_PSWEEP(float, float2, 8, 32);
   }
+#undef HS_PSWEEP
 }
 
 void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,

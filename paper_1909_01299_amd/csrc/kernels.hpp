@@ -49,9 +49,11 @@ int xform_lines_tiles(const XformDesc& d);
 
 // Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
 constexpr int kTwiddleN = 512;
+// lt: lines per workgroup (4, 8 or 16; 0 or an unusable value = default)
 void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
-               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st);
+               const void* tw, const void* src, void* dst, int nrhs, hipStream_t st, int lt = 0);
 int dst_lines_per_wg(int prec, int V);
+bool dst_lt_ok(int prec, int V, int lt);
 
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st);
@@ -61,8 +63,12 @@ int xform_y_tiles(const XformYDesc& d, int ct);
 // batched launch over descriptors (max_modes = largest na * nb).
 size_t sweep_lds_bytes(int prec, int nz);
 constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
+// chunks: z-line chunks per mode (8, 16 or 32, each at most 16 rows; 256 / chunks
+// modes per workgroup); 0 or an unusable value = default for max_nz
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st);
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks = 0);
+int sweep_default_chunks(int nz);
+bool sweep_chunks_ok(int chunks, int nz);
 
 // Face / interface contractions (axis 0: over a, max_units = nz * nb lines;
 // axis 1: over b, max_units = nz * ceil(na / 64) column groups).

@@ -13,7 +13,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <fstream>
 #include <map>
+#include <sstream>
 
 namespace hs {
 
@@ -108,6 +111,13 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   if (op.max_rhs < 0 || op.max_rhs > 4096) { err = "max_rhs out of range"; return HS_ERR_ARG; }
   max_rhs = op.max_rhs > 0 ? op.max_rhs : 1;
   flags = op.flags;
+  {
+    const int cb = (flags >> 1) & 3;
+    if (cb) {
+      tune_chunks = 4 << cb;   // 8, 16, 32
+      if (!sweep_chunks_ok(tune_chunks, NZ)) { err = "requested z chunking cannot hold nz"; return HS_ERR_ARG; }
+    }
+  }
   decomposed = !sepx.empty() || !sepy.empty();
   for (auto& rx : runs(NX, sepx)) max_block_n = std::max(max_block_n, rx.second - rx.first + 1);
   for (auto& ry : runs(NY, sepy)) max_block_n = std::max(max_block_n, ry.second - ry.first + 1);
@@ -808,7 +818,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
       dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
-                dst, nrhs, st);
+                dst, nrhs, st, tune_lt);
 }
 
 void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
@@ -827,7 +837,7 @@ void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
       dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, nrhs,
-                st);
+                st, tune_lt);
 }
 
 void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st) {
@@ -885,7 +895,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, T, dtab64, W, nrhs, st);
+    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -893,7 +903,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     const double nglob = double(NX) * NY * NZ;
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, dtab64, W, nrhs, st);
+    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
     stage_begin("face_contract", R * nblk * 2 * esz, R * nblk * 2 * 2 * 8, st);
     contract(prec, 0, p_facex, int(d_facex.size()), lines_x(d_facex), T, W, nrhs, st);
@@ -916,7 +926,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
-    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, dtab64, W, nrhs, st);
+    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
     stage_begin("sigma_contract", R * nglob * 2 * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, 0, p_sigx, int(d_sigx.size()), lines_x(d_sigx), T, W, nrhs, st);
@@ -933,7 +943,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
-    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, T, dtab64, W, nrhs, st);
+    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
   }
   // step 7: inverse transforms into u
@@ -1018,6 +1028,103 @@ hs_status Plan::residual(const void* f, const void* u, void* r, int apply_only, 
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
   hs::residual(sten, f, u, r, 1, apply_only, nrhs, st);
   if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+}  // namespace hs
+
+namespace hs {
+
+// ---------------------------------------------------------------------------
+// Autotuning: time every usable (z chunking, sine lines per workgroup) pair on
+// this plan's shapes with hipEvents and keep the fastest; results are cached
+// in a JSON-lines file keyed by device architecture and plan shape.
+// ---------------------------------------------------------------------------
+hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { err = "hipGetDeviceProperties failed"; return HS_ERR_DEVICE; }
+  std::ostringstream key;
+  key << prop.gcnArchName << "|p" << prec << "|" << NX << "x" << NY << "x" << NZ << "|r" << nrhs << "|sx";
+  for (int v : sepx) key << v << ",";
+  key << "|sy";
+  for (int v : sepy) key << v << ",";
+  key << "|ax";
+  for (auto& a : axes) key << a.n << (a.dstV ? "s" : "d") << ",";
+  const std::string k = key.str();
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const std::string tag = "\"key\": \"" + k + "\"";
+      if (line.find(tag) == std::string::npos) continue;
+      int c = 0, l = 0;
+      const size_t pc = line.find("\"chunks\": "), pl = line.find("\"lines\": ");
+      if (pc != std::string::npos && pl != std::string::npos) {
+        c = std::atoi(line.c_str() + pc + 10);
+        l = std::atoi(line.c_str() + pl + 9);
+        tune_chunks = c;
+        tune_lt = l;
+        return HS_OK;
+      }
+    }
+  }
+  std::vector<int> chunks, lts;
+  for (int c : {8, 16, 32})
+    if (sweep_chunks_ok(c, NZ)) chunks.push_back(c);
+  bool any_dst = false;
+  for (auto& a : axes) any_dst |= a.dstV != 0;
+  for (int l : {4, 8, 16}) {
+    bool ok = true;
+    for (auto& a : axes)
+      if (a.dstV) ok &= dst_lt_ok(prec, a.dstV, l);
+    if (ok && any_dst) lts.push_back(l);
+  }
+  if (lts.empty()) lts.push_back(0);
+  const size_t bytes = size_t(nrhs) * NX * NY * NZ * 16;
+  void *f = nullptr, *u = nullptr;
+  if (hipMalloc(&f, bytes) != hipSuccess || hipMalloc(&u, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (f) (void)hipFree(f);
+    err = "tuning buffers could not be allocated";
+    return HS_ERR_ALLOC;
+  }
+  (void)hipMemset(f, 0, bytes);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float best = 1e30f;
+  int bc = 0, bl = 0;
+  const bool was_on = prof_on;
+  prof_on = false;
+  for (int c : chunks)
+    for (int l : lts) {
+      tune_chunks = c;
+      tune_lt = l;
+      std::string e2;
+      if (solve(f, u, nrhs, st, e2) != HS_OK) continue;
+      (void)hipEventRecord(e0, st);
+      for (int rep = 0; rep < 3; ++rep) (void)solve(f, u, nrhs, st, e2);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; bc = c; bl = l; }
+    }
+  prof_on = was_on;
+  tune_chunks = bc;
+  tune_lt = bl;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(f);
+  (void)hipFree(u);
+  if (cache_path && *cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl
+        << ", \"ms_per_solve\": " << best / 3 << "}\n";
+  }
   return HS_OK;
 }
 

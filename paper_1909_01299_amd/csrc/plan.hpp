@@ -83,6 +83,8 @@ struct Plan {
   double2* dsten = nullptr;      // FP64 stencil arrays
   StencilGeom sten{};
   double min_pivot = 0;
+  int tune_chunks = 0;           // z-line chunks per mode (0 = default for NZ)
+  int tune_lt = 0;               // sine-transform lines per workgroup (0 = default)
   double fp64_below = -1e300;    // complex64 path: z solves of modes with Re(lam_x + lam_y) <= this in FP64
   int64_t n_fp64_modes = 0;
 
@@ -138,6 +140,7 @@ struct Plan {
   hs_status grad_k2(const void* u, const void* a, void* grad, int nrhs, hipStream_t st, std::string& err);
   hs_status residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
                      std::string& err);
+  hs_status tune(int nrhs, const char* cache_path, hipStream_t st, std::string& err);
 
   // one pass of the block (or decomposed) solver in compute precision
   void solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st);

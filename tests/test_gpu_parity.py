@@ -121,6 +121,34 @@ def test_manufactured_solution_and_stencil(hs):
     assert np.linalg.norm(r) < 1e-9 * np.linalg.norm(ref)
 
 
+def test_autotune_keeps_parity_and_caches(hs, tmp_path):
+    rng = np.random.default_rng(17)
+    p = W.random_problem(31, 27, 70, 3, rng, pml_y=3)
+    p = W.Problem(W.uniform_steps(31), p.hy, p.hz, p.layer_of_z, p.k2)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    cache = str(tmp_path / "tune.jsonl")
+    plan = hs.Plan(p, "c128", max_rhs=2)
+    t1 = plan.tune(2, cache)
+    assert t1["z_chunks"] in (8, 16, 32) and t1["sine_lines"] in (4, 8, 16)
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < TOL128
+    plan2 = hs.Plan(p, "c128", max_rhs=2)
+    assert plan2.tune(2, cache) == t1          # served from the cache
+    assert len(open(cache).read().splitlines()) == 1
+
+
+@pytest.mark.parametrize("chunks", [8, 16, 32])
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_every_z_chunking_vs_oracle(hs, chunks, prec):
+    rng = np.random.default_rng(chunks)
+    p = W.random_problem(21, 17, 100, 4, rng, pml_x=3)
+    f = W.complex_normal(rng, (1,) + p.shape)
+    plan = hs.Plan(p, prec, z_chunks=chunks)
+    assert plan.info()["z_chunks"] == chunks
+    u = plan.solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < (TOL128 if prec == "c128" else TOL64R)
+
+
 # ------------------------------------------------------------------ decomposition
 
 DECOMP = [
