@@ -199,23 +199,26 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   const int t = along ? int(threadIdx.x & 15) : int(threadIdx.x / LT);
   const int g = l0 + li;
   const bool ok = g < lines;
-  const int p = ok ? g / d.Q : 0, q = ok ? g % d.Q : 0;
+  const int gc = ok ? g : lines - 1;   // a valid line for lanes past the end
+  const int p = gc / d.Q, q = gc % d.Q;
   const CI* sl = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
-  // odd extension y_j, j = t + 16 v: y_j = x_{j-1} (0 < j < N), -x_{2N-j-1} (j > N), 0 else
+  // odd extension y_j, j = t + 16 v: y_j = x_{j-1} (0 < j < N), -x_{2N-j-1} (j > N), 0 else.
+  // Every lane loads from a valid (clamped) address; sign and zeros are applied
+  // afterwards, so all loads are in flight together.
   C a[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int j = t + 16 * v;
-    C val = mk<R>(0, 0);
-    if (ok && j != 0 && j != N) {
-      const int e = j < N ? j - 1 : 2 * N - j - 1;
-      val = cvt<C>(sl[(int64_t)e * d.src_i]);
-      if (j > N) {
-        val.x = -val.x;
-        val.y = -val.y;
-      }
-    }
-    a[v] = val;
+    int e = j < N ? j - 1 : 2 * N - j - 1;
+    e = e < 0 ? 0 : (e > n - 1 ? n - 1 : e);
+    a[v] = cvt<C>(sl[(int64_t)e * d.src_i]);
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const int j = t + 16 * v;
+    const R fac = (!ok || j == 0 || j == N) ? R(0) : (j < N ? R(1) : R(-1));
+    a[v].x *= fac;
+    a[v].y *= fac;
   }
   fft_reg<C, V>(a, tw);
 #pragma unroll
