@@ -123,15 +123,20 @@ struct SweepDesc {
 };
 
 // Contraction of a spectral array X(r,z,b,a) = src + r*src_r + (z*nb + b)*na + a
-// with up to kMaxTerms coefficient vectors:
-//   axis 0: out_t(r,z,b) = sum_a c_t[a] X(r,z,b,a)
-//   axis 1: out_t(r,z,a) = sum_b c_t[b] X(r,z,b,a)
-// out_t(r,z,i) = dst + t*dst_t + r*dst_r + z*dst_z + i.
+// along both axes in one read, with up to kMaxTerms coefficient vectors each:
+//   out_x,t(r,z,b) = sum_a cx_t[a] X(r,z,b,a)   at dx + t*dx_t + r*dx_r + z*dx_z + b
+//   out_y,t(r,z,a) = sum_b cy_t[b] X(r,z,b,a)   at dy + t*dy_t + r*dy_r + z*dy_z + a
+// A z plane is split into nslab slabs of `rows` rows b; with nslab > 1 the
+// y sums of each slab go to part + r*part_r + s*part_s + t*part_t + z*part_z + a
+// and a second pass adds the slabs in order.
 struct ContractDesc {
-  int32_t na, nb, nz, nterms;
+  int32_t na, nb, nz, nxt, nyt, nslab, rows, pad;
   int64_t src, src_r;
-  int64_t coef[kMaxTerms]; int32_t coef_stride[kMaxTerms];   // table offsets
-  int64_t dst, dst_t, dst_r, dst_z;
+  int64_t cx[kMaxTerms], cy[kMaxTerms];   // table offsets
+  int32_t cx_stride[kMaxTerms], cy_stride[kMaxTerms];
+  int64_t dx, dx_t, dx_r, dx_z;
+  int64_t dy, dy_t, dy_r, dy_z;
+  int64_t part, part_s, part_t, part_r, part_z;
 };
 
 }  // namespace hs

@@ -569,92 +569,182 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 }
 
 
-// Contraction over a (contiguous): out_t(r,z,b) = sum_a c_t[a] X(r,z,b,a).
-// 16 lines (z, b) per workgroup, 16 lanes stride over a, then a 16-lane sum.
-template <typename R>
-__global__ __launch_bounds__(256) void k_contract_x(const ContractDesc* __restrict__ descs,
-                                                    const cplx<R>* __restrict__ tab,
-                                                    cplx<R>* __restrict__ ws) {
+// Fused contraction over both axes of a plane X(r,z,b,a) (a contiguous): one
+// workgroup reads the rows b of one slab of one z plane once and forms
+//   out_x,t(b) = sum_a cx_t[a] X(b,a)   (complete in the workgroup)
+//   out_y,t(a) = sum_b cy_t[b] X(b,a)   (over the slab's rows)
+// A row is spread over L = min(64, pow2 >= na) lanes of a wave, each lane
+// holding SMAX >= ceil(na / L) columns; a wave holds 64 / L rows at a time.
+// Coefficients are staged in LDS, zero past na, so every lane loads from a
+// valid (clamped) column and all loads of U rows are in flight together.
+// With full-wave rows the x sums of the U rows are reduced together: the
+// first butterfly steps exchange half of the rows each (transposed
+// reduction), so 4 rows cost 7 exchanges instead of 24 (2 rows: 6, not 12).
+template <typename R, int SMAX>
+__global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict__ descs, int max_slab,
+                                                  const cplx<R>* __restrict__ tab, cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
+  constexpr int U = SMAX <= 2 ? 4 : 2;
+  constexpr int SW = SMAX * 64;   // LDS stride of one x term
+  extern __shared__ unsigned char smem_raw[];
   const ContractDesc d = descs[blockIdx.y];
-  const int64_t lines = (int64_t)d.nz * d.nb;
-  const int64_t line = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-  if ((int64_t)blockIdx.x * 16 >= lines) return;
-  const int lane = threadIdx.x & 15;
+  const int z = blockIdx.x / max_slab, slab = blockIdx.x % max_slab;
+  if (z >= d.nz || slab >= d.nslab) return;
   const int r = blockIdx.z;
-  const bool ok = line < lines;
-  C acc[kMaxTerms];
-#pragma unroll
-  for (int t = 0; t < kMaxTerms; ++t) acc[t] = mk<R>(0, 0);
-  if (ok) {
-    const C* x = ws + d.src + (int64_t)r * d.src_r + line * d.na;
-#pragma unroll 4
-    for (int a = lane; a < d.na; a += 16) {
-      const C v = x[a];
-#pragma unroll
-      for (int t = 0; t < kMaxTerms; ++t)
-        if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)a * d.coef_stride[t]], v, acc[t]);
-    }
-  }
+  const int na = d.na;
+  int L = 1;
+  while (L < na && L < 64) L <<= 1;
+  const int G = 64 / L;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int la = lane & (L - 1), rg = w * G + lane / L, RG = 4 * G;
+  const int b0 = slab * d.rows, nrow = min(d.nb, b0 + d.rows) - b0;
+  C* cxs = reinterpret_cast<C*>(smem_raw);   // [nxt][SMAX*64], zero past na
+  C* cys = cxs + d.nxt * SW;                 // [nyt][rows]
+  C* yb = cys + d.nyt * d.rows;              // [3][kMaxTerms][64]
 #pragma unroll
   for (int t = 0; t < kMaxTerms; ++t) {
-    if (t < d.nterms) {
-      C v = acc[t];
-      v = cadd(v, shfl_xor_c(v, 8, 16));
-      v = cadd(v, shfl_xor_c(v, 4, 16));
-      v = cadd(v, shfl_xor_c(v, 2, 16));
-      v = cadd(v, shfl_xor_c(v, 1, 16));
-      if (ok && lane == 0) {
-        const int z = int(line / d.nb), bq = int(line % d.nb);
-        ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + bq] = v;
+    if (t < d.nxt)
+      for (int i = threadIdx.x; i < SW; i += 256)
+        cxs[t * SW + i] = i < na ? tab[d.cx[t] + (int64_t)i * d.cx_stride[t]] : mk<R>(0, 0);
+    if (t < d.nyt)
+      for (int i = threadIdx.x; i < nrow; i += 256) cys[t * d.rows + i] = tab[d.cy[t] + (int64_t)(b0 + i) * d.cy_stride[t]];
+  }
+  __syncthreads();
+
+  C yacc[SMAX][kMaxTerms];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s)
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) yacc[s][t] = mk<R>(0, 0);
+  const C* xp = ws + d.src + (int64_t)r * d.src_r + ((int64_t)z * d.nb + b0) * na;
+  int col[SMAX];
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) col[s] = min(la + s * L, na - 1);
+  const bool full = L == 64;
+  const bool hi5 = (lane & 32) != 0, hi4 = (lane & 16) != 0;
+  for (int i0 = rg; i0 < nrow; i0 += U * RG) {
+    C xv[U][SMAX];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * na;
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s) xv[u][s] = xp[row + col[s]];
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < d.nyt) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int bi = i0 + u * RG;
+          const C cv = cys[t * d.rows + min(bi, nrow - 1)];
+          const C c = bi < nrow ? cv : mk<R>(0, 0);
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) yacc[s][t] = cfma(c, xv[u][s], yacc[s][t]);
+        }
       }
+      if (t < d.nxt) {
+        C p[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          p[u] = mk<R>(0, 0);
+#pragma unroll
+          for (int s = 0; s < SMAX; ++s) p[u] = cfma(cxs[t * SW + la + s * L], xv[u][s], p[u]);
+        }
+        if (full) {
+          C v;
+          int ur;
+          if constexpr (U == 4) {
+            // rows {0,1} stay in the low half-wave, rows {2,3} in the high one
+            const C q0 = cadd(hi5 ? p[2] : p[0], shfl_xor_c(hi5 ? p[0] : p[2], 32, 64));
+            const C q1 = cadd(hi5 ? p[3] : p[1], shfl_xor_c(hi5 ? p[1] : p[3], 32, 64));
+            // row (hi5 ? 2 : 0) + (hi4 ? 1 : 0) stays
+            v = cadd(hi4 ? q1 : q0, shfl_xor_c(hi4 ? q0 : q1, 16, 64));
+            ur = (hi5 ? 2 : 0) + (hi4 ? 1 : 0);
+          } else {
+            // row 0 stays in the low half-wave, row 1 in the high one
+            v = cadd(hi5 ? p[1] : p[0], shfl_xor_c(hi5 ? p[0] : p[1], 32, 64));
+            v = cadd(v, shfl_xor_c(v, 16, 64));
+            ur = hi5 ? 1 : 0;
+          }
+#pragma unroll
+          for (int m = 8; m >= 1; m >>= 1) v = cadd(v, shfl_xor_c(v, m, 64));
+          const int bi = i0 + ur * RG;
+          const bool wr = U == 4 ? (lane & 15) == 0 : (lane & 31) == 0;
+          if (wr && bi < nrow)
+            ws[d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z + b0 + bi] = v;
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            C v = p[u];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) {
+              const C o = shfl_xor_c(v, m, 64);
+              if (m < L) v = cadd(v, o);
+            }
+            const int bi = i0 + u * RG;
+            if (la == 0 && bi < nrow) ws[d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z + b0 + bi] = v;
+          }
+        }
+      }
+    }
+  }
+  // y sums: over the row groups of a wave, then over the four waves (fixed order)
+  const int S = (na + L - 1) / L;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+    if (m >= L) {
+#pragma unroll
+      for (int s = 0; s < SMAX; ++s)
+#pragma unroll
+        for (int t = 0; t < kMaxTerms; ++t)
+          if (t < d.nyt) yacc[s][t] = cadd(yacc[s][t], shfl_xor_c(yacc[s][t], m, 64));
+    }
+  }
+  const bool split = d.nslab > 1;
+#pragma unroll
+  for (int s = 0; s < SMAX; ++s) {
+    if (s < S && d.nyt > 0) {
+      if (w > 0 && lane < L)
+#pragma unroll
+        for (int t = 0; t < kMaxTerms; ++t)
+          if (t < d.nyt) yb[((w - 1) * kMaxTerms + t) * 64 + lane] = yacc[s][t];
+      __syncthreads();
+      const int a = la + s * L;
+      if (w == 0 && lane < L && a < na) {
+#pragma unroll
+        for (int t = 0; t < kMaxTerms; ++t) {
+          if (t < d.nyt) {
+            C v = cadd(yacc[s][t], yb[(0 * kMaxTerms + t) * 64 + lane]);
+            v = cadd(v, yb[(1 * kMaxTerms + t) * 64 + lane]);
+            v = cadd(v, yb[(2 * kMaxTerms + t) * 64 + lane]);
+            const int64_t o = split ? d.part + (int64_t)r * d.part_r + (int64_t)slab * d.part_s + t * d.part_t +
+                                          (int64_t)z * d.part_z + a
+                                    : d.dy + t * d.dy_t + (int64_t)r * d.dy_r + (int64_t)z * d.dy_z + a;
+            ws[o] = v;
+          }
+        }
+      }
+      __syncthreads();
     }
   }
 }
 
-// Contraction over b (strided): out_t(r,z,a) = sum_b c_t[b] X(r,z,b,a).
-// 64 columns a x 4 row groups per workgroup; the groups meet in LDS.
+// Slab sums of the y contractions of split planes, added in slab order.
 template <typename R>
-__global__ __launch_bounds__(256) void k_contract_y(const ContractDesc* __restrict__ descs,
-                                                    const cplx<R>* __restrict__ tab,
-                                                    cplx<R>* __restrict__ ws) {
+__global__ __launch_bounds__(256) void k_contract_fin(const ContractDesc* __restrict__ descs,
+                                                      cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
-  __shared__ C part[3][kMaxTerms][64];
   const ContractDesc d = descs[blockIdx.y];
-  const int ncol = (d.na + 63) / 64;
-  if ((int)blockIdx.x >= ncol * d.nz) return;
-  const int z = blockIdx.x / ncol;
-  const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
-  const int a = (blockIdx.x % ncol) * 64 + c;
-  const bool ok = a < d.na;
+  if (d.nslab <= 1) return;
   const int r = blockIdx.z;
-  const C* x = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.nb * d.na + (ok ? a : 0);
-  C acc[kMaxTerms];
-#pragma unroll
-  for (int t = 0; t < kMaxTerms; ++t) acc[t] = mk<R>(0, 0);
-  if (ok) {
-#pragma unroll 4
-    for (int b = grp; b < d.nb; b += 4) {
-      const C v = x[(int64_t)b * d.na];
-#pragma unroll
-      for (int t = 0; t < kMaxTerms; ++t)
-        if (t < d.nterms) acc[t] = cfma(tab[d.coef[t] + (int64_t)b * d.coef_stride[t]], v, acc[t]);
-    }
-  }
-  if (grp > 0) {
-#pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) part[grp - 1][t][c] = acc[t];
-  }
-  __syncthreads();
-  if (grp == 0 && ok) {
-#pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) {
-      if (t < d.nterms) {
-        C v = cadd(cadd(acc[t], part[0][t][c]), cadd(part[1][t][c], part[2][t][c]));
-        ws[d.dst + t * d.dst_t + (int64_t)r * d.dst_r + (int64_t)z * d.dst_z + a] = v;
-      }
-    }
-  }
+  const int64_t per_t = (int64_t)d.nz * d.na;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d.nyt * per_t) return;
+  const int t = int(e / per_t), z = int((e % per_t) / d.na), a = int(e % d.na);
+  const C* p = ws + d.part + (int64_t)r * d.part_r + t * d.part_t + (int64_t)z * d.part_z + a;
+  C v = p[0];
+  for (int s = 1; s < d.nslab; ++s) v = cadd(v, p[(int64_t)s * d.part_s]);
+  ws[d.dy + t * d.dy_t + (int64_t)r * d.dy_r + (int64_t)z * d.dy_z + a] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,22 +1120,73 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 #undef HS_PSWEEP
 }
 
-void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,
-              int nrhs, hipStream_t st) {
-  if (ndesc == 0 || nrhs == 0 || max_units == 0) return;
-  if (axis == 0) {
-    const dim3 grid(unsigned((max_units + 15) / 16), ndesc, nrhs);
-    if (prec == 0)
-      hipLaunchKernelGGL((k_contract_x<double>), grid, dim3(256), 0, st, d, (const double2*)tab, (double2*)ws);
-    else
-      hipLaunchKernelGGL((k_contract_x<float>), grid, dim3(256), 0, st, d, (const float2*)tab, (float2*)ws);
-  } else {
-    const dim3 grid(unsigned(max_units), ndesc, nrhs);
-    if (prec == 0)
-      hipLaunchKernelGGL((k_contract_y<double>), grid, dim3(256), 0, st, d, (const double2*)tab, (double2*)ws);
-    else
-      hipLaunchKernelGGL((k_contract_y<float>), grid, dim3(256), 0, st, d, (const float2*)tab, (float2*)ws);
+void contract_split(ContractDesc& d) {
+  // about 16K elements per workgroup: whole planes for blocks, row slabs for
+  // the global plane so that there are enough workgroups to fill the chip
+  const int64_t elems = (int64_t)d.na * d.nb;
+  int nslab = int(std::max<int64_t>(1, std::min<int64_t>(d.nb, (elems + 16383) / 16384)));
+  d.rows = (d.nb + nslab - 1) / nslab;
+  d.nslab = d.rows > 0 ? (d.nb + d.rows - 1) / d.rows : 1;
+}
+
+static int contract_lanes(int na) {
+  int L = 1;
+  while (L < na && L < 64) L <<= 1;
+  return L;
+}
+
+ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec) {
+  ContractLaunch L;
+  L.ndesc = ndesc;
+  size_t lds_elems = 0, lds_x = 0;
+  for (int i = 0; i < ndesc; ++i) {
+    const int ln = contract_lanes(d[i].na);
+    const int S = (d[i].na + ln - 1) / ln;
+    L.max_slab = std::max(L.max_slab, d[i].nslab);
+    L.smax = std::max(L.smax, S);
+    L.max_nz = std::max(L.max_nz, d[i].nz);
+    if (d[i].nslab > 1) L.fin_units = std::max<int64_t>(L.fin_units, (int64_t)d[i].nyt * d[i].nz * d[i].na);
+    lds_elems = std::max<size_t>(lds_elems, size_t(d[i].nyt) * d[i].rows + 3 * kMaxTerms * 64);
+    lds_x = std::max<size_t>(lds_x, size_t(d[i].nxt));
   }
+  L.smax = L.smax <= 1 ? 1 : L.smax <= 2 ? 2 : L.smax <= 4 ? 4 : L.smax <= 6 ? 6 : 8;
+  L.lds = (lds_elems + lds_x * L.smax * 64) * (prec == 0 ? 16 : 8);
+  return L;
+}
+
+template <typename R, int SMAX>
+static void launch_contract(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
+                            hipStream_t st) {
+  using C = cplx<R>;
+  const dim3 grid(unsigned(L.max_nz * L.max_slab), unsigned(L.ndesc), unsigned(nrhs));
+  hipLaunchKernelGGL((k_contract<R, SMAX>), grid, dim3(256), L.lds, st, d, L.max_slab, (const C*)tab, (C*)ws);
+  if (L.fin_units > 0)
+    hipLaunchKernelGGL((k_contract_fin<R>), dim3(unsigned((L.fin_units + 255) / 256), L.ndesc, nrhs), dim3(256), 0,
+                       st, d, (C*)ws);
+}
+
+template <typename R>
+static void contract_r(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
+                       hipStream_t st) {
+  if (L.smax <= 1)
+    launch_contract<R, 1>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 2)
+    launch_contract<R, 2>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 4)
+    launch_contract<R, 4>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 6)
+    launch_contract<R, 6>(d, L, tab, ws, nrhs, st);
+  else
+    launch_contract<R, 8>(d, L, tab, ws, nrhs, st);
+}
+
+void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
+              hipStream_t st) {
+  if (L.ndesc == 0 || nrhs == 0 || L.max_nz == 0) return;
+  if (prec == 0)
+    contract_r<double>(d, L, tab, ws, nrhs, st);
+  else
+    contract_r<float>(d, L, tab, ws, nrhs, st);
 }
 
 void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st) {

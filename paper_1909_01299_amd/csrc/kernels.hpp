@@ -70,10 +70,18 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 int sweep_default_chunks(int nz);
 bool sweep_chunks_ok(int chunks, int nz);
 
-// Face / interface contractions (axis 0: over a, max_units = nz * nb lines;
-// axis 1: over b, max_units = nz * ceil(na / 64) column groups).
-void contract(int prec, int axis, const ContractDesc* d, int ndesc, int64_t max_units, const void* tab, void* ws,
-              int nrhs, hipStream_t st);
+// Fused two-axis contractions of spectral arrays (each array read once).
+// contract_split chooses the row slabs of a descriptor (nslab, rows) from its
+// plane size; contract_launch gathers the launch shape of a descriptor list.
+struct ContractLaunch {
+  int ndesc = 0, max_slab = 1, smax = 1, max_nz = 0;
+  int64_t fin_units = 0;   // largest nyt * nz * na over split descriptors (0: none split)
+  size_t lds = 0;          // dynamic LDS bytes
+};
+void contract_split(ContractDesc& d);
+ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec);
+void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
+              hipStream_t st);
 
 void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st);
 void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,

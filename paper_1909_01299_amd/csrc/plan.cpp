@@ -360,6 +360,17 @@ void Plan::layout_workspace() {
   for (auto& B : blocks) B.spec = take(R * NZ * B.nbx * B.nby);
   if (decomposed) {
     for (auto& B : blocks) B.vt = take(R * NZ * B.nbx * B.nby);
+    // slab partial sums of contractions over planes too large for one workgroup
+    auto part_elems = [&](int na, int nb, int nyt) -> int64_t {
+      ContractDesc c{};
+      c.na = na; c.nb = nb;
+      contract_split(c);
+      return c.nslab > 1 ? R * c.nslab * nyt * NZ * (int64_t)na : 0;
+    };
+    for (auto& B : blocks) {
+      const int64_t n = part_elems(B.nbx, B.nby, 2);
+      B.cpart = n > 0 ? take(n) : 0;
+    }
     const int64_t faces = (int64_t)blocks.size() * R * 4 * NZ * NF;
     w_face = take(faces);
     w_vface = take(faces);
@@ -370,6 +381,8 @@ void Plan::layout_workspace() {
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
     w_gspec = take(R * NZ * (int64_t)NX * NY);
+    const int64_t np = part_elems(NX, NY, nsy);
+    w_cpart = np > 0 ? take(np) : 0;
   }
   ws_elems = size_t(off);
   const size_t esz = prec == 0 ? 16 : 8;
@@ -389,7 +402,15 @@ void Plan::build_descriptors() {
   s_fwdx = {}; s_invx = {}; s_fwdy = {}; s_invy = {};
   d_sweep.clear();
   d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear();
-  d_facex.clear(); d_facey.clear(); d_sigx.clear(); d_sigy.clear();
+  d_face.clear(); d_sig.clear();
+  // slab partials of a split contraction: [r][slab][t][z][a]
+  auto set_part = [](ContractDesc& c, int64_t off) {
+    c.part = off;
+    c.part_z = c.na;
+    c.part_t = (int64_t)c.nz * c.na;
+    c.part_s = c.nyt * c.part_t;
+    c.part_r = c.nslab * c.part_s;
+  };
   d_vface.clear(); d_gface.clear(); d_glob_in.clear(); d_glob_out.clear(); d_lift.clear();
   const int64_t gplane = (int64_t)NX * NY;
   const int64_t f_r = gplane * NZ;
@@ -457,18 +478,18 @@ void Plan::build_descriptors() {
     sb.out = B.vt;
     d_sweepB.push_back(sb);
     const int64_t fbase = w_face + (int64_t)bi * R * 4 * face_f;
-    ContractDesc cx{};
-    cx.na = B.nbx; cx.nb = B.nby; cx.nz = NZ; cx.nterms = 2;
-    cx.src = B.vt; cx.src_r = spec_r;
-    cx.coef[0] = AX.inv; cx.coef_stride[0] = 1;                                // W_x[0][a]
-    cx.coef[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; cx.coef_stride[1] = 1;  // W_x[n-1][a]
-    cx.dst = fbase; cx.dst_t = face_f; cx.dst_r = 4 * face_f; cx.dst_z = NF;
-    d_facex.push_back(cx);
-    ContractDesc cy = cx;
-    cy.coef[0] = AY.inv; cy.coef_stride[0] = 1;
-    cy.coef[1] = AY.inv + (int64_t)(B.nby - 1) * B.nby; cy.coef_stride[1] = 1;
-    cy.dst = fbase + 2 * face_f;
-    d_facey.push_back(cy);
+    ContractDesc c{};
+    c.na = B.nbx; c.nb = B.nby; c.nz = NZ; c.nxt = 2; c.nyt = 2;
+    c.src = B.vt; c.src_r = spec_r;
+    c.cx[0] = AX.inv; c.cx_stride[0] = 1;                                // W_x[0][a]
+    c.cx[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; c.cx_stride[1] = 1;  // W_x[n-1][a]
+    c.cy[0] = AY.inv; c.cy_stride[0] = 1;                                // W_y[0][b]
+    c.cy[1] = AY.inv + (int64_t)(B.nby - 1) * B.nby; c.cy_stride[1] = 1;  // W_y[n-1][b]
+    c.dx = fbase; c.dx_t = face_f; c.dx_r = 4 * face_f; c.dx_z = NF;
+    c.dy = fbase + 2 * face_f; c.dy_t = face_f; c.dy_r = 4 * face_f; c.dy_z = NF;
+    contract_split(c);
+    set_part(c, B.cpart);
+    d_face.push_back(c);
     // face values v(y) = sum_b W_y[y][b] e(b) (faces 0, 1) and v(x) = sum_a W_x[x][a] e(a) (faces 2, 3)
     XformDesc vf{};
     vf.tab = AY.inv; vf.n_in = vf.n_out = B.nby; vf.P = 2 * NZ; vf.Q = 1;
@@ -555,21 +576,17 @@ void Plan::build_descriptors() {
     g.gx_z = NY; g.gy_z = NX;
     d_sweepG.push_back(g);
     // w~ contracted with the rows of W at the separators: Q_x[s](b) = sum_a W_x[s][a] w~(a,b)
-    if (nsx > 0) {
+    if (nsx + nsy > 0) {
       ContractDesc c{};
-      c.na = NX; c.nb = NY; c.nz = NZ; c.nterms = nsx;
+      c.na = NX; c.nb = NY; c.nz = NZ; c.nxt = nsx; c.nyt = nsy;
       c.src = w_gspec; c.src_r = g.out_r;
-      for (int i = 0; i < nsx; ++i) { c.coef[i] = GX.inv + (int64_t)sepx[i] * NX; c.coef_stride[i] = 1; }
-      c.dst = w_Qx; c.dst_t = (int64_t)NZ * NY; c.dst_r = (int64_t)nsx * NZ * NY; c.dst_z = NY;
-      d_sigx.push_back(c);
-    }
-    if (nsy > 0) {
-      ContractDesc c{};
-      c.na = NX; c.nb = NY; c.nz = NZ; c.nterms = nsy;
-      c.src = w_gspec; c.src_r = g.out_r;
-      for (int j = 0; j < nsy; ++j) { c.coef[j] = GY.inv + (int64_t)sepy[j] * NY; c.coef_stride[j] = 1; }
-      c.dst = w_Qy; c.dst_t = (int64_t)NZ * NX; c.dst_r = (int64_t)nsy * NZ * NX; c.dst_z = NX;
-      d_sigy.push_back(c);
+      for (int i = 0; i < nsx; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[i] * NX; c.cx_stride[i] = 1; }
+      for (int j = 0; j < nsy; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[j] * NY; c.cy_stride[j] = 1; }
+      c.dx = w_Qx; c.dx_t = (int64_t)NZ * NY; c.dx_r = (int64_t)nsx * NZ * NY; c.dx_z = NY;
+      c.dy = w_Qy; c.dy_t = (int64_t)NZ * NX; c.dy_r = (int64_t)nsy * NZ * NX; c.dy_z = NX;
+      contract_split(c);
+      set_part(c, w_cpart);
+      d_sig.push_back(c);
     }
     sg.NX = NX; sg.NY = NY; sg.nz = NZ; sg.nsx = nsx; sg.nsy = nsy; sg.NF = NF;
     sg.rmax = max_rhs; sg.nbx_blocks = nbx_blocks;
@@ -577,6 +594,8 @@ void Plan::build_descriptors() {
     sg.rx = w_rx; sg.ry = w_ry; sg.wx = w_wx; sg.wy = w_wy;
     sg.cx_lo = cx_lo; sg.cx_hi = cx_hi; sg.cy_lo = cy_lo; sg.cy_hi = cy_hi;
   }
+  cl_face = contract_launch(d_face.data(), int(d_face.size()), prec);
+  cl_sig = contract_launch(d_sig.data(), int(d_sig.size()), prec);
 }
 
 hs_status Plan::upload(std::string& err) {
@@ -669,7 +688,7 @@ hs_status Plan::upload_descs(std::string& err) {
   reg(d_vface, &p_vface); reg(d_gface, &p_gface);
   reg(d_glob_in, &p_glob_in); reg(d_glob_out, &p_glob_out);
   reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
-  reg(d_facex, &p_facex); reg(d_facey, &p_facey); reg(d_sigx, &p_sigx); reg(d_sigy, &p_sigy);
+  reg(d_face, &p_face); reg(d_sig, &p_sig);
   reg(d_lift, &p_lift);
   if (!ddesc && hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
   if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail("descriptors");
@@ -854,16 +873,6 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.na * d.nb);
     return m;
   };
-  auto lines_x = [](const std::vector<ContractDesc>& v) {
-    int64_t m = 0;
-    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * d.nb);
-    return m;
-  };
-  auto cols_y = [](const std::vector<ContractDesc>& v) {
-    int64_t m = 0;
-    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.nz * ((d.na + 63) / 64));
-    return m;
-  };
   // algorithmic work of the stages (per call, all right-hand sides)
   const double R = nrhs;
   const double esz = prec == 0 ? 16.0 : 8.0;
@@ -905,9 +914,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
-    stage_begin("face_contract", R * nblk * 2 * esz, R * nblk * 2 * 2 * 8, st);
-    contract(prec, 0, p_facex, int(d_facex.size()), lines_x(d_facex), T, W, nrhs, st);
-    contract(prec, 1, p_facey, int(d_facey.size()), cols_y(d_facey), T, W, nrhs, st);
+    stage_begin("face_contract", R * (nblk + nface) * esz, R * nblk * 4 * 8, st);
+    contract(prec, p_face, cl_face, T, W, nrhs, st);
     stage_end();
     double ffl = 0;
     for (auto& B : blocks) ffl += double(NZ) * 2.0 * (double(B.nby) * B.nby + double(B.nbx) * B.nbx) * 8.0;
@@ -928,9 +936,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, T, dtab64, W, nrhs, st, tune_chunks);
     stage_end();
-    stage_begin("sigma_contract", R * nglob * 2 * esz, R * nglob * (nsx + nsy) * 8, st);
-    contract(prec, 0, p_sigx, int(d_sigx.size()), lines_x(d_sigx), T, W, nrhs, st);
-    contract(prec, 1, p_sigy, int(d_sigy.size()), cols_y(d_sigy), T, W, nrhs, st);
+    stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
+    contract(prec, p_sig, cl_sig, T, W, nrhs, st);
     stage_end();
     stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
     xform_lines(prec, 0, 0, 0, p_glob_out, int(d_glob_out.size()), tiles_lines(d_glob_out), T, W, W, nrhs, st);

@@ -30,6 +30,7 @@ struct Block {
   int sep_lo_x = -1, sep_hi_x = -1, sep_lo_y = -1, sep_hi_y = -1;
   int64_t spec = 0;              // workspace offset of the block spectral array
   int64_t vt = 0;                // workspace offset of its spectral block solution v~ (steps 2-3)
+  int64_t cpart = 0;             // slab partial sums of its face contraction (split planes only)
 };
 
 // One transform stage: dense-table descriptors plus sine-FFT descriptors per V.
@@ -98,6 +99,7 @@ struct Plan {
   int64_t w_face = 0, w_vface = 0, w_gface = 0, w_Gface = 0;
   int64_t w_rx = 0, w_ry = 0, w_Rx = 0, w_Ry = 0, w_Qx = 0, w_Qy = 0, w_wx = 0, w_wy = 0;
   int64_t w_gspec = 0;           // global spectral solution w~ of the interface solve
+  int64_t w_cpart = 0;           // slab partial sums of the interface contraction (split plane only)
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;
@@ -106,12 +108,13 @@ struct Plan {
   std::vector<XformDesc> d_vface, d_gface, d_glob_in, d_glob_out;
   int64_t twid = 0;                  // twiddle table offset
   std::vector<SweepDesc> d_sweep, d_sweepB, d_sweepC, d_sweepG;
-  std::vector<ContractDesc> d_facex, d_facey, d_sigx, d_sigy;
+  std::vector<ContractDesc> d_face, d_sig;
+  ContractLaunch cl_face, cl_sig;
   std::vector<LiftBlock> d_lift;
   // device pointers of each list
   const XformDesc *p_vface = nullptr, *p_gface = nullptr, *p_glob_in = nullptr, *p_glob_out = nullptr;
   const SweepDesc *p_sweep = nullptr, *p_sweepB = nullptr, *p_sweepC = nullptr, *p_sweepG = nullptr;
-  const ContractDesc *p_facex = nullptr, *p_facey = nullptr, *p_sigx = nullptr, *p_sigy = nullptr;
+  const ContractDesc *p_face = nullptr, *p_sig = nullptr;
   const LiftBlock* p_lift = nullptr;
   SigmaGeom sg{};
   int64_t max_modes_blk = 0;
