@@ -332,211 +332,310 @@ __device__ __forceinline__ C crcp_fast(C z) {
 
 constexpr int PS_LMAX = 16;   // rows per chunk held in registers
 
+// Rows of a chunk: every chunk of a line has the same length, so that loop
+// bounds are uniform across the workgroup; the line is padded past nz.
+__host__ __device__ __forceinline__ int psweep_rows(int nz, int chunks) {
+  const int l = (nz + chunks - 1) / chunks;
+  return l < 2 ? 2 : l;
+}
+
+// Padded rows past the end of a line have zero couplings and a large real
+// diagonal: they never influence real rows, and their (finite) values are
+// discarded.
+constexpr double kPadDiag = 1099511627776.0;   // 2^40
+
 // RS: storage precision of the workspace arrays; R: arithmetic precision and
 // precision of the tables `tab`.
+//
+// One workgroup solves MW modes; each mode's z line is cut into P chunks of
+// Lc rows, one lane per chunk:
+//  1. per chunk, a top-down elimination (keeping the reciprocal pivots) gives
+//     the local solution, the response to a unit value in the first row and
+//     the response to a unit value in the last row, at the last row; a
+//     bottom-up elimination gives the same three at the first row;
+//  2. one lane per mode solves the reduced system on the chunk end values;
+//  3. every chunk is solved again with its neighbours' end values moved to the
+//     right-hand side, with the stored pivots (no divisions).
 template <typename RS, typename R, int P, int MW>
 __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* __restrict__ tab,
-                                            cplx<RS>* __restrict__ ws, unsigned char* smem_raw) {
+                                            cplx<RS>* __restrict__ ws, unsigned char* smem_raw, int xcap) {
   using C = cplx<R>;
   using CS = cplx<RS>;
   using Q = typename quad_of<R>::type;
   const int na = d.na, nb = d.nb, nz = d.nz;
   const int64_t plane = (int64_t)na * nb;
   const int64_t m0 = (int64_t)blockIdx.x * MW;
-  Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z
-  C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nz) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
-  for (int k = threadIdx.x; k < nz; k += 256) {
-    const C dg = tab[d.zdiag + k];
+  const int Lc = psweep_rows(nz, P);
+  const int nzp = P * Lc;
+  Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z, padded to nzp rows
+  C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nzp) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
+  C* gxs = xch + 6 * P * MW;                 // x-type term lines [t][2 rows b][nzp]
+  for (int k = threadIdx.x; k < nzp; k += 256) {
     Q q;
-    q.x = dg.x;
-    q.y = dg.y;
-    q.z = tab[d.zlo + k].x;
-    q.w = tab[d.zup + k].x;
+    if (k < nz) {
+      const C dg = tab[d.zdiag + k];
+      q.x = dg.x;
+      q.y = dg.y;
+      q.z = tab[d.zlo + k].x;
+      q.w = k + 1 < nz ? tab[d.zup + k].x : R(0);
+    } else {
+      q.x = R(kPadDiag);
+      q.y = R(0);
+      q.z = R(0);
+      q.w = R(0);
+    }
     zt[k] = q;
+  }
+  // The x-type low-rank terms G_t(b, z) are shared by every mode of a row b;
+  // the workgroup's modes lie on at most two rows when na >= MW, whose lines
+  // are staged in LDS once (rows past the line hold the last row). Staging
+  // pays where a dense right-hand side is read as well (its loads overlap);
+  // without one the extra round trip costs more than it saves.
+  const int r = blockIdx.z;
+  const int b_lo = int(m0 / na);
+  const bool xstage = d.dense_in && d.nxt > 0 && na >= MW && 2 * d.nxt * nzp <= xcap;
+  if (xstage) {
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < d.nxt) {
+        const CS* g = ws + d.gx[t] + (int64_t)r * d.gx_r;
+        for (int i = threadIdx.x; i < 2 * nzp; i += 256) {
+          const int br = min(b_lo + i / nzp, nb - 1), k = min(i % nzp, nz - 1);
+          gxs[t * 2 * nzp + i] = cvt<C>(g[br + (int64_t)k * d.gx_z]);
+        }
+      }
+    }
   }
   const int ml = threadIdx.x % MW, j = threadIdx.x / MW;
   const int64_t m = m0 + ml;
   const bool mact = m < plane;
-  const int np = nz >= 2 * P ? P : (nz / 2 > 0 ? nz / 2 : 1);   // chunks in use (each >= 2 rows)
-  const bool cact = j < np;
-  const bool act = mact && cact;
-  const int k0 = (j * nz) / np;
-  const int len = cact ? ((j + 1) * nz) / np - k0 : 0;
-  const int a = mact ? int(m % na) : 0, b = mact ? int(m / na) : 0;
-  const int r = blockIdx.z;
+  const int64_t mc = mact ? m : 0;
+  const int k0 = j * Lc;
+  // rows addressed in memory: kb .. kb + nv - 1 (clamped into the line)
+  const int kb = k0 < nz ? k0 : nz - 1;
+  const int nv = k0 < nz ? min(nz - k0, Lc) : 1;
+  const int a = int(mc % na), b = int(mc / na);
   const C s = mact ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
   auto X = [&](int f, int jj) -> C& { return xch[(jj * 6 + f) * MW + ml]; };
 
-  // right-hand side of the chunk
+  // right-hand side of the chunk. Every register row is loaded, rows past the
+  // chunk or the line from the last valid row: their values only reach rows
+  // that are never used or padded rows. Row offsets fit in 32 bits (a line
+  // holds at most 512 planes of at most 512 x 512 modes).
   C rb[PS_LMAX];
-  const CS* src = ws + d.data + (int64_t)r * d.data_r + m;
+  auto row_off = [&](int kk, uint32_t stride) -> uint32_t {
+    return kk < nv ? uint32_t(kk) * stride : uint32_t(nv - 1) * stride;
+  };
+  if (d.dense_in) {
+    const CS* src = ws + d.data + (int64_t)r * d.data_r + mc + (int64_t)kb * plane;
 #pragma unroll
-  for (int kk = 0; kk < PS_LMAX; ++kk)
-    rb[kk] = (act && d.dense_in && kk < len) ? cvt<C>(src[(int64_t)(k0 + kk) * plane]) : mk<R>(0, 0);
-  // low-rank terms: a chunk's values are loaded together (row index clamped
-  // into the chunk so every load is valid), then accumulated
-  const int lastk = k0 + (len > 0 ? len - 1 : 0);
+    for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cvt<C>(src[row_off(kk, uint32_t(plane))]);
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = mk<R>(0, 0);
+  }
+  // low-rank terms: coefficient of the mode times a line shared by a row of
+  // modes; staged x-type lines are added after the barrier
 #pragma unroll
   for (int i = 0; i < 2 * kMaxTerms; ++i) {
     const bool isx = i < kMaxTerms;
     const int t = isx ? i : i - kMaxTerms;
-    if (act && t < (isx ? d.nxt : d.nyt)) {
+    if (t < (isx ? d.nxt : d.nyt) && !(isx && xstage)) {
       const C c = isx ? tab[d.colx[t] + (int64_t)a * d.colx_stride[t]]
                       : tab[d.coly[t] + (int64_t)b * d.coly_stride[t]];
-      const CS* g = isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a;
       const int64_t gz = isx ? d.gx_z : d.gy_z;
-      C gv[PS_LMAX];
+      const CS* g = (isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a) +
+                    (int64_t)kb * gz;
 #pragma unroll
-      for (int kk = 0; kk < PS_LMAX; ++kk) gv[kk] = cvt<C>(g[(int64_t)min(k0 + kk, lastk) * gz]);
-#pragma unroll
-      for (int kk = 0; kk < PS_LMAX; ++kk)
-        if (kk < len) rb[kk] = cfma(c, gv[kk], rb[kk]);
+      for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cfma(c, cvt<C>(g[row_off(kk, uint32_t(gz))]), rb[kk]);
     }
   }
   __syncthreads();
-
-  // 1. local eliminations: top-down gives the last row, bottom-up the first row
-  if (act) {
-    C cp = mk<R>(0, 0), yb = mk<R>(0, 0), yv = mk<R>(0, 0), ipl = mk<R>(0, 0);
+  if (xstage) {
+    const int brow = mact ? b - b_lo : 0;
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk) {
-      if (kk < len) {
-        const Q q = zt[k0 + kk];
-        const R lo = kk > 0 ? q.z : R(0);
-        C piv;
-        piv.x = q.x + s.x - lo * cp.x;
-        piv.y = q.y + s.y - lo * cp.y;
-        const C ip = crcp_fast(piv);
-        C t;
-        t.x = rb[kk].x - lo * yb.x;
-        t.y = rb[kk].y - lo * yb.y;
-        yb = cmul(t, ip);
-        t.x = (kk == 0 ? R(1) : R(0)) - lo * yv.x;
-        t.y = -lo * yv.y;
-        yv = cmul(t, ip);
-        cp.x = q.w * ip.x;
-        cp.y = q.w * ip.y;
-        ipl = ip;
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < d.nxt) {
+        const C c = tab[d.colx[t] + (int64_t)a * d.colx_stride[t]];
+        const C* gl = gxs + (t * 2 + brow) * nzp;
+#pragma unroll
+        for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cfma(c, gl[min(k0 + kk, nzp - 1)], rb[kk]);
       }
     }
-    C cn = mk<R>(0, 0), zb = mk<R>(0, 0), zw = mk<R>(0, 0), ipf = mk<R>(0, 0);
+  }
+
+  // 1. local eliminations: y (local solution), v (unit value in the first
+  // row), w (unit value in the last row) at the chunk's last row (top-down)
+  // and first row (bottom-up)
+  C ip[PS_LMAX];
+  C yl = mk<R>(0, 0), vl = mk<R>(0, 0), wl = mk<R>(0, 0);
+  C yf = mk<R>(0, 0), vf = mk<R>(0, 0), wf = mk<R>(0, 0);
+  {
+    C cp = mk<R>(0, 0);
+#pragma unroll
+    for (int kk = 0; kk < PS_LMAX; ++kk) {
+      if (kk < Lc) {
+        const Q q = zt[k0 + kk];
+        C piv;
+        piv.x = q.x + s.x - q.z * cp.x;
+        piv.y = q.y + s.y - q.z * cp.y;
+        const C ipk = crcp_fast(piv);
+        ip[kk] = ipk;
+        C t;
+        t.x = rb[kk].x - q.z * yl.x;
+        t.y = rb[kk].y - q.z * yl.y;
+        yl = cmul(t, ipk);
+        t.x = (kk == 0 ? R(1) : R(0)) - q.z * vl.x;
+        t.y = -q.z * vl.y;
+        vl = cmul(t, ipk);
+        cp.x = q.w * ipk.x;
+        cp.y = q.w * ipk.y;
+        wl = ipk;
+      }
+    }
+    C cn = mk<R>(0, 0);
 #pragma unroll
     for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
-      if (kk < len) {
+      if (kk < Lc) {
         const Q q = zt[k0 + kk];
-        const R up = kk < len - 1 ? q.w : R(0);
         C piv;
-        piv.x = q.x + s.x - up * cn.x;
-        piv.y = q.y + s.y - up * cn.y;
-        const C ip = crcp_fast(piv);
+        piv.x = q.x + s.x - q.w * cn.x;
+        piv.y = q.y + s.y - q.w * cn.y;
+        const C ipk = crcp_fast(piv);
         C t;
-        t.x = rb[kk].x - up * zb.x;
-        t.y = rb[kk].y - up * zb.y;
-        zb = cmul(t, ip);
-        t.x = (kk == len - 1 ? R(1) : R(0)) - up * zw.x;
-        t.y = -up * zw.y;
-        zw = cmul(t, ip);
-        cn.x = q.z * ip.x;
-        cn.y = q.z * ip.y;
-        ipf = ip;
+        t.x = rb[kk].x - q.w * yf.x;
+        t.y = rb[kk].y - q.w * yf.y;
+        yf = cmul(t, ipk);
+        t.x = (kk == Lc - 1 ? R(1) : R(0)) - q.w * wf.x;
+        t.y = -q.w * wf.y;
+        wf = cmul(t, ipk);
+        cn.x = q.z * ipk.x;
+        cn.y = q.z * ipk.y;
+        vf = ipk;
       }
     }
-    X(0, j) = zb;    // y first
-    X(1, j) = yb;    // y last
-    X(2, j) = ipf;   // v first
-    X(3, j) = yv;    // v last
-    X(4, j) = zw;    // w first
-    X(5, j) = ipl;   // w last
+  }
+
+  // 2. reduced system on the chunk end values F_j (first) and L_j (last):
+  //   F_j = yf_j - al_j vf_j L_{j-1} - be_j wf_j F_{j+1}
+  //   L_j = yl_j - al_j vl_j L_{j-1} - be_j wl_j F_{j+1}
+  // (al_j: coupling of the chunk's first row to the row before, be_j: of its
+  // last row to the row after). Forward elimination gives L_j = p_j + q_j F_{j+1}
+  // with q_j = (A_j q_{j-1} + B_j) / (C_j q_{j-1} + 1), a Moebius map carried in
+  // homogeneous form (n, d) so that its chain has no divisions; then
+  // p_j = alpha_j + beta_j p_{j-1} and F_j = g_j + h_j F_{j+1} are affine
+  // chains. The chains run on one lane per mode; every division in between
+  // runs on the chunk's own lane.
+  const R al = zt[k0].z, be = zt[k0 + Lc - 1].w;
+  {
+    C Am = csub(cmul(vl, wf), cmul(wl, vf));
+    Am.x *= al * be;
+    Am.y *= al * be;
+    X(0, j) = Am;
+    X(1, j) = mk<R>(-be * wl.x, -be * wl.y);
+    X(2, j) = mk<R>(al * vf.x, al * vf.y);
   }
   __syncthreads();
-
-  // 2. reduced system on the chunk ends (one lane per mode)
-  if (j == 0 && mact) {
-    C p = mk<R>(0, 0), qv = mk<R>(0, 0);
-    for (int jj = 0; jj < np; ++jj) {
-      const int c0 = (jj * nz) / np, c1 = ((jj + 1) * nz) / np - 1;
-      const R al = zt[c0].z, be = zt[c1].w;
-      const C yf = X(0, jj), yl = X(1, jj), vf = X(2, jj), vl = X(3, jj), wf = X(4, jj), wl = X(5, jj);
-      // D = 1 + al vf q
-      C D = cmul(vf, qv);
-      D.x = R(1) + al * D.x;
-      D.y = al * D.y;
-      const C iD = crcp_fast(D);
-      C t = cmul(vf, p);
-      t.x = yf.x - al * t.x;
-      t.y = yf.y - al * t.y;
-      const C g = cmul(t, iD);
-      C h = cmul(wf, iD);
-      h.x = -be * h.x;
-      h.y = -be * h.y;
-      // p' = yl - al vl (p + q g) ;  q' = -al vl q h - be wl
-      const C pq = cfma(qv, g, p);
-      C vlpq = cmul(vl, pq);
-      C pn;
-      pn.x = yl.x - al * vlpq.x;
-      pn.y = yl.y - al * vlpq.y;
-      C vlqh = cmul(vl, cmul(qv, h));
-      C qn;
-      qn.x = -al * vlqh.x - be * wl.x;
-      qn.y = -al * vlqh.y - be * wl.y;
-      p = pn;
-      qv = qn;
-      X(0, jj) = g;
-      X(1, jj) = h;
-      X(2, jj) = p;
-      X(3, jj) = qv;
-    }
-    C Fn = mk<R>(0, 0);
-    for (int jj = np - 1; jj >= 0; --jj) {
-      const C F = cfma(X(1, jj), Fn, X(0, jj));
-      const C L = cfma(X(3, jj), Fn, X(2, jj));
-      X(0, jj) = F;
-      X(1, jj) = L;
-      Fn = F;
+  if (j == 0) {
+    C n = mk<R>(0, 0), dd = mk<R>(1, 0);
+#pragma unroll
+    for (int jj = 0; jj < P; ++jj) {
+      const C Am = X(0, jj), Bm = X(1, jj), Cm = X(2, jj);
+      C n2 = cfma(Bm, dd, cmul(Am, n));
+      C d2 = cfma(Cm, n, dd);
+      if ((jj & 3) == 3) {
+        // rescale by a power of two (the pair is only defined up to a factor)
+        const R mag = fabs(n2.x) + fabs(n2.y) + fabs(d2.x) + fabs(d2.y);
+        const R sc = mag > R(0) ? ldexp(R(1), -ilogb(mag)) : R(1);
+        n2.x *= sc; n2.y *= sc; d2.x *= sc; d2.y *= sc;
+      }
+      n = n2;
+      dd = d2;
+      X(3, jj) = n;
+      X(4, jj) = dd;
     }
   }
   __syncthreads();
+  C qm = mk<R>(0, 0);   // q_{j-1}
+  if (j > 0) qm = cmul(X(3, j - 1), crcp_fast(X(4, j - 1)));
+  C gy, gp, hj;
+  {
+    C D = mk<R>(al * vf.x, al * vf.y);
+    D = cfma(D, qm, mk<R>(1, 0));                 // 1 + al vf q_{j-1}
+    const C iD = crcp_fast(D);
+    gy = cmul(yf, iD);
+    gp = cmul(vf, iD);
+    gp.x *= -al;
+    gp.y *= -al;
+    hj = cmul(wf, iD);
+    hj.x *= -be;
+    hj.y *= -be;
+    const C alv = mk<R>(-al * vl.x, -al * vl.y);   // -al vl
+    X(0, j) = cfma(alv, cmul(qm, gy), yl);          // alpha = yl - al vl q gy
+    X(1, j) = cmul(alv, cfma(qm, gp, mk<R>(1, 0)));  // beta = -al vl (1 + q gp)
+  }
+  __syncthreads();
+  if (j == 0) {
+    C pp = mk<R>(0, 0);
+#pragma unroll
+    for (int jj = 0; jj < P; ++jj) {
+      pp = cfma(X(1, jj), pp, X(0, jj));
+      X(2, jj) = pp;
+    }
+  }
+  __syncthreads();
+  const C pm = j > 0 ? X(2, j - 1) : mk<R>(0, 0);   // p_{j-1}
+  X(3, j) = cfma(gp, pm, gy);                        // g_j
+  X(4, j) = hj;
+  __syncthreads();
+  if (j == 0) {
+    C F = mk<R>(0, 0);
+#pragma unroll
+    for (int jj = P - 1; jj >= 0; --jj) {
+      F = cfma(X(4, jj), F, X(3, jj));
+      X(5, jj) = F;
+    }
+  }
+  __syncthreads();
 
-  // 3. re-solve each chunk with its neighbours' end values
-  if (act) {
-    const C XL = j > 0 ? X(1, j - 1) : mk<R>(0, 0);
-    const C XR = j + 1 < np ? X(0, j + 1) : mk<R>(0, 0);
-    C cr[PS_LMAX];
-    C cp = mk<R>(0, 0), dp = mk<R>(0, 0);
+  // 3. re-solve each chunk with its neighbours' end values, reusing the pivots
+  {
+    const C Fj = X(5, j);
+    const C XL = j > 0 ? cfma(qm, Fj, pm) : mk<R>(0, 0);   // L_{j-1} = p_{j-1} + q_{j-1} F_j
+    const C XR = j + 1 < P ? X(5, j + 1) : mk<R>(0, 0);   // F_{j+1}
+    C dp = mk<R>(0, 0);
 #pragma unroll
     for (int kk = 0; kk < PS_LMAX; ++kk) {
-      if (kk < len) {
+      if (kk < Lc) {
         const Q q = zt[k0 + kk];
         C rhs = rb[kk];
         if (kk == 0) rhs = cfms(mk<R>(q.z, 0), XL, rhs);
-        if (kk == len - 1) rhs = cfms(mk<R>(q.w, 0), XR, rhs);
-        const R lo = kk > 0 ? q.z : R(0);
-        C piv;
-        piv.x = q.x + s.x - lo * cp.x;
-        piv.y = q.y + s.y - lo * cp.y;
-        const C ip = crcp_fast(piv);
+        if (kk == Lc - 1) rhs = cfms(mk<R>(q.w, 0), XR, rhs);
         C t;
-        t.x = rhs.x - lo * dp.x;
-        t.y = rhs.y - lo * dp.y;
-        dp = cmul(t, ip);
+        t.x = rhs.x - q.z * dp.x;
+        t.y = rhs.y - q.z * dp.y;
+        dp = cmul(t, ip[kk]);
         rb[kk] = dp;
-        cp.x = q.w * ip.x;
-        cp.y = q.w * ip.y;
-        cr[kk] = cp;
       }
     }
     C xn = mk<R>(0, 0);
 #pragma unroll
     for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
-      if (kk < len) {
-        if (kk < len - 1) rb[kk] = cfms(cr[kk], xn, rb[kk]);
+      if (kk < Lc) {
+        const R up = zt[k0 + kk].w;
+        C c;
+        c.x = up * ip[kk].x;
+        c.y = up * ip[kk].y;
+        rb[kk] = cfms(c, xn, rb[kk]);
         xn = rb[kk];
       }
     }
-    CS* dst = ws + d.out + (int64_t)r * d.out_r + m;
+    if (mact) {
+      CS* dst = ws + d.out + (int64_t)r * d.out_r + m + (int64_t)k0 * plane;
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk)
-      if (kk < len) dst[(int64_t)(k0 + kk) * plane] = cvt<CS>(rb[kk]);
+      for (int kk = 0; kk < PS_LMAX; ++kk)
+        if (kk < Lc && k0 + kk < nz) dst[(int64_t)kk * plane] = cvt<CS>(rb[kk]);
+    }
   }
 }
 
@@ -544,14 +643,14 @@ template <typename R, int P, int MW>
 __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 const double2* __restrict__ tab64,
-                                                cplx<R>* __restrict__ ws) {
+                                                cplx<R>* __restrict__ ws, int xcap) {
   static_assert(P * MW == 256, "256 lanes per workgroup");
   extern __shared__ unsigned char smem_raw[];
   const SweepDesc d = descs[blockIdx.y];
   const int64_t plane = (int64_t)d.na * d.nb;
   if ((int64_t)blockIdx.x * MW >= plane) return;
   if constexpr (sizeof(R) == 8) {
-    psweep_body<R, R, P, MW>(d, tab, ws, smem_raw);
+    psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
   } else {
     // complex64 storage: a workgroup holding a mode near resonance (small
     // Re(lam_x + lam_y)) runs its z solves in FP64 from the FP64 tables
@@ -562,9 +661,9 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
       low = tab64[d.lam_x + a].x + tab64[d.lam_y + b].x <= d.fp64_below;
     }
     if (__syncthreads_or(low))
-      psweep_body<R, double, P, MW>(d, tab64, ws, smem_raw);
+      psweep_body<R, double, P, MW>(d, tab64, ws, smem_raw, xcap);
     else
-      psweep_body<R, R, P, MW>(d, tab, ws, smem_raw);
+      psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
   }
 }
 
@@ -1086,10 +1185,20 @@ void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles1
 
 int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct) * d.P; }
 
-size_t sweep_lds_bytes(int prec, int nz) {
+// Staged x-type term lines: at most this many bytes of LDS.
+constexpr size_t kSweepStageBytes = 32768;
+
+int sweep_stage_cap(int nz, int chunks, int max_xterms) {
+  const int64_t need = 2LL * max_xterms * chunks * psweep_rows(nz, chunks);
+  return need > 0 && need * int64_t(sizeof(double2)) <= int64_t(kSweepStageBytes) ? int(need) : 0;
+}
+
+size_t sweep_lds_bytes(int prec, int nz, int chunks, int max_xterms) {
   // sized for FP64 arithmetic, which the complex64 kernel may switch to
   (void)prec;
-  return (size_t(nz) * sizeof(double4) + 255) / 256 * 256 + 6 * 256 * sizeof(double2);
+  const size_t rows = size_t(chunks) * psweep_rows(nz, chunks);
+  return (rows * sizeof(double4) + 255) / 256 * 256 + 6 * 256 * sizeof(double2) +
+         size_t(sweep_stage_cap(nz, chunks, max_xterms)) * sizeof(double2);
 }
 
 int sweep_default_chunks(int nz) { return nz > 16 * PS_LMAX ? 32 : 16; }
@@ -1098,16 +1207,17 @@ bool sweep_chunks_ok(int chunks, int nz) {
   return (chunks == 8 || chunks == 16 || chunks == 32) && nz <= chunks * PS_LMAX;
 }
 
-void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, const void* tab,
+void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
            const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   if (!sweep_chunks_ok(chunks, max_nz)) chunks = sweep_default_chunks(max_nz);
-  const size_t lds = sweep_lds_bytes(prec, max_nz);
+  const size_t lds = sweep_lds_bytes(prec, max_nz, chunks, max_xterms);
+  const int xcap = sweep_stage_cap(max_nz, chunks, max_xterms);
   const int mw = 256 / chunks;
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
 #define HS_PSWEEP(RR, CC, PP, MM)                                                                        \
   hipLaunchKernelGGL((k_psweep<RR, PP, MM>), grid, dim3(256), lds, st, d, (const CC*)tab, (const double2*)tab64, \
-                     (CC*)ws)
+                     (CC*)ws, xcap)
   if (prec == 0) {
     if (chunks == 32) HS_PSWEEP(double, double2, 32, 8);
     else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16);
