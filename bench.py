@@ -176,7 +176,8 @@ def main():
         dtm, stages_m = time_solves(plan_m, f, um, args.steps, args.warmup)
         mixed = {"value": p.unknowns * nrhs / (dtm / args.steps), "ms_per_step": dtm / args.steps * 1e3,
                  "refine_steps": plan_m.info()["refine_steps"], "u": um.cpu().numpy(),
-                 "roofline": roofline(stages_m, "c64")}
+                 "roofline": roofline(stages_m, "c64"),
+                 "stages": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages_m}}
         del plan_m
 
     cpu = None
@@ -212,7 +213,8 @@ def main():
         "mixed_c64_refine": None if mixed is None else {
             "value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
             "refine_steps": mixed["refine_steps"], "rel_err_vs_oracle": rel_err_mixed,
-            "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"]},
+            "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"],
+            "stages_ms_per_step": mixed["stages"]},
         "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
         "plan_seconds": info["plan_seconds"],
         "tuned": tuned,

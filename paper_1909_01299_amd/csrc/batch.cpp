@@ -256,10 +256,13 @@ void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
 }
 
 void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
+  bool any_fp64 = false;
+  for (const Plan* p : plans) any_fp64 = any_fp64 || p->n_fp64_modes > 0;
   auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
-    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks);
+    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks,
+          any_fp64);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

@@ -639,7 +639,13 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   }
 }
 
-template <typename R, int P, int MW>
+// complex128: every workgroup runs the FP64 body. complex64 storage: a
+// workgroup holding a mode near resonance (small Re(lam_x + lam_y)) runs its z
+// solves in FP64 from the FP64 tables; FP64SEL = false launches solve the
+// other workgroups in FP32, FP64SEL = true launches only the flagged ones.
+// Both launches evaluate the same predicate, so every workgroup runs in
+// exactly one of them, and each kernel gets its own register allocation.
+template <typename R, int P, int MW, bool FP64SEL>
 __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 const double2* __restrict__ tab64,
@@ -652,15 +658,15 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
   if constexpr (sizeof(R) == 8) {
     psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
   } else {
-    // complex64 storage: a workgroup holding a mode near resonance (small
-    // Re(lam_x + lam_y)) runs its z solves in FP64 from the FP64 tables
     const int64_t m = (int64_t)blockIdx.x * MW + threadIdx.x % MW;
     bool low = false;
     if (m < plane) {
       const int a = int(m % d.na), b = int(m / d.na);
       low = tab64[d.lam_x + a].x + tab64[d.lam_y + b].x <= d.fp64_below;
     }
-    if (__syncthreads_or(low))
+    const bool wg_low = __syncthreads_or(low) != 0;
+    if (wg_low != FP64SEL) return;
+    if constexpr (FP64SEL)
       psweep_body<R, double, P, MW>(d, tab64, ws, smem_raw, xcap);
     else
       psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
@@ -1193,12 +1199,11 @@ int sweep_stage_cap(int nz, int chunks, int max_xterms) {
   return need > 0 && need * int64_t(sizeof(double2)) <= int64_t(kSweepStageBytes) ? int(need) : 0;
 }
 
-size_t sweep_lds_bytes(int prec, int nz, int chunks, int max_xterms) {
-  // sized for FP64 arithmetic, which the complex64 kernel may switch to
-  (void)prec;
+size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms) {
+  // arith_bytes: 8 for FP64 arithmetic, 4 for FP32
   const size_t rows = size_t(chunks) * psweep_rows(nz, chunks);
-  return (rows * sizeof(double4) + 255) / 256 * 256 + 6 * 256 * sizeof(double2) +
-         size_t(sweep_stage_cap(nz, chunks, max_xterms)) * sizeof(double2);
+  const size_t cs = 2 * size_t(arith_bytes);   // one complex value
+  return (rows * 2 * cs + 255) / 256 * 256 + 6 * 256 * cs + size_t(sweep_stage_cap(nz, chunks, max_xterms)) * cs;
 }
 
 int sweep_default_chunks(int nz) { return nz > 16 * PS_LMAX ? 32 : 16; }
@@ -1208,24 +1213,30 @@ bool sweep_chunks_ok(int chunks, int nz) {
 }
 
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks) {
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   if (!sweep_chunks_ok(chunks, max_nz)) chunks = sweep_default_chunks(max_nz);
-  const size_t lds = sweep_lds_bytes(prec, max_nz, chunks, max_xterms);
+  size_t lds = sweep_lds_bytes(prec == 0 ? 8 : 4, max_nz, chunks, max_xterms);
   const int xcap = sweep_stage_cap(max_nz, chunks, max_xterms);
   const int mw = 256 / chunks;
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
-#define HS_PSWEEP(RR, CC, PP, MM)                                                                        \
-  hipLaunchKernelGGL((k_psweep<RR, PP, MM>), grid, dim3(256), lds, st, d, (const CC*)tab, (const double2*)tab64, \
-                     (CC*)ws, xcap)
+#define HS_PSWEEP(RR, CC, PP, MM, SEL)                                                                   \
+  hipLaunchKernelGGL((k_psweep<RR, PP, MM, SEL>), grid, dim3(256), lds, st, d, (const CC*)tab,              \
+                     (const double2*)tab64, (CC*)ws, xcap)
   if (prec == 0) {
-    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8);
-    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16);
-    else HS_PSWEEP(double, double2, 8, 32);
+    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false);
+    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false);
+    else HS_PSWEEP(double, double2, 8, 32, false);
   } else {
-    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8);
-    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16);
-    else HS_PSWEEP(float, float2, 8, 32);
+    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, false);
+    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, false);
+    else HS_PSWEEP(float, float2, 8, 32, false);
+    if (fp64_modes) {
+      lds = sweep_lds_bytes(8, max_nz, chunks, max_xterms);
+      if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, true);
+      else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, true);
+      else HS_PSWEEP(float, float2, 8, 32, true);
+    }
   }
 #undef HS_PSWEEP
 }

@@ -61,13 +61,15 @@ int xform_y_tiles(const XformYDesc& d, int ct);
 
 // z solves: LDS of one workgroup (z tables + chunk-end exchange), and the
 // batched launch over descriptors (max_modes = largest na * nb).
-size_t sweep_lds_bytes(int prec, int nz, int chunks, int max_xterms);
+size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms);
 constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
 // chunks: z-line chunks per mode (8, 16 or 32, each at most 16 rows; 256 / chunks
 // modes per workgroup); 0 or an unusable value = default for max_nz
-// max_xterms: largest number of x-type low-rank terms over the descriptors.
+// max_xterms: largest number of x-type low-rank terms over the descriptors;
+// fp64_modes: complex64 only, some mode lies at or below its descriptor's
+// fp64_below (a second launch solves those workgroups in FP64).
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks = 0);
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes);
 int sweep_default_chunks(int nz);
 bool sweep_chunks_ok(int chunks, int nz);
 

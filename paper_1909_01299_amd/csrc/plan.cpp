@@ -909,7 +909,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks);
+    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks,
+          n_fp64_modes > 0);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -917,7 +918,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     const double nglob = double(NX) * NY * NZ;
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, xterms(d_sweepB), T, dtab64, W, nrhs, st, tune_chunks);
+    sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, xterms(d_sweepB), T, dtab64, W, nrhs, st, tune_chunks,
+          n_fp64_modes > 0);
     stage_end();
     stage_begin("face_contract", R * (nblk + nface) * esz, R * nblk * 4 * 8, st);
     contract(prec, p_face, cl_face, T, W, nrhs, st);
@@ -939,7 +941,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
-    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks);
+    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
+          n_fp64_modes > 0);
     stage_end();
     stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
@@ -955,7 +958,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
-    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks);
+    sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,
+          n_fp64_modes > 0);
     stage_end();
   }
   // step 7: inverse transforms into u
