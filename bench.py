@@ -124,6 +124,57 @@ def cpu_baseline(problem, f, repeat_budget_s=20.0):
                                          f"({t:.2f} s each; eigen tables {t_plan:.2f} s excluded)"}
 
 
+def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63)):
+    """Batched workload: 64 independent blocks of uneven sizes (half uniform,
+    half with stretched complex ends), 8 right-hand sides each, every stage one
+    batched launch in a captured graph; complex128 batch vs complex64 +
+    FP64-refinement batch on the same inputs."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    blocks = W.c3_blocks()
+    nrhs = 8
+    unknowns = sum(b.problem.unknowns for b in blocks)
+    fs = [hs.to_device(W.c3_rhs(i, b.problem, nrhs)) for i, b in enumerate(blocks)]
+    us = [torch.empty_like(f) for f in fs]
+    out = {"workload": f"c3_batched 64 blocks (32 uniform, 32 stretched ends), n_x,n_y in [32,256], "
+                       f"n_z in [64,256], {nrhs} RHS each",
+           "unknowns": unknowns, "nrhs": nrhs}
+    for prec in ("c128", "mixed"):
+        t0 = time.perf_counter()
+        plans = [hs.Plan(b.problem, prec, max_rhs=1) for b in blocks]
+        batch = hs.Batch(plans, [nrhs] * len(plans))
+        t_plan = time.perf_counter() - t0
+        for _ in range(warmup):
+            batch.solve(fs, us)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.solve(fs, us)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rec = {"value": unknowns * nrhs / dt, "unit": "unknowns*RHS/s", "ms_per_step": dt * 1e3,
+               "plan_seconds": t_plan}
+        if prec == "mixed":
+            rec["refine_steps"] = plans[0].info()["refine_steps"]
+        if with_oracle:
+            from oracle import separable
+            errs = []
+            for i in sample_blocks:
+                pb = blocks[i].problem
+                f1 = W.c3_rhs(i, pb, nrhs)[:1]
+                ref = separable.solve(pb, f1)
+                got = us[i][:1].cpu().numpy()
+                errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+            rec["rel_err_vs_oracle_max"] = max(errs)
+            rec["oracle_sample"] = f"blocks {list(sample_blocks)}, RHS 0"
+        out[prec] = rec
+        del batch, plans
+        torch.cuda.empty_cache()
+    out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +187,8 @@ def main():
     ap.add_argument("--pml", type=int, default=16)
     ap.add_argument("--nz", type=int, default=200)
     ap.add_argument("--layers", type=int, default=20)
+    ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
+    ap.add_argument("--c3-steps", type=int, default=5)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -188,6 +241,12 @@ def main():
         if mixed is not None:
             rel_err_mixed = float(np.linalg.norm(mixed["u"] - u_ref) / np.linalg.norm(u_ref))
 
+    c3 = None
+    if not args.no_c3:
+        del plan
+        torch.cuda.empty_cache()
+        c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline)
+
     rf = roofline(stages, "c128")
     if rf is not None:
         rf["traffic"] = traffic_for(rf["kernel"])
@@ -215,6 +274,7 @@ def main():
             "refine_steps": mixed["refine_steps"], "rel_err_vs_oracle": rel_err_mixed,
             "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"],
             "stages_ms_per_step": mixed["stages"]},
+        "batched_c3": c3,
         "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
         "plan_seconds": info["plan_seconds"],
         "tuned": tuned,
