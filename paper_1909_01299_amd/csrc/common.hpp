@@ -80,6 +80,7 @@ struct XformDesc {
   int64_t dst, dst_r, dst_p, dst_q;
   int32_t sine;     // 1: table is the real orthonormal sine matrix (imaginary part zero)
   int32_t pad_;
+  int64_t ftab;     // offset of the same table as real MFMA fragments (see xform_mfma.hip)
 };
 
 // Dense transform along a strided axis, in place: for plane p of RHS r and
@@ -89,6 +90,7 @@ struct XformYDesc {
   int32_t n, ncols;
   int32_t P, pad_;
   int64_t data, s_r, s_p, s_k;
+  int64_t ftab;     // offset of the same table as real MFMA fragments
 };
 
 // Orthonormal sine transform (DST-I, n = N - 1 points, N a power of two) of

@@ -26,66 +26,6 @@ __device__ __forceinline__ CO cvt(CI v) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense transform along the contiguous axis (x lines, face lines, interface
-// lines): dst[line][o] (+)= sum_k T[o][k] src[line][k].
-// Tile: 16 lines x 16 outputs per workgroup, K staged through LDS in chunks.
-// ---------------------------------------------------------------------------
-constexpr int XL_T = 16;
-constexpr int XL_K = 32;
-
-template <typename R, typename CI, typename CO, bool ACC>
-__global__ __launch_bounds__(256) void k_xform_lines(const XformDesc* __restrict__ descs,
-                                                     const cplx<R>* __restrict__ tab,
-                                                     const CI* __restrict__ src, CO* __restrict__ dst) {
-  using C = cplx<R>;
-  const XformDesc d = descs[blockIdx.y];
-  const int r = blockIdx.z;
-  const int lines = d.P * d.Q;
-  const int ntl = (lines + XL_T - 1) / XL_T;
-  const int nto = (d.n_out + XL_T - 1) / XL_T;
-  const int tile = blockIdx.x;
-  if (tile >= ntl * nto) return;
-  const int tl = tile % ntl, to = tile / ntl;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __shared__ C sA[XL_T][XL_K + 1];
-  __shared__ C sT[XL_T][XL_K + 1];
-  C acc = mk<R>(0, 0);
-  const CI* s0 = src + d.src + (int64_t)r * d.src_r;
-  const C* T = tab + d.tab;
-  for (int k0 = 0; k0 < d.n_in; k0 += XL_K) {
-    for (int e = threadIdx.x; e < XL_T * XL_K; e += 256) {
-      const int li = e / XL_K, kk = e % XL_K;
-      const int L = tl * XL_T + li, k = k0 + kk;
-      C v = mk<R>(0, 0);
-      if (L < lines && k < d.n_in) {
-        const int p = L / d.Q, q = L % d.Q;
-        v = cvt<C>(s0[(int64_t)p * d.src_p + (int64_t)q * d.src_q + k]);
-      }
-      sA[li][kk] = v;
-      const int O = to * XL_T + li;
-      sT[li][kk] = (O < d.n_out && k < d.n_in) ? T[(int64_t)O * d.n_in + k] : mk<R>(0, 0);
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < XL_K; ++kk) acc = cfma(sA[ty][kk], sT[tx][kk], acc);
-    __syncthreads();
-  }
-  const int L = tl * XL_T + ty, o = to * XL_T + tx;
-  if (L < lines && o < d.n_out) {
-    const int p = L / d.Q, q = L % d.Q;
-    CO* out = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + o;
-    if (ACC) {
-      CO prev = *out;
-      prev.x += acc.x;
-      prev.y += acc.y;
-      *out = prev;
-    } else {
-      *out = cvt<CO>(acc);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Dense transform along a strided axis, in place: for plane p and columns
 // [c0, c0 + CT), data[o][c] = sum_k T[o][k] data[k][c].  The whole column
 // panel is staged in LDS before any output is written.
@@ -1065,36 +1005,6 @@ inline unsigned grid1(int64_t n) { return unsigned((n + 255) / 256); }
 // launchers
 // ---------------------------------------------------------------------------
 
-template <typename R, typename CI, typename CO, bool ACC>
-static void launch_lines_t(const XformDesc* d, int ndesc, int max_tiles, const void* tab, const void* src,
-                           void* dst, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_xform_lines<R, CI, CO, ACC>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
-                     (const cplx<R>*)tab, (const CI*)src, (CO*)dst);
-}
-
-void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
-                 const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
-  if (ndesc == 0 || max_tiles == 0 || nrhs == 0) return;
-  if (prec == 0) {
-    launch_lines_t<double, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-    return;
-  }
-  // complex64 compute; boundary kernels may read or write complex128
-  if (!in64 && !out64) {
-    launch_lines_t<float, float2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-  } else if (in64 && !out64) {
-    launch_lines_t<float, double2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-  } else if (!in64 && out64) {
-    if (acc)
-      launch_lines_t<float, float2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-    else
-      launch_lines_t<float, float2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-  } else {
-    launch_lines_t<float, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
-  }
-}
-
-
 // ---------------------------------------------------------------- sine transform
 int dst_lines_per_wg(int prec, int V) {
   // exchange rows of 17 V + 1 real values, at most 40 KB of LDS per workgroup
@@ -1159,14 +1069,14 @@ void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, 
   }
 }
 
-int xform_lines_tiles(const XformDesc& d) {
-  const int lines = d.P * d.Q;
-  return ((lines + XL_T - 1) / XL_T) * ((d.n_out + XL_T - 1) / XL_T);
-}
-
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st) {
   if (ndesc == 0 || nrhs == 0) return;
+  if (xform_y_mfma_ok(prec, max_n)) {
+    // matrix cores; 16-column tiles, the same tile count as max_tiles16
+    xform_y_mfma(prec, d, ndesc, max_n, max_tiles16, tab, ws, nrhs, st);
+    return;
+  }
   const bool wide = max_n <= 256;
   const int CT = wide ? 16 : 8;
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);

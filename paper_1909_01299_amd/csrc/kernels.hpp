@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <complex>
+
 #include "common.hpp"
 
 namespace hs {
@@ -43,9 +45,19 @@ struct StencilGeom {
   const double2 *mx, *my, *mz;
 };
 
+// Dense transforms on matrix cores (xform_mfma.hip).
 void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
                  const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
 int xform_lines_tiles(const XformDesc& d);
+// y planes on matrix cores: n <= 256 (complex128) or 512 (complex64)
+bool xform_y_mfma_ok(int prec, int max_n);
+int xform_y_mfma_tiles(const XformYDesc& d);
+void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles, const void* tab, void* ws,
+                  int nrhs, hipStream_t st);
+// Fragment image of an n_out x n_in complex table (row-major): real values,
+// mfma_table_reals(n_out, n_in) of them.
+int64_t mfma_table_reals(int n_out, int n_in);
+void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double* out);
 
 // Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
 constexpr int kTwiddleN = 512;

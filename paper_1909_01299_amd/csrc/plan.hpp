@@ -21,6 +21,7 @@ struct Axis {
   int dstV = 0;                        // > 0: sine transform by FFT with V = (n + 1) / 8
   AxisEig e;
   int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
+  int64_t ffwd = 0, finv = 0;          // the same tables as real MFMA fragments
 };
 
 struct Block {

@@ -1,0 +1,391 @@
+// Dense transforms on matrix cores (gfx950 MFMA), used for the generalized
+// eigenvector tables of non-uniform axes (and of uniform axes whose length
+// has no power-of-two sine transform), and for face / interface lines.
+//
+// A complex n_out x n_in table T acts on interleaved complex data as a real
+// matrix E of size 2 n_out x 2 n_in:
+//     E[2o+c][2i+c'] = [[Re T, -Im T], [Im T, Re T]][c][c'] (o, i)
+// so that (E v)[2o+c] is component c of (T v)[o] for interleaved v.  E is
+// stored once per table, zero-padded to multiples of 16 in both dimensions
+// and pre-arranged in 16 x 4 MFMA operand fragments: fragment (mt, ks) holds
+// E[16 mt + l % 16][4 ks + l / 16] at lane l, so a fragment load is one
+// contiguous 64-value read.
+//
+// x lines (contiguous): C[line][n] = sum_k X[line][k] E[n][k]  (data = A operand,
+//   staged in LDS; table = B operand read as fragments).
+// y planes (in place): C[m][x] = sum_k E[m][k] X[k][x] with X[2i+c][x] the
+//   component c of element (i, x); a workgroup owns 16 columns of one plane,
+//   holds all of K for them in LDS and computes every output row before
+//   writing, so no other workgroup touches its columns.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace hs {
+
+namespace {
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+template <typename R> struct mfma;
+template <> struct mfma<double> {
+  using acc = f64x4_t;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in element i of lane l (column l % 16)
+  static __device__ __forceinline__ int row(int l, int i) { return 4 * i + (l >> 4); }
+};
+template <> struct mfma<float> {
+  using acc = f32x4_t;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int i) { return 4 * (l >> 4) + i; }
+};
+
+template <typename T> struct comp_of;
+template <> struct comp_of<double2> { using type = double; };
+template <> struct comp_of<float2> { using type = float; };
+
+template <typename CI>
+__device__ __forceinline__ typename comp_of<CI>::type comp(const CI& v, int c) {
+  return c ? v.y : v.x;
+}
+
+// ------------------------------------------------------------------ x lines
+constexpr int XM_BM = 64;   // lines per workgroup
+constexpr int XM_BN = 64;   // real outputs per workgroup (32 complex)
+constexpr int XM_KC = 16;   // reals per K chunk (8 complex inputs)
+constexpr int XM_LD = XM_KC + 1;   // LDS row stride (odd: rows fall in distinct banks)
+
+template <typename R, typename CI, typename CO, bool ACC>
+__global__ __launch_bounds__(256) void k_xform_lines_mfma(const XformDesc* __restrict__ descs,
+                                                         const cplx<R>* __restrict__ tab,
+                                                         const CI* __restrict__ src, CO* __restrict__ dst) {
+  using M = mfma<R>;
+  using acc_t = typename M::acc;
+  __shared__ R As[2][XM_BM * XM_LD];
+  const XformDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int64_t lines = (int64_t)d.P * d.Q;
+  const int ntiles = (2 * d.n_out + XM_BN - 1) / XM_BN;
+  const int64_t lt = blockIdx.x / ntiles;
+  const int nt = int(blockIdx.x % ntiles);
+  if (lt * XM_BM >= lines) return;
+  const int K2 = 2 * d.n_in;
+  const int nchunk = (K2 + XM_KC - 1) / XM_KC;
+  const int KS = nchunk * 4;               // k-steps of 4 in the fragment table
+  const int MT = (2 * d.n_out + 15) / 16;  // 16-row fragment tiles of the table
+  const R* ft = reinterpret_cast<const R*>(tab + d.ftab);
+
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  const int wm = w >> 1, wn = w & 1;       // wave tile: 32 lines x 32 outputs
+
+  // global -> LDS: thread loads complex elements 2*(tid%4), +1 of line tid/4
+  const int ld_line = tid >> 2, ld_c = (tid & 3) * 2;
+  const int64_t Lld = lt * XM_BM + ld_line;
+  const bool ld_ok = Lld < lines;
+  const CI* sline;
+  {
+    const int64_t Lc = ld_ok ? Lld : lines - 1;
+    const int p = int(Lc / d.Q), q = int(Lc % d.Q);
+    sline = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
+  }
+  auto load_chunk = [&](int ch, R (&v)[4]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = ch * (XM_KC / 2) + ld_c + e;   // complex input index
+      const CI x = sline[i < d.n_in ? i : d.n_in - 1];
+      const bool ok = ld_ok && i < d.n_in;
+      v[2 * e] = ok ? R(x.x) : R(0);
+      v[2 * e + 1] = ok ? R(x.y) : R(0);
+    }
+  };
+  auto store_chunk = [&](int buf, const R (&v)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) As[buf][ld_line * XM_LD + 2 * ld_c + e] = v[e];
+  };
+
+  acc_t c[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c[i][j] = acc_t{0, 0, 0, 0};
+
+  // table fragment tiles of this wave (16 real outputs each)
+  int mt[2];
+  bool mt_ok[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    mt[j] = nt * (XM_BN / 16) + wn * 2 + j;
+    mt_ok[j] = mt[j] < MT;
+  }
+
+  // table fragments of a chunk: 4 k-steps x 2 tiles, fetched one chunk ahead
+  // (tiles past MT read tile MT - 1 and are zeroed)
+  const R* fj[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) fj[j] = ft + (int64_t)min(mt[j], MT - 1) * KS * 64 + l;
+  auto load_frags = [&](int ch, R (&b)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[s][j] = fj[j][(ch * 4 + s) * 64];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (!mt_ok[j]) b[s][j] = R(0);
+  };
+  R v[4];
+  R bfr[4][2], bnx[4][2];
+  load_frags(0, bfr);
+  load_chunk(0, v);
+  store_chunk(0, v);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) {
+      load_chunk(ch + 1, v);
+      load_frags(ch + 1, bnx);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      R afr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) afr[i] = As[buf][(wm * 32 + i * 16 + (l & 15)) * XM_LD + s * 4 + (l >> 4)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c[i][j] = M::mma(afr[i], bfr[s][j], c[i][j]);
+    }
+    if (ch + 1 < nchunk) {
+      store_chunk(buf ^ 1, v);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bfr[s][j] = bnx[s][j];
+    }
+    __syncthreads();
+  }
+
+  // results: row = line, column = real output index (interleaved complex)
+  using RO = typename comp_of<CO>::type;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t L = lt * XM_BM + wm * 32 + i * 16 + M::row(l, e);
+      if (L >= lines) continue;
+      const int p = int(L / d.Q), q = int(L % d.Q);
+      RO* dline = reinterpret_cast<RO*>(dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p +
+                                        (int64_t)q * d.dst_q);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = nt * XM_BN + wn * 32 + j * 16 + (l & 15);
+        if (n < 2 * d.n_out) {
+          if (ACC)
+            dline[n] = RO(dline[n] + RO(c[i][j][e]));
+          else
+            dline[n] = RO(c[i][j][e]);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ y planes
+constexpr int YM_NC = 16;    // complex columns per workgroup
+constexpr int YM_THREADS = 512;
+constexpr int YM_WAVES = YM_THREADS / 64;
+
+// NT output tiles (rows 16 (w + 8 j), j < NT) of one wave over all of K; the
+// table fragments of 4 k-steps are fetched one group ahead.
+template <typename R, int NT>
+__device__ __forceinline__ void y_tiles(const R* __restrict__ ft, const R* Bs, int KS, int K2, int w, int l,
+                                        cplx<R>* base, int64_t s_k, int x, bool xok) {
+  using M = mfma<R>;
+  using acc_t = typename M::acc;
+  const R* fj[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) fj[j] = ft + (int64_t)(w + YM_WAVES * j) * KS * 64 + l;
+  R acur[4][NT], anx[4][NT];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acur[s][j] = fj[j][s * 64];
+  acc_t c[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) c[j] = acc_t{0, 0, 0, 0};
+  const int ngroups = KS / 4;
+  for (int g = 0; g < ngroups; ++g) {
+    const int gn = g + 1 < ngroups ? g + 1 : g;   // last group re-reads itself
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) anx[s][j] = fj[j][(gn * 4 + s) * 64];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const R b = Bs[((g * 4 + s) * 4 + (l >> 4)) * YM_NC + (l & 15)];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) c[j] = M::mma(acur[s][j], b, c[j]);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acur[s][j] = anx[s][j];
+  }
+  // every read of this workgroup's columns is done (all of K sits in LDS)
+  if (xok) {
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = (w + YM_WAVES * j) * 16 + M::row(l, e);
+        if (m < K2) {
+          R* o = reinterpret_cast<R*>(base + (int64_t)(m >> 1) * s_k + x);
+          o[m & 1] = c[j][e];
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int TPW>   // TPW: most 16-row output tiles per wave
+__global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma(const XformYDesc* __restrict__ descs,
+                                                            const cplx<R>* __restrict__ tab,
+                                                            cplx<R>* __restrict__ ws) {
+  extern __shared__ unsigned char smem_raw[];
+  R* Bs = reinterpret_cast<R*>(smem_raw);   // [KS*4][YM_NC]
+  const XformYDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int cblocks = (d.ncols + YM_NC - 1) / YM_NC;
+  const int p = blockIdx.x / cblocks, cb = blockIdx.x % cblocks;
+  if (p >= d.P) return;
+  const int n = d.n;
+  const int K2 = 2 * n;
+  const int KS = ((K2 + 15) / 16) * 4;     // a multiple of 4
+  const int MT = (K2 + 15) / 16;
+  const R* ft = reinterpret_cast<const R*>(tab + d.ftab);
+  cplx<R>* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
+  const int x0 = cb * YM_NC;
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+
+  // the whole K extent of the 16 columns into LDS (rows past 2n are zero)
+  for (int e = tid; e < KS * 2 * YM_NC; e += YM_THREADS) {
+    const int i = e / YM_NC, col = e % YM_NC;
+    const int x = x0 + col;
+    cplx<R> v = mk<R>(0, 0);
+    if (i < n && x < d.ncols) v = base[(int64_t)i * d.s_k + x];
+    Bs[(2 * i) * YM_NC + col] = v.x;
+    Bs[(2 * i + 1) * YM_NC + col] = v.y;
+  }
+
+  __syncthreads();
+  // this wave's output tiles: w, w + 8, ... below MT (a wave-uniform count)
+  const int ntw = MT > w ? (MT - w + YM_WAVES - 1) / YM_WAVES : 0;
+  const int x = x0 + (l & 15);
+  switch (ntw < TPW ? ntw : TPW) {
+    case 0: break;
+#define HS_YCASE(N) \
+    case N: if constexpr (N <= TPW) y_tiles<R, N>(ft, Bs, KS, K2, w, l, base, d.s_k, x, x < d.ncols); break;
+    HS_YCASE(1) HS_YCASE(2) HS_YCASE(3) HS_YCASE(4) HS_YCASE(5) HS_YCASE(6) HS_YCASE(7) HS_YCASE(8)
+#undef HS_YCASE
+    default: break;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+int64_t mfma_table_reals(int n_out, int n_in) {
+  const int64_t rows = ((2 * n_out + 15) / 16) * 16;
+  const int64_t cols = ((2 * n_in + 15) / 16) * 16;
+  return rows * cols;
+}
+
+void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double* out) {
+  const int MT = (2 * n_out + 15) / 16;
+  const int KS = ((2 * n_in + 15) / 16) * 4;
+  for (int mt = 0; mt < MT; ++mt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int m = mt * 16 + (l % 16), k = ks * 4 + (l / 16);
+        double v = 0;
+        if (m < 2 * n_out && k < 2 * n_in) {
+          const std::complex<double> t = T[(size_t)(m / 2) * n_in + (k / 2)];
+          const int c = m % 2, cp = k % 2;
+          v = (c == cp) ? t.real() : (c == 0 ? -t.imag() : t.imag());
+        }
+        out[((size_t)mt * KS + ks) * 64 + l] = v;
+      }
+}
+
+int xform_lines_tiles(const XformDesc& d) {
+  const int64_t lines = (int64_t)d.P * d.Q;
+  return int(((lines + XM_BM - 1) / XM_BM) * ((2 * d.n_out + XM_BN - 1) / XM_BN));
+}
+
+template <typename R, typename CI, typename CO, bool ACC>
+static void launch_lines_mfma(const XformDesc* d, int ndesc, int max_tiles, const void* tab, const void* src,
+                              void* dst, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL((k_xform_lines_mfma<R, CI, CO, ACC>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
+                     (const cplx<R>*)tab, (const CI*)src, (CO*)dst);
+}
+
+void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
+                 const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
+  if (ndesc == 0 || max_tiles == 0 || nrhs == 0) return;
+  if (prec == 0) {
+    if (acc)
+      launch_lines_mfma<double, double2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    else
+      launch_lines_mfma<double, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    return;
+  }
+  // complex64 compute; boundary passes may read or write complex128
+  if (!in64 && !out64) {
+    launch_lines_mfma<float, float2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else if (in64 && !out64) {
+    launch_lines_mfma<float, double2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else if (!in64 && out64) {
+    if (acc)
+      launch_lines_mfma<float, float2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    else
+      launch_lines_mfma<float, float2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  } else {
+    launch_lines_mfma<float, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+  }
+}
+
+bool xform_y_mfma_ok(int prec, int max_n) { return max_n <= (prec == 0 ? 256 : 512); }
+
+int xform_y_mfma_tiles(const XformYDesc& d) { return ((d.ncols + YM_NC - 1) / YM_NC) * d.P; }
+
+void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles, const void* tab, void* ws,
+                  int nrhs, hipStream_t st) {
+  if (ndesc == 0 || nrhs == 0 || max_tiles == 0) return;
+  // output tiles per wave: ceil(2 max_n / 16 / 8) <= 4 (n <= 256) or 8 (n <= 512)
+  const size_t rows = size_t((2 * max_n + 15) / 16) * 16;
+  const dim3 grid(max_tiles, ndesc, nrhs);
+  if (prec == 0) {
+    const size_t lds = rows * YM_NC * sizeof(double);
+    hipLaunchKernelGGL((k_xform_y_mfma<double, 4>), grid, dim3(YM_THREADS), lds, st, d, (const double2*)tab,
+                       (double2*)ws);
+  } else {
+    const size_t lds = rows * YM_NC * sizeof(float);
+    if (max_n <= 256)
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 4>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+                         (float2*)ws);
+    else
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 8>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+                         (float2*)ws);
+  }
+}
+
+}  // namespace hs
