@@ -199,6 +199,9 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
       sl.max_lines[v] = m;
     }
   };
+  // dense lists: matrix-core descriptors first (see run_lines_list / run_y_list)
+  partition_lines(s_fwdx.dense); partition_lines(s_fwdx_res.dense); partition_lines(s_invx.dense);
+  partition_y(prec, s_fwdy.dense); partition_y(prec, s_invy.dense);
   reg_stage(s_fwdx); reg_stage(s_fwdx_res); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
   reg(d_sweep, &p_sweep);
   if (blob.size() > ddesc_bytes) {
@@ -224,9 +227,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
                   hipStream_t st) {
   const void* T = tab();
   if (!sl.dense.empty()) {
-    int m = 0;
-    for (auto& d : sl.dense) m = std::max(m, xform_lines_tiles(d));
-    xform_lines(prec, in64, out64, acc, sl.p_dense, int(sl.dense.size()), m, T, src, dst, 1, st);
+    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, src, dst, 1, st);
   }
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
@@ -238,15 +239,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
 
 void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
   const void* T = tab();
-  if (!sl.dense.empty()) {
-    int m16 = 0, m8 = 0, mn = 0;
-    for (auto& d : sl.dense) {
-      m16 = std::max(m16, xform_y_tiles(d, 16));
-      m8 = std::max(m8, xform_y_tiles(d, 8));
-      mn = std::max(mn, d.n);
-    }
-    xform_y(prec, sl.p_dense, int(sl.dense.size()), mn, m16, m8, T, ws, 1, st);
-  }
+  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, ws, 1, st);
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
   for (int v = 0; v < kNumV; ++v)

@@ -1072,11 +1072,6 @@ void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, 
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st) {
   if (ndesc == 0 || nrhs == 0) return;
-  if (xform_y_mfma_ok(prec, max_n)) {
-    // matrix cores; 16-column tiles, the same tile count as max_tiles16
-    xform_y_mfma(prec, d, ndesc, max_n, max_tiles16, tab, ws, nrhs, st);
-    return;
-  }
   const bool wide = max_n <= 256;
   const int CT = wide ? 16 : 8;
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <complex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -45,15 +46,31 @@ struct StencilGeom {
   const double2 *mx, *my, *mz;
 };
 
-// Dense transforms on matrix cores (xform_mfma.hip).
-void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
+// Dense transforms (xform_mfma.hip): matrix cores for long lines in numbers
+// that fill the chip, complex FMA tiles otherwise; the choice and the grid
+// come from the host copy of the descriptor list.
+struct LinesLaunch {
+  int tiles = 0;
+  bool mfma = false;
+};
+bool xform_lines_use_mfma(const XformDesc& d);
+LinesLaunch xform_lines_launch(const XformDesc* host_descs, int ndesc, bool mfma);
+void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, const LinesLaunch& L,
                  const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
-int xform_lines_tiles(const XformDesc& d);
-// y planes on matrix cores: n <= 256 (complex128) or 512 (complex64)
-bool xform_y_mfma_ok(int prec, int max_n);
+// y planes on matrix cores: 32 <= n <= 256 (complex128) or 512 (complex64)
+bool xform_y_use_mfma(int prec, int n);
 int xform_y_mfma_tiles(const XformYDesc& d);
 void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles, const void* tab, void* ws,
                   int nrhs, hipStream_t st);
+// Lists of dense descriptors are partitioned once (matrix-core descriptors
+// first, order otherwise kept; the count is returned) and launched in two
+// parts, so a block takes the same kernel in any list it belongs to.
+int partition_lines(std::vector<XformDesc>& v);
+int partition_y(int prec, std::vector<XformYDesc>& v);
+void run_lines_list(int prec, int in64, int out64, int acc, const XformDesc* dev, const std::vector<XformDesc>& host,
+                    const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
+void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab, void* ws,
+                int nrhs, hipStream_t st);
 // Fragment image of an n_out x n_in complex table (row-major): real values,
 // mfma_table_reals(n_out, n_in) of them.
 int64_t mfma_table_reals(int n_out, int n_in);

@@ -694,6 +694,10 @@ hs_status Plan::upload_descs(std::string& err) {
       sl.max_lines[v] = m;
     }
   };
+  // dense lists: matrix-core descriptors first (see run_lines_list / run_y_list)
+  partition_lines(s_fwdx.dense); partition_lines(s_invx.dense);
+  partition_y(prec, s_fwdy.dense); partition_y(prec, s_invy.dense);
+  partition_lines(d_vface); partition_lines(d_gface); partition_lines(d_glob_in); partition_lines(d_glob_out);
   reg_stage(s_fwdx); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
   reg(d_vface, &p_vface); reg(d_gface, &p_gface);
   reg(d_glob_in, &p_glob_in); reg(d_glob_out, &p_glob_out);
@@ -838,9 +842,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
                  int nrhs, hipStream_t st) {
   const void* T = tab();
   if (!sl.dense.empty()) {
-    int m = 0;
-    for (auto& d : sl.dense) m = std::max(m, xform_lines_tiles(d));
-    xform_lines(prec, in64, out64, acc, sl.p_dense, int(sl.dense.size()), m, T, src, dst, nrhs, st);
+    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, src, dst, nrhs, st);
   }
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
@@ -852,15 +854,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
 
 void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
   const void* T = tab();
-  if (!sl.dense.empty()) {
-    int m16 = 0, m8 = 0, mn = 0;
-    for (auto& d : sl.dense) {
-      m16 = std::max(m16, xform_y_tiles(d, 16));
-      m8 = std::max(m8, xform_y_tiles(d, 8));
-      mn = std::max(mn, d.n);
-    }
-    xform_y(prec, sl.p_dense, int(sl.dense.size()), mn, m16, m8, T, ws, nrhs, st);
-  }
+  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, ws, nrhs, st);
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
   for (int v = 0; v < kNumV; ++v)
@@ -873,11 +867,6 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   const void* T = tab();
   void* W = ws;
   const int nb = int(blocks.size());
-  auto tiles_lines = [](const std::vector<XformDesc>& v) {
-    int m = 0;
-    for (auto& d : v) m = std::max(m, xform_lines_tiles(d));
-    return m;
-  };
   auto xterms = [](const std::vector<SweepDesc>& v) {
     int m = 0;
     for (auto& d : v) m = std::max(m, d.nxt);
@@ -937,7 +926,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     double ffl = 0;
     for (auto& B : blocks) ffl += double(NZ) * 2.0 * (double(B.nby) * B.nby + double(B.nbx) * B.nbx) * 8.0;
     stage_begin("face_xform", R * nface * 2 * esz, R * ffl, st);
-    xform_lines(prec, 0, 0, 0, p_vface, int(d_vface.size()), tiles_lines(d_vface), T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_vface, d_vface, T, W, W, nrhs, st);
     stage_end();
     // step 4: residual on the separators
     SigmaGeom g = sg;
@@ -948,7 +937,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     // step 5: global interface solve, evaluated on the separators
     const double gfl = double(NZ) * (nsx * double(NY) * NY + nsy * double(NX) * NX) * 8.0;
     stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
-    xform_lines(prec, 0, 0, 0, p_glob_in, int(d_glob_in.size()), tiles_lines(d_glob_in), T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
@@ -958,14 +947,14 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
     stage_end();
     stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
-    xform_lines(prec, 0, 0, 0, p_glob_out, int(d_glob_out.size()), tiles_lines(d_glob_out), T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_glob_out, d_glob_out, T, W, W, nrhs, st);
     stage_end();
     // step 6: lift the separator values into the blocks and sweep again
     stage_begin("lift", R * nface * 2 * esz, R * nface * 6, st);
     lift(prec, g, p_lift, nb, W, nrhs, st);
     stage_end();
     stage_begin("lift_xform", R * nface * 2 * esz, R * ffl, st);
-    xform_lines(prec, 0, 0, 0, p_gface, int(d_gface.size()), tiles_lines(d_gface), T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_gface, d_gface, T, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,

@@ -22,6 +22,9 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
+#include <vector>
+
 namespace hs {
 
 namespace {
@@ -300,6 +303,73 @@ __global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma(const XformYDesc* _
   }
 }
 
+// ------------------------------------------------------------------ small line sets
+// Few or short lines (interface and face lines, narrow PML blocks): complex
+// FMA on 16 x 16 output tiles, K staged through LDS; more workgroups than the
+// matrix-core tiling would give for such sizes.
+template <typename CO, typename CI>
+__device__ __forceinline__ CO cvt(CI v) {
+  CO o;
+  o.x = (decltype(o.x))v.x;
+  o.y = (decltype(o.y))v.y;
+  return o;
+}
+
+constexpr int XL_T = 16;
+constexpr int XL_K = 32;
+
+template <typename R, typename CI, typename CO, bool ACC>
+__global__ __launch_bounds__(256) void k_xform_lines_small(const XformDesc* __restrict__ descs,
+                                                     const cplx<R>* __restrict__ tab,
+                                                     const CI* __restrict__ src, CO* __restrict__ dst) {
+  using C = cplx<R>;
+  const XformDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int lines = d.P * d.Q;
+  const int ntl = (lines + XL_T - 1) / XL_T;
+  const int nto = (d.n_out + XL_T - 1) / XL_T;
+  const int tile = blockIdx.x;
+  if (tile >= ntl * nto) return;
+  const int tl = tile % ntl, to = tile / ntl;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ C sA[XL_T][XL_K + 1];
+  __shared__ C sT[XL_T][XL_K + 1];
+  C acc = mk<R>(0, 0);
+  const CI* s0 = src + d.src + (int64_t)r * d.src_r;
+  const C* T = tab + d.tab;
+  for (int k0 = 0; k0 < d.n_in; k0 += XL_K) {
+    for (int e = threadIdx.x; e < XL_T * XL_K; e += 256) {
+      const int li = e / XL_K, kk = e % XL_K;
+      const int L = tl * XL_T + li, k = k0 + kk;
+      C v = mk<R>(0, 0);
+      if (L < lines && k < d.n_in) {
+        const int p = L / d.Q, q = L % d.Q;
+        v = cvt<C>(s0[(int64_t)p * d.src_p + (int64_t)q * d.src_q + k]);
+      }
+      sA[li][kk] = v;
+      const int O = to * XL_T + li;
+      sT[li][kk] = (O < d.n_out && k < d.n_in) ? T[(int64_t)O * d.n_in + k] : mk<R>(0, 0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < XL_K; ++kk) acc = cfma(sA[ty][kk], sT[tx][kk], acc);
+    __syncthreads();
+  }
+  const int L = tl * XL_T + ty, o = to * XL_T + tx;
+  if (L < lines && o < d.n_out) {
+    const int p = L / d.Q, q = L % d.Q;
+    CO* out = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + o;
+    if (ACC) {
+      CO prev = *out;
+      prev.x += acc.x;
+      prev.y += acc.y;
+      *out = prev;
+    } else {
+      *out = cvt<CO>(acc);
+    }
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -326,44 +396,64 @@ void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double
       }
 }
 
-int xform_lines_tiles(const XformDesc& d) {
-  const int64_t lines = (int64_t)d.P * d.Q;
-  return int(((lines + XM_BM - 1) / XM_BM) * ((2 * d.n_out + XM_BN - 1) / XM_BN));
+bool xform_lines_use_mfma(const XformDesc& d) {
+  // matrix cores for long lines in numbers that fill the chip (per right-hand
+  // side, so a block takes the same kernel alone and in a batch)
+  return std::max(d.n_in, d.n_out) >= 24 && (int64_t)d.P * d.Q >= 1024;
+}
+
+LinesLaunch xform_lines_launch(const XformDesc* d, int ndesc, bool mfma) {
+  LinesLaunch L;
+  L.mfma = mfma;
+  int64_t m = 0;
+  for (int i = 0; i < ndesc; ++i) {
+    const int64_t lines = (int64_t)d[i].P * d[i].Q;
+    const int64_t t = mfma ? ((lines + XM_BM - 1) / XM_BM) * ((2 * d[i].n_out + XM_BN - 1) / XM_BN)
+                           : ((lines + XL_T - 1) / XL_T) * ((d[i].n_out + XL_T - 1) / XL_T);
+    m = std::max(m, t);
+  }
+  L.tiles = int(m);
+  return L;
 }
 
 template <typename R, typename CI, typename CO, bool ACC>
-static void launch_lines_mfma(const XformDesc* d, int ndesc, int max_tiles, const void* tab, const void* src,
-                              void* dst, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL((k_xform_lines_mfma<R, CI, CO, ACC>), dim3(max_tiles, ndesc, nrhs), dim3(256), 0, st, d,
-                     (const cplx<R>*)tab, (const CI*)src, (CO*)dst);
+static void launch_lines(const XformDesc* d, int ndesc, const LinesLaunch& L, const void* tab, const void* src,
+                         void* dst, int nrhs, hipStream_t st) {
+  const dim3 grid(L.tiles, ndesc, nrhs);
+  if (L.mfma)
+    hipLaunchKernelGGL((k_xform_lines_mfma<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
+                       (const CI*)src, (CO*)dst);
+  else
+    hipLaunchKernelGGL((k_xform_lines_small<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
+                       (const CI*)src, (CO*)dst);
 }
 
-void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, int max_tiles,
+void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, const LinesLaunch& L,
                  const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
-  if (ndesc == 0 || max_tiles == 0 || nrhs == 0) return;
+  if (ndesc == 0 || L.tiles == 0 || nrhs == 0) return;
   if (prec == 0) {
     if (acc)
-      launch_lines_mfma<double, double2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+      launch_lines<double, double2, double2, true>(d, ndesc, L, tab, src, dst, nrhs, st);
     else
-      launch_lines_mfma<double, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+      launch_lines<double, double2, double2, false>(d, ndesc, L, tab, src, dst, nrhs, st);
     return;
   }
   // complex64 compute; boundary passes may read or write complex128
   if (!in64 && !out64) {
-    launch_lines_mfma<float, float2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    launch_lines<float, float2, float2, false>(d, ndesc, L, tab, src, dst, nrhs, st);
   } else if (in64 && !out64) {
-    launch_lines_mfma<float, double2, float2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    launch_lines<float, double2, float2, false>(d, ndesc, L, tab, src, dst, nrhs, st);
   } else if (!in64 && out64) {
     if (acc)
-      launch_lines_mfma<float, float2, double2, true>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+      launch_lines<float, float2, double2, true>(d, ndesc, L, tab, src, dst, nrhs, st);
     else
-      launch_lines_mfma<float, float2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+      launch_lines<float, float2, double2, false>(d, ndesc, L, tab, src, dst, nrhs, st);
   } else {
-    launch_lines_mfma<float, double2, double2, false>(d, ndesc, max_tiles, tab, src, dst, nrhs, st);
+    launch_lines<float, double2, double2, false>(d, ndesc, L, tab, src, dst, nrhs, st);
   }
 }
 
-bool xform_y_mfma_ok(int prec, int max_n) { return max_n <= (prec == 0 ? 256 : 512); }
+bool xform_y_use_mfma(int prec, int n) { return n >= 32 && n <= (prec == 0 ? 256 : 512); }
 
 int xform_y_mfma_tiles(const XformYDesc& d) { return ((d.ncols + YM_NC - 1) / YM_NC) * d.P; }
 
@@ -385,6 +475,52 @@ void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_t
     else
       hipLaunchKernelGGL((k_xform_y_mfma<float, 8>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
                          (float2*)ws);
+  }
+}
+
+int partition_lines(std::vector<XformDesc>& v) {
+  auto it = std::stable_partition(v.begin(), v.end(), [](const XformDesc& d) { return xform_lines_use_mfma(d); });
+  return int(it - v.begin());
+}
+
+int partition_y(int prec, std::vector<XformYDesc>& v) {
+  auto it = std::stable_partition(v.begin(), v.end(), [prec](const XformYDesc& d) { return xform_y_use_mfma(prec, d.n); });
+  return int(it - v.begin());
+}
+
+void run_lines_list(int prec, int in64, int out64, int acc, const XformDesc* dev, const std::vector<XformDesc>& host,
+                    const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
+  const int n = int(host.size());
+  int nm = 0;
+  while (nm < n && xform_lines_use_mfma(host[nm])) ++nm;
+  if (nm > 0)
+    xform_lines(prec, in64, out64, acc, dev, nm, xform_lines_launch(host.data(), nm, true), tab, src, dst, nrhs, st);
+  if (nm < n)
+    xform_lines(prec, in64, out64, acc, dev + nm, n - nm, xform_lines_launch(host.data() + nm, n - nm, false), tab,
+                src, dst, nrhs, st);
+}
+
+void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab, void* ws,
+                int nrhs, hipStream_t st) {
+  const int n = int(host.size());
+  int nm = 0;
+  while (nm < n && xform_y_use_mfma(prec, host[nm].n)) ++nm;
+  auto extent = [&](int b, int e, int& max_n, int& t16, int& t8) {
+    max_n = t16 = t8 = 0;
+    for (int i = b; i < e; ++i) {
+      max_n = std::max(max_n, host[i].n);
+      t16 = std::max(t16, xform_y_tiles(host[i], 16));
+      t8 = std::max(t8, xform_y_tiles(host[i], 8));
+    }
+  };
+  int max_n, t16, t8;
+  if (nm > 0) {
+    extent(0, nm, max_n, t16, t8);
+    xform_y_mfma(prec, dev, nm, max_n, t16, tab, ws, nrhs, st);   // 16-column tiles
+  }
+  if (nm < n) {
+    extent(nm, n, max_n, t16, t8);
+    xform_y(prec, dev + nm, n - nm, max_n, t16, t8, tab, ws, nrhs, st);
   }
 }
 
