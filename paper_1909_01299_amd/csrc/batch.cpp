@@ -142,7 +142,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         s_invx.dst[v].push_back(ix);
       } else {
         XformDesc fx{};
-        fx.tab = T0 + AX.fwd; fx.ftab = T0 + AX.ffwd; fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
+        fx.tab = T0 + AX.fwd; set_frag(fx, AX, true, T0); fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
         fx.src = fo; fx.src_p = plane; fx.src_q = B.nbx;
         fx.dst = spec; fx.dst_p = plane; fx.dst_q = B.nbx;
         s_fwdx.dense.push_back(fx);
@@ -150,7 +150,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         fr.src = ro;
         s_fwdx_res.dense.push_back(fr);
         XformDesc ix = fx;
-        ix.tab = T0 + AX.inv; ix.ftab = T0 + AX.finv; ix.src = spec; ix.dst = uo;
+        ix.tab = T0 + AX.inv; set_frag(ix, AX, false, T0); ix.src = spec; ix.dst = uo;
         s_invx.dense.push_back(ix);
       }
       if (AY.dstV) {
@@ -163,11 +163,11 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         s_invy.dst[v].push_back(dy);
       } else {
         XformYDesc fy{};
-        fy.tab = T0 + AY.fwd; fy.ftab = T0 + AY.ffwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
+        fy.tab = T0 + AY.fwd; set_frag(fy, AY, true, T0); fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
         fy.data = spec; fy.s_p = plane; fy.s_k = B.nbx;
         s_fwdy.dense.push_back(fy);
         XformYDesc iy = fy;
-        iy.tab = T0 + AY.inv; iy.ftab = T0 + AY.finv;
+        iy.tab = T0 + AY.inv; set_frag(iy, AY, false, T0);
         s_invy.dense.push_back(iy);
       }
       SweepDesc s{};

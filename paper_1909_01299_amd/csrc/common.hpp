@@ -79,8 +79,8 @@ struct XformDesc {
   int64_t src, src_r, src_p, src_q;
   int64_t dst, dst_r, dst_p, dst_q;
   int32_t sine;     // 1: table is the real orthonormal sine matrix (imaginary part zero)
-  int32_t pad_;
-  int64_t ftab;     // offset of the same table as real MFMA fragments (see xform_mfma.hip)
+  int32_t real_tab; // 1: ftab holds the real table itself, 0: its real embedding
+  int64_t ftab;     // offset of the same table as MFMA fragments (see xform_mfma.hip)
 };
 
 // Dense transform along a strided axis, in place: for plane p of RHS r and
@@ -88,9 +88,9 @@ struct XformDesc {
 struct XformYDesc {
   int64_t tab;
   int32_t n, ncols;
-  int32_t P, pad_;
+  int32_t P, real_tab;   // real_tab: as in XformDesc
   int64_t data, s_r, s_p, s_k;
-  int64_t ftab;     // offset of the same table as real MFMA fragments
+  int64_t ftab;     // offset of the same table as MFMA fragments
 };
 
 // Orthonormal sine transform (DST-I, n = N - 1 points, N a power of two) of

@@ -52,16 +52,17 @@ struct StencilGeom {
 struct LinesLaunch {
   int tiles = 0;
   bool mfma = false;
+  bool real = false;   // matrix cores with a real table (descriptors with real_tab)
 };
 bool xform_lines_use_mfma(const XformDesc& d);
-LinesLaunch xform_lines_launch(const XformDesc* host_descs, int ndesc, bool mfma);
+LinesLaunch xform_lines_launch(const XformDesc* host_descs, int ndesc, bool mfma, bool real);
 void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int ndesc, const LinesLaunch& L,
                  const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
 // y planes on matrix cores: 32 <= n <= 256 (complex128) or 512 (complex64)
 bool xform_y_use_mfma(int prec, int n);
 int xform_y_mfma_tiles(const XformYDesc& d);
 void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles, const void* tab, void* ws,
-                  int nrhs, hipStream_t st);
+                  int nrhs, hipStream_t st, bool real);
 // Lists of dense descriptors are partitioned once (matrix-core descriptors
 // first, order otherwise kept; the count is returned) and launched in two
 // parts, so a block takes the same kernel in any list it belongs to.
@@ -75,6 +76,9 @@ void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& 
 // mfma_table_reals(n_out, n_in) of them.
 int64_t mfma_table_reals(int n_out, int n_in);
 void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double* out);
+// Fragment image of a real table (the real parts of T): mfma_rtable_reals of them.
+int64_t mfma_rtable_reals(int n_out, int n_in);
+void mfma_rtable_build(const std::complex<double>* T, int n_out, int n_in, double* out);
 
 // Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
 constexpr int kTwiddleN = 512;

@@ -155,6 +155,7 @@ hs_status Plan::build_tables(std::string& err) {
     Axis a;
     a.n = n;
     a.sine = axis_is_uniform(n, h) && !(flags & 1);
+    a.real_tables = axis_is_uniform(n, h);
     const int N = n + 1;
     if (a.sine && N >= 16 && N <= 256 && (N & (N - 1)) == 0) a.dstV = N / 8;
     if (axis_is_uniform(n, h)) {
@@ -207,9 +208,13 @@ hs_status Plan::build_tables(std::string& err) {
     return off;
   };
   // real MFMA fragment image of a table, two reals per complex slot
-  auto push_frag = [&](const std::vector<cd>& T, int n) {
-    std::vector<double> re(size_t(mfma_table_reals(n, n)));
-    mfma_table_build(T.data(), n, n, re.data());
+  auto push_frag = [&](const std::vector<cd>& T, int n, bool real) {
+    std::vector<double> re(size_t(real ? mfma_rtable_reals(n, n) : mfma_table_reals(n, n)));
+    if (real)
+      mfma_rtable_build(T.data(), n, n, re.data());
+    else
+      mfma_table_build(T.data(), n, n, re.data());
+    re.resize(re.size() + (re.size() & 1));
     std::vector<cd> packed(re.size() / 2);
     for (size_t j = 0; j < packed.size(); ++j) packed[j] = cd(re[2 * j], re[2 * j + 1]);
     return push(packed);
@@ -218,8 +223,12 @@ hs_status Plan::build_tables(std::string& err) {
     a.fwd = push(a.e.Winv);
     a.inv = push(a.e.W);
     a.lam = push(a.e.lam);
-    a.ffwd = push_frag(a.e.Winv, a.n);
-    a.finv = push_frag(a.e.W, a.n);
+    a.ffwd = push_frag(a.e.Winv, a.n, false);
+    a.finv = push_frag(a.e.W, a.n, false);
+    if (a.real_tables) {
+      a.rfwd = push_frag(a.e.Winv, a.n, true);
+      a.rinv = push_frag(a.e.W, a.n, true);
+    }
   }
   {
     std::vector<cd> tw(kTwiddleN);
@@ -444,13 +453,13 @@ void Plan::build_descriptors() {
       s_invx.dst[vidx(AX.dstV)].push_back(ix);
     } else {
       XformDesc fx{};
-      fx.tab = AX.fwd; fx.ftab = AX.ffwd; fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
+      fx.tab = AX.fwd; set_frag(fx, AX, true); fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
       fx.src = (int64_t)B.y0 * NX + B.x0; fx.src_r = f_r; fx.src_p = gplane; fx.src_q = NX;
       fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.nbx;
       fx.sine = AX.sine;
       s_fwdx.dense.push_back(fx);
       XformDesc ix = fx;
-      ix.tab = AX.inv; ix.ftab = AX.finv;
+      ix.tab = AX.inv; set_frag(ix, AX, false);
       ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
       ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
       s_invx.dense.push_back(ix);
@@ -464,11 +473,11 @@ void Plan::build_descriptors() {
       s_invy.dst[vidx(AY.dstV)].push_back(dy);
     } else {
       XformYDesc fy{};
-      fy.tab = AY.fwd; fy.ftab = AY.ffwd; fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
+      fy.tab = AY.fwd; set_frag(fy, AY, true); fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
       fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.nbx;
       s_fwdy.dense.push_back(fy);
       XformYDesc iy = fy;
-      iy.tab = AY.inv; iy.ftab = AY.finv;
+      iy.tab = AY.inv; set_frag(iy, AY, false);
       s_invy.dense.push_back(iy);
     }
 
@@ -502,12 +511,12 @@ void Plan::build_descriptors() {
     d_face.push_back(c);
     // face values v(y) = sum_b W_y[y][b] e(b) (faces 0, 1) and v(x) = sum_a W_x[x][a] e(a) (faces 2, 3)
     XformDesc vf{};
-    vf.tab = AY.inv; vf.ftab = AY.finv; vf.n_in = vf.n_out = B.nby; vf.P = 2 * NZ; vf.Q = 1;
+    vf.tab = AY.inv; set_frag(vf, AY, false); vf.n_in = vf.n_out = B.nby; vf.P = 2 * NZ; vf.Q = 1;
     vf.src = fbase; vf.src_r = 4 * face_f; vf.src_p = NF; vf.src_q = 0;
     vf.dst = w_vface + (fbase - w_face); vf.dst_r = 4 * face_f; vf.dst_p = NF; vf.dst_q = 0;
     d_vface.push_back(vf);
     XformDesc vf2 = vf;
-    vf2.tab = AX.inv; vf2.ftab = AX.finv; vf2.n_in = vf2.n_out = B.nbx;
+    vf2.tab = AX.inv; set_frag(vf2, AX, false); vf2.n_in = vf2.n_out = B.nbx;
     vf2.src = fbase + 2 * face_f; vf2.dst = vf.dst + 2 * face_f;
     d_vface.push_back(vf2);
     // step 6: lift, transform by the block's W^{-1}
@@ -520,10 +529,10 @@ void Plan::build_descriptors() {
     const int64_t gbase = w_gface + (fbase - w_face);
     const int64_t Gbase = w_Gface + (fbase - w_face);
     XformDesc gf = vf;
-    gf.tab = AY.fwd; gf.ftab = AY.ffwd; gf.src = gbase; gf.dst = Gbase;
+    gf.tab = AY.fwd; set_frag(gf, AY, true); gf.src = gbase; gf.dst = Gbase;
     d_gface.push_back(gf);
     XformDesc gf2 = vf2;
-    gf2.tab = AX.fwd; gf2.ftab = AX.ffwd; gf2.src = gbase + 2 * face_f; gf2.dst = Gbase + 2 * face_f;
+    gf2.tab = AX.fwd; set_frag(gf2, AX, true); gf2.src = gbase + 2 * face_f; gf2.dst = Gbase + 2 * face_f;
     d_gface.push_back(gf2);
     // steps 6-7: block solve of f^ + g^ (g^ generated from the four faces), in place
     SweepDesc sc = s;
@@ -545,24 +554,24 @@ void Plan::build_descriptors() {
     // step 5 input: R_x[s](b) = sum_y W_y^{-1}[b][y] r(s, y); R_y[t](a) = sum_x W_x^{-1}[a][x] r(x, t)
     if (nsx > 0) {
       XformDesc d{};
-      d.tab = GY.fwd; d.ftab = GY.ffwd; d.n_in = d.n_out = NY; d.P = nsx * NZ; d.Q = 1;
+      d.tab = GY.fwd; set_frag(d, GY, true); d.n_in = d.n_out = NY; d.P = nsx * NZ; d.Q = 1;
       d.src = w_rx; d.src_r = (int64_t)nsx * NZ * NY; d.src_p = NY;
       d.dst = w_Rx; d.dst_r = d.src_r; d.dst_p = NY;
       d_glob_in.push_back(d);
       XformDesc o{};
-      o.tab = GY.inv; o.ftab = GY.finv; o.n_in = o.n_out = NY; o.P = nsx * NZ; o.Q = 1;
+      o.tab = GY.inv; set_frag(o, GY, false); o.n_in = o.n_out = NY; o.P = nsx * NZ; o.Q = 1;
       o.src = w_Qx; o.src_r = d.src_r; o.src_p = NY;
       o.dst = w_wx; o.dst_r = d.src_r; o.dst_p = NY;
       d_glob_out.push_back(o);
     }
     if (nsy > 0) {
       XformDesc d{};
-      d.tab = GX.fwd; d.ftab = GX.ffwd; d.n_in = d.n_out = NX; d.P = nsy * NZ; d.Q = 1;
+      d.tab = GX.fwd; set_frag(d, GX, true); d.n_in = d.n_out = NX; d.P = nsy * NZ; d.Q = 1;
       d.src = w_ry; d.src_r = (int64_t)nsy * NZ * NX; d.src_p = NX;
       d.dst = w_Ry; d.dst_r = d.src_r; d.dst_p = NX;
       d_glob_in.push_back(d);
       XformDesc o{};
-      o.tab = GX.inv; o.ftab = GX.finv; o.n_in = o.n_out = NX; o.P = nsy * NZ; o.Q = 1;
+      o.tab = GX.inv; set_frag(o, GX, false); o.n_in = o.n_out = NX; o.P = nsy * NZ; o.Q = 1;
       o.src = w_Qy; o.src_r = d.src_r; o.src_p = NX;
       o.dst = w_wy; o.dst_r = d.src_r; o.dst_p = NX;
       d_glob_out.push_back(o);

@@ -19,10 +19,21 @@ struct Axis {
   int n = 0;
   bool sine = false;
   int dstV = 0;                        // > 0: sine transform by FFT with V = (n + 1) / 8
+  bool real_tables = false;            // uniform axis: W and W^{-1} are real sine matrices
   AxisEig e;
   int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
-  int64_t ffwd = 0, finv = 0;          // the same tables as real MFMA fragments
+  int64_t ffwd = 0, finv = 0;          // the same tables as MFMA fragments of their real embedding
+  int64_t rfwd = -1, rinv = -1;        // uniform axes (real sine tables): fragments of the tables themselves
 };
+
+// Matrix-core table of a dense descriptor: the real table where the axis has
+// one, else the real embedding of the complex table (offsets + base).
+template <typename D>
+inline void set_frag(D& d, const Axis& a, bool fwd, int64_t base = 0) {
+  const bool real = a.rfwd >= 0;
+  d.real_tab = real ? 1 : 0;
+  d.ftab = base + (real ? (fwd ? a.rfwd : a.rinv) : (fwd ? a.ffwd : a.finv));
+}
 
 struct Block {
   int bi = 0, bj = 0;            // block column / row

@@ -303,6 +303,246 @@ __global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma(const XformYDesc* _
   }
 }
 
+// ------------------------------------------------------------------ real tables
+// A real table T (the sine matrix of a uniform axis whose length has no
+// power-of-two sine transform) acts on the real and imaginary parts alike, so
+// the product needs no embedding: its fragments hold T itself (fragment
+// (mt, ks) holds T[16 mt + l % 16][4 ks + l / 16] at lane l), and
+//   x lines: rows are (line, component) pairs, K = n_in;
+//   y planes: columns are (column, component) pairs, 2 x 16 per workgroup.
+// Half the products of the embedded form.
+
+template <typename R, typename CI, typename CO, bool ACC>
+__global__ __launch_bounds__(256) void k_xform_lines_mfma_real(const XformDesc* __restrict__ descs,
+                                                              const cplx<R>* __restrict__ tab,
+                                                              const CI* __restrict__ src, CO* __restrict__ dst) {
+  using M = mfma<R>;
+  using acc_t = typename M::acc;
+  constexpr int BL = XM_BM / 2;            // 32 lines = 64 (line, component) rows
+  __shared__ R As[2][XM_BM * XM_LD];       // [row = 2 line + c][k]
+  const XformDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int64_t lines = (int64_t)d.P * d.Q;
+  const int ntiles = (d.n_out + XM_BN - 1) / XM_BN;
+  const int64_t lt = blockIdx.x / ntiles;
+  const int nt = int(blockIdx.x % ntiles);
+  if (lt * BL >= lines) return;
+  const int nchunk = (d.n_in + XM_KC - 1) / XM_KC;
+  const int KS = nchunk * 4;
+  const int MT = (d.n_out + 15) / 16;
+  const R* ft = reinterpret_cast<const R*>(tab + d.ftab);
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = w >> 1, wn = w & 1;
+
+  // global -> LDS: thread loads complex inputs 2*(tid%8), +1 of line tid/8
+  const int ld_line = tid >> 3, ld_c = (tid & 7) * 2;
+  const int64_t Lld = lt * BL + ld_line;
+  const bool ld_ok = Lld < lines;
+  const CI* sline;
+  {
+    const int64_t Lc = ld_ok ? Lld : lines - 1;
+    const int p = int(Lc / d.Q), q = int(Lc % d.Q);
+    sline = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
+  }
+  auto load_chunk = [&](int ch, R (&v)[4]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int i = ch * XM_KC + ld_c + e;
+      const CI x = sline[i < d.n_in ? i : d.n_in - 1];
+      const bool ok = ld_ok && i < d.n_in;
+      v[2 * e] = ok ? R(x.x) : R(0);
+      v[2 * e + 1] = ok ? R(x.y) : R(0);
+    }
+  };
+  auto store_chunk = [&](int buf, const R (&v)[4]) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      As[buf][(2 * ld_line) * XM_LD + ld_c + e] = v[2 * e];
+      As[buf][(2 * ld_line + 1) * XM_LD + ld_c + e] = v[2 * e + 1];
+    }
+  };
+  int mt[2];
+  bool mt_ok[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    mt[j] = nt * (XM_BN / 16) + wn * 2 + j;
+    mt_ok[j] = mt[j] < MT;
+  }
+  const R* fj[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) fj[j] = ft + (int64_t)min(mt[j], MT - 1) * KS * 64 + l;
+  auto load_frags = [&](int ch, R (&b)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[s][j] = fj[j][(ch * 4 + s) * 64];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (!mt_ok[j]) b[s][j] = R(0);
+  };
+  acc_t c[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c[i][j] = acc_t{0, 0, 0, 0};
+  R v[4];
+  R bfr[4][2], bnx[4][2];
+  load_frags(0, bfr);
+  load_chunk(0, v);
+  store_chunk(0, v);
+  __syncthreads();
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nchunk) {
+      load_chunk(ch + 1, v);
+      load_frags(ch + 1, bnx);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      R afr[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) afr[i] = As[buf][(wm * 32 + i * 16 + (l & 15)) * XM_LD + s * 4 + (l >> 4)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) c[i][j] = M::mma(afr[i], bfr[s][j], c[i][j]);
+    }
+    if (ch + 1 < nchunk) {
+      store_chunk(buf ^ 1, v);
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bfr[s][j] = bnx[s][j];
+    }
+    __syncthreads();
+  }
+  using RO = typename comp_of<CO>::type;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = wm * 32 + i * 16 + M::row(l, e);   // (line, component) row
+      const int64_t L = lt * BL + (row >> 1);
+      if (L >= lines) continue;
+      const int cc = row & 1;
+      const int p = int(L / d.Q), q = int(L % d.Q);
+      RO* dline = reinterpret_cast<RO*>(dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p +
+                                        (int64_t)q * d.dst_q);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = nt * XM_BN + wn * 32 + j * 16 + (l & 15);
+        if (o < d.n_out) {
+          if (ACC)
+            dline[2 * o + cc] = RO(dline[2 * o + cc] + RO(c[i][j][e]));
+          else
+            dline[2 * o + cc] = RO(c[i][j][e]);
+        }
+      }
+    }
+  }
+}
+
+// NT row tiles x 2 column tiles (32 real columns) of one wave for a real table.
+template <typename R, int NT>
+__device__ __forceinline__ void y_tiles_real(const R* __restrict__ ft, const R* Bs, int KS, int n, int w, int l,
+                                             cplx<R>* base, int64_t s_k, int x0, int ncols) {
+  using M = mfma<R>;
+  using acc_t = typename M::acc;
+  const R* fj[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) fj[j] = ft + (int64_t)(w + YM_WAVES * j) * KS * 64 + l;
+  R acur[4][NT], anx[4][NT];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acur[s][j] = fj[j][s * 64];
+  acc_t c[NT][2];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) c[j][0] = c[j][1] = acc_t{0, 0, 0, 0};
+  const int ngroups = KS / 4;
+  for (int g = 0; g < ngroups; ++g) {
+    const int gn = g + 1 < ngroups ? g + 1 : g;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) anx[s][j] = fj[j][(gn * 4 + s) * 64];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = (g * 4 + s) * 4 + (l >> 4);
+      const R b0 = Bs[k * (2 * YM_NC) + (l & 15)];
+      const R b1 = Bs[k * (2 * YM_NC) + 16 + (l & 15)];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        c[j][0] = M::mma(acur[s][j], b0, c[j][0]);
+        c[j][1] = M::mma(acur[s][j], b1, c[j][1]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int j = 0; j < NT; ++j) acur[s][j] = anx[s][j];
+  }
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = h * 16 + (l & 15);   // (column, component) index
+      const int x = x0 + (col >> 1);
+      if (x >= ncols) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int o = (w + YM_WAVES * j) * 16 + M::row(l, e);
+        if (o < n) {
+          R* out = reinterpret_cast<R*>(base + (int64_t)o * s_k + x);
+          out[col & 1] = c[j][h][e];
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int TPW>
+__global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma_real(const XformYDesc* __restrict__ descs,
+                                                                 const cplx<R>* __restrict__ tab,
+                                                                 cplx<R>* __restrict__ ws) {
+  extern __shared__ unsigned char smem_raw[];
+  R* Bs = reinterpret_cast<R*>(smem_raw);   // [KS*4][2*YM_NC]: row k = element k of 16 complex columns
+  const XformYDesc d = descs[blockIdx.y];
+  const int r = blockIdx.z;
+  const int cblocks = (d.ncols + YM_NC - 1) / YM_NC;
+  const int p = blockIdx.x / cblocks, cb = blockIdx.x % cblocks;
+  if (p >= d.P) return;
+  const int n = d.n;
+  const int KS = ((n + 15) / 16) * 4;
+  const int MT = (n + 15) / 16;
+  const R* ft = reinterpret_cast<const R*>(tab + d.ftab);
+  cplx<R>* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
+  const int x0 = cb * YM_NC;
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int e = tid; e < KS * 4 * YM_NC; e += YM_THREADS) {
+    const int i = e / YM_NC, col = e % YM_NC;
+    const int x = x0 + col;
+    cplx<R> v = mk<R>(0, 0);
+    if (i < n && x < d.ncols) v = base[(int64_t)i * d.s_k + x];
+    Bs[i * (2 * YM_NC) + 2 * col] = v.x;
+    Bs[i * (2 * YM_NC) + 2 * col + 1] = v.y;
+  }
+  __syncthreads();
+  const int ntw = MT > w ? (MT - w + YM_WAVES - 1) / YM_WAVES : 0;
+  switch (ntw < TPW ? ntw : TPW) {
+    case 0: break;
+#define HS_YCASE(N) \
+    case N: if constexpr (N <= TPW) y_tiles_real<R, N>(ft, Bs, KS, n, w, l, base, d.s_k, x0, d.ncols); break;
+    HS_YCASE(1) HS_YCASE(2) HS_YCASE(3) HS_YCASE(4)
+#undef HS_YCASE
+    default: break;
+  }
+}
+
 // ------------------------------------------------------------------ small line sets
 // Few or short lines (interface and face lines, narrow PML blocks): complex
 // FMA on 16 x 16 output tiles, K staged through LDS; more workgroups than the
@@ -373,6 +613,21 @@ __global__ __launch_bounds__(256) void k_xform_lines_small(const XformDesc* __re
 }  // namespace
 
 // ------------------------------------------------------------------ host side
+int64_t mfma_rtable_reals(int n_out, int n_in) {
+  return int64_t((n_out + 15) / 16) * 16 * (((n_in + 15) / 16) * 16);
+}
+
+void mfma_rtable_build(const std::complex<double>* T, int n_out, int n_in, double* out) {
+  const int MT = (n_out + 15) / 16;
+  const int KS = ((n_in + 15) / 16) * 4;
+  for (int mt = 0; mt < MT; ++mt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int m = mt * 16 + (l % 16), k = ks * 4 + (l / 16);
+        out[((size_t)mt * KS + ks) * 64 + l] = (m < n_out && k < n_in) ? T[(size_t)m * n_in + k].real() : 0.0;
+      }
+}
+
 int64_t mfma_table_reals(int n_out, int n_in) {
   const int64_t rows = ((2 * n_out + 15) / 16) * 16;
   const int64_t cols = ((2 * n_in + 15) / 16) * 16;
@@ -402,14 +657,20 @@ bool xform_lines_use_mfma(const XformDesc& d) {
   return std::max(d.n_in, d.n_out) >= 24 && (int64_t)d.P * d.Q >= 1024;
 }
 
-LinesLaunch xform_lines_launch(const XformDesc* d, int ndesc, bool mfma) {
+LinesLaunch xform_lines_launch(const XformDesc* d, int ndesc, bool mfma, bool real) {
   LinesLaunch L;
   L.mfma = mfma;
+  L.real = real;
   int64_t m = 0;
   for (int i = 0; i < ndesc; ++i) {
     const int64_t lines = (int64_t)d[i].P * d[i].Q;
-    const int64_t t = mfma ? ((lines + XM_BM - 1) / XM_BM) * ((2 * d[i].n_out + XM_BN - 1) / XM_BN)
-                           : ((lines + XL_T - 1) / XL_T) * ((d[i].n_out + XL_T - 1) / XL_T);
+    int64_t t;
+    if (mfma && real)
+      t = ((lines + XM_BM / 2 - 1) / (XM_BM / 2)) * ((d[i].n_out + XM_BN - 1) / XM_BN);
+    else if (mfma)
+      t = ((lines + XM_BM - 1) / XM_BM) * ((2 * d[i].n_out + XM_BN - 1) / XM_BN);
+    else
+      t = ((lines + XL_T - 1) / XL_T) * ((d[i].n_out + XL_T - 1) / XL_T);
     m = std::max(m, t);
   }
   L.tiles = int(m);
@@ -420,7 +681,10 @@ template <typename R, typename CI, typename CO, bool ACC>
 static void launch_lines(const XformDesc* d, int ndesc, const LinesLaunch& L, const void* tab, const void* src,
                          void* dst, int nrhs, hipStream_t st) {
   const dim3 grid(L.tiles, ndesc, nrhs);
-  if (L.mfma)
+  if (L.mfma && L.real)
+    hipLaunchKernelGGL((k_xform_lines_mfma_real<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
+                       (const CI*)src, (CO*)dst);
+  else if (L.mfma)
     hipLaunchKernelGGL((k_xform_lines_mfma<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
                        (const CI*)src, (CO*)dst);
   else
@@ -458,8 +722,20 @@ bool xform_y_use_mfma(int prec, int n) { return n >= 32 && n <= (prec == 0 ? 256
 int xform_y_mfma_tiles(const XformYDesc& d) { return ((d.ncols + YM_NC - 1) / YM_NC) * d.P; }
 
 void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles, const void* tab, void* ws,
-                  int nrhs, hipStream_t st) {
+                  int nrhs, hipStream_t st, bool real) {
   if (ndesc == 0 || nrhs == 0 || max_tiles == 0) return;
+  if (real) {
+    // rows of n reals x 32 real columns; at most 4 row tiles per wave
+    const size_t rows = size_t((max_n + 15) / 16) * 16;
+    const dim3 grid(max_tiles, ndesc, nrhs);
+    if (prec == 0)
+      hipLaunchKernelGGL((k_xform_y_mfma_real<double, 4>), grid, dim3(YM_THREADS), rows * 2 * YM_NC * sizeof(double),
+                         st, d, (const double2*)tab, (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_xform_y_mfma_real<float, 4>), grid, dim3(YM_THREADS), rows * 2 * YM_NC * sizeof(float),
+                         st, d, (const float2*)tab, (float2*)ws);
+    return;
+  }
   // output tiles per wave: ceil(2 max_n / 16 / 8) <= 4 (n <= 256) or 8 (n <= 512)
   const size_t rows = size_t((2 * max_n + 15) / 16) * 16;
   const dim3 grid(max_tiles, ndesc, nrhs);
@@ -478,49 +754,54 @@ void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_t
   }
 }
 
+// group of a descriptor: 0 matrix cores with a real table, 1 matrix cores
+// with an embedded table, 2 complex FMA tiles
+static int lines_group(const XformDesc& d) { return xform_lines_use_mfma(d) ? (d.real_tab ? 0 : 1) : 2; }
+static int y_group(int prec, const XformYDesc& d) { return xform_y_use_mfma(prec, d.n) ? (d.real_tab ? 0 : 1) : 2; }
+
 int partition_lines(std::vector<XformDesc>& v) {
-  auto it = std::stable_partition(v.begin(), v.end(), [](const XformDesc& d) { return xform_lines_use_mfma(d); });
-  return int(it - v.begin());
+  std::stable_sort(v.begin(), v.end(),
+                   [](const XformDesc& a, const XformDesc& b) { return lines_group(a) < lines_group(b); });
+  return int(std::count_if(v.begin(), v.end(), [](const XformDesc& d) { return lines_group(d) < 2; }));
 }
 
 int partition_y(int prec, std::vector<XformYDesc>& v) {
-  auto it = std::stable_partition(v.begin(), v.end(), [prec](const XformYDesc& d) { return xform_y_use_mfma(prec, d.n); });
-  return int(it - v.begin());
+  std::stable_sort(v.begin(), v.end(),
+                   [prec](const XformYDesc& a, const XformYDesc& b) { return y_group(prec, a) < y_group(prec, b); });
+  return int(std::count_if(v.begin(), v.end(), [prec](const XformYDesc& d) { return y_group(prec, d) < 2; }));
 }
 
 void run_lines_list(int prec, int in64, int out64, int acc, const XformDesc* dev, const std::vector<XformDesc>& host,
                     const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
   const int n = int(host.size());
-  int nm = 0;
-  while (nm < n && xform_lines_use_mfma(host[nm])) ++nm;
-  if (nm > 0)
-    xform_lines(prec, in64, out64, acc, dev, nm, xform_lines_launch(host.data(), nm, true), tab, src, dst, nrhs, st);
-  if (nm < n)
-    xform_lines(prec, in64, out64, acc, dev + nm, n - nm, xform_lines_launch(host.data() + nm, n - nm, false), tab,
+  for (int b = 0; b < n;) {
+    const int g = lines_group(host[b]);
+    int e = b;
+    while (e < n && lines_group(host[e]) == g) ++e;
+    xform_lines(prec, in64, out64, acc, dev + b, e - b, xform_lines_launch(host.data() + b, e - b, g < 2, g == 0), tab,
                 src, dst, nrhs, st);
+    b = e;
+  }
 }
 
 void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab, void* ws,
                 int nrhs, hipStream_t st) {
   const int n = int(host.size());
-  int nm = 0;
-  while (nm < n && xform_y_use_mfma(prec, host[nm].n)) ++nm;
-  auto extent = [&](int b, int e, int& max_n, int& t16, int& t8) {
-    max_n = t16 = t8 = 0;
-    for (int i = b; i < e; ++i) {
-      max_n = std::max(max_n, host[i].n);
-      t16 = std::max(t16, xform_y_tiles(host[i], 16));
-      t8 = std::max(t8, xform_y_tiles(host[i], 8));
+  for (int b = 0; b < n;) {
+    const int g = y_group(prec, host[b]);
+    int e = b;
+    int max_n = 0, t16 = 0, t8 = 0;
+    while (e < n && y_group(prec, host[e]) == g) {
+      max_n = std::max(max_n, host[e].n);
+      t16 = std::max(t16, xform_y_tiles(host[e], 16));
+      t8 = std::max(t8, xform_y_tiles(host[e], 8));
+      ++e;
     }
-  };
-  int max_n, t16, t8;
-  if (nm > 0) {
-    extent(0, nm, max_n, t16, t8);
-    xform_y_mfma(prec, dev, nm, max_n, t16, tab, ws, nrhs, st);   // 16-column tiles
-  }
-  if (nm < n) {
-    extent(nm, n, max_n, t16, t8);
-    xform_y(prec, dev + nm, n - nm, max_n, t16, t8, tab, ws, nrhs, st);
+    if (g < 2)
+      xform_y_mfma(prec, dev + b, e - b, max_n, t16, tab, ws, nrhs, st, g == 0);   // 16-column tiles
+    else
+      xform_y(prec, dev + b, e - b, max_n, t16, t8, tab, ws, nrhs, st);
+    b = e;
   }
 }
 

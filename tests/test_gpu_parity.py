@@ -293,3 +293,33 @@ def test_mixed_precision_decomposed(hs):
     plan = hs.Plan(p, "mixed")
     u = plan.solve(dev(f)).cpu().numpy()
     assert per_rhs_err(u, separable.solve(p, f)) < TOL64R
+
+
+# ------------------------------------------------------------------ matrix-core transforms
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec,tol", [("c128", TOL128), ("mixed", TOL64R)])
+@pytest.mark.parametrize("cfg", [
+    # uniform, n + 1 not a power of two: real sine table on matrix cores (x lines >= 1024)
+    dict(nx=70, ny=50, nz=40, pml_x=0, pml_y=0),
+    # stretched ends: embedded complex table on matrix cores, both axes
+    dict(nx=66, ny=45, nz=36, pml_x=8, pml_y=5),
+    # mixed: real table along x, complex along y; y panel wider than 16 columns
+    dict(nx=100, ny=40, nz=33, pml_x=0, pml_y=6),
+    # narrow block: complex FMA tiles along x, matrix cores along y
+    dict(nx=20, ny=64, nz=70, pml_x=3, pml_y=0),
+])
+def test_dense_transform_kernels_vs_oracle(hs, prec, tol, cfg):
+    """Each dense-transform kernel family (real table, embedded complex table,
+    small-tile fallback) against the oracle, alone and inside a batch."""
+    import torch
+    rng = np.random.default_rng(31)
+    p = W.random_problem(cfg["nx"], cfg["ny"], cfg["nz"], 3, rng, pml_x=cfg["pml_x"], pml_y=cfg["pml_y"])
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, prec, max_rhs=2)
+    u = plan.solve(dev(f)).cpu().numpy()
+    ref = separable.solve(p, f)
+    assert per_rhs_err(u, ref) < tol
+    batch = hs.Batch([plan], [2])
+    ub = batch.solve([dev(f)])[0]
+    torch.cuda.synchronize()
+    assert np.array_equal(ub.cpu().numpy(), u)
