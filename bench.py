@@ -81,6 +81,107 @@ def roofline(stages, prec):
             "bytes_per_launch": top["bytes_per_launch"], "flops_per_launch": top["flops_per_launch"]}
 
 
+# ---------------------------------------------------------------- counter runs
+# HBM traffic of the stage kernels comes from two rocprofv3 --pmc runs of
+# `bench.py --counters` (FETCH_SIZE, then WRITE_SIZE) and two of
+# `bench.py --copy` (a plain 1 GiB copy: the same counters' reading for known
+# bytes gives the scale factors); `bench.py --traffic-summary F W CF CW` turns
+# the four output folders into profiles/pmc_traffic.json.
+COPY_BYTES = 1 << 30
+
+
+def copy_run():
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.ones(COPY_BYTES // 16, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
+
+
+def counters_run(args):
+    """Three solves of the decomposed workload (complex128, default tiling);
+    per solve the stage kernels are dispatched in a fixed order."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    torch.cuda.set_device(0)
+    p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
+    f = hs.to_device(f_np)
+    u = torch.empty_like(f)
+    plan = hs.Plan(p, "c128", max_rhs=1)
+    for _ in range(3):
+        plan.solve(f, out=u)
+    torch.cuda.synchronize()
+    info = plan.info()
+    mw = 256 // info["z_chunks"]
+    print(json.dumps({"solves": 3, "global_sweep_grid": -(-p.nx * p.ny // mw) * 256,
+                      "z_chunks": info["z_chunks"]}), flush=True)
+
+
+def _counter_rows(folder, counter):
+    import csv
+    import glob
+    out = []
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]),
+                                float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def _stage_labels(rows, global_grid):
+    """Label the z-solve dispatches: per solve the block sweep runs twice
+    (v before u) and the global sweep once; contractions: faces, then Σ."""
+    labels = []
+    nblk = ncon = 0
+    for _, name, grid, _ in rows:
+        if "k_psweep" in name:
+            if grid == global_grid:
+                labels.append("zsweep_global")
+            else:
+                labels.append("zsweep_blocks_v" if nblk % 2 == 0 else "zsweep_blocks_u")
+                nblk += 1
+        elif "k_contract<" in name:
+            labels.append("face_contract" if ncon % 2 == 0 else "sigma_contract")
+            ncon += 1
+        else:
+            labels.append(None)
+    return labels
+
+
+def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
+    scale = {}
+    for key, folder, counter in (("fetch", cfdir, "FETCH_SIZE"), ("write", cwdir, "WRITE_SIZE")):
+        rows = [r for r in _counter_rows(folder, counter) if "copy" in r[1].lower() or "elementwise" in r[1]]
+        kib = max(r[3] for r in rows)
+        scale[key] = COPY_BYTES / (kib * 1024.0)
+    stages = {}
+    for key, folder, counter in (("fetch", fdir, "FETCH_SIZE"), ("write", wdir, "WRITE_SIZE")):
+        rows = [r for r in _counter_rows(folder, counter) if "hs::" in r[1]]
+        for lab, r in zip(_stage_labels(rows, global_grid), rows):
+            if lab is None:
+                continue
+            rec = stages.setdefault(lab, {"fetch_kib": [], "write_kib": []})
+            rec[key + "_kib"].append(r[3])
+    out = {"source_hash": kernel_source_hash(), "copy_scale": scale, "stages": {}}
+    for lab, rec in stages.items():
+        fk = float(np.mean(rec["fetch_kib"])) if rec["fetch_kib"] else 0.0
+        wk = float(np.mean(rec["write_kib"])) if rec["write_kib"] else 0.0
+        out["stages"][lab] = {"fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+                              "bytes_per_launch": fk * 1024 * scale["fetch"] + wk * 1024 * scale["write"],
+                              "dispatches": len(rec["fetch_kib"])}
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def traffic_for(kernel_stage: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, only while the kernel sources are unchanged."""
@@ -189,13 +290,28 @@ def main():
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
     ap.add_argument("--c3-steps", type=int, default=5)
+    ap.add_argument("--copy", action="store_true", help="counter calibration: a plain 1 GiB copy")
+    ap.add_argument("--counters", action="store_true", help="three complex128 solves for counter runs")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
+                    help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
+    ap.add_argument("--global-grid", type=int, default=0, help="grid size of the global sweep (--counters prints it)")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.global_grid)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
               "(sharding by right-hand side and frequency needs no communication; "
               "see the design notes).", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy:
+        copy_run()
+        return
+    if args.counters:
+        counters_run(args)
+        return
 
     import torch
     import paper_1909_01299_amd as hs

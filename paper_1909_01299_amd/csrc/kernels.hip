@@ -13,6 +13,17 @@ namespace hs {
 
 namespace {
 
+// Streaming store of a complex value (written once, not re-read by this
+// kernel): marked non-temporal so that it does not displace reused lines.
+__device__ __forceinline__ void st_stream(double2* p, double2 v) {
+  typedef double v2d __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2d{v.x, v.y}, reinterpret_cast<v2d*>(p));
+}
+__device__ __forceinline__ void st_stream(float2* p, float2 v) {
+  typedef float v2f __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(v2f{v.x, v.y}, reinterpret_cast<v2f*>(p));
+}
+
 template <typename T> struct real_of;
 template <> struct real_of<double2> { using type = double; };
 template <> struct real_of<float2> { using type = float; };
@@ -574,7 +585,14 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
       CS* dst = ws + d.out + (int64_t)r * d.out_r + m + (int64_t)k0 * plane;
 #pragma unroll
       for (int kk = 0; kk < PS_LMAX; ++kk)
-        if (kk < Lc && k0 + kk < nz) dst[(int64_t)kk * plane] = cvt<CS>(rb[kk]);
+        if (kk < Lc && k0 + kk < nz) {
+          // complex128 block solves: the output streams past the reused
+          // low-rank lines (non-temporal stores measured faster there only)
+          if (sizeof(RS) == 8 && d.dense_in)
+            st_stream(dst + (int64_t)kk * plane, cvt<CS>(rb[kk]));
+          else
+            dst[(int64_t)kk * plane] = cvt<CS>(rb[kk]);
+        }
     }
   }
 }
