@@ -128,17 +128,22 @@ struct SweepDesc {
 // along both axes in one read, with up to kMaxTerms coefficient vectors each:
 //   out_x,t(r,z,b) = sum_a cx_t[a] X(r,z,b,a)   at dx + t*dx_t + r*dx_r + z*dx_z + b
 //   out_y,t(r,z,a) = sum_b cy_t[b] X(r,z,b,a)   at dy + t*dy_t + r*dy_r + z*dy_z + a
-// A z plane is split into nslab slabs of `rows` rows b; with nslab > 1 the
-// y sums of each slab go to part + r*part_r + s*part_s + t*part_t + z*part_z + a
+// A z plane is split into nslab slabs of `rows` rows b and ncs slabs of
+// `cols` columns a.  With nslab > 1 the y sums of each row slab go to
+//   part + r*part_r + s*part_s + t*part_t + z*part_z + a,
+// with ncs > 1 the x sums of each column slab go to
+//   xpart + r*xpart_r + c*xpart_s + t*xpart_t + z*xpart_z + b,
 // and a second pass adds the slabs in order.
 struct ContractDesc {
-  int32_t na, nb, nz, nxt, nyt, nslab, rows, pad;
+  int32_t na, nb, nz, nxt, nyt, nslab, rows, ncs;
+  int32_t cols, pad;
   int64_t src, src_r;
   int64_t cx[kMaxTerms], cy[kMaxTerms];   // table offsets
   int32_t cx_stride[kMaxTerms], cy_stride[kMaxTerms];
   int64_t dx, dx_t, dx_r, dx_z;
   int64_t dy, dy_t, dy_r, dy_z;
   int64_t part, part_s, part_t, part_r, part_z;
+  int64_t xpart, xpart_s, xpart_t, xpart_r, xpart_z;
 };
 
 }  // namespace hs

@@ -644,17 +644,19 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 // first butterfly steps exchange half of the rows each (transposed
 // reduction), so 4 rows cost 7 exchanges instead of 24 (2 rows: 6, not 12).
 template <typename R, int SMAX>
-__global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict__ descs, int max_slab,
+__global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict__ descs, int max_slab, int max_cs,
                                                   const cplx<R>* __restrict__ tab, cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
   constexpr int U = SMAX <= 2 ? 4 : 2;
   constexpr int SW = SMAX * 64;   // LDS stride of one x term
   extern __shared__ unsigned char smem_raw[];
   const ContractDesc d = descs[blockIdx.y];
-  const int z = blockIdx.x / max_slab, slab = blockIdx.x % max_slab;
-  if (z >= d.nz || slab >= d.nslab) return;
+  const int z = blockIdx.x / (max_slab * max_cs);
+  const int cs = (blockIdx.x / max_slab) % max_cs, slab = blockIdx.x % max_slab;
+  if (z >= d.nz || slab >= d.nslab || cs >= d.ncs) return;
   const int r = blockIdx.z;
-  const int na = d.na;
+  const int c0 = cs * d.cols;                      // first column of this column slab
+  const int na = min(d.na, c0 + d.cols) - c0;      // its columns
   int L = 1;
   while (L < na && L < 64) L <<= 1;
   const int G = 64 / L;
@@ -668,7 +670,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   for (int t = 0; t < kMaxTerms; ++t) {
     if (t < d.nxt)
       for (int i = threadIdx.x; i < SW; i += 256)
-        cxs[t * SW + i] = i < na ? tab[d.cx[t] + (int64_t)i * d.cx_stride[t]] : mk<R>(0, 0);
+        cxs[t * SW + i] = i < na ? tab[d.cx[t] + (int64_t)(c0 + i) * d.cx_stride[t]] : mk<R>(0, 0);
     if (t < d.nyt)
       for (int i = threadIdx.x; i < nrow; i += 256) cys[t * d.rows + i] = tab[d.cy[t] + (int64_t)(b0 + i) * d.cy_stride[t]];
   }
@@ -679,17 +681,23 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   for (int s = 0; s < SMAX; ++s)
 #pragma unroll
     for (int t = 0; t < kMaxTerms; ++t) yacc[s][t] = mk<R>(0, 0);
-  const C* xp = ws + d.src + (int64_t)r * d.src_r + ((int64_t)z * d.nb + b0) * na;
+  const C* xp = ws + d.src + (int64_t)r * d.src_r + ((int64_t)z * d.nb + b0) * d.na + c0;
   int col[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) col[s] = min(la + s * L, na - 1);
   const bool full = L == 64;
   const bool hi5 = (lane & 32) != 0, hi4 = (lane & 16) != 0;
+  // x sums of this column slab: final, or a partial added by the second pass
+  auto xout = [&](int t) -> int64_t {
+    return d.ncs > 1 ? d.xpart + (int64_t)r * d.xpart_r + (int64_t)cs * d.xpart_s + t * d.xpart_t +
+                           (int64_t)z * d.xpart_z
+                     : d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z;
+  };
   for (int i0 = rg; i0 < nrow; i0 += U * RG) {
     C xv[U][SMAX];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * na;
+      const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * d.na;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) xv[u][s] = xp[row + col[s]];
     }
@@ -733,8 +741,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
           for (int m = 8; m >= 1; m >>= 1) v = cadd(v, shfl_xor_c(v, m, 64));
           const int bi = i0 + ur * RG;
           const bool wr = U == 4 ? (lane & 15) == 0 : (lane & 31) == 0;
-          if (wr && bi < nrow)
-            ws[d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z + b0 + bi] = v;
+          if (wr && bi < nrow) ws[xout(t) + b0 + bi] = v;
         } else {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
@@ -745,7 +752,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
               if (m < L) v = cadd(v, o);
             }
             const int bi = i0 + u * RG;
-            if (la == 0 && bi < nrow) ws[d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z + b0 + bi] = v;
+            if (la == 0 && bi < nrow) ws[xout(t) + b0 + bi] = v;
           }
         }
       }
@@ -772,8 +779,9 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
         for (int t = 0; t < kMaxTerms; ++t)
           if (t < d.nyt) yb[((w - 1) * kMaxTerms + t) * 64 + lane] = yacc[s][t];
       __syncthreads();
-      const int a = la + s * L;
-      if (w == 0 && lane < L && a < na) {
+      const int al = la + s * L;
+      const int a = c0 + al;
+      if (w == 0 && lane < L && al < na) {
 #pragma unroll
         for (int t = 0; t < kMaxTerms; ++t) {
           if (t < d.nyt) {
@@ -792,22 +800,36 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   }
 }
 
-// Slab sums of the y contractions of split planes, added in slab order.
+// Slab sums of split planes, added in slab order: y sums over row slabs
+// (elements [0, nyt*nz*na)), then x sums over column slabs (the next
+// nxt*nz*nb elements).
 template <typename R>
 __global__ __launch_bounds__(256) void k_contract_fin(const ContractDesc* __restrict__ descs,
                                                       cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
   const ContractDesc d = descs[blockIdx.y];
-  if (d.nslab <= 1) return;
   const int r = blockIdx.z;
-  const int64_t per_t = (int64_t)d.nz * d.na;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= d.nyt * per_t) return;
-  const int t = int(e / per_t), z = int((e % per_t) / d.na), a = int(e % d.na);
-  const C* p = ws + d.part + (int64_t)r * d.part_r + t * d.part_t + (int64_t)z * d.part_z + a;
-  C v = p[0];
-  for (int s = 1; s < d.nslab; ++s) v = cadd(v, p[(int64_t)s * d.part_s]);
-  ws[d.dy + t * d.dy_t + (int64_t)r * d.dy_r + (int64_t)z * d.dy_z + a] = v;
+  const int64_t ny_el = d.nslab > 1 ? (int64_t)d.nyt * d.nz * d.na : 0;
+  const int64_t nx_el = d.ncs > 1 ? (int64_t)d.nxt * d.nz * d.nb : 0;
+  int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < ny_el) {
+    const int64_t per_t = (int64_t)d.nz * d.na;
+    const int t = int(e / per_t), z = int((e % per_t) / d.na), a = int(e % d.na);
+    const C* p = ws + d.part + (int64_t)r * d.part_r + t * d.part_t + (int64_t)z * d.part_z + a;
+    C v = p[0];
+    for (int s = 1; s < d.nslab; ++s) v = cadd(v, p[(int64_t)s * d.part_s]);
+    ws[d.dy + t * d.dy_t + (int64_t)r * d.dy_r + (int64_t)z * d.dy_z + a] = v;
+    return;
+  }
+  e -= ny_el;
+  if (e < nx_el) {
+    const int64_t per_t = (int64_t)d.nz * d.nb;
+    const int t = int(e / per_t), z = int((e % per_t) / d.nb), b = int(e % d.nb);
+    const C* p = ws + d.xpart + (int64_t)r * d.xpart_r + t * d.xpart_t + (int64_t)z * d.xpart_z + b;
+    C v = p[0];
+    for (int c = 1; c < d.ncs; ++c) v = cadd(v, p[(int64_t)c * d.xpart_s]);
+    ws[d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z + b] = v;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,9 +1187,12 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 }
 
 void contract_split(ContractDesc& d) {
-  // about 16K elements per workgroup: whole planes for blocks, row slabs for
-  // the global plane so that there are enough workgroups to fill the chip
-  const int64_t elems = (int64_t)d.na * d.nb;
+  // at most 512 columns per workgroup (8 per lane); about 16K elements per
+  // workgroup: whole planes for blocks, row slabs for the global plane so
+  // that there are enough workgroups to fill the chip
+  d.ncs = (d.na + 511) / 512;
+  d.cols = (d.na + d.ncs - 1) / d.ncs;
+  const int64_t elems = (int64_t)d.cols * d.nb;
   int nslab = int(std::max<int64_t>(1, std::min<int64_t>(d.nb, (elems + 16383) / 16384)));
   d.rows = (d.nb + nslab - 1) / nslab;
   d.nslab = d.rows > 0 ? (d.nb + d.rows - 1) / d.rows : 1;
@@ -1184,12 +1209,15 @@ ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec) {
   L.ndesc = ndesc;
   size_t lds_elems = 0, lds_x = 0;
   for (int i = 0; i < ndesc; ++i) {
-    const int ln = contract_lanes(d[i].na);
-    const int S = (d[i].na + ln - 1) / ln;
+    const int ln = contract_lanes(d[i].cols);
+    const int S = (d[i].cols + ln - 1) / ln;
     L.max_slab = std::max(L.max_slab, d[i].nslab);
+    L.max_cs = std::max(L.max_cs, d[i].ncs);
     L.smax = std::max(L.smax, S);
     L.max_nz = std::max(L.max_nz, d[i].nz);
-    if (d[i].nslab > 1) L.fin_units = std::max<int64_t>(L.fin_units, (int64_t)d[i].nyt * d[i].nz * d[i].na);
+    const int64_t fin = (d[i].nslab > 1 ? (int64_t)d[i].nyt * d[i].nz * d[i].na : 0) +
+                        (d[i].ncs > 1 ? (int64_t)d[i].nxt * d[i].nz * d[i].nb : 0);
+    L.fin_units = std::max<int64_t>(L.fin_units, fin);
     lds_elems = std::max<size_t>(lds_elems, size_t(d[i].nyt) * d[i].rows + 3 * kMaxTerms * 64);
     lds_x = std::max<size_t>(lds_x, size_t(d[i].nxt));
   }
@@ -1202,8 +1230,9 @@ template <typename R, int SMAX>
 static void launch_contract(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
                             hipStream_t st) {
   using C = cplx<R>;
-  const dim3 grid(unsigned(L.max_nz * L.max_slab), unsigned(L.ndesc), unsigned(nrhs));
-  hipLaunchKernelGGL((k_contract<R, SMAX>), grid, dim3(256), L.lds, st, d, L.max_slab, (const C*)tab, (C*)ws);
+  const dim3 grid(unsigned(L.max_nz * L.max_slab * L.max_cs), unsigned(L.ndesc), unsigned(nrhs));
+  hipLaunchKernelGGL((k_contract<R, SMAX>), grid, dim3(256), L.lds, st, d, L.max_slab, L.max_cs, (const C*)tab,
+                     (C*)ws);
   if (L.fin_units > 0)
     hipLaunchKernelGGL((k_contract_fin<R>), dim3(unsigned((L.fin_units + 255) / 256), L.ndesc, nrhs), dim3(256), 0,
                        st, d, (C*)ws);

@@ -110,8 +110,8 @@ bool sweep_chunks_ok(int chunks, int nz);
 // contract_split chooses the row slabs of a descriptor (nslab, rows) from its
 // plane size; contract_launch gathers the launch shape of a descriptor list.
 struct ContractLaunch {
-  int ndesc = 0, max_slab = 1, smax = 1, max_nz = 0;
-  int64_t fin_units = 0;   // largest nyt * nz * na over split descriptors (0: none split)
+  int ndesc = 0, max_slab = 1, max_cs = 1, smax = 1, max_nz = 0;
+  int64_t fin_units = 0;   // largest count of slab sums of a split descriptor (0: none split)
   size_t lds = 0;          // dynamic LDS bytes
 };
 void contract_split(ContractDesc& d);

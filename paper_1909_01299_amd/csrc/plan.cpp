@@ -380,14 +380,15 @@ void Plan::layout_workspace() {
   if (decomposed) {
     for (auto& B : blocks) B.vt = take(R * NZ * B.nbx * B.nby);
     // slab partial sums of contractions over planes too large for one workgroup
-    auto part_elems = [&](int na, int nb, int nyt) -> int64_t {
+    auto part_elems = [&](int na, int nb, int nxt, int nyt) -> int64_t {
       ContractDesc c{};
       c.na = na; c.nb = nb;
       contract_split(c);
-      return c.nslab > 1 ? R * c.nslab * nyt * NZ * (int64_t)na : 0;
+      return (c.nslab > 1 ? R * c.nslab * nyt * NZ * (int64_t)na : 0) +
+             (c.ncs > 1 ? R * c.ncs * nxt * NZ * (int64_t)nb : 0);
     };
     for (auto& B : blocks) {
-      const int64_t n = part_elems(B.nbx, B.nby, 2);
+      const int64_t n = part_elems(B.nbx, B.nby, 2, 2);
       B.cpart = n > 0 ? take(n) : 0;
     }
     const int64_t faces = (int64_t)blocks.size() * R * 4 * NZ * NF;
@@ -400,7 +401,7 @@ void Plan::layout_workspace() {
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
     w_gspec = take(R * NZ * (int64_t)NX * NY);
-    const int64_t np = part_elems(NX, NY, nsy);
+    const int64_t np = part_elems(NX, NY, nsx, nsy);
     w_cpart = np > 0 ? take(np) : 0;
   }
   ws_elems = size_t(off);
@@ -422,13 +423,20 @@ void Plan::build_descriptors() {
   d_sweep.clear();
   d_sweepB.clear(); d_sweepC.clear(); d_sweepG.clear();
   d_face.clear(); d_sig.clear();
-  // slab partials of a split contraction: [r][slab][t][z][a]
-  auto set_part = [](ContractDesc& c, int64_t off) {
+  // slab partials of a split contraction: y sums [r][row slab][t][z][a], then
+  // x sums [r][column slab][t][z][b]
+  auto set_part = [&](ContractDesc& c, int64_t off) {
     c.part = off;
     c.part_z = c.na;
     c.part_t = (int64_t)c.nz * c.na;
     c.part_s = c.nyt * c.part_t;
     c.part_r = c.nslab * c.part_s;
+    const int64_t ysize = c.nslab > 1 ? (int64_t)max_rhs * c.part_r : 0;
+    c.xpart = off + ysize;
+    c.xpart_z = c.nb;
+    c.xpart_t = (int64_t)c.nz * c.nb;
+    c.xpart_s = c.nxt * c.xpart_t;
+    c.xpart_r = c.ncs * c.xpart_s;
   };
   d_vface.clear(); d_gface.clear(); d_glob_in.clear(); d_glob_out.clear(); d_lift.clear();
   const int64_t gplane = (int64_t)NX * NY;

@@ -158,6 +158,22 @@ DECOMP = [
 ]
 
 
+@pytest.mark.parametrize("prec,tol", [("c128", TOL128), ("mixed", TOL64R)])
+@pytest.mark.parametrize("cfg", [
+    dict(nx=600, ny=24, nz=9, sx=[100, 350], sy=[11], pml=6),   # global x axis > 512 columns
+    dict(nx=30, ny=530, nz=7, sx=[14], sy=[200, 400], pml=4),    # global y axis > 512 rows
+])
+def test_decomposed_wide_global_axis_vs_oracle(hs, prec, tol, cfg):
+    """Global axes longer than one contraction workgroup's 512 columns (the
+    plane is split into column slabs whose sums are added afterwards)."""
+    rng = np.random.default_rng(41)
+    p = W.random_problem(cfg["nx"], cfg["ny"], cfg["nz"], 3, rng, sep_x=cfg["sx"], sep_y=cfg["sy"],
+                         pml_x=cfg["pml"], pml_y=cfg["pml"])
+    f = W.complex_normal(rng, (1,) + p.shape)
+    u = hs.Plan(p, prec).solve(dev(f)).cpu().numpy()
+    assert per_rhs_err(u, separable.solve(p, f)) < tol
+
+
 @pytest.mark.parametrize("cfg", DECOMP)
 def test_decomposed_vs_sparse_lu(hs, cfg):
     rng = np.random.default_rng(cfg["nx"] + cfg["ny"])
