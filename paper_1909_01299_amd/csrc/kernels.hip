@@ -137,7 +137,11 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   constexpr int N = L / 2;
   constexpr int n = N - 1;
   constexpr int XS = 17 * V + 1;   // LDS row of one line: 17 slots per 16 values, odd pad
-  __shared__ R xbuf[LT * XS];      // real and imaginary parts exchanged in turn
+  // complex exchange in one pass where it fits in 64 KB (the register array
+  // of the first stage dies before the second is filled); otherwise real and
+  // imaginary parts are exchanged in turn
+  constexpr bool CX = size_t(LT) * XS * 2 * sizeof(R) <= 65536;
+  __shared__ R xbuf[CX ? 2 * LT * XS : LT * XS];
   const DstDesc d = descs[blockIdx.y];
   const int lines = d.P * d.Q;
   const int l0 = blockIdx.x * LT;
@@ -174,9 +178,24 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   fft_reg<C, V>(a, tw);
 #pragma unroll
   for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % L) * (TW_N / L)]);
-  R* wrow = xbuf + li * XS;
   constexpr int G = V >= 16 ? V / 16 : 1;
   C b[G][16];
+  if constexpr (CX) {
+    C* crow = reinterpret_cast<C*>(xbuf) + li * XS;
+#pragma unroll
+    for (int k2 = 0; k2 < V; ++k2) crow[k2 * 17 + t] = a[k2];
+    __syncthreads();
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+      const int k2 = t + 16 * gg;
+      if (k2 < V) {
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) b[gg][tt] = crow[k2 * 17 + tt];
+        fft_reg<C, 16>(b[gg], tw);
+      }
+    }
+  } else {
+  R* wrow = xbuf + li * XS;
 #pragma unroll
   for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2].x;
   __syncthreads();
@@ -200,6 +219,7 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
       for (int tt = 0; tt < 16; ++tt) b[gg][tt].y = wrow[k2 * 17 + tt];
       fft_reg<C, 16>(b[gg], tw);
     }
+  }
   }
   if (!ok) return;
   const R sc = R(0.5) * R(sqrt(2.0 / double(N)));
@@ -964,31 +984,32 @@ template <typename CO>
 __global__ __launch_bounds__(256) void k_residual(StencilGeom g, const double2* __restrict__ f,
                                                   const double2* __restrict__ u, CO* __restrict__ out,
                                                   int negate_f) {
-  const int r = blockIdx.z;
-  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  const int x = int(e % g.nx);
-  const int y = int((e / g.nx) % g.ny);
-  const int z = int(e / ((int64_t)g.nx * g.ny));
-  const double2* ur = u + r * n;
+  // one workgroup per (y, z) row of one right-hand side, lanes along x
+  const int y = blockIdx.x, z = blockIdx.y, r = blockIdx.z;
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const double2 c = ur[e];
-  double2 au = cmul(cadd(cadd(g.xd[x], g.yd[y]), g.zd[z]), c);
-  if (x > 0) au = cfma(g.xl[x], ur[e - 1], au);
-  if (x + 1 < g.nx) au = cfma(g.xu[x], ur[e + 1], au);
-  if (y > 0) au = cfma(g.yl[y], ur[e - sy], au);
-  if (y + 1 < g.ny) au = cfma(g.yu[y], ur[e + sy], au);
-  if (z > 0) au = cfma(g.zl[z], ur[e - sz], au);
-  if (z + 1 < g.nz) au = cfma(g.zu[z], ur[e + sz], au);
-  double2 res;
-  if (negate_f) {  // out = A u
-    res = au;
-  } else {
-    const double2 fv = f[r * n + e];
-    res = csub(fv, au);
+  const int64_t n = sz * g.nz;
+  const int64_t row = (int64_t)r * n + (int64_t)z * sz + (int64_t)y * sy;
+  const double2* ur = u + row;
+  const double2 dyz = cadd(g.yd[y], g.zd[z]);
+  const double2 cyl = g.yl[y], cyu = g.yu[y], czl = g.zl[z], czu = g.zu[z];
+  const bool hy0 = y > 0, hy1 = y + 1 < g.ny, hz0 = z > 0, hz1 = z + 1 < g.nz;
+  for (int x = threadIdx.x; x < g.nx; x += 256) {
+    const double2 c = ur[x];
+    double2 au = cmul(cadd(g.xd[x], dyz), c);
+    if (x > 0) au = cfma(g.xl[x], ur[x - 1], au);
+    if (x + 1 < g.nx) au = cfma(g.xu[x], ur[x + 1], au);
+    if (hy0) au = cfma(cyl, ur[x - sy], au);
+    if (hy1) au = cfma(cyu, ur[x + sy], au);
+    if (hz0) au = cfma(czl, ur[x - sz], au);
+    if (hz1) au = cfma(czu, ur[x + sz], au);
+    double2 res;
+    if (negate_f) {  // out = A u
+      res = au;
+    } else {
+      res = csub(f[row + x], au);
+    }
+    out[row + x] = cvt<CO>(res);
   }
-  out[r * n + e] = cvt<CO>(res);
 }
 
 // Adjoint pre/post scaling with the mass matrix M = Mx (x) My (x) Mz of eq. (3):
@@ -1306,10 +1327,10 @@ void residual(const StencilGeom& g, const void* f, const void* u, void* out, int
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   if (n == 0 || nrhs == 0) return;
   if (out64)
-    hipLaunchKernelGGL((k_residual<double2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+    hipLaunchKernelGGL((k_residual<double2>), dim3(g.ny, g.nz, nrhs), dim3(256), 0, st, g,
                        (const double2*)f, (const double2*)u, (double2*)out, apply_only);
   else
-    hipLaunchKernelGGL((k_residual<float2>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g,
+    hipLaunchKernelGGL((k_residual<float2>), dim3(g.ny, g.nz, nrhs), dim3(256), 0, st, g,
                        (const double2*)f, (const double2*)u, (float2*)out, apply_only);
 }
 
