@@ -182,6 +182,30 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
     print(json.dumps(out), flush=True)
 
 
+def stats_summary(trace_csv: str, title: str, command: str):
+    """Text summary of a rocprofv3 kernel trace: per kernel and grid, the
+    number of dispatches, the average duration and the share of the total."""
+    import csv
+    import re
+    agg = {}
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].replace("hs::(anonymous namespace)::", "")
+            name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", name)
+            name = re.sub(r"\(hs::.*|\(.*", "", name).replace("void ", "")
+            grid = "x".join(r["Grid_Size_" + a] for a in "XYZ")
+            key = (name, grid)
+            a = agg.setdefault(key, [0, 0.0])
+            a[0] += 1
+            a[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    tot = sum(v[1] for v in agg.values())
+    print(f"# rocprofv3 kernel statistics: {title}")
+    print(f"# command (R = repository root): {command}")
+    print("# columns: dispatches, average us, share of kernel time %, kernel, grid (work-items x*y*z)")
+    for (name, grid), (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"{n:6d} {t / n:10.1f} {100 * t / tot:7.2f}  {name}  grid={grid}")
+
+
 def traffic_for(kernel_stage: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, only while the kernel sources are unchanged."""
@@ -225,7 +249,7 @@ def cpu_baseline(problem, f, repeat_budget_s=20.0):
                                          f"({t:.2f} s each; eigen tables {t_plan:.2f} s excluded)"}
 
 
-def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63)):
+def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c128", "mixed")):
     """Batched workload: 64 independent blocks of uneven sizes (half uniform,
     half with stretched complex ends), 8 right-hand sides each, every stage one
     batched launch in a captured graph; complex128 batch vs complex64 +
@@ -241,7 +265,7 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63)):
     out = {"workload": f"c3_batched 64 blocks (32 uniform, 32 stretched ends), n_x,n_y in [32,256], "
                        f"n_z in [64,256], {nrhs} RHS each",
            "unknowns": unknowns, "nrhs": nrhs}
-    for prec in ("c128", "mixed"):
+    for prec in precs:
         t0 = time.perf_counter()
         plans = [hs.Plan(b.problem, prec, max_rhs=1) for b in blocks]
         batch = hs.Batch(plans, [nrhs] * len(plans))
@@ -272,7 +296,8 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63)):
         out[prec] = rec
         del batch, plans
         torch.cuda.empty_cache()
-    out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    if "mixed" in out and "c128" in out:
+        out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
     return out
 
 
@@ -295,9 +320,15 @@ def main():
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--global-grid", type=int, default=0, help="grid size of the global sweep (--counters prints it)")
+    ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
+    ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
+                    help="print a text summary of a rocprofv3 kernel trace")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.global_grid)
+        return
+    if args.stats_summary:
+        stats_summary(*args.stats_summary)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -308,6 +339,10 @@ def main():
 
     if args.copy:
         copy_run()
+        return
+    if args.c3_only:
+        precs = ("c128", "mixed") if args.c3_only == "both" else (args.c3_only,)
+        print(json.dumps(bench_c3(args.c3_steps, 1, False, precs=precs)), flush=True)
         return
     if args.counters:
         counters_run(args)
