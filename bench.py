@@ -249,7 +249,7 @@ def cpu_baseline(problem, f, repeat_budget_s=20.0):
                                          f"({t:.2f} s each; eigen tables {t_plan:.2f} s excluded)"}
 
 
-def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c128", "mixed")):
+def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c128", "mixed"), refine_steps=1):
     """Batched workload: 64 independent blocks of uneven sizes (half uniform,
     half with stretched complex ends), 8 right-hand sides each, every stage one
     batched launch in a captured graph; complex128 batch vs complex64 +
@@ -267,7 +267,8 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
            "unknowns": unknowns, "nrhs": nrhs}
     for prec in precs:
         t0 = time.perf_counter()
-        plans = [hs.Plan(b.problem, prec, max_rhs=1) for b in blocks]
+        plans = [hs.Plan(b.problem, prec, max_rhs=1, refine_steps=refine_steps if prec == "mixed" else 0)
+                 for b in blocks]
         batch = hs.Batch(plans, [nrhs] * len(plans))
         t_plan = time.perf_counter() - t0
         for _ in range(warmup):
@@ -315,6 +316,8 @@ def main():
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
     ap.add_argument("--c3-steps", type=int, default=5)
+    ap.add_argument("--refine-steps", type=int, default=1,
+                    help="FP64-residual refinement steps of the mixed-precision solves (-1: none)")
     ap.add_argument("--copy", action="store_true", help="counter calibration: a plain 1 GiB copy")
     ap.add_argument("--counters", action="store_true", help="three complex128 solves for counter runs")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
@@ -342,7 +345,7 @@ def main():
         return
     if args.c3_only:
         precs = ("c128", "mixed") if args.c3_only == "both" else (args.c3_only,)
-        print(json.dumps(bench_c3(args.c3_steps, 1, False, precs=precs)), flush=True)
+        print(json.dumps(bench_c3(args.c3_steps, 1, False, precs=precs, refine_steps=args.refine_steps)), flush=True)
         return
     if args.counters:
         counters_run(args)
@@ -359,7 +362,7 @@ def main():
     u = torch.empty_like(f)
 
     if args.mixed_only:
-        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs)
+        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
         um = torch.empty_like(f)
         dtm, _ = time_solves(plan_m, f, um, args.steps, args.warmup, profile=False)
         print(json.dumps({"mixed_ms_per_step": dtm / args.steps * 1e3}), flush=True)
@@ -374,7 +377,7 @@ def main():
 
     mixed = None
     if not args.no_mixed:
-        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs)
+        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
         plan_m.tune(nrhs)
         um = torch.empty_like(f)
         dtm, stages_m = time_solves(plan_m, f, um, args.steps, args.warmup)
@@ -396,7 +399,7 @@ def main():
     if not args.no_c3:
         del plan
         torch.cuda.empty_cache()
-        c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline)
+        c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline, refine_steps=args.refine_steps)
 
     rf = roofline(stages, "c128")
     if rf is not None:

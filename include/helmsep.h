@@ -91,7 +91,8 @@ typedef struct {
 
 typedef struct {
   hs_precision prec;
-  int32_t refine_steps;   /* HS_C64_REFINE: correction steps (default 2 when <= 0) */
+  int32_t refine_steps;   /* HS_C64_REFINE: correction steps (default 2 when 0;
+                             a negative value: none, one complex64 pass)       */
   int32_t max_rhs;        /* largest nrhs a solve will be called with (>= 1)       */
   int32_t flags;          /* bit 0: force the dense transform on uniform axes;
                              bits 1-2: z-line chunks per mode (0 auto, 1: 8, 2: 16,
@@ -114,6 +115,9 @@ typedef struct {
                                FP64 with the workgroup that holds them        */
   int32_t z_chunks;         /* z-line chunks per mode in use (hs_plan_tune)   */
   int32_t sine_lines;       /* sine-transform lines per workgroup (0 = default) */
+  int32_t n_split_fp16;     /* HS_C64_REFINE: axes whose dense tables run on fp16
+                               matrix cores as two-term splits (n <= 256, or
+                               n <= 512 for real sine tables)                */
 } hs_info;
 
 /* Build a plan: validates the grid and blocks (HS_ERR_ARG), computes the 1D

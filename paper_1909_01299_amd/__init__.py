@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("kappa_max", ctypes.c_double), ("eig_resid_max", ctypes.c_double),
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
-                ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32)]
+                ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32),
+                ("n_split_fp16", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -29,6 +29,7 @@ Batch::~Batch() {
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (dtab64) (void)hipFree(dtab64);
   if (dtab32) (void)hipFree(dtab32);
+  if (dtab16) (void)hipFree(dtab16);
   if (ddesc) (void)hipFree(ddesc);
 }
 
@@ -71,6 +72,19 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
       err = "table upload failed";
       return HS_ERR_ALLOC;
     }
+    std::vector<_Float16> h;
+    for (const Plan* p : plans) {
+      h16_off.push_back(int64_t(h.size()) / 8);
+      h.insert(h.end(), p->h16.begin(), p->h16.end());
+    }
+    if (!h.empty() && (hipMalloc(&dtab16, h.size() * sizeof(_Float16)) != hipSuccess ||
+                       hipMemcpy(dtab16, h.data(), h.size() * sizeof(_Float16), hipMemcpyHostToDevice) != hipSuccess)) {
+      (void)hipGetLastError();
+      err = "table upload failed";
+      return HS_ERR_ALLOC;
+    }
+  } else {
+    h16_off.assign(plans.size(), 0);
   }
   // workspace: spectral arrays of every (plan, rhs), then the complex64 residuals
   int64_t off = 0;
@@ -121,6 +135,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
     const Axis& AX = p->axes[B.ax];
     const Axis& AY = p->axes[B.ay];
     const int64_t T0 = tab_off[i];
+    const int64_t H0 = h16_off[i];
     const int64_t plane = (int64_t)B.nbx * B.nby;
     const int64_t N = plane * p->NZ;
     for (int r = 0; r < nrhs[i]; ++r) {
@@ -142,7 +157,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         s_invx.dst[v].push_back(ix);
       } else {
         XformDesc fx{};
-        fx.tab = T0 + AX.fwd; set_frag(fx, AX, true, T0); fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
+        fx.tab = T0 + AX.fwd; set_frag(fx, AX, true, T0, H0); fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
         fx.src = fo; fx.src_p = plane; fx.src_q = B.nbx;
         fx.dst = spec; fx.dst_p = plane; fx.dst_q = B.nbx;
         s_fwdx.dense.push_back(fx);
@@ -150,7 +165,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         fr.src = ro;
         s_fwdx_res.dense.push_back(fr);
         XformDesc ix = fx;
-        ix.tab = T0 + AX.inv; set_frag(ix, AX, false, T0); ix.src = spec; ix.dst = uo;
+        ix.tab = T0 + AX.inv; set_frag(ix, AX, false, T0, H0); ix.src = spec; ix.dst = uo;
         s_invx.dense.push_back(ix);
       }
       if (AY.dstV) {
@@ -163,11 +178,11 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         s_invy.dst[v].push_back(dy);
       } else {
         XformYDesc fy{};
-        fy.tab = T0 + AY.fwd; set_frag(fy, AY, true, T0); fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
+        fy.tab = T0 + AY.fwd; set_frag(fy, AY, true, T0, H0); fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
         fy.data = spec; fy.s_p = plane; fy.s_k = B.nbx;
         s_fwdy.dense.push_back(fy);
         XformYDesc iy = fy;
-        iy.tab = T0 + AY.inv; set_frag(iy, AY, false, T0);
+        iy.tab = T0 + AY.inv; set_frag(iy, AY, false, T0, H0);
         s_invy.dense.push_back(iy);
       }
       SweepDesc s{};
@@ -227,7 +242,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
                   hipStream_t st) {
   const void* T = tab();
   if (!sl.dense.empty()) {
-    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, src, dst, 1, st);
+    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, dtab16, src, dst, 1, st);
   }
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
@@ -239,7 +254,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
 
 void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
   const void* T = tab();
-  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, ws, 1, st);
+  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, dtab16, ws, 1, st);
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
   for (int v = 0; v < kNumV; ++v)

@@ -22,6 +22,8 @@ struct Batch {
   std::vector<int64_t> tab_off;   // per plan, element offset of its tables
   void* dtab64 = nullptr;
   void* dtab32 = nullptr;
+  void* dtab16 = nullptr;         // complex64 path: split-fp16 fragment images
+  std::vector<int64_t> h16_off;   // per plan, 16-byte-unit offset of its fp16 image
   size_t tab_elems = 0;
   // workspace layout: per (plan, rhs) spectral array; complex64 residual per plan
   std::vector<int64_t> spec_off;  // per plan, first rhs (elements of the compute precision)

@@ -129,10 +129,12 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   }
   info->min_pivot = p.min_pivot;
   info->plan_seconds = p.plan_seconds;
-  info->table_bytes = p.tab_elems * (p.prec == 0 ? 16 : 24);
+  info->table_bytes = p.tab_elems * (p.prec == 0 ? 16 : 24) + p.h16.size() * 2;
   info->n_fp64_modes = p.n_fp64_modes;
   info->z_chunks = hs::sweep_chunks_ok(p.tune_chunks, p.NZ) ? p.tune_chunks : hs::sweep_default_chunks(p.NZ);
   info->sine_lines = p.tune_lt;
+  for (auto& a : p.axes)
+    if (a.hfwd >= 0) ++info->n_split_fp16;
   return ret(HS_OK, "");
 }
 

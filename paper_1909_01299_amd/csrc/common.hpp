@@ -81,6 +81,9 @@ struct XformDesc {
   int32_t sine;     // 1: table is the real orthonormal sine matrix (imaginary part zero)
   int32_t real_tab; // 1: ftab holds the real table itself, 0: its real embedding
   int64_t ftab;     // offset of the same table as MFMA fragments (see xform_mfma.hip)
+  int64_t htab = -1;   // complex64 path: offset (16-byte units) of its split-fp16 fragments, -1 if none
+  float hsinv = 1.f;   // 1 / the power-of-two scale of those fragments (see xform_h3.hip)
+  int32_t pad_ = 0;
 };
 
 // Dense transform along a strided axis, in place: for plane p of RHS r and
@@ -91,6 +94,9 @@ struct XformYDesc {
   int32_t P, real_tab;   // real_tab: as in XformDesc
   int64_t data, s_r, s_p, s_k;
   int64_t ftab;     // offset of the same table as MFMA fragments
+  int64_t htab = -1;   // as in XformDesc
+  float hsinv = 1.f;
+  int32_t pad_ = 0;
 };
 
 // Orthonormal sine transform (DST-I, n = N - 1 points, N a power of two) of

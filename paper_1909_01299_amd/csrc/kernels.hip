@@ -980,35 +980,63 @@ __global__ __launch_bounds__(256) void k_sigma_scatter(SigmaGeom g, const cplx<R
 // ---------------------------------------------------------------------------
 // FP64 residual r = f - A u with the 7-point stencil of eq. (2) (D-form).
 // ---------------------------------------------------------------------------
+// Residual r = f - A u (or A u) of the 7-point operator in FP64.  A
+// workgroup owns a 64 (x) x 8 (y) tile of columns and marches along a chunk of
+// z: u at z - 1, z, z + 1 stay in registers, the plane z of the tile (with its
+// one-point x / y halo) goes through LDS, so u is read once plus the halo.
+// Outside the grid u counts as zero (Dirichlet), which drops the boundary
+// terms; the terms are summed in the order centre, x-1, x+1, y-1, y+1, z-1, z+1.
+constexpr int RZ_TX = 64, RZ_TY = 8, RZ_ZC = 32;
 template <typename CO>
-__global__ __launch_bounds__(256) void k_residual(StencilGeom g, const double2* __restrict__ f,
-                                                  const double2* __restrict__ u, CO* __restrict__ out,
-                                                  int negate_f) {
-  // one workgroup per (y, z) row of one right-hand side, lanes along x
-  const int y = blockIdx.x, z = blockIdx.y, r = blockIdx.z;
+__global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const double2* __restrict__ f,
+                                                            const double2* __restrict__ u, CO* __restrict__ out,
+                                                            int negate_f) {
+  __shared__ double2 t[RZ_TY + 2][RZ_TX + 2];
+  const int tx = threadIdx.x & (RZ_TX - 1), ty = threadIdx.x / RZ_TX;
+  const int xt = (g.nx + RZ_TX - 1) / RZ_TX;
+  const int x0 = (blockIdx.x % xt) * RZ_TX, y0 = (blockIdx.x / xt) * RZ_TY;
+  const int z0 = blockIdx.y * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool in = x < g.nx && y < g.ny;
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const int64_t n = sz * g.nz;
-  const int64_t row = (int64_t)r * n + (int64_t)z * sz + (int64_t)y * sy;
-  const double2* ur = u + row;
-  const double2 dyz = cadd(g.yd[y], g.zd[z]);
-  const double2 cyl = g.yl[y], cyu = g.yu[y], czl = g.zl[z], czu = g.zu[z];
-  const bool hy0 = y > 0, hy1 = y + 1 < g.ny, hz0 = z > 0, hz1 = z + 1 < g.nz;
-  for (int x = threadIdx.x; x < g.nx; x += 256) {
-    const double2 c = ur[x];
-    double2 au = cmul(cadd(g.xd[x], dyz), c);
-    if (x > 0) au = cfma(g.xl[x], ur[x - 1], au);
-    if (x + 1 < g.nx) au = cfma(g.xu[x], ur[x + 1], au);
-    if (hy0) au = cfma(cyl, ur[x - sy], au);
-    if (hy1) au = cfma(cyu, ur[x + sy], au);
-    if (hz0) au = cfma(czl, ur[x - sz], au);
-    if (hz1) au = cfma(czu, ur[x + sz], au);
-    double2 res;
-    if (negate_f) {  // out = A u
-      res = au;
-    } else {
-      res = csub(f[row + x], au);
+  const int64_t base = (int64_t)blockIdx.z * sz * g.nz;
+  const int64_t col = base + (in ? (int64_t)y * sy + x : 0);
+  const double2 zero = mk<double>(0, 0);
+  const double2 cxd = in ? g.xd[x] : zero, cyd = in ? g.yd[y] : zero;
+  const double2 cxl = in ? g.xl[x] : zero, cxu = in ? g.xu[x] : zero;
+  const double2 cyl = in ? g.yl[y] : zero, cyu = in ? g.yu[y] : zero;
+  // halo sources of this thread (x halo: first / last lane of a row; y halo: first / last row)
+  const int hx = tx == 0 ? x0 - 1 : (tx == RZ_TX - 1 ? x0 + RZ_TX : -1);
+  const bool hx_ok = hx >= 0 && hx < g.nx && y < g.ny;
+  const int hy = ty == 0 ? y0 - 1 : (ty == RZ_TY - 1 ? y0 + RZ_TY : -1);
+  const bool hy_ok = hy >= 0 && hy < g.ny && x < g.nx;
+  const int64_t hxo = base + (hx_ok ? (int64_t)y * sy + hx : 0);
+  const int64_t hyo = base + (hy_ok ? (int64_t)hy * sy + x : 0);
+  const int hxc = tx == 0 ? 0 : RZ_TX + 1, hyr = ty == 0 ? 0 : RZ_TY + 1;
+  double2 um = (in && z0 > 0) ? u[col + (z0 - 1) * sz] : zero;
+  double2 uc = in ? u[col + z0 * sz] : zero;
+  for (int z = z0; z < z1; ++z) {
+    const double2 up = (in && z + 1 < g.nz) ? u[col + (z + 1) * sz] : zero;
+    const double2 fz = (in && !negate_f) ? f[col + z * sz] : zero;
+    const double2 vx = hx_ok ? u[hxo + z * sz] : zero;
+    const double2 vy = hy_ok ? u[hyo + z * sz] : zero;
+    t[ty + 1][tx + 1] = uc;
+    if (tx == 0 || tx == RZ_TX - 1) t[ty + 1][hxc] = vx;
+    if (ty == 0 || ty == RZ_TY - 1) t[hyr][tx + 1] = vy;
+    __syncthreads();
+    if (in) {
+      double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
+      au = cfma(cxl, t[ty + 1][tx], au);
+      au = cfma(cxu, t[ty + 1][tx + 2], au);
+      au = cfma(cyl, t[ty][tx + 1], au);
+      au = cfma(cyu, t[ty + 2][tx + 1], au);
+      au = cfma(g.zl[z], um, au);
+      au = cfma(g.zu[z], up, au);
+      out[col + z * sz] = cvt<CO>(negate_f ? au : csub(fz, au));
     }
-    out[row + x] = cvt<CO>(res);
+    __syncthreads();
+    um = uc;
+    uc = up;
   }
 }
 
@@ -1326,12 +1354,14 @@ void residual(const StencilGeom& g, const void* f, const void* u, void* out, int
               int nrhs, hipStream_t st) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   if (n == 0 || nrhs == 0) return;
+  const dim3 grid(unsigned(((g.nx + RZ_TX - 1) / RZ_TX) * ((g.ny + RZ_TY - 1) / RZ_TY)),
+                  unsigned((g.nz + RZ_ZC - 1) / RZ_ZC), unsigned(nrhs));
   if (out64)
-    hipLaunchKernelGGL((k_residual<double2>), dim3(g.ny, g.nz, nrhs), dim3(256), 0, st, g,
-                       (const double2*)f, (const double2*)u, (double2*)out, apply_only);
+    hipLaunchKernelGGL((k_residual<double2>), grid, dim3(RZ_TX * RZ_TY), 0, st, g, (const double2*)f,
+                       (const double2*)u, (double2*)out, apply_only);
   else
-    hipLaunchKernelGGL((k_residual<float2>), dim3(g.ny, g.nz, nrhs), dim3(256), 0, st, g,
-                       (const double2*)f, (const double2*)u, (float2*)out, apply_only);
+    hipLaunchKernelGGL((k_residual<float2>), grid, dim3(RZ_TX * RZ_TY), 0, st, g, (const double2*)f,
+                       (const double2*)u, (float2*)out, apply_only);
 }
 
 void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st) {

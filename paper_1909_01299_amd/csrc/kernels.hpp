@@ -68,10 +68,11 @@ void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_t
 // parts, so a block takes the same kernel in any list it belongs to.
 int partition_lines(std::vector<XformDesc>& v);
 int partition_y(int prec, std::vector<XformYDesc>& v);
+// htab: split-fp16 fragment tables (complex64 path; descriptors with htab >= 0)
 void run_lines_list(int prec, int in64, int out64, int acc, const XformDesc* dev, const std::vector<XformDesc>& host,
-                    const void* tab, const void* src, void* dst, int nrhs, hipStream_t st);
-void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab, void* ws,
-                int nrhs, hipStream_t st);
+                    const void* tab, const void* htab, const void* src, void* dst, int nrhs, hipStream_t st);
+void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab,
+                const void* htab, void* ws, int nrhs, hipStream_t st);
 // Fragment image of an n_out x n_in complex table (row-major): real values,
 // mfma_table_reals(n_out, n_in) of them.
 int64_t mfma_table_reals(int n_out, int n_in);
@@ -79,6 +80,21 @@ void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double
 // Fragment image of a real table (the real parts of T): mfma_rtable_reals of them.
 int64_t mfma_rtable_reals(int n_out, int n_in);
 void mfma_rtable_build(const std::complex<double>* T, int n_out, int n_in, double* out);
+
+// Complex64 dense transforms on fp16 matrix cores with a two-term split
+// (xform_h3.hip): tables of at most 256 complex (512 real) points per axis.
+bool h3_fits(int n, bool real);
+int64_t h3_table_frags(int n_out, int n_in, bool real);   // 16-byte units
+// writes h3_table_frags * 8 halves; returns 1 / the table's power-of-two scale
+float h3_table_build(const std::complex<double>* T, int n_out, int n_in, bool real, _Float16* out);
+// panel width class of a descriptor (4: rows of at most 256 halves, else 2);
+// lists are grouped by it so each launch takes the widest panel it can
+int h3_width(const XformDesc& d);
+int h3_width(const XformYDesc& d);
+void xform_lines_h3(int in64, int out64, int acc, const XformDesc* dev, const XformDesc* host, int ndesc,
+                    const void* htab, const void* src, void* dst, int nrhs, hipStream_t st);
+void xform_y_h3(const XformYDesc* dev, const XformYDesc* host, int ndesc, const void* htab, void* ws, int nrhs,
+                hipStream_t st);
 
 // Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
 constexpr int kTwiddleN = 512;

@@ -57,6 +57,7 @@ Plan::~Plan() {
   for (auto e : ev_pool) (void)hipEventDestroy(e);
   if (dtab64) (void)hipFree(dtab64);
   if (dtab32) (void)hipFree(dtab32);
+  if (dtab16) (void)hipFree(dtab16);
   if (dint) (void)hipFree(dint);
   if (dsten) (void)hipFree(dsten);
   if (ddesc) (void)hipFree(ddesc);
@@ -107,7 +108,7 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   const hs_options& op = o ? *o : def;
   if (op.prec != HS_C128 && op.prec != HS_C64_REFINE) { err = "unknown precision"; return HS_ERR_ARG; }
   prec = op.prec == HS_C128 ? 0 : 1;
-  refine_steps = prec ? (op.refine_steps > 0 ? op.refine_steps : 2) : 0;
+  refine_steps = prec ? (op.refine_steps > 0 ? op.refine_steps : (op.refine_steps < 0 ? 0 : 2)) : 0;
   if (op.max_rhs < 0 || op.max_rhs > 4096) { err = "max_rhs out of range"; return HS_ERR_ARG; }
   max_rhs = op.max_rhs > 0 ? op.max_rhs : 1;
   flags = op.flags;
@@ -228,6 +229,24 @@ hs_status Plan::build_tables(std::string& err) {
     if (a.real_tables) {
       a.rfwd = push_frag(a.e.Winv, a.n, true);
       a.rinv = push_frag(a.e.W, a.n, true);
+    }
+  }
+  // complex64 path: split-fp16 fragments of the matrix-core tables
+  h16.clear();
+  if (prec == 1) {
+    auto push_h = [&](const std::vector<cd>& T, int n, bool real, float& sinv) {
+      const int64_t off = int64_t(h16.size()) / 8;
+      const int64_t units = h3_table_frags(n, n, real);
+      h16.resize(h16.size() + size_t(units) * 8);
+      sinv = h3_table_build(T.data(), n, n, real, h16.data() + off * 8);
+      h16.resize(size_t(align_up(int64_t(h16.size()), 128)));   // 256-byte aligned tables
+      return off;
+    };
+    for (auto& a : axes) {
+      const bool real = a.rfwd >= 0;
+      if (!h3_fits(a.n, real)) continue;
+      a.hfwd = push_h(a.e.Winv, a.n, real, a.hsfwd);
+      a.hinv = push_h(a.e.W, a.n, real, a.hsinv);
     }
   }
   {
@@ -643,6 +662,11 @@ hs_status Plan::upload(std::string& err) {
     if (hipMalloc(&dtab32, tab_elems * sizeof(float2)) != hipSuccess) return fail("tables");
     if (hipMemcpy(dtab32, t32.data(), tab_elems * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess)
       return fail("tables");
+    if (!h16.empty()) {
+      if (hipMalloc(&dtab16, h16.size() * sizeof(_Float16)) != hipSuccess) return fail("tables");
+      if (hipMemcpy(dtab16, h16.data(), h16.size() * sizeof(_Float16), hipMemcpyHostToDevice) != hipSuccess)
+        return fail("tables");
+    }
   }
   // integer tables
   std::vector<int32_t> iv;
@@ -859,7 +883,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
                  int nrhs, hipStream_t st) {
   const void* T = tab();
   if (!sl.dense.empty()) {
-    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, src, dst, nrhs, st);
+    run_lines_list(prec, in64, out64, acc, sl.p_dense, sl.dense, T, dtab16, src, dst, nrhs, st);
   }
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
@@ -871,7 +895,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
 
 void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
   const void* T = tab();
-  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, ws, nrhs, st);
+  if (!sl.dense.empty()) run_y_list(prec, sl.p_dense, sl.dense, T, dtab16, ws, nrhs, st);
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
   for (int v = 0; v < kNumV; ++v)
@@ -943,7 +967,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     double ffl = 0;
     for (auto& B : blocks) ffl += double(NZ) * 2.0 * (double(B.nby) * B.nby + double(B.nbx) * B.nbx) * 8.0;
     stage_begin("face_xform", R * nface * 2 * esz, R * ffl, st);
-    run_lines_list(prec, 0, 0, 0, p_vface, d_vface, T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_vface, d_vface, T, dtab16, W, W, nrhs, st);
     stage_end();
     // step 4: residual on the separators
     SigmaGeom g = sg;
@@ -954,7 +978,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     // step 5: global interface solve, evaluated on the separators
     const double gfl = double(NZ) * (nsx * double(NY) * NY + nsy * double(NX) * NX) * 8.0;
     stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
-    run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, dtab16, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
@@ -964,14 +988,14 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
     stage_end();
     stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
-    run_lines_list(prec, 0, 0, 0, p_glob_out, d_glob_out, T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_glob_out, d_glob_out, T, dtab16, W, W, nrhs, st);
     stage_end();
     // step 6: lift the separator values into the blocks and sweep again
     stage_begin("lift", R * nface * 2 * esz, R * nface * 6, st);
     lift(prec, g, p_lift, nb, W, nrhs, st);
     stage_end();
     stage_begin("lift_xform", R * nface * 2 * esz, R * ffl, st);
-    run_lines_list(prec, 0, 0, 0, p_gface, d_gface, T, W, W, nrhs, st);
+    run_lines_list(prec, 0, 0, 0, p_gface, d_gface, T, dtab16, W, W, nrhs, st);
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,

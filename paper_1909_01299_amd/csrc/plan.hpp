@@ -24,15 +24,23 @@ struct Axis {
   int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
   int64_t ffwd = 0, finv = 0;          // the same tables as MFMA fragments of their real embedding
   int64_t rfwd = -1, rinv = -1;        // uniform axes (real sine tables): fragments of the tables themselves
+  // complex64 path: the matrix-core tables (real or embedded, as above) as
+  // split-fp16 fragments (16-byte units in the fp16 image; -1: none) and the
+  // inverses of their scales
+  int64_t hfwd = -1, hinv = -1;
+  float hsfwd = 1.f, hsinv = 1.f;
 };
 
 // Matrix-core table of a dense descriptor: the real table where the axis has
 // one, else the real embedding of the complex table (offsets + base).
 template <typename D>
-inline void set_frag(D& d, const Axis& a, bool fwd, int64_t base = 0) {
+inline void set_frag(D& d, const Axis& a, bool fwd, int64_t base = 0, int64_t hbase = 0) {
   const bool real = a.rfwd >= 0;
   d.real_tab = real ? 1 : 0;
   d.ftab = base + (real ? (fwd ? a.rfwd : a.rinv) : (fwd ? a.ffwd : a.finv));
+  const int64_t h = fwd ? a.hfwd : a.hinv;
+  d.htab = h >= 0 ? hbase + h : -1;
+  d.hsinv = fwd ? a.hsfwd : a.hsinv;
 }
 
 struct Block {
@@ -85,11 +93,13 @@ struct Plan {
   int nbx_blocks = 1, nby_blocks = 1;
   bool decomposed = false;
   std::vector<cd> htab;          // host FP64 table image
+  std::vector<_Float16> h16;     // complex64 path: split-fp16 fragment image (8 halves per unit)
   int64_t zlo = 0, zdiag = 0, zup = 0;
   int64_t cx_lo = 0, cx_hi = 0, cy_lo = 0, cy_hi = 0;
   std::vector<int64_t> lift_cf;  // per block 4 coefficient offsets
   void* dtab64 = nullptr;
   void* dtab32 = nullptr;
+  void* dtab16 = nullptr;
   size_t tab_elems = 0;
   int32_t* dint = nullptr;       // sep_x | sep_y | xblk | xloc | yblk | yloc | layer_of_z
   int64_t i_sepx = 0, i_sepy = 0, i_xblk = 0, i_xloc = 0, i_yblk = 0, i_yloc = 0, i_layer = 0;

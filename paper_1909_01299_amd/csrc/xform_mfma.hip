@@ -754,38 +754,51 @@ void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_t
   }
 }
 
-// group of a descriptor: 0 matrix cores with a real table, 1 matrix cores
-// with an embedded table, 2 complex FMA tiles
-static int lines_group(const XformDesc& d) { return xform_lines_use_mfma(d) ? (d.real_tab ? 0 : 1) : 2; }
-static int y_group(int prec, const XformYDesc& d) { return xform_y_use_mfma(prec, d.n) ? (d.real_tab ? 0 : 1) : 2; }
+// group of a descriptor: 0..3 split-fp16 matrix cores (complex64 path):
+// real table wide / narrow panels, embedded table wide / narrow; 4 / 5 matrix
+// cores in the compute precision with a real / embedded table; 6 complex FMA
+// tiles
+static int lines_group(const XformDesc& d) {
+  if (!xform_lines_use_mfma(d)) return 6;
+  if (d.htab >= 0) return (d.real_tab ? 0 : 2) + (h3_width(d) == 4 ? 0 : 1);
+  return d.real_tab ? 4 : 5;
+}
+static int y_group(int prec, const XformYDesc& d) {
+  if (!xform_y_use_mfma(prec, d.n)) return 6;
+  if (d.htab >= 0) return (d.real_tab ? 0 : 2) + (h3_width(d) == 4 ? 0 : 1);
+  return d.real_tab ? 4 : 5;
+}
 
 int partition_lines(std::vector<XformDesc>& v) {
   std::stable_sort(v.begin(), v.end(),
                    [](const XformDesc& a, const XformDesc& b) { return lines_group(a) < lines_group(b); });
-  return int(std::count_if(v.begin(), v.end(), [](const XformDesc& d) { return lines_group(d) < 2; }));
+  return int(std::count_if(v.begin(), v.end(), [](const XformDesc& d) { return lines_group(d) < 6; }));
 }
 
 int partition_y(int prec, std::vector<XformYDesc>& v) {
   std::stable_sort(v.begin(), v.end(),
                    [prec](const XformYDesc& a, const XformYDesc& b) { return y_group(prec, a) < y_group(prec, b); });
-  return int(std::count_if(v.begin(), v.end(), [prec](const XformYDesc& d) { return y_group(prec, d) < 2; }));
+  return int(std::count_if(v.begin(), v.end(), [prec](const XformYDesc& d) { return y_group(prec, d) < 6; }));
 }
 
 void run_lines_list(int prec, int in64, int out64, int acc, const XformDesc* dev, const std::vector<XformDesc>& host,
-                    const void* tab, const void* src, void* dst, int nrhs, hipStream_t st) {
+                    const void* tab, const void* htab, const void* src, void* dst, int nrhs, hipStream_t st) {
   const int n = int(host.size());
   for (int b = 0; b < n;) {
     const int g = lines_group(host[b]);
     int e = b;
     while (e < n && lines_group(host[e]) == g) ++e;
-    xform_lines(prec, in64, out64, acc, dev + b, e - b, xform_lines_launch(host.data() + b, e - b, g < 2, g == 0), tab,
-                src, dst, nrhs, st);
+    if (g < 4)
+      xform_lines_h3(in64, out64, acc, dev + b, host.data() + b, e - b, htab, src, dst, nrhs, st);
+    else
+      xform_lines(prec, in64, out64, acc, dev + b, e - b, xform_lines_launch(host.data() + b, e - b, g < 6, g == 4),
+                  tab, src, dst, nrhs, st);
     b = e;
   }
 }
 
-void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab, void* ws,
-                int nrhs, hipStream_t st) {
+void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& host, const void* tab,
+                const void* htab, void* ws, int nrhs, hipStream_t st) {
   const int n = int(host.size());
   for (int b = 0; b < n;) {
     const int g = y_group(prec, host[b]);
@@ -797,8 +810,10 @@ void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& 
       t8 = std::max(t8, xform_y_tiles(host[e], 8));
       ++e;
     }
-    if (g < 2)
-      xform_y_mfma(prec, dev + b, e - b, max_n, t16, tab, ws, nrhs, st, g == 0);   // 16-column tiles
+    if (g < 4)
+      xform_y_h3(dev + b, host.data() + b, e - b, htab, ws, nrhs, st);
+    else if (g < 6)
+      xform_y_mfma(prec, dev + b, e - b, max_n, t16, tab, ws, nrhs, st, g == 4);   // 16-column tiles
     else
       xform_y(prec, dev + b, e - b, max_n, t16, t8, tab, ws, nrhs, st);
     b = e;
