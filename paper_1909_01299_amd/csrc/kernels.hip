@@ -981,60 +981,50 @@ __global__ __launch_bounds__(256) void k_sigma_scatter(SigmaGeom g, const cplx<R
 // FP64 residual r = f - A u with the 7-point stencil of eq. (2) (D-form).
 // ---------------------------------------------------------------------------
 // Residual r = f - A u (or A u) of the 7-point operator in FP64.  A
-// workgroup owns a 64 (x) x 8 (y) tile of columns and marches along a chunk of
-// z: u at z - 1, z, z + 1 stay in registers, the plane z of the tile (with its
-// one-point x / y halo) goes through LDS, so u is read once plus the halo.
-// Outside the grid u counts as zero (Dirichlet), which drops the boundary
-// terms; the terms are summed in the order centre, x-1, x+1, y-1, y+1, z-1, z+1.
-constexpr int RZ_TX = 64, RZ_TY = 8, RZ_ZC = 32;
+// workgroup owns a 64 (x) x 4 (y) tile of columns and marches along a chunk
+// of z: u at z - 1 and z stay in registers, u at z + 1 is the one new HBM
+// read per point, and the x / y neighbours of plane z come through L1 (the
+// tile reads them itself).  No barriers, so the unrolled march keeps several
+// planes of loads in flight.  Outside the grid u counts as zero (Dirichlet),
+// which drops the boundary terms; the terms are summed in the order centre,
+// x-1, x+1, y-1, y+1, z-1, z+1.
+constexpr int RZ_TX = 64, RZ_TY = 4, RZ_ZC = 32;
 template <typename CO>
 __global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const double2* __restrict__ f,
                                                             const double2* __restrict__ u, CO* __restrict__ out,
                                                             int negate_f) {
-  __shared__ double2 t[RZ_TY + 2][RZ_TX + 2];
   const int tx = threadIdx.x & (RZ_TX - 1), ty = threadIdx.x / RZ_TX;
   const int xt = (g.nx + RZ_TX - 1) / RZ_TX;
-  const int x0 = (blockIdx.x % xt) * RZ_TX, y0 = (blockIdx.x / xt) * RZ_TY;
+  const int x = (blockIdx.x % xt) * RZ_TX + tx, y = (blockIdx.x / xt) * RZ_TY + ty;
+  if (x >= g.nx || y >= g.ny) return;
   const int z0 = blockIdx.y * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
-  const int x = x0 + tx, y = y0 + ty;
-  const bool in = x < g.nx && y < g.ny;
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const int64_t base = (int64_t)blockIdx.z * sz * g.nz;
-  const int64_t col = base + (in ? (int64_t)y * sy + x : 0);
+  const double2* uc0 = u + (int64_t)blockIdx.z * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
+  const int64_t col = uc0 - u;
   const double2 zero = mk<double>(0, 0);
-  const double2 cxd = in ? g.xd[x] : zero, cyd = in ? g.yd[y] : zero;
-  const double2 cxl = in ? g.xl[x] : zero, cxu = in ? g.xu[x] : zero;
-  const double2 cyl = in ? g.yl[y] : zero, cyu = in ? g.yu[y] : zero;
-  // halo sources of this thread (x halo: first / last lane of a row; y halo: first / last row)
-  const int hx = tx == 0 ? x0 - 1 : (tx == RZ_TX - 1 ? x0 + RZ_TX : -1);
-  const bool hx_ok = hx >= 0 && hx < g.nx && y < g.ny;
-  const int hy = ty == 0 ? y0 - 1 : (ty == RZ_TY - 1 ? y0 + RZ_TY : -1);
-  const bool hy_ok = hy >= 0 && hy < g.ny && x < g.nx;
-  const int64_t hxo = base + (hx_ok ? (int64_t)y * sy + hx : 0);
-  const int64_t hyo = base + (hy_ok ? (int64_t)hy * sy + x : 0);
-  const int hxc = tx == 0 ? 0 : RZ_TX + 1, hyr = ty == 0 ? 0 : RZ_TY + 1;
-  double2 um = (in && z0 > 0) ? u[col + (z0 - 1) * sz] : zero;
-  double2 uc = in ? u[col + z0 * sz] : zero;
+  const double2 cxd = g.xd[x], cyd = g.yd[y];
+  const double2 cxl = g.xl[x], cxu = g.xu[x], cyl = g.yl[y], cyu = g.yu[y];
+  const bool hx0 = x > 0, hx1 = x + 1 < g.nx, hy0 = y > 0, hy1 = y + 1 < g.ny;
+  double2 um = z0 > 0 ? uc0[(int64_t)(z0 - 1) * sz] : zero;
+  double2 uc = uc0[(int64_t)z0 * sz];
+#pragma unroll 4
   for (int z = z0; z < z1; ++z) {
-    const double2 up = (in && z + 1 < g.nz) ? u[col + (z + 1) * sz] : zero;
-    const double2 fz = (in && !negate_f) ? f[col + z * sz] : zero;
-    const double2 vx = hx_ok ? u[hxo + z * sz] : zero;
-    const double2 vy = hy_ok ? u[hyo + z * sz] : zero;
-    t[ty + 1][tx + 1] = uc;
-    if (tx == 0 || tx == RZ_TX - 1) t[ty + 1][hxc] = vx;
-    if (ty == 0 || ty == RZ_TY - 1) t[hyr][tx + 1] = vy;
-    __syncthreads();
-    if (in) {
-      double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
-      au = cfma(cxl, t[ty + 1][tx], au);
-      au = cfma(cxu, t[ty + 1][tx + 2], au);
-      au = cfma(cyl, t[ty][tx + 1], au);
-      au = cfma(cyu, t[ty + 2][tx + 1], au);
-      au = cfma(g.zl[z], um, au);
-      au = cfma(g.zu[z], up, au);
-      out[col + z * sz] = cvt<CO>(negate_f ? au : csub(fz, au));
-    }
-    __syncthreads();
+    const double2* pz = uc0 + (int64_t)z * sz;
+    const double2 up = z + 1 < g.nz ? pz[sz] : zero;
+    const double2 vxl = hx0 ? pz[-1] : zero, vxu = hx1 ? pz[1] : zero;
+    const double2 vyl = hy0 ? pz[-sy] : zero, vyu = hy1 ? pz[sy] : zero;
+    double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
+    au = cfma(cxl, vxl, au);
+    au = cfma(cxu, vxu, au);
+    au = cfma(cyl, vyl, au);
+    au = cfma(cyu, vyu, au);
+    au = cfma(g.zl[z], um, au);
+    au = cfma(g.zu[z], up, au);
+    const int64_t e = col + (int64_t)z * sz;
+    if (negate_f)
+      out[e] = cvt<CO>(au);
+    else
+      out[e] = cvt<CO>(csub(f[e], au));
     um = uc;
     uc = up;
   }
