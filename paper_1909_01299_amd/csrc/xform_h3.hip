@@ -51,6 +51,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 
 constexpr int H3_THREADS = 512;
 constexpr int H3_WAVES = H3_THREADS / 64;
+constexpr int H3_RED = 32;   // LDS bytes of the maxima in front of the panel
 constexpr int H3_PPW = 1;   // panels per workgroup: the loads of the next overlap the products of the current
 
 // Panel width: 16 CT columns.  CT = 4 where the panel rows are at most 256
@@ -98,7 +99,7 @@ __device__ __forceinline__ float wg_max(float m, float* red) {
 // ks multiplies: two register sets in turn (no copies between them, so no
 // wait lands right after a load), each load group fenced from the products by
 // a scheduling barrier so it is issued before them.
-template <int NO, int CT, typename Epi>
+template <int NO, int CT, bool SYNC, typename Epi>
 __device__ __forceinline__ void h3_tiles(const h8_t* __restrict__ ft, const _Float16* hi, const _Float16* lo,
                                          int LK, int KS, int w, int l, Epi&& epi) {
   const h8_t* fa[NO];
@@ -141,6 +142,7 @@ __device__ __forceinline__ void h3_tiles(const h8_t* __restrict__ ft, const _Flo
     __builtin_amdgcn_sched_barrier(0);
     step(ks + 1, h1, l1);
   }
+  if (SYNC) __syncthreads();   // every wave is done with the panel before results replace it
 #pragma unroll
   for (int j = 0; j < NO; ++j)
 #pragma unroll
@@ -148,18 +150,19 @@ __device__ __forceinline__ void h3_tiles(const h8_t* __restrict__ ft, const _Flo
 }
 
 // The wave's output tiles w, w + 8, ... below MT (a wave-uniform count; at
-// most 4 for K <= 512, 2 for K <= 256).
-template <int CT, typename Epi>
+// most 4 for K <= 512, 2 for K <= 256).  SYNC: one workgroup barrier between
+// the products and the results (in every wave, with or without tiles).
+template <int CT, bool SYNC, typename Epi>
 __device__ __forceinline__ void h3_dispatch(int MT, const h8_t* ft, const _Float16* hi, const _Float16* lo, int LK,
                                             int KS, int w, int l, Epi&& epi) {
   constexpr int NOMAX = CT == 4 ? 2 : 4;
   const int ntw = MT > w ? (MT - w + H3_WAVES - 1) / H3_WAVES : 0;
   switch (ntw < NOMAX ? ntw : NOMAX) {
-    case 1: h3_tiles<1, CT>(ft, hi, lo, LK, KS, w, l, epi); break;
-    case 2: h3_tiles<2, CT>(ft, hi, lo, LK, KS, w, l, epi); break;
-    case 3: if constexpr (NOMAX >= 3) h3_tiles<3, CT>(ft, hi, lo, LK, KS, w, l, epi); break;
-    case 4: if constexpr (NOMAX >= 4) h3_tiles<4, CT>(ft, hi, lo, LK, KS, w, l, epi); break;
-    default: break;
+    case 1: h3_tiles<1, CT, SYNC>(ft, hi, lo, LK, KS, w, l, epi); break;
+    case 2: h3_tiles<2, CT, SYNC>(ft, hi, lo, LK, KS, w, l, epi); break;
+    case 3: if constexpr (NOMAX >= 3) h3_tiles<3, CT, SYNC>(ft, hi, lo, LK, KS, w, l, epi); break;
+    case 4: if constexpr (NOMAX >= 4) h3_tiles<4, CT, SYNC>(ft, hi, lo, LK, KS, w, l, epi); break;
+    default: if (SYNC) __syncthreads(); break;
   }
 }
 
@@ -249,9 +252,9 @@ __global__ __launch_bounds__(H3_THREADS, 4) void k_xform_lines_h3(const XformDes
   const int NCP = EMB ? Kp / 2 : Kp;            // complex slots per line, padding included
   const int N = EMB ? 2 * d.n_out : d.n_out;
   const int MT = (N + 15) / 16, KS = Kp / 32;
-  _Float16* hi = reinterpret_cast<_Float16*>(smem_raw);
+  float* red = reinterpret_cast<float*>(smem_raw);   // H3_WAVES partial maxima, then the panel
+  _Float16* hi = reinterpret_cast<_Float16*>(smem_raw + H3_RED);
   _Float16* lo = hi + C * LK;
-  float* red = reinterpret_cast<float*>(lo + C * LK);
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const h8_t* ft = htab + d.htab;
@@ -294,27 +297,68 @@ __global__ __launch_bounds__(H3_THREADS, 4) void k_xform_lines_h3(const XformDes
     __syncthreads();
     if (pi + 1 < pe) load(L0 + VL);
 
+    // results go through LDS (line-major, odd row stride) so each wave then
+    // writes (or accumulates into) whole lines with contiguous accesses
     const float oscale = ldexpf(d.hsinv, -ex);
-    h3_dispatch<CT>(MT, ft, hi, lo, LK, KS, w, l, [&](int mt, int ct, const f4_t& a) {
+    float2* stg = reinterpret_cast<float2*>(smem_raw + H3_RED);
+    const int SO = d.n_out | 1;
+    h3_dispatch<CT, true>(MT, ft, hi, lo, LK, KS, w, l, [&](int mt, int ct, const f4_t& a) {
       const int c = 16 * ct + (l & 15);
-      const int64_t L = L0 + (EMB ? c : c >> 1);
       float2 z0, z1;
-      int b;
+      int b, line;
       if (EMB) {
         b = 8 * mt + 2 * (l >> 4);
+        line = c;
         z0 = make_float2(a[0], a[1]);
         z1 = make_float2(a[2], a[3]);
       } else {
         pair_exchange(a, odd, z0, z1);
         b = 16 * mt + 4 * (l >> 4) + 2 * odd;
+        line = c >> 1;
       }
-      if (L >= lines) return;
-      const unsigned Lu = unsigned(L), Qu = unsigned(d.Q);   // line counts stay below 2^31
-      const int p = int(Lu / Qu), q = int(Lu % Qu);
-      CO* dl = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q;
-      if (b < d.n_out) st_c<CO, ACC>(dl + b, make_float2(z0.x * oscale, z0.y * oscale));
-      if (b + 1 < d.n_out) st_c<CO, ACC>(dl + b + 1, make_float2(z1.x * oscale, z1.y * oscale));
+      if (b < d.n_out) stg[line * SO + b] = make_float2(z0.x * oscale, z0.y * oscale);
+      if (b + 1 < d.n_out) stg[line * SO + b + 1] = make_float2(z1.x * oscale, z1.y * oscale);
     });
+    __syncthreads();
+    constexpr int OT = (EMB ? 8 : 16) / CT;   // 64 OT >= n_out
+    CO* dls[LPW];
+    CO old[LPW][OT];
+#pragma unroll
+    for (int a = 0; a < LPW; ++a) {
+      const int64_t L = L0 + w + H3_WAVES * a;
+      const unsigned Lc = unsigned(L < lines ? L : lines - 1), Qu = unsigned(d.Q);
+      const int p = int(Lc / Qu), q = int(Lc % Qu);
+      dls[a] = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q;
+      if (ACC) {
+#pragma unroll
+        for (int it = 0; it < OT; ++it) {
+          const int i = l + 64 * it;
+          if (L < lines && i < d.n_out) old[a][it] = dls[a][i];
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < LPW; ++a) {
+      const int c = w + H3_WAVES * a;
+      if (L0 + c >= lines) continue;
+#pragma unroll
+      for (int it = 0; it < OT; ++it) {
+        const int i = l + 64 * it;
+        if (i < d.n_out) {
+          const float2 v2 = stg[c * SO + i];
+          using RO = decltype(old[0][0].x);
+          CO o;
+          if (ACC) {
+            o.x = RO(old[a][it].x + RO(v2.x));
+            o.y = RO(old[a][it].y + RO(v2.y));
+          } else {
+            o.x = RO(v2.x);
+            o.y = RO(v2.y);
+          }
+          dls[a][i] = o;
+        }
+      }
+    }
   }
 }
 
@@ -344,9 +388,9 @@ __global__ __launch_bounds__(H3_THREADS, 4) void k_xform_y_h3(const XformYDesc* 
   const int LK = Kp;
   const int NCP = EMB ? Kp / 2 : Kp;             // rows of the panel, padding included
   const int MT = (K + 15) / 16, KS = Kp / 32;
-  _Float16* hi = reinterpret_cast<_Float16*>(smem_raw);
+  float* red = reinterpret_cast<float*>(smem_raw);   // H3_WAVES partial maxima, then the panel
+  _Float16* hi = reinterpret_cast<_Float16*>(smem_raw + H3_RED);
   _Float16* lo = hi + C * LK;
-  float* red = reinterpret_cast<float*>(lo + C * LK);
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int col = l % VC;
@@ -383,7 +427,7 @@ __global__ __launch_bounds__(H3_THREADS, 4) void k_xform_y_h3(const XformYDesc* 
     if (pi + 1 < pe) load(pan + 1);
 
     const float oscale = ldexpf(d.hsinv, -ex);
-    h3_dispatch<CT>(MT, ft, hi, lo, LK, KS, w, l, [&](int mt, int ct, const f4_t& a) {
+    h3_dispatch<CT, false>(MT, ft, hi, lo, LK, KS, w, l, [&](int mt, int ct, const f4_t& a) {
       const int c = 16 * ct + (l & 15);
       const int xo = x0 + (EMB ? c : c >> 1);
       float2 z0, z1;
@@ -405,7 +449,13 @@ __global__ __launch_bounds__(H3_THREADS, 4) void k_xform_y_h3(const XformYDesc* 
 
 size_t h3_lds_bytes(int K, int CT) {
   const int LK = (K + 63) & ~63;
-  return size_t(2) * 16 * CT * LK * sizeof(_Float16) + H3_WAVES * sizeof(float);
+  return H3_RED + size_t(2) * 16 * CT * LK * sizeof(_Float16);
+}
+
+// x lines also stage their results: lines per panel x (n_out | 1) complex64
+size_t h3_lines_lds_bytes(int K, int n_out_max, int CT, bool real) {
+  const size_t stage = H3_RED + size_t(real ? 8 : 16) * CT * size_t(n_out_max | 1) * sizeof(float2);
+  return std::max(h3_lds_bytes(K, CT), stage);
 }
 
 }  // namespace
@@ -500,11 +550,14 @@ void xform_lines_h3(int in64, int out64, int acc, const XformDesc* dev, const Xf
     ct = std::min(ct, h3_width(host[i]));
     kmax = std::max(kmax, desc_k(host[i]));
   }
-  int tiles = 0;
-  for (int i = 0; i < ndesc; ++i) tiles = std::max(tiles, h3_lines_tiles(host[i], ct));
+  int tiles = 0, nomax = 0;
+  for (int i = 0; i < ndesc; ++i) {
+    tiles = std::max(tiles, h3_lines_tiles(host[i], ct));
+    nomax = std::max(nomax, host[i].n_out);
+  }
   if (tiles == 0) return;
-  const size_t lds = h3_lds_bytes(kmax, ct);
   const bool real = host[0].real_tab != 0;
+  const size_t lds = h3_lines_lds_bytes(kmax, nomax, ct, real);
   if (real && ct == 4)
     lines_h3_io<false, 4>(in64, out64, acc, dev, ndesc, tiles, lds, htab, src, dst, nrhs, st);
   else if (real)
