@@ -27,6 +27,7 @@ Batch::~Batch() {
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  side_stream_destroy(side);
   if (dtab64) (void)hipFree(dtab64);
   if (dtab32) (void)hipFree(dtab32);
   if (dtab16) (void)hipFree(dtab16);
@@ -104,7 +105,9 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
     if (prec == 1) bytes += align_up(int64_t(nrhs[i]) * p->NX * p->NY * p->NZ * 8, 256);
   }
   ws_bytes = bytes;
-  if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+  if (hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      (prec == 1 && !side_stream_create(side))) {
+    (void)hipGetLastError();
     err = "stream creation failed";
     return HS_ERR_DEVICE;
   }
@@ -270,7 +273,7 @@ void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
     sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks,
-          any_fp64);
+          any_fp64, &side);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

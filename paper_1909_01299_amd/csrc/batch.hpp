@@ -44,6 +44,7 @@ struct Batch {
   size_t ddesc_bytes = 0;
   // graph
   hipStream_t cap_stream = nullptr;
+  SideStream side;                // complex64 path: stream of the FP64 z solves
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 

@@ -1196,30 +1196,55 @@ bool sweep_chunks_ok(int chunks, int nz) {
   return (chunks == 8 || chunks == 16 || chunks == 32) && nz <= chunks * PS_LMAX;
 }
 
+bool side_stream_create(SideStream& s) {
+  if (hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&s.fork, hipEventDisableTiming) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&s.join, hipEventDisableTiming) != hipSuccess) return false;
+  return true;
+}
+
+void side_stream_destroy(SideStream& s) {
+  if (s.fork) (void)hipEventDestroy(s.fork);
+  if (s.join) (void)hipEventDestroy(s.join);
+  if (s.st) (void)hipStreamDestroy(s.st);
+  s = SideStream{};
+}
+
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes) {
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes,
+           const SideStream* side) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   if (!sweep_chunks_ok(chunks, max_nz)) chunks = sweep_default_chunks(max_nz);
   size_t lds = sweep_lds_bytes(prec == 0 ? 8 : 4, max_nz, chunks, max_xterms);
   const int xcap = sweep_stage_cap(max_nz, chunks, max_xterms);
   const int mw = 256 / chunks;
   const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
-#define HS_PSWEEP(RR, CC, PP, MM, SEL)                                                                   \
-  hipLaunchKernelGGL((k_psweep<RR, PP, MM, SEL>), grid, dim3(256), lds, st, d, (const CC*)tab,              \
+#define HS_PSWEEP(RR, CC, PP, MM, SEL, STREAM, LDS)                                                       \
+  hipLaunchKernelGGL((k_psweep<RR, PP, MM, SEL>), grid, dim3(256), LDS, STREAM, d, (const CC*)tab,          \
                      (const double2*)tab64, (CC*)ws, xcap)
   if (prec == 0) {
-    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false);
-    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false);
-    else HS_PSWEEP(double, double2, 8, 32, false);
+    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false, st, lds);
+    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false, st, lds);
+    else HS_PSWEEP(double, double2, 8, 32, false, st, lds);
   } else {
-    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, false);
-    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, false);
-    else HS_PSWEEP(float, float2, 8, 32, false);
+    const size_t lds64 = sweep_lds_bytes(8, max_nz, chunks, max_xterms);
+    const bool fork = fp64_modes && side && side->st;
+    hipStream_t s64 = fork ? side->st : st;
+    if (fork) {
+      (void)hipEventRecord(side->fork, st);
+      (void)hipStreamWaitEvent(s64, side->fork, 0);
+    }
     if (fp64_modes) {
-      lds = sweep_lds_bytes(8, max_nz, chunks, max_xterms);
-      if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, true);
-      else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, true);
-      else HS_PSWEEP(float, float2, 8, 32, true);
+      if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, true, s64, lds64);
+      else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, true, s64, lds64);
+      else HS_PSWEEP(float, float2, 8, 32, true, s64, lds64);
+    }
+    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, false, st, lds);
+    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, false, st, lds);
+    else HS_PSWEEP(float, float2, 8, 32, false, st, lds);
+    if (fork) {
+      (void)hipEventRecord(side->join, s64);
+      (void)hipStreamWaitEvent(st, side->join, 0);
     }
   }
 #undef HS_PSWEEP

@@ -117,8 +117,19 @@ constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 
 // max_xterms: largest number of x-type low-rank terms over the descriptors;
 // fp64_modes: complex64 only, some mode lies at or below its descriptor's
 // fp64_below (a second launch solves those workgroups in FP64).
+// side: a second stream (default priority) and two events; when given, the
+// FP64 launch runs on it beside the FP32 one (disjoint modes), joined before
+// sweep returns, so its few long workgroups overlap the bulk launch.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes);
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes,
+           const SideStream* side = nullptr);
+// creates / destroys a SideStream on the current device (false on failure)
+bool side_stream_create(SideStream& s);
+void side_stream_destroy(SideStream& s);
 int sweep_default_chunks(int nz);
 bool sweep_chunks_ok(int chunks, int nz);
 

@@ -55,6 +55,7 @@ bool check_seps(int n, const std::vector<int32_t>& s, std::string& err, const ch
 
 Plan::~Plan() {
   for (auto e : ev_pool) (void)hipEventDestroy(e);
+  side_stream_destroy(side);
   if (dtab64) (void)hipFree(dtab64);
   if (dtab32) (void)hipFree(dtab32);
   if (dtab16) (void)hipFree(dtab16);
@@ -141,6 +142,11 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   build_descriptors();
   set_fp64_threshold();
   st = upload(err);
+  if (st == HS_OK && prec == 1 && !side_stream_create(side)) {
+    (void)hipGetLastError();
+    err = "stream creation failed";
+    st = HS_ERR_DEVICE;
+  }
   plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st;
 }
@@ -950,7 +956,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0);
+          n_fp64_modes > 0, &side);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -959,7 +965,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, xterms(d_sweepB), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0);
+          n_fp64_modes > 0, &side);
     stage_end();
     stage_begin("face_contract", R * (nblk + nface) * esz, R * nblk * 4 * 8, st);
     contract(prec, p_face, cl_face, T, W, nrhs, st);
@@ -982,7 +988,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0);
+          n_fp64_modes > 0, &side);
     stage_end();
     stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
@@ -999,7 +1005,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0);
+          n_fp64_modes > 0, &side);
     stage_end();
   }
   // step 7: inverse transforms into u

@@ -109,6 +109,7 @@ struct Plan {
   int tune_chunks = 0;           // z-line chunks per mode (0 = default for NZ)
   int tune_lt = 0;               // sine-transform lines per workgroup (0 = default)
   double fp64_below = -1e300;    // complex64 path: z solves of modes with Re(lam_x + lam_y) <= this in FP64
+  SideStream side;               // complex64 path: stream of the FP64 z solves
   int64_t n_fp64_modes = 0;
 
   // ---------------- workspace (layout for max_rhs)
