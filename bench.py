@@ -117,7 +117,8 @@ def counters_run(args):
     torch.cuda.synchronize()
     info = plan.info()
     mw = 256 // info["z_chunks"]
-    print(json.dumps({"solves": 3, "global_sweep_grid": -(-p.nx * p.ny // mw) * 256,
+    tiles = -(-p.ny * (-(-p.nx // 32) * 32) // mw)      # workgroups the sweep launch provisions
+    print(json.dumps({"solves": 3, "global_sweep_grid": -(-tiles // 8) * 8 * 256,
                       "z_chunks": info["z_chunks"]}), flush=True)
 
 

@@ -94,7 +94,7 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
     spec_off.push_back(off);
     off = align_up(off + int64_t(nrhs[i]) * p->NX * p->NY * p->NZ, 64);
     max_nz = std::max(max_nz, p->NZ);
-    max_modes = std::max<int64_t>(max_modes, (int64_t)p->NX * p->NY);
+    max_modes = std::max<int64_t>(max_modes, sweep_modes_bound(p->NX, p->NY));
   }
   ws_elems = size_t(off);
   const size_t esz = prec == 0 ? 16 : 8;

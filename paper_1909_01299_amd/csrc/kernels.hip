@@ -301,7 +301,10 @@ __device__ __forceinline__ C crcp_fast(C z) {
   return r;
 }
 
-constexpr int PS_LMAX = 16;   // rows per chunk held in registers
+constexpr int PS_LMAX = 16;   // most rows per chunk held in registers
+// Register rows L of a kernel instance: 8 where the chunks are that short (half
+// the registers, twice the resident waves), else PS_LMAX.
+__host__ __device__ __forceinline__ int psweep_regrows(int lc) { return lc <= 8 ? 8 : PS_LMAX; }
 
 // Rows of a chunk: every chunk of a line has the same length, so that loop
 // bounds are uniform across the workgroup; the line is padded past nz.
@@ -315,6 +318,47 @@ __host__ __device__ __forceinline__ int psweep_rows(int nz, int chunks) {
 // discarded.
 constexpr double kPadDiag = 1099511627776.0;   // 2^40
 
+// Workgroups of a launch are dealt to the 8 XCDs in turn (each XCD has its own
+// L2). xcd_linear renumbers workgroup i of n so that every XCD takes one
+// contiguous range of the new numbers (a permutation of 0..n-1).
+__device__ __forceinline__ int xcd_linear(int i, int n) {
+  const int q = n >> 3, rm = n & 7, x = i & 7;
+  return x * q + min(x, rm) + (i >> 3);
+}
+
+// Modes of a workgroup. A solve whose right-hand side is only low-rank terms
+// (no dense input) on rows of at least MW modes: tile t covers modes
+// a0 .. a0 + MW - 1 of one row b (t = column band * nb + b), and the tiles are
+// renumbered so that an XCD takes whole column bands, whose y-type low-rank
+// lines then stay in its L2 while it walks the rows. Otherwise MW consecutive
+// modes of the plane: workgroups in flight then read one contiguous stretch
+// of a dense input, which HBM serves better than scattered rows.
+struct SweepTile {
+  bool two_d;      // one row of the plane
+  int64_t m0;      // first mode
+  int a0, b;       // first column and row (tiles)
+};
+__device__ __forceinline__ bool psweep_two_d(const SweepDesc& d, int mw) { return !d.dense_in && d.na >= mw; }
+__device__ __forceinline__ int64_t psweep_tiles(const SweepDesc& d, int mw) {
+  return psweep_two_d(d, mw) ? (int64_t)d.nb * ((d.na + mw - 1) / mw) : ((int64_t)d.na * d.nb + mw - 1) / mw;
+}
+__device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, int mw, int tiles) {
+  const int nb = d.nb, na = d.na;
+  SweepTile st;
+  st.two_d = psweep_two_d(d, mw);
+  if (st.two_d) {
+    const int t = xcd_linear(int(blockIdx.x), tiles);
+    st.a0 = (t / nb) * mw;
+    st.b = t % nb;
+    st.m0 = (int64_t)st.b * na + st.a0;
+  } else {
+    st.m0 = (int64_t)blockIdx.x * mw;
+    st.a0 = 0;
+    st.b = 0;
+  }
+  return st;
+}
+
 // RS: storage precision of the workspace arrays; R: arithmetic precision and
 // precision of the tables `tab`.
 //
@@ -327,15 +371,15 @@ constexpr double kPadDiag = 1099511627776.0;   // 2^40
 //  2. one lane per mode solves the reduced system on the chunk end values;
 //  3. every chunk is solved again with its neighbours' end values moved to the
 //     right-hand side, with the stored pivots (no divisions).
-template <typename RS, typename R, int P, int MW>
+template <typename RS, typename R, int P, int MW, int L>
 __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* __restrict__ tab,
-                                            cplx<RS>* __restrict__ ws, unsigned char* smem_raw, int xcap) {
+                                            cplx<RS>* __restrict__ ws, unsigned char* smem_raw, int xcap,
+                                            const SweepTile& tile) {
   using C = cplx<R>;
   using CS = cplx<RS>;
   using Q = typename quad_of<R>::type;
   const int na = d.na, nb = d.nb, nz = d.nz;
   const int64_t plane = (int64_t)na * nb;
-  const int64_t m0 = (int64_t)blockIdx.x * MW;
   const int Lc = psweep_rows(nz, P);
   const int nzp = P * Lc;
   Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z, padded to nzp rows
@@ -358,12 +402,12 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     zt[k] = q;
   }
   // The x-type low-rank terms G_t(b, z) are shared by every mode of a row b;
-  // the workgroup's modes lie on at most two rows when na >= MW, whose lines
-  // are staged in LDS once (rows past the line hold the last row). Staging
-  // pays where a dense right-hand side is read as well (its loads overlap);
-  // without one the extra round trip costs more than it saves.
+  // consecutive modes lie on at most two rows when na >= MW, whose lines are
+  // staged in LDS once (rows past the line hold the last row). Staging pays
+  // where a dense right-hand side is read as well (its loads overlap); without
+  // one the extra round trip costs more than it saves.
   const int r = blockIdx.z;
-  const int b_lo = int(m0 / na);
+  const int b_lo = int(tile.m0 / na);
   const bool xstage = d.dense_in && d.nxt > 0 && na >= MW && 2 * d.nxt * nzp <= xcap;
   if (xstage) {
 #pragma unroll
@@ -378,14 +422,13 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     }
   }
   const int ml = threadIdx.x % MW, j = threadIdx.x / MW;
-  const int64_t m = m0 + ml;
-  const bool mact = m < plane;
-  const int64_t mc = mact ? m : 0;
+  const bool mact = tile.two_d ? tile.a0 + ml < na : tile.m0 + ml < plane;
+  const int64_t m = mact ? tile.m0 + ml : 0;
   const int k0 = j * Lc;
   // rows addressed in memory: kb .. kb + nv - 1 (clamped into the line)
   const int kb = k0 < nz ? k0 : nz - 1;
   const int nv = k0 < nz ? min(nz - k0, Lc) : 1;
-  const int a = int(mc % na), b = int(mc / na);
+  const int a = int(m % na), b = int(m / na);
   const C s = mact ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
   auto X = [&](int f, int jj) -> C& { return xch[(jj * 6 + f) * MW + ml]; };
 
@@ -393,17 +436,17 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   // chunk or the line from the last valid row: their values only reach rows
   // that are never used or padded rows. Row offsets fit in 32 bits (a line
   // holds at most 512 planes of at most 512 x 512 modes).
-  C rb[PS_LMAX];
+  C rb[L];
   auto row_off = [&](int kk, uint32_t stride) -> uint32_t {
     return kk < nv ? uint32_t(kk) * stride : uint32_t(nv - 1) * stride;
   };
   if (d.dense_in) {
-    const CS* src = ws + d.data + (int64_t)r * d.data_r + mc + (int64_t)kb * plane;
+    const CS* src = ws + d.data + (int64_t)r * d.data_r + m + (int64_t)kb * plane;
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cvt<C>(src[row_off(kk, uint32_t(plane))]);
+    for (int kk = 0; kk < L; ++kk) rb[kk] = cvt<C>(src[row_off(kk, uint32_t(plane))]);
   } else {
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = mk<R>(0, 0);
+    for (int kk = 0; kk < L; ++kk) rb[kk] = mk<R>(0, 0);
   }
   // low-rank terms: coefficient of the mode times a line shared by a row of
   // modes; staged x-type lines are added after the barrier
@@ -418,7 +461,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
       const CS* g = (isx ? ws + d.gx[t] + (int64_t)r * d.gx_r + b : ws + d.gy[t] + (int64_t)r * d.gy_r + a) +
                     (int64_t)kb * gz;
 #pragma unroll
-      for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cfma(c, cvt<C>(g[row_off(kk, uint32_t(gz))]), rb[kk]);
+      for (int kk = 0; kk < L; ++kk) rb[kk] = cfma(c, cvt<C>(g[row_off(kk, uint32_t(gz))]), rb[kk]);
     }
   }
   __syncthreads();
@@ -430,7 +473,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
         const C c = tab[d.colx[t] + (int64_t)a * d.colx_stride[t]];
         const C* gl = gxs + (t * 2 + brow) * nzp;
 #pragma unroll
-        for (int kk = 0; kk < PS_LMAX; ++kk) rb[kk] = cfma(c, gl[min(k0 + kk, nzp - 1)], rb[kk]);
+        for (int kk = 0; kk < L; ++kk) rb[kk] = cfma(c, gl[min(k0 + kk, nzp - 1)], rb[kk]);
       }
     }
   }
@@ -438,13 +481,13 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   // 1. local eliminations: y (local solution), v (unit value in the first
   // row), w (unit value in the last row) at the chunk's last row (top-down)
   // and first row (bottom-up)
-  C ip[PS_LMAX];
+  C ip[L];
   C yl = mk<R>(0, 0), vl = mk<R>(0, 0), wl = mk<R>(0, 0);
   C yf = mk<R>(0, 0), vf = mk<R>(0, 0), wf = mk<R>(0, 0);
   {
     C cp = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk) {
+    for (int kk = 0; kk < L; ++kk) {
       if (kk < Lc) {
         const Q q = zt[k0 + kk];
         C piv;
@@ -466,7 +509,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     }
     C cn = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
+    for (int kk = L - 1; kk >= 0; --kk) {
       if (kk < Lc) {
         const Q q = zt[k0 + kk];
         C piv;
@@ -576,7 +619,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     const C XR = j + 1 < P ? X(5, j + 1) : mk<R>(0, 0);   // F_{j+1}
     C dp = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = 0; kk < PS_LMAX; ++kk) {
+    for (int kk = 0; kk < L; ++kk) {
       if (kk < Lc) {
         const Q q = zt[k0 + kk];
         C rhs = rb[kk];
@@ -591,7 +634,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     }
     C xn = mk<R>(0, 0);
 #pragma unroll
-    for (int kk = PS_LMAX - 1; kk >= 0; --kk) {
+    for (int kk = L - 1; kk >= 0; --kk) {
       if (kk < Lc) {
         const R up = zt[k0 + kk].w;
         C c;
@@ -604,7 +647,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     if (mact) {
       CS* dst = ws + d.out + (int64_t)r * d.out_r + m + (int64_t)k0 * plane;
 #pragma unroll
-      for (int kk = 0; kk < PS_LMAX; ++kk)
+      for (int kk = 0; kk < L; ++kk)
         if (kk < Lc && k0 + kk < nz) {
           // complex128 block solves: the output streams past the reused
           // low-rank lines (non-temporal stores measured faster there only)
@@ -623,7 +666,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
 // other workgroups in FP32, FP64SEL = true launches only the flagged ones.
 // Both launches evaluate the same predicate, so every workgroup runs in
 // exactly one of them, and each kernel gets its own register allocation.
-template <typename R, int P, int MW, bool FP64SEL>
+template <typename R, int P, int MW, int L, bool FP64SEL>
 __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 const double2* __restrict__ tab64,
@@ -631,23 +674,25 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
   static_assert(P * MW == 256, "256 lanes per workgroup");
   extern __shared__ unsigned char smem_raw[];
   const SweepDesc d = descs[blockIdx.y];
-  const int64_t plane = (int64_t)d.na * d.nb;
-  if ((int64_t)blockIdx.x * MW >= plane) return;
+  const int64_t tiles = psweep_tiles(d, MW);
+  if ((int64_t)blockIdx.x >= tiles) return;
+  const SweepTile tile = psweep_tile(d, MW, int(tiles));
   if constexpr (sizeof(R) == 8) {
-    psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
+    psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
   } else {
-    const int64_t m = (int64_t)blockIdx.x * MW + threadIdx.x % MW;
+    const int ml = threadIdx.x % MW;
     bool low = false;
-    if (m < plane) {
+    if (tile.two_d ? tile.a0 + ml < d.na : tile.m0 + ml < (int64_t)d.na * d.nb) {
+      const int64_t m = tile.m0 + ml;
       const int a = int(m % d.na), b = int(m / d.na);
       low = tab64[d.lam_x + a].x + tab64[d.lam_y + b].x <= d.fp64_below;
     }
     const bool wg_low = __syncthreads_or(low) != 0;
     if (wg_low != FP64SEL) return;
     if constexpr (FP64SEL)
-      psweep_body<R, double, P, MW>(d, tab64, ws, smem_raw, xcap);
+      psweep_body<R, double, P, MW, L>(d, tab64, ws, smem_raw, xcap, tile);
     else
-      psweep_body<R, R, P, MW>(d, tab, ws, smem_raw, xcap);
+      psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
   }
 }
 
@@ -1218,10 +1263,21 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
   size_t lds = sweep_lds_bytes(prec == 0 ? 8 : 4, max_nz, chunks, max_xterms);
   const int xcap = sweep_stage_cap(max_nz, chunks, max_xterms);
   const int mw = 256 / chunks;
-  const dim3 grid(unsigned((max_modes + mw - 1) / mw), ndesc, nrhs);
+  // max_modes: largest nb * (na rounded up to 32) over the descriptors, which
+  // covers the tiles of either mode packing; a multiple of 8 workgroups along
+  // x keeps workgroup i of every descriptor on XCD i mod 8
+  const int64_t tiles = (max_modes + mw - 1) / mw;
+  const dim3 grid(unsigned((tiles + 7) / 8 * 8), ndesc, nrhs);
+  const bool short_rows = psweep_regrows(psweep_rows(max_nz, chunks)) == 8;
 #define HS_PSWEEP(RR, CC, PP, MM, SEL, STREAM, LDS)                                                       \
-  hipLaunchKernelGGL((k_psweep<RR, PP, MM, SEL>), grid, dim3(256), LDS, STREAM, d, (const CC*)tab,          \
-                     (const double2*)tab64, (CC*)ws, xcap)
+  do {                                                                                                     \
+    if (short_rows)                                                                                        \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, 8, SEL>), grid, dim3(256), LDS, STREAM, d, (const CC*)tab,  \
+                         (const double2*)tab64, (CC*)ws, xcap);                                            \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, PS_LMAX, SEL>), grid, dim3(256), LDS, STREAM, d,            \
+                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap);                            \
+  } while (0)
   if (prec == 0) {
     if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false, st, lds);
     else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false, st, lds);

@@ -109,7 +109,7 @@ void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles1
 int xform_y_tiles(const XformYDesc& d, int ct);
 
 // z solves: LDS of one workgroup (z tables + chunk-end exchange), and the
-// batched launch over descriptors (max_modes = largest na * nb).
+// batched launch over descriptors (max_modes = largest sweep_modes_bound(na, nb)).
 size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms);
 constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
 // chunks: z-line chunks per mode (8, 16 or 32, each at most 16 rows; 256 / chunks
@@ -131,6 +131,8 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 bool side_stream_create(SideStream& s);
 void side_stream_destroy(SideStream& s);
 int sweep_default_chunks(int nz);
+// modes a launch provisions for one descriptor of na x nb modes
+inline int64_t sweep_modes_bound(int na, int nb) { return (int64_t)nb * ((na + 31) / 32 * 32); }
 bool sweep_chunks_ok(int chunks, int nz);
 
 // Fused two-axis contractions of spectral arrays (each array read once).

@@ -921,7 +921,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   };
   auto modes = [](const std::vector<SweepDesc>& v) {
     int64_t m = 0;
-    for (auto& d : v) m = std::max<int64_t>(m, (int64_t)d.na * d.nb);
+    for (auto& d : v) m = std::max<int64_t>(m, sweep_modes_bound(d.na, d.nb));
     return m;
   };
   // algorithmic work of the stages (per call, all right-hand sides)

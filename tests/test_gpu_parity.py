@@ -86,10 +86,11 @@ def test_sine_fft_path_vs_oracle_and_dense(hs, shape):
     assert per_rhs_err(um, u) < TOL64R
 
 
-@pytest.mark.parametrize("nz", [2, 3, 31, 32, 33, 255, 256, 257, 300, 512])
+@pytest.mark.parametrize("nz", [2, 3, 31, 32, 33, 128, 129, 255, 256, 257, 300, 512])
 def test_z_line_lengths_vs_oracle(hs, nz):
     """z solves split each line into up to 16 (32 beyond 256 rows) chunks;
-    cover short lines, chunk-count boundaries and ragged chunks."""
+    cover short lines, chunk-count boundaries, ragged chunks and the switch
+    between 8 and 16 register rows per chunk (128 / 129 rows in 16 chunks)."""
     rng = np.random.default_rng(nz)
     p = W.random_problem(9, 7, nz, min(5, nz), rng, pml_x=2)
     f = W.complex_normal(rng, (1,) + p.shape)
