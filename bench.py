@@ -303,6 +303,57 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
     return out
 
 
+def bench_c5(steps, refine_steps=1):
+    """Large decomposed grid: core 512 + 32 PML cells per side (575 x 575
+    interior nodes), n_z = 256 in 60 layers, 16 point sources off the
+    separators, k^2 scaled by omega^2 for omega in (1, 1.5, 2, 3).  One plan
+    per precision; each frequency is one k^2 update (hs_set_k2, not timed)
+    followed by solves of all 16 right-hand sides at once.  The relative
+    residual |f - A u| / |f| of the last solve (FP64 stencil on the GPU) is
+    reported per frequency; parity with the oracle at this size is a test."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    p, srcs, omegas = W.c5_multi_rhs()
+    nrhs = len(srcs)
+    f = torch.zeros((nrhs,) + p.shape, dtype=torch.complex128, device="cuda")
+    for r, (x, y, z) in enumerate(srcs):
+        f[r, z, y, x] = 1.0
+    u = torch.empty_like(f)
+    out = {"workload": f"c5_large {p.nx}x{p.ny}x{p.nz}, 4x4 blocks + interface reduction, PML 32/side, "
+                       f"60 layers, {nrhs} point sources x {len(omegas)} frequencies",
+           "unknowns": p.unknowns, "nrhs": nrhs, "omegas": list(omegas)}
+    fnorm = float(torch.linalg.vector_norm(f[0]))
+    for prec in ("c128", "mixed"):
+        t0 = time.perf_counter()
+        plan = hs.Plan(p, prec, max_rhs=nrhs, refine_steps=refine_steps if prec == "mixed" else 0)
+        t_plan = time.perf_counter() - t0
+        total = 0.0
+        resid = []
+        for om in omegas:
+            plan.set_k2(p.k2 * om ** 2)
+            plan.solve(f, out=u)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.solve(f, out=u)
+            torch.cuda.synchronize()
+            total += (time.perf_counter() - t0) / steps
+            r = plan.residual(f[:1], u[:1])
+            resid.append(float(torch.linalg.vector_norm(r)) / fnorm)
+            del r
+        rec = {"value": p.unknowns * nrhs * len(omegas) / total, "unit": "unknowns*RHS/s",
+               "ms_per_frequency": total / len(omegas) * 1e3, "plan_seconds": t_plan,
+               "rel_residual_rhs0_per_omega": resid}
+        if prec == "mixed":
+            rec["refine_steps"] = plan.info()["refine_steps"]
+        out[prec] = rec
+        del plan
+        torch.cuda.empty_cache()
+    out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +376,8 @@ def main():
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--global-grid", type=int, default=0, help="grid size of the global sweep (--counters prints it)")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
+    ap.add_argument("--c5-only", action="store_true",
+                    help="time only the large 575x575x256 grid, 16 sources x 4 frequencies (c128 vs mixed)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
     args = ap.parse_args()
@@ -350,6 +403,9 @@ def main():
         return
     if args.counters:
         counters_run(args)
+        return
+    if args.c5_only:
+        print(json.dumps(bench_c5(max(1, min(args.steps, 3)), refine_steps=args.refine_steps)), flush=True)
         return
 
     import torch
