@@ -11,7 +11,11 @@ Workload (one step = one full solve of the decomposed grid):
 Prints one JSON line: unknowns*RHS/s of the complex128 solve, the mixed
 complex64 + FP64-refinement solve beside it, the roofline of the dominant
 kernel from hipEvents recorded on the solve's stream, and the FP64 CPU oracle
-timed on the host.
+timed on the host.  The same line carries two more workloads, each in
+complex128 and in mixed precision: 64 independent blocks of uneven sizes with
+8 right-hand sides each as one captured graph per solve ("batched_c3"), and
+the large 575 x 575 x 256 grid with 16 point sources at 4 frequencies
+("large_c5").
 """
 from __future__ import annotations
 
@@ -42,30 +46,45 @@ def kernel_source_hash() -> str:
 
 
 def time_solves(plan, f, u, steps, warmup, profile=True):
+    """Wall time of `steps` solves.  With profile: an untimed run of as many
+    solves with hipEvents around every stage (on the solve's stream) gives the
+    stage table and the dominant stage; in the timed run only that stage is
+    bracketed by events (two per solve), so its kernel time is measured over
+    the timed region itself.  Returns (seconds, stage table, dominant stage
+    record from the timed region)."""
     import torch
     for _ in range(warmup):
         plan.solve(f, out=u)
     torch.cuda.synchronize()
+    stages, dom = [], None
     if profile:
         plan.profile(True)
         plan.profile_read()          # reset accumulators
+        for _ in range(steps):
+            plan.solve(f, out=u)
+        torch.cuda.synchronize()
+        stages = plan.profile_read()
+        top = max(stages, key=lambda s: s["ms"])["name"]
+        plan.profile(True, only=top)
+        plan.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.solve(f, out=u)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stages = plan.profile_read() if profile else []
     if profile:
+        rec = [s for s in plan.profile_read() if s["launches"] > 0]
+        dom = rec[0] if rec else None
         plan.profile(False)
-    return dt, stages
+    return dt, stages, dom
 
 
-def roofline(stages, prec):
-    """Dominant stage by total time; bound from its algorithmic bytes/flops."""
-    if not stages:
+def roofline(top, prec):
+    """Roofline of the dominant stage (its events from the timed region):
+    bound from its algorithmic bytes/flops per launch."""
+    if not top:
         return None
-    top = max(stages, key=lambda s: s["ms"])
     avg_s = top["ms"] / top["launches"] / 1e3
     peak_flops = PEAK_F64 if prec == "c128" else PEAK_F32
     t_mem = top["bytes_per_launch"] / PEAK_HBM
@@ -183,18 +202,30 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
     print(json.dumps(out), flush=True)
 
 
-def stats_summary(trace_csv: str, title: str, command: str):
+def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool = False):
     """Text summary of a rocprofv3 kernel trace: per kernel and grid, the
-    number of dispatches, the average duration and the share of the total."""
+    number of dispatches, the average duration and the share of the total.
+    stage_labels (complex128 decomposed solves): z sweeps over one plane are
+    the global solve; the block sweeps of a solve run twice, v then u, and
+    are listed apart."""
     import csv
     import re
     agg = {}
+    seen = {}
     with open(trace_csv) as fh:
-        for r in csv.DictReader(fh):
+        rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
+        for r in rows:
             name = r["Kernel_Name"].replace("hs::(anonymous namespace)::", "")
             name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", name)
             name = re.sub(r"\(hs::.*|\(.*", "", name).replace("void ", "")
             grid = "x".join(r["Grid_Size_" + a] for a in "XYZ")
+            if stage_labels and name.startswith("k_psweep"):
+                if r["Grid_Size_Y"] == "1":
+                    name += " [zsweep_global]"
+                else:
+                    n = seen.get((name, grid), 0)
+                    seen[(name, grid)] = n + 1
+                    name += " [zsweep_blocks_v]" if n % 2 == 0 else " [zsweep_blocks_u]"
             key = (name, grid)
             a = agg.setdefault(key, [0, 0.0])
             a[0] += 1
@@ -367,6 +398,7 @@ def main():
     ap.add_argument("--nz", type=int, default=200)
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
+    ap.add_argument("--no-c5", action="store_true", help="skip the large 575x575x256 measurement")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--refine-steps", type=int, default=1,
                     help="FP64-residual refinement steps of the mixed-precision solves (-1: none)")
@@ -380,12 +412,14 @@ def main():
                     help="time only the large 575x575x256 grid, 16 sources x 4 frequencies (c128 vs mixed)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
+    ap.add_argument("--stage-labels", action="store_true",
+                    help="with --stats-summary: list the z sweeps of decomposed solves by stage")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.global_grid)
         return
     if args.stats_summary:
-        stats_summary(*args.stats_summary)
+        stats_summary(*args.stats_summary, stage_labels=args.stage_labels)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -421,13 +455,13 @@ def main():
     if args.mixed_only:
         plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
         um = torch.empty_like(f)
-        dtm, _ = time_solves(plan_m, f, um, args.steps, args.warmup, profile=False)
+        dtm, _, _ = time_solves(plan_m, f, um, args.steps, args.warmup, profile=False)
         print(json.dumps({"mixed_ms_per_step": dtm / args.steps * 1e3}), flush=True)
         return
     plan = hs.Plan(p, "c128", max_rhs=nrhs)
     tuned = plan.tune(nrhs)
     info = plan.info()
-    dt, stages = time_solves(plan, f, u, args.steps, args.warmup)
+    dt, stages, dom = time_solves(plan, f, u, args.steps, args.warmup)
     ms = dt / args.steps * 1e3
     value = p.unknowns * nrhs / (dt / args.steps)
     u_gpu = u.cpu().numpy()
@@ -437,10 +471,10 @@ def main():
         plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
         plan_m.tune(nrhs)
         um = torch.empty_like(f)
-        dtm, stages_m = time_solves(plan_m, f, um, args.steps, args.warmup)
+        dtm, stages_m, dom_m = time_solves(plan_m, f, um, args.steps, args.warmup)
         mixed = {"value": p.unknowns * nrhs / (dtm / args.steps), "ms_per_step": dtm / args.steps * 1e3,
                  "refine_steps": plan_m.info()["refine_steps"], "u": um.cpu().numpy(),
-                 "roofline": roofline(stages_m, "c64"),
+                 "roofline": roofline(dom_m, "c64"),
                  "stages": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages_m}}
         del plan_m
 
@@ -457,8 +491,12 @@ def main():
         del plan
         torch.cuda.empty_cache()
         c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline, refine_steps=args.refine_steps)
+    c5 = None
+    if not args.no_c5:
+        torch.cuda.empty_cache()
+        c5 = bench_c5(2, refine_steps=args.refine_steps)
 
-    rf = roofline(stages, "c128")
+    rf = roofline(dom, "c128")
     if rf is not None:
         rf["traffic"] = traffic_for(rf["kernel"])
     line = {
@@ -486,6 +524,7 @@ def main():
             "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"],
             "stages_ms_per_step": mixed["stages"]},
         "batched_c3": c3,
+        "large_c5": c5,
         "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
         "plan_seconds": info["plan_seconds"],
         "tuned": tuned,

@@ -189,6 +189,11 @@ typedef struct {
 } hs_stage_time;
 
 hs_status hs_profile_enable(hs_plan plan, int32_t on);
+/* Restrict the events of enabled profiling to the stage named `stage` (a name
+ * hs_profile_read reports; other stages then record nothing and add no
+ * events to the stream), or record every stage again (stage = NULL).  Names
+ * of 32 or more characters are HS_ERR_ARG; an unknown name records nothing. */
+hs_status hs_profile_only(hs_plan plan, const char* stage);
 hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int32_t* n_out);
 
 /* Batched solve of many independent plans (one block each, any sizes) and

@@ -85,6 +85,7 @@ EXPORTS = {
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "hs_profile_only": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "hs_axis_eig": (ctypes.c_int, [ctypes.c_int32] + [ctypes.c_void_p] * 5),
     "hs_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -213,8 +214,10 @@ class Plan:
         inf = self.info()
         return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"]}
 
-    def profile(self, on: bool = True):
-        """Record hipEvents around every stage of subsequent solves."""
+    def profile(self, on: bool = True, only: Optional[str] = None):
+        """Record hipEvents around every stage of subsequent solves, or only
+        around the stage named `only`."""
+        _check(lib().hs_profile_only(self._h, None if only is None else only.encode()))
         _check(lib().hs_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self) -> list:

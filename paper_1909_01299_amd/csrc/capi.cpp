@@ -150,6 +150,13 @@ hs_status hs_profile_enable(hs_plan plan, int32_t on) {
   return ret(plan->p.profile_enable(on != 0, err), err);
 }
 
+hs_status hs_profile_only(hs_plan plan, const char* stage) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  if (stage && std::strlen(stage) >= sizeof(hs_stage_time{}.name)) return ret(HS_ERR_ARG, "stage name too long");
+  plan->p.prof_only = stage ? stage : "";
+  return ret(HS_OK, "");
+}
+
 hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int32_t* n_out) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
   std::string err;

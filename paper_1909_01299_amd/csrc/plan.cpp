@@ -828,7 +828,7 @@ hs_status Plan::profile_enable(bool on, std::string& err) {
 }
 
 void Plan::stage_begin(const char* name, double bytes, double flops, hipStream_t st) {
-  if (!prof_on) return;
+  if (!prof_on || (!prof_only.empty() && prof_only != name)) return;
   int id = -1;
   for (size_t i = 0; i < prof.size(); ++i)
     if (prof[i].name == name) { id = int(i); break; }

@@ -145,6 +145,7 @@ struct Plan {
 
   // ---------------- per-stage event timing
   bool prof_on = false;
+  std::string prof_only;   // non-empty: only this stage records events
   std::vector<StageProf> prof;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
