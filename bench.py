@@ -189,7 +189,13 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
                 continue
             rec = stages.setdefault(lab, {"fetch_kib": [], "write_kib": []})
             rec[key + "_kib"].append(r[3])
-    out = {"source_hash": kernel_source_hash(), "copy_scale": scale, "stages": {}}
+    run = "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 $R/bench.py {a}"
+    out = {"source_hash": kernel_source_hash(),
+           "commands (R = repository root)": [
+               run.format(c="FETCH_SIZE", d=fdir, a="--counters"), run.format(c="WRITE_SIZE", d=wdir, a="--counters"),
+               run.format(c="FETCH_SIZE", d=cfdir, a="--copy"), run.format(c="WRITE_SIZE", d=cwdir, a="--copy"),
+               f"python3 $R/bench.py --traffic-summary {fdir} {wdir} {cfdir} {cwdir} --global-grid {global_grid}"],
+           "copy_scale": scale, "stages": {}}
     for lab, rec in stages.items():
         fk = float(np.mean(rec["fetch_kib"])) if rec["fetch_kib"] else 0.0
         wk = float(np.mean(rec["write_kib"])) if rec["write_kib"] else 0.0
