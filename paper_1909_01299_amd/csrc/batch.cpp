@@ -222,6 +222,21 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
   partition_y(prec, s_fwdy.dense); partition_y(prec, s_invy.dense);
   reg_stage(s_fwdx); reg_stage(s_fwdx_res); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
   reg(d_sweep, &p_sweep);
+  // near-resonance selections: every descriptor reads its own plan's FP64 table
+  for (int c = 0; c < 3; ++c) {
+    sel_dev[c] = SweepSel{};
+    sel_host[c] = SweepSelHost{};
+    if (prec != 1 || !sweep_chunks_ok(8 << c, max_nz)) continue;
+    auto lam_re = [&](int64_t off) {
+      const size_t i = size_t(std::upper_bound(tab_off.begin(), tab_off.end(), off) - tab_off.begin()) - 1;
+      return plans[i]->htab[off - tab_off[i]].real();
+    };
+    sweep_select(d_sweep.data(), int(d_sweep.size()), max_modes, 8 << c, lam_re, sel_host[c]);
+    sel_dev[c].n = int(sel_host[c].list.size());
+    sel_dev[c].words = sel_host[c].words;
+    reg(sel_host[c].list, &sel_dev[c].list);
+    reg(sel_host[c].bits, &sel_dev[c].bits);
+  }
   if (blob.size() > ddesc_bytes) {
     if (ddesc) (void)hipFree(ddesc);
     ddesc = nullptr;
@@ -267,13 +282,11 @@ void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
 }
 
 void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
-  bool any_fp64 = false;
-  for (const Plan* p : plans) any_fp64 = any_fp64 || p->n_fp64_modes > 0;
   auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
     sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks,
-          any_fp64, &side);
+          prec == 1 ? sel_dev : nullptr, &side);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

@@ -40,6 +40,9 @@ struct Batch {
   StageList<XformYDesc> s_fwdy, s_invy;
   std::vector<SweepDesc> d_sweep;
   const SweepDesc* p_sweep = nullptr;
+  // complex64: near-resonance selection of d_sweep for chunk counts 8, 16, 32
+  SweepSelHost sel_host[3];
+  SweepSel sel_dev[3];
   void* ddesc = nullptr;
   size_t ddesc_bytes = 0;
   // graph

@@ -9,6 +9,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <functional>
+
 namespace hs {
 
 namespace {
@@ -321,9 +323,9 @@ constexpr double kPadDiag = 1099511627776.0;   // 2^40
 // Workgroups of a launch are dealt to the 8 XCDs in turn (each XCD has its own
 // L2). xcd_linear renumbers workgroup i of n so that every XCD takes one
 // contiguous range of the new numbers (a permutation of 0..n-1).
-__device__ __forceinline__ int xcd_linear(int i, int n) {
+__host__ __device__ __forceinline__ int xcd_linear(int i, int n) {
   const int q = n >> 3, rm = n & 7, x = i & 7;
-  return x * q + min(x, rm) + (i >> 3);
+  return x * q + (x < rm ? x : rm) + (i >> 3);
 }
 
 // Modes of a workgroup. A solve whose right-hand side is only low-rank terms
@@ -338,25 +340,34 @@ struct SweepTile {
   int64_t m0;      // first mode
   int a0, b;       // first column and row (tiles)
 };
-__device__ __forceinline__ bool psweep_two_d(const SweepDesc& d, int mw) { return !d.dense_in && d.na >= mw; }
-__device__ __forceinline__ int64_t psweep_tiles(const SweepDesc& d, int mw) {
+__host__ __device__ __forceinline__ bool psweep_two_d(const SweepDesc& d, int mw) {
+  return !d.dense_in && d.na >= mw;
+}
+__host__ __device__ __forceinline__ int64_t psweep_tiles(const SweepDesc& d, int mw) {
   return psweep_two_d(d, mw) ? (int64_t)d.nb * ((d.na + mw - 1) / mw) : ((int64_t)d.na * d.nb + mw - 1) / mw;
 }
-__device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, int mw, int tiles) {
+// tile of workgroup wg < tiles
+__host__ __device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, int mw, int tiles, int wg) {
   const int nb = d.nb, na = d.na;
   SweepTile st;
   st.two_d = psweep_two_d(d, mw);
   if (st.two_d) {
-    const int t = xcd_linear(int(blockIdx.x), tiles);
+    const int t = xcd_linear(wg, tiles);
     st.a0 = (t / nb) * mw;
     st.b = t % nb;
     st.m0 = (int64_t)st.b * na + st.a0;
   } else {
-    st.m0 = (int64_t)blockIdx.x * mw;
+    st.m0 = (int64_t)wg * mw;
     st.a0 = 0;
     st.b = 0;
   }
   return st;
+}
+// mode ml (< mw) of a tile: false past the row (tiles) or the plane
+__host__ __device__ __forceinline__ bool psweep_mode(const SweepDesc& d, const SweepTile& t, int ml, int64_t& m) {
+  const bool on = t.two_d ? t.a0 + ml < d.na : t.m0 + ml < (int64_t)d.na * d.nb;
+  m = on ? t.m0 + ml : 0;
+  return on;
 }
 
 // RS: storage precision of the workspace arrays; R: arithmetic precision and
@@ -422,8 +433,8 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     }
   }
   const int ml = threadIdx.x % MW, j = threadIdx.x / MW;
-  const bool mact = tile.two_d ? tile.a0 + ml < na : tile.m0 + ml < plane;
-  const int64_t m = mact ? tile.m0 + ml : 0;
+  int64_t m;
+  const bool mact = psweep_mode(d, tile, ml, m);
   const int k0 = j * Lc;
   // rows addressed in memory: kb .. kb + nv - 1 (clamped into the line)
   const int kb = k0 < nz ? k0 : nz - 1;
@@ -662,38 +673,35 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
 
 // complex128: every workgroup runs the FP64 body. complex64 storage: a
 // workgroup holding a mode near resonance (small Re(lam_x + lam_y)) runs its z
-// solves in FP64 from the FP64 tables; FP64SEL = false launches solve the
-// other workgroups in FP32, FP64SEL = true launches only the flagged ones.
-// Both launches evaluate the same predicate, so every workgroup runs in
-// exactly one of them, and each kernel gets its own register allocation.
+// solves in FP64 from the FP64 tables.  The host lists those workgroups once
+// per k^2 and chunking (SweepSel): FP64SEL = true launches run exactly the
+// listed (descriptor, workgroup) pairs, FP64SEL = false launches skip the
+// workgroups whose bit is set and solve the others in FP32.  Every workgroup
+// thus runs in exactly one of them, and each kernel gets its own register
+// allocation.
 template <typename R, int P, int MW, int L, bool FP64SEL>
 __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 const double2* __restrict__ tab64,
-                                                cplx<R>* __restrict__ ws, int xcap) {
+                                                cplx<R>* __restrict__ ws, int xcap, SweepSel sel) {
   static_assert(P * MW == 256, "256 lanes per workgroup");
   extern __shared__ unsigned char smem_raw[];
-  const SweepDesc d = descs[blockIdx.y];
-  const int64_t tiles = psweep_tiles(d, MW);
-  if ((int64_t)blockIdx.x >= tiles) return;
-  const SweepTile tile = psweep_tile(d, MW, int(tiles));
-  if constexpr (sizeof(R) == 8) {
-    psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
-  } else {
-    const int ml = threadIdx.x % MW;
-    bool low = false;
-    if (tile.two_d ? tile.a0 + ml < d.na : tile.m0 + ml < (int64_t)d.na * d.nb) {
-      const int64_t m = tile.m0 + ml;
-      const int a = int(m % d.na), b = int(m / d.na);
-      low = tab64[d.lam_x + a].x + tab64[d.lam_y + b].x <= d.fp64_below;
-    }
-    const bool wg_low = __syncthreads_or(low) != 0;
-    if (wg_low != FP64SEL) return;
-    if constexpr (FP64SEL)
-      psweep_body<R, double, P, MW, L>(d, tab64, ws, smem_raw, xcap, tile);
-    else
-      psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
+  int di = int(blockIdx.y), wg = int(blockIdx.x);
+  if constexpr (FP64SEL) {
+    const int2 e = sel.list[blockIdx.x];
+    di = e.x;
+    wg = e.y;
+  } else if (sel.bits && ((sel.bits[(int64_t)di * sel.words + (wg >> 5)] >> (wg & 31)) & 1u)) {
+    return;
   }
+  const SweepDesc d = descs[di];
+  const int64_t tiles = psweep_tiles(d, MW);
+  if ((int64_t)wg >= tiles) return;
+  const SweepTile tile = psweep_tile(d, MW, int(tiles), wg);
+  if constexpr (sizeof(R) == 8 || !FP64SEL)
+    psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
+  else
+    psweep_body<R, double, P, MW, L>(d, tab64, ws, smem_raw, xcap, tile);
 }
 
 
@@ -1255,35 +1263,75 @@ void side_stream_destroy(SideStream& s) {
   s = SideStream{};
 }
 
+int sweep_effective_chunks(int chunks, int max_nz) {
+  return sweep_chunks_ok(chunks, max_nz) ? chunks : sweep_default_chunks(max_nz);
+}
+
+// max_modes: largest nb * (na rounded up to 32) over the descriptors, which
+// covers the tiles of either mode packing; a multiple of 8 workgroups along x
+// keeps workgroup i of every descriptor on XCD i mod 8
+int sweep_grid_x(int64_t max_modes, int chunks) {
+  const int mw = 256 / chunks;
+  const int64_t tiles = (max_modes + mw - 1) / mw;
+  return int((tiles + 7) / 8 * 8);
+}
+
+void sweep_select(const SweepDesc* d, int ndesc, int64_t max_modes, int chunks,
+                  const std::function<double(int64_t)>& lam_re, SweepSelHost& out) {
+  const int mw = 256 / chunks;
+  out.words = (sweep_grid_x(max_modes, chunks) + 31) / 32;
+  out.list.clear();
+  out.bits.assign(size_t(ndesc) * out.words, 0u);
+  for (int di = 0; di < ndesc; ++di) {
+    const SweepDesc& s = d[di];
+    const int64_t tiles = psweep_tiles(s, mw);
+    for (int wg = 0; wg < tiles; ++wg) {
+      const SweepTile t = psweep_tile(s, mw, int(tiles), wg);
+      bool low = false;
+      for (int ml = 0; ml < mw && !low; ++ml) {
+        int64_t m;
+        if (!psweep_mode(s, t, ml, m)) continue;
+        const int a = int(m % s.na), b = int(m / s.na);
+        low = lam_re(s.lam_x + a) + lam_re(s.lam_y + b) <= s.fp64_below;
+      }
+      if (low) {
+        out.list.push_back(make_int2(di, wg));
+        out.bits[size_t(di) * out.words + (wg >> 5)] |= 1u << (wg & 31);
+      }
+    }
+  }
+}
+
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes,
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, const SweepSel* sel,
            const SideStream* side) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
-  if (!sweep_chunks_ok(chunks, max_nz)) chunks = sweep_default_chunks(max_nz);
+  chunks = sweep_effective_chunks(chunks, max_nz);
   size_t lds = sweep_lds_bytes(prec == 0 ? 8 : 4, max_nz, chunks, max_xterms);
   const int xcap = sweep_stage_cap(max_nz, chunks, max_xterms);
-  const int mw = 256 / chunks;
-  // max_modes: largest nb * (na rounded up to 32) over the descriptors, which
-  // covers the tiles of either mode packing; a multiple of 8 workgroups along
-  // x keeps workgroup i of every descriptor on XCD i mod 8
-  const int64_t tiles = (max_modes + mw - 1) / mw;
-  const dim3 grid(unsigned((tiles + 7) / 8 * 8), ndesc, nrhs);
+  const dim3 grid(unsigned(sweep_grid_x(max_modes, chunks)), ndesc, nrhs);
+  // complex64: the selection made for this chunking (one per chunk count)
+  SweepSel sc{};
+  if (prec != 0 && sel) sc = sel[chunks == 8 ? 0 : chunks == 16 ? 1 : 2];
+  if (sc.n == 0) sc.bits = nullptr;   // nothing selected: no bit to test
   const bool short_rows = psweep_regrows(psweep_rows(max_nz, chunks)) == 8;
-#define HS_PSWEEP(RR, CC, PP, MM, SEL, STREAM, LDS)                                                       \
+#define HS_PSWEEP(RR, CC, PP, MM, SEL, STREAM, LDS, GRID)                                                 \
   do {                                                                                                     \
     if (short_rows)                                                                                        \
-      hipLaunchKernelGGL((k_psweep<RR, PP, MM, 8, SEL>), grid, dim3(256), LDS, STREAM, d, (const CC*)tab,  \
-                         (const double2*)tab64, (CC*)ws, xcap);                                            \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, 8, SEL>), GRID, dim3(256), LDS, STREAM, d, (const CC*)tab,  \
+                         (const double2*)tab64, (CC*)ws, xcap, sc);                                        \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_psweep<RR, PP, MM, PS_LMAX, SEL>), grid, dim3(256), LDS, STREAM, d,            \
-                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap);                            \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, PS_LMAX, SEL>), GRID, dim3(256), LDS, STREAM, d,            \
+                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap, sc);                        \
   } while (0)
   if (prec == 0) {
-    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false, st, lds);
-    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false, st, lds);
-    else HS_PSWEEP(double, double2, 8, 32, false, st, lds);
+    if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false, st, lds, grid);
+    else if (chunks == 16) HS_PSWEEP(double, double2, 16, 16, false, st, lds, grid);
+    else HS_PSWEEP(double, double2, 8, 32, false, st, lds, grid);
   } else {
     const size_t lds64 = sweep_lds_bytes(8, max_nz, chunks, max_xterms);
+    const bool fp64_modes = sc.n > 0;
+    const dim3 grid64(unsigned(sc.n), 1, nrhs);
     const bool fork = fp64_modes && side && side->st;
     hipStream_t s64 = fork ? side->st : st;
     if (fork) {
@@ -1291,13 +1339,13 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
       (void)hipStreamWaitEvent(s64, side->fork, 0);
     }
     if (fp64_modes) {
-      if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, true, s64, lds64);
-      else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, true, s64, lds64);
-      else HS_PSWEEP(float, float2, 8, 32, true, s64, lds64);
+      if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, true, s64, lds64, grid64);
+      else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, true, s64, lds64, grid64);
+      else HS_PSWEEP(float, float2, 8, 32, true, s64, lds64, grid64);
     }
-    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, false, st, lds);
-    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, false, st, lds);
-    else HS_PSWEEP(float, float2, 8, 32, false, st, lds);
+    if (chunks == 32) HS_PSWEEP(float, float2, 32, 8, false, st, lds, grid);
+    else if (chunks == 16) HS_PSWEEP(float, float2, 16, 16, false, st, lds, grid);
+    else HS_PSWEEP(float, float2, 8, 32, false, st, lds, grid);
     if (fork) {
       (void)hipEventRecord(side->join, s64);
       (void)hipStreamWaitEvent(st, side->join, 0);

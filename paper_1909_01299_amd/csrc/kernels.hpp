@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <complex>
+#include <functional>
 #include <vector>
 
 #include "common.hpp"
@@ -115,8 +116,6 @@ constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 
 // chunks: z-line chunks per mode (8, 16 or 32, each at most 16 rows; 256 / chunks
 // modes per workgroup); 0 or an unusable value = default for max_nz
 // max_xterms: largest number of x-type low-rank terms over the descriptors;
-// fp64_modes: complex64 only, some mode lies at or below its descriptor's
-// fp64_below (a second launch solves those workgroups in FP64).
 // side: a second stream (default priority) and two events; when given, the
 // FP64 launch runs on it beside the FP32 one (disjoint modes), joined before
 // sweep returns, so its few long workgroups overlap the bulk launch.
@@ -124,8 +123,33 @@ struct SideStream {
   hipStream_t st = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
 };
+// Near-resonance selection of a complex64 sweep launch for one chunk count:
+// the (descriptor, workgroup) pairs whose workgroup holds a mode with
+// Re(lam_x + lam_y) <= its descriptor's fp64_below (run by the FP64 launch),
+// and the same as one bit per workgroup (skipped by the FP32 launch), `words`
+// 32-bit words per descriptor.  Device pointers; n = 0: no FP64 launch.
+struct SweepSel {
+  const int2* list = nullptr;
+  const uint32_t* bits = nullptr;
+  int n = 0, words = 0;
+};
+struct SweepSelHost {
+  std::vector<int2> list;
+  std::vector<uint32_t> bits;
+  int words = 0;
+};
+// chunk count a sweep launch uses for a requested one (0 or unusable: default)
+int sweep_effective_chunks(int chunks, int max_nz);
+// workgroups along x of a sweep launch
+int sweep_grid_x(int64_t max_modes, int chunks);
+// host: selection of descriptors d[0..ndesc) for the launch shape of
+// (max_modes, chunks); lam_re(off) is the real part of the FP64 table at off
+void sweep_select(const SweepDesc* d, int ndesc, int64_t max_modes, int chunks,
+                  const std::function<double(int64_t)>& lam_re, SweepSelHost& out);
+// sel: complex64 only, three selections (chunk counts 8, 16, 32) or NULL (no
+// mode in FP64)
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
-           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, bool fp64_modes,
+           const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, const SweepSel* sel,
            const SideStream* side = nullptr);
 // creates / destroys a SideStream on the current device (false on failure)
 bool side_stream_create(SideStream& s);

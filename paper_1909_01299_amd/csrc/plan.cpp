@@ -751,10 +751,39 @@ hs_status Plan::upload_descs(std::string& err) {
   reg(d_sweep, &p_sweep); reg(d_sweepB, &p_sweepB); reg(d_sweepC, &p_sweepC); reg(d_sweepG, &p_sweepG);
   reg(d_face, &p_face); reg(d_sig, &p_sig);
   reg(d_lift, &p_lift);
-  if (!ddesc && hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
+  // near-resonance selections (their sizes follow k^2)
+  const std::vector<SweepDesc>* lists[4] = {&d_sweep, &d_sweepB, &d_sweepC, &d_sweepG};
+  for (int i = 0; i < 4; ++i)
+    for (int c = 0; c < 3; ++c) {
+      SweepSelHost& h = sel_host[i][c];
+      SweepSel& sd = sel_dev[i][c];
+      sd = SweepSel{};
+      h = SweepSelHost{};
+      const int chunks = 8 << c;
+      if (prec != 1 || lists[i]->empty() || !sweep_chunks_ok(chunks, NZ)) continue;
+      sweep_select(lists[i]->data(), int(lists[i]->size()), sweep_modes(*lists[i]), chunks,
+                   [&](int64_t off) { return htab[off].real(); }, h);
+      sd.n = int(h.list.size());
+      sd.words = h.words;
+      reg(h.list, &sd.list);
+      reg(h.bits, &sd.bits);
+    }
+  if (blob.size() > ddesc_bytes) {
+    if (ddesc) (void)hipFree(ddesc);
+    ddesc = nullptr;
+    ddesc_bytes = 0;
+    if (hipMalloc(&ddesc, std::max<size_t>(blob.size(), 256)) != hipSuccess) return fail("descriptors");
+    ddesc_bytes = std::max<size_t>(blob.size(), 256);
+  }
   if (hipMemcpy(ddesc, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return fail("descriptors");
   for (auto& f : fx) *f.dst = (const unsigned char*)ddesc + f.off;
   return HS_OK;
+}
+
+int64_t Plan::sweep_modes(const std::vector<SweepDesc>& v) {
+  int64_t m = 0;
+  for (auto& d : v) m = std::max<int64_t>(m, sweep_modes_bound(d.na, d.nb));
+  return m;
 }
 
 hs_status Plan::set_k2(const double* k2v, std::string& err) {
@@ -919,11 +948,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     for (auto& d : v) m = std::max(m, d.nxt);
     return m;
   };
-  auto modes = [](const std::vector<SweepDesc>& v) {
-    int64_t m = 0;
-    for (auto& d : v) m = std::max<int64_t>(m, sweep_modes_bound(d.na, d.nb));
-    return m;
-  };
+  auto modes = [](const std::vector<SweepDesc>& v) { return sweep_modes(v); };
+  auto sel = [&](int list) -> const SweepSel* { return prec == 1 ? sel_dev[list] : nullptr; };
   // algorithmic work of the stages (per call, all right-hand sides)
   const double R = nrhs;
   const double esz = prec == 0 ? 16.0 : 8.0;
@@ -955,8 +981,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   stage_end();
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
-    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0, &side);
+    sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks, sel(0),
+          &side);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -965,7 +991,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, xterms(d_sweepB), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0, &side);
+          sel(1), &side);
     stage_end();
     stage_begin("face_contract", R * (nblk + nface) * esz, R * nblk * 4 * 8, st);
     contract(prec, p_face, cl_face, T, W, nrhs, st);
@@ -988,7 +1014,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0, &side);
+          sel(3), &side);
     stage_end();
     stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
@@ -1005,7 +1031,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,
-          n_fp64_modes > 0, &side);
+          sel(2), &side);
     stage_end();
   }
   // step 7: inverse transforms into u

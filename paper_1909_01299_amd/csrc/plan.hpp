@@ -126,6 +126,7 @@ struct Plan {
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;
+  size_t ddesc_bytes = 0;
   StageList<XformDesc> s_fwdx, s_invx;
   StageList<XformYDesc> s_fwdy, s_invy;
   std::vector<XformDesc> d_vface, d_gface, d_glob_in, d_glob_out;
@@ -137,6 +138,11 @@ struct Plan {
   // device pointers of each list
   const XformDesc *p_vface = nullptr, *p_gface = nullptr, *p_glob_in = nullptr, *p_glob_out = nullptr;
   const SweepDesc *p_sweep = nullptr, *p_sweepB = nullptr, *p_sweepC = nullptr, *p_sweepG = nullptr;
+  // complex64: near-resonance selections of the four sweep lists (d_sweep,
+  // d_sweepB, d_sweepC, d_sweepG) for chunk counts 8, 16, 32 (device copies
+  // in the descriptor buffer; rebuilt with the FP64 threshold)
+  SweepSelHost sel_host[4][3];
+  SweepSel sel_dev[4][3];
   const ContractDesc *p_face = nullptr, *p_sig = nullptr;
   const LiftBlock* p_lift = nullptr;
   SigmaGeom sg{};
@@ -180,6 +186,8 @@ struct Plan {
   void build_descriptors();
   hs_status upload(std::string& err);
   hs_status upload_descs(std::string& err);
+  // modes a sweep launch over the list provisions (largest sweep_modes_bound)
+  static int64_t sweep_modes(const std::vector<SweepDesc>& v);
   void set_fp64_threshold();
   hs_status scan_pivots(std::string& err);
   const void* tab() const { return prec == 0 ? dtab64 : dtab32; }
