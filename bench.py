@@ -135,10 +135,7 @@ def counters_run(args):
         plan.solve(f, out=u)
     torch.cuda.synchronize()
     info = plan.info()
-    mw = 256 // info["z_chunks"]
-    tiles = -(-p.ny * (-(-p.nx // 32) * 32) // mw)      # workgroups the sweep launch provisions
-    print(json.dumps({"solves": 3, "global_sweep_grid": -(-tiles // 8) * 8 * 256,
-                      "z_chunks": info["z_chunks"]}), flush=True)
+    print(json.dumps({"solves": 3, "z_chunks": info["z_chunks"]}), flush=True)
 
 
 def _counter_rows(folder, counter):
@@ -155,18 +152,19 @@ def _counter_rows(folder, counter):
     return out
 
 
-def _stage_labels(rows, global_grid):
-    """Label the z-solve dispatches: per solve the block sweep runs twice
-    (v before u) and the global sweep once; contractions: faces, then Σ."""
+SWEEP_ORDER = ("zsweep_blocks_v", "zsweep_global", "zsweep_blocks_u")
+
+
+def _stage_labels(rows):
+    """Label the dispatches of complex128 decomposed solves: per solve the z
+    sweeps run in the order block sweep v, global sweep, block sweep u;
+    contractions: faces, then Σ."""
     labels = []
-    nblk = ncon = 0
+    nsw = ncon = 0
     for _, name, grid, _ in rows:
         if "k_psweep" in name:
-            if grid == global_grid:
-                labels.append("zsweep_global")
-            else:
-                labels.append("zsweep_blocks_v" if nblk % 2 == 0 else "zsweep_blocks_u")
-                nblk += 1
+            labels.append(SWEEP_ORDER[nsw % 3])
+            nsw += 1
         elif "k_contract<" in name:
             labels.append("face_contract" if ncon % 2 == 0 else "sigma_contract")
             ncon += 1
@@ -175,7 +173,7 @@ def _stage_labels(rows, global_grid):
     return labels
 
 
-def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
+def traffic_summary(fdir, wdir, cfdir, cwdir):
     scale = {}
     for key, folder, counter in (("fetch", cfdir, "FETCH_SIZE"), ("write", cwdir, "WRITE_SIZE")):
         rows = [r for r in _counter_rows(folder, counter) if "copy" in r[1].lower() or "elementwise" in r[1]]
@@ -184,7 +182,7 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
     stages = {}
     for key, folder, counter in (("fetch", fdir, "FETCH_SIZE"), ("write", wdir, "WRITE_SIZE")):
         rows = [r for r in _counter_rows(folder, counter) if "hs::" in r[1]]
-        for lab, r in zip(_stage_labels(rows, global_grid), rows):
+        for lab, r in zip(_stage_labels(rows), rows):
             if lab is None:
                 continue
             rec = stages.setdefault(lab, {"fetch_kib": [], "write_kib": []})
@@ -194,7 +192,7 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
            "commands (R = repository root)": [
                run.format(c="FETCH_SIZE", d=fdir, a="--counters"), run.format(c="WRITE_SIZE", d=wdir, a="--counters"),
                run.format(c="FETCH_SIZE", d=cfdir, a="--copy"), run.format(c="WRITE_SIZE", d=cwdir, a="--copy"),
-               f"python3 $R/bench.py --traffic-summary {fdir} {wdir} {cfdir} {cwdir} --global-grid {global_grid}"],
+               f"python3 $R/bench.py --traffic-summary {fdir} {wdir} {cfdir} {cwdir}"],
            "copy_scale": scale, "stages": {}}
     for lab, rec in stages.items():
         fk = float(np.mean(rec["fetch_kib"])) if rec["fetch_kib"] else 0.0
@@ -211,13 +209,13 @@ def traffic_summary(fdir, wdir, cfdir, cwdir, global_grid):
 def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool = False):
     """Text summary of a rocprofv3 kernel trace: per kernel and grid, the
     number of dispatches, the average duration and the share of the total.
-    stage_labels (complex128 decomposed solves): z sweeps over one plane are
-    the global solve; the block sweeps of a solve run twice, v then u, and
-    are listed apart."""
+    stage_labels (complex128 decomposed solves): the z sweeps of a solve run
+    in the order block sweep v, global sweep, block sweep u, and are listed
+    apart."""
     import csv
     import re
     agg = {}
-    seen = {}
+    nsw = 0
     with open(trace_csv) as fh:
         rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
         for r in rows:
@@ -226,12 +224,8 @@ def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool =
             name = re.sub(r"\(hs::.*|\(.*", "", name).replace("void ", "")
             grid = "x".join(r["Grid_Size_" + a] for a in "XYZ")
             if stage_labels and name.startswith("k_psweep"):
-                if r["Grid_Size_Y"] == "1":
-                    name += " [zsweep_global]"
-                else:
-                    n = seen.get((name, grid), 0)
-                    seen[(name, grid)] = n + 1
-                    name += " [zsweep_blocks_v]" if n % 2 == 0 else " [zsweep_blocks_u]"
+                name += f" [{SWEEP_ORDER[nsw % 3]}]"
+                nsw += 1
             key = (name, grid)
             a = agg.setdefault(key, [0, 0.0])
             a[0] += 1
@@ -412,7 +406,6 @@ def main():
     ap.add_argument("--counters", action="store_true", help="three complex128 solves for counter runs")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
-    ap.add_argument("--global-grid", type=int, default=0, help="grid size of the global sweep (--counters prints it)")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
     ap.add_argument("--c5-only", action="store_true",
                     help="time only the large 575x575x256 grid, 16 sources x 4 frequencies (c128 vs mixed)")
@@ -422,7 +415,7 @@ def main():
                     help="with --stats-summary: list the z sweeps of decomposed solves by stage")
     args = ap.parse_args()
     if args.traffic_summary:
-        traffic_summary(*args.traffic_summary, args.global_grid)
+        traffic_summary(*args.traffic_summary)
         return
     if args.stats_summary:
         stats_summary(*args.stats_summary, stage_labels=args.stage_labels)
