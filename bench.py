@@ -423,8 +423,9 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver has no multi-GPU path "
-              "(sharding by right-hand side and frequency needs no communication; "
-              "see the design notes).", file=sys.stderr)
+              "(right-hand sides and frequencies shard across GPUs with a replicated plan "
+              "and no communication; blocks of one decomposed grid would exchange only the "
+              "separator lines around the global interface solve).", file=sys.stderr)
         sys.exit(2)
 
     if args.copy:

@@ -10,8 +10,9 @@ What it computes (Druskin & Zaslavsky, Sec. 2):
 
 * ``operator``  -- the 7-point finite-volume operator of eq. (2)/(3), written
   in the D-form A = Dx (x) I (x) I + I (x) Dy (x) I + I (x) I (x) (Dz - k^2(z)),
-  with D_d = M_d^{-1} K_d (reading of the sign and of sigma = 1 in the design
-  notes), as an explicit neighbour stencil and as a sparse Kronecker sum.
+  with D_d = M_d^{-1} K_d (minus the paper's operator, sigma = 1, the constant
+  lambda replaced by a layered k^2(z)), as an explicit neighbour stencil and as
+  a sparse Kronecker sum.
 * ``direct``    -- u = A^{-1} f by sparse LU (brute force, small grids).
 * ``separable`` -- u = A^{-1} f on the undecomposed grid by the generalized
   1D eigenproblems of Sec. 2 (K W = M W Lambda, explicit inverse of W) and
