@@ -199,7 +199,11 @@ hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int
 /* Batched solve of many independent plans (one block each, any sizes) and
  * right-hand sides, enqueued as one captured HIP graph per call.
  * nrhs[i] right-hand sides for plans[i]; the plans must outlive the batch and
- * share one precision. */
+ * share one precision.  The batch copies the plans' tables when it is created:
+ * later hs_set_k2 calls on a plan do not reach it (create a new batch).  Its
+ * launch shapes (z chunking, sine lines per workgroup) are those of plans[0]
+ * when the graph is captured (first solve, or new array pointers).  Errors: HS_ERR_ARG (decomposed plans, mixed precisions or devices,
+ * nrhs outside [1, 4096]), HS_ERR_ALLOC, HS_ERR_DEVICE. */
 hs_status hs_batch_create(const hs_plan* plans, int32_t nplans, const int32_t* nrhs,
                           hs_batch* out);
 size_t hs_batch_workspace_bytes(hs_batch batch);
