@@ -54,6 +54,7 @@ struct LinesLaunch {
   int tiles = 0;
   bool mfma = false;
   bool real = false;   // matrix cores with a real table (descriptors with real_tab)
+  int tm = 1;          // complex FMA tiles: 16 tm x 16 tm outputs per workgroup
 };
 bool xform_lines_use_mfma(const XformDesc& d);
 LinesLaunch xform_lines_launch(const XformDesc* host_descs, int ndesc, bool mfma, bool real);

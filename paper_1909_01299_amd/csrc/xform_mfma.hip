@@ -545,8 +545,10 @@ __global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma_real(const XformYDe
 
 // ------------------------------------------------------------------ small line sets
 // Few or short lines (interface and face lines, narrow PML blocks): complex
-// FMA on 16 x 16 output tiles, K staged through LDS; more workgroups than the
-// matrix-core tiling would give for such sizes.
+// FMA on 16 x 16 output tiles, K staged through LDS in steps of 32; more
+// workgroups than the matrix-core tiling would give for such sizes.  The next
+// step's data and table values are loaded into registers while the current
+// step is multiplied, so a workgroup waits for memory once, not once per step.
 template <typename CO, typename CI>
 __device__ __forceinline__ CO cvt(CI v) {
   CO o;
@@ -558,54 +560,100 @@ __device__ __forceinline__ CO cvt(CI v) {
 constexpr int XL_T = 16;
 constexpr int XL_K = 32;
 
-template <typename R, typename CI, typename CO, bool ACC>
+// TM x TM outputs per thread: a workgroup owns 16 TM lines x 16 TM outputs.
+template <typename R, typename CI, typename CO, bool ACC, int TM>
 __global__ __launch_bounds__(256) void k_xform_lines_small(const XformDesc* __restrict__ descs,
                                                      const cplx<R>* __restrict__ tab,
                                                      const CI* __restrict__ src, CO* __restrict__ dst) {
   using C = cplx<R>;
+  constexpr int TT = XL_T * TM;                 // tile edge
+  constexpr int NE = TT * XL_K / 256;           // elements of each array per thread and step
+  static_assert(NE * 256 == TT * XL_K, "whole steps per thread");
   const XformDesc d = descs[blockIdx.y];
   const int r = blockIdx.z;
   const int lines = d.P * d.Q;
-  const int ntl = (lines + XL_T - 1) / XL_T;
-  const int nto = (d.n_out + XL_T - 1) / XL_T;
+  const int ntl = (lines + TT - 1) / TT;
+  const int nto = (d.n_out + TT - 1) / TT;
   const int tile = blockIdx.x;
   if (tile >= ntl * nto) return;
   const int tl = tile % ntl, to = tile / ntl;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  __shared__ C sA[XL_T][XL_K + 1];
-  __shared__ C sT[XL_T][XL_K + 1];
-  C acc = mk<R>(0, 0);
+  __shared__ C sA[TT][XL_K + 1];
+  __shared__ C sT[TT][XL_K + 1];
+  C acc[TM][TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TM; ++j) acc[i][j] = mk<R>(0, 0);
   const CI* s0 = src + d.src + (int64_t)r * d.src_r;
   const C* T = tab + d.tab;
+  // element e = threadIdx.x + 256 i of a step: row e / XL_K, column e % XL_K;
+  // the line and table-row offsets of this thread's rows do not change
+  int64_t aoff[NE], toff[NE];
+  bool aok[NE], tok[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int li = (threadIdx.x + 256 * i) / XL_K;
+    const int L = tl * TT + li, O = to * TT + li;
+    aok[i] = L < lines;
+    const int Lc = aok[i] ? L : 0;
+    aoff[i] = (int64_t)(Lc / d.Q) * d.src_p + (int64_t)(Lc % d.Q) * d.src_q;
+    tok[i] = O < d.n_out;
+    toff[i] = (int64_t)(tok[i] ? O : 0) * d.n_in;
+  }
+  C ra[NE], rt[NE];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int k = k0 + (threadIdx.x + 256 * i) % XL_K;
+      const bool kin = k < d.n_in;
+      ra[i] = (aok[i] && kin) ? cvt<C>(s0[aoff[i] + k]) : mk<R>(0, 0);
+      rt[i] = (tok[i] && kin) ? T[toff[i] + k] : mk<R>(0, 0);
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < d.n_in; k0 += XL_K) {
-    for (int e = threadIdx.x; e < XL_T * XL_K; e += 256) {
-      const int li = e / XL_K, kk = e % XL_K;
-      const int L = tl * XL_T + li, k = k0 + kk;
-      C v = mk<R>(0, 0);
-      if (L < lines && k < d.n_in) {
-        const int p = L / d.Q, q = L % d.Q;
-        v = cvt<C>(s0[(int64_t)p * d.src_p + (int64_t)q * d.src_q + k]);
-      }
-      sA[li][kk] = v;
-      const int O = to * XL_T + li;
-      sT[li][kk] = (O < d.n_out && k < d.n_in) ? T[(int64_t)O * d.n_in + k] : mk<R>(0, 0);
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      const int e = threadIdx.x + 256 * i;
+      sA[e / XL_K][e % XL_K] = ra[i];
+      sT[e / XL_K][e % XL_K] = rt[i];
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < XL_K; ++kk) acc = cfma(sA[ty][kk], sT[tx][kk], acc);
+    if (k0 + XL_K < d.n_in) fetch(k0 + XL_K);
+#pragma unroll 4
+    for (int kk = 0; kk < XL_K; ++kk) {
+      C a[TM], t[TM];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        a[i] = sA[ty + XL_T * i][kk];
+        t[i] = sT[tx + XL_T * i][kk];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j) acc[i][j] = cfma(a[i], t[j], acc[i][j]);
+    }
     __syncthreads();
   }
-  const int L = tl * XL_T + ty, o = to * XL_T + tx;
-  if (L < lines && o < d.n_out) {
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int L = tl * TT + ty + XL_T * i;
+    if (L >= lines) continue;
     const int p = L / d.Q, q = L % d.Q;
-    CO* out = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q + o;
-    if (ACC) {
-      CO prev = *out;
-      prev.x += acc.x;
-      prev.y += acc.y;
-      *out = prev;
-    } else {
-      *out = cvt<CO>(acc);
+    CO* out = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q;
+#pragma unroll
+    for (int j = 0; j < TM; ++j) {
+      const int o = to * TT + tx + XL_T * j;
+      if (o >= d.n_out) continue;
+      if (ACC) {
+        CO prev = out[o];
+        prev.x += acc[i][j].x;
+        prev.y += acc[i][j].y;
+        out[o] = prev;
+      } else {
+        out[o] = cvt<CO>(acc[i][j]);
+      }
     }
   }
 }
@@ -674,6 +722,24 @@ LinesLaunch xform_lines_launch(const XformDesc* d, int ndesc, bool mfma, bool re
     m = std::max(m, t);
   }
   L.tiles = int(m);
+  if (!mfma) {
+    // 32 x 32 tiles (2 x 2 outputs per thread: half the table and data
+    // re-reads per output) where every descriptor has more than 16 outputs and
+    // they still give each CU a workgroup
+    int64_t m2 = 0, sum2 = 0;
+    bool wide = ndesc > 0;
+    for (int i = 0; i < ndesc; ++i) {
+      const int64_t lines = (int64_t)d[i].P * d[i].Q;
+      const int64_t t = ((lines + 2 * XL_T - 1) / (2 * XL_T)) * ((d[i].n_out + 2 * XL_T - 1) / (2 * XL_T));
+      wide = wide && d[i].n_out > XL_T;
+      m2 = std::max(m2, t);
+      sum2 += t;
+    }
+    if (wide && sum2 >= 256) {
+      L.tm = 2;
+      L.tiles = int(m2);
+    }
+  }
   return L;
 }
 
@@ -687,8 +753,11 @@ static void launch_lines(const XformDesc* d, int ndesc, const LinesLaunch& L, co
   else if (L.mfma)
     hipLaunchKernelGGL((k_xform_lines_mfma<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
                        (const CI*)src, (CO*)dst);
+  else if (L.tm == 2)
+    hipLaunchKernelGGL((k_xform_lines_small<R, CI, CO, ACC, 2>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
+                       (const CI*)src, (CO*)dst);
   else
-    hipLaunchKernelGGL((k_xform_lines_small<R, CI, CO, ACC>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
+    hipLaunchKernelGGL((k_xform_lines_small<R, CI, CO, ACC, 1>), grid, dim3(256), 0, st, d, (const cplx<R>*)tab,
                        (const CI*)src, (CO*)dst);
 }
 
