@@ -138,6 +138,34 @@ def test_autotune_keeps_parity_and_caches(hs, tmp_path):
     assert len(open(cache).read().splitlines()) == 1
 
 
+def test_stage_profiling_all_and_single_stage(hs):
+    """hipEvents around every stage, or around one named stage only (the
+    benchmark's timed region); profiling leaves the result bit-identical."""
+    import torch
+    rng = np.random.default_rng(23)
+    p = W.decomposed_problem(24, 3, 10, 2, rng)
+    f = dev(W.complex_normal(rng, (1,) + p.shape))
+    plan = hs.Plan(p, "c128")
+    u0 = plan.solve(f).cpu().numpy()
+    plan.profile(True)
+    plan.profile_read()
+    u1 = plan.solve(f).cpu().numpy()
+    st = {s["name"]: s for s in plan.profile_read()}
+    assert {"xform_x_fwd", "zsweep_blocks_v", "zsweep_global", "zsweep_blocks_u", "xform_x_inv"} <= set(st)
+    assert all(s["launches"] == 1 and s["ms"] > 0 for s in st.values())
+    plan.profile(True, only="zsweep_global")
+    for _ in range(3):
+        plan.solve(f)
+    torch.cuda.synchronize()
+    got = [s for s in plan.profile_read() if s["launches"] > 0]
+    assert [s["name"] for s in got] == ["zsweep_global"] and got[0]["launches"] == 3
+    assert got[0]["bytes_per_launch"] > 0
+    with pytest.raises(hs.HSError):
+        plan.profile(True, only="x" * 40)
+    plan.profile(False)
+    assert np.array_equal(u0, u1)
+
+
 @pytest.mark.parametrize("chunks", [8, 16, 32])
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
 def test_every_z_chunking_vs_oracle(hs, chunks, prec):

@@ -144,3 +144,5 @@ def test_null_and_status_strings(hs):
     assert L.hs_solve(None, None, None, 1, None) == hs.HS_ERR_ARG
     assert b"NULL" in L.hs_last_error()
     assert L.hs_plan_workspace_bytes(None, 1) == 0
+    assert L.hs_profile_only(None, b"zsweep_block") == hs.HS_ERR_ARG
+    assert L.hs_profile_enable(None, 1) == hs.HS_ERR_ARG
