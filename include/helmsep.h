@@ -124,7 +124,9 @@ typedef struct {
  * generalized eigen tables of every block axis and of the global axes in FP64
  * on the host (Sec. 2, A_d W = M_d W Lambda with W = 0 on the block walls),
  * scans the z pivots of every mode, and uploads the tables to the current
- * device (HS_ERR_DEVICE without one).  `blocks` and `opts` may be NULL. */
+ * device (HS_ERR_DEVICE without one).  `blocks` and `opts` may be NULL.
+ * Size limits (HS_ERR_ARG beyond them): nx ny nz <= 2^34, nx ny <= 2^28,
+ * nz <= 512, every block side <= 512. */
 hs_status hs_plan_create(const hs_grid* grid, const hs_blocks* blocks,
                          const hs_options* opts, hs_plan* out);
 void hs_plan_destroy(hs_plan plan);

@@ -445,8 +445,9 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
 
   // right-hand side of the chunk. Every register row is loaded, rows past the
   // chunk or the line from the last valid row: their values only reach rows
-  // that are never used or padded rows. Row offsets fit in 32 bits (a line
-  // holds at most 512 planes of at most 512 x 512 modes).
+  // that are never used or padded rows. Row offsets fit in 32 bits (at most
+  // 15 planes past the chunk's first row; plans hold at most 2^28 modes per
+  // plane).
   C rb[L];
   auto row_off = [&](int kk, uint32_t stride) -> uint32_t {
     return kk < nv ? uint32_t(kk) * stride : uint32_t(nv - 1) * stride;

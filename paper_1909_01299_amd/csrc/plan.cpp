@@ -69,6 +69,8 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   if (!g) { err = "grid is NULL"; return HS_ERR_ARG; }
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) { err = "nx, ny, nz must be >= 1"; return HS_ERR_ARG; }
   if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 34) { err = "grid too large"; return HS_ERR_ARG; }
+  // the z solves address the rows of a chunk (at most 16) with 32-bit plane offsets
+  if ((int64_t)g->nx * g->ny > (int64_t)1 << 28) { err = "x-y plane too large (> 2^28 nodes)"; return HS_ERR_ARG; }
   if (!g->hx || !g->hy || !g->hz || !g->layer_of_z || !g->k2) { err = "grid arrays must be non-NULL"; return HS_ERR_ARG; }
   if (g->nlayers < 1) { err = "nlayers must be >= 1"; return HS_ERR_ARG; }
   NX = g->nx; NY = g->ny; NZ = g->nz; nlayers = g->nlayers;

@@ -129,6 +129,10 @@ def test_argument_errors_before_device(hs):
     hx[3] = 0
     assert _create(hs, W.Problem(hx, p.hy, p.hz, p.layer_of_z, p.k2))[0] == hs.HS_ERR_ARG
     assert _create(hs, p, opts=hs._Options(7, 0, 1, 0))[0] == hs.HS_ERR_ARG   # unknown precision
+    # an x-y plane beyond 2^28 nodes (step arrays of the right lengths, nz = 1)
+    big = W.Problem(np.ones(16386), np.ones(16386), np.ones(2), np.zeros(1, np.int32), p.k2[:1])
+    st, msg = _create(hs, big)
+    assert st == hs.HS_ERR_ARG and "plane" in msg, msg
     # a valid grid reaches the device check
     st, msg = _create(hs, p, sep_x=[4])
     if not _gpu():
