@@ -331,6 +331,29 @@ def test_mixed_precision_near_resonance_modes_run_fp64(hs):
     assert hs.Plan(p, "c128").info()["n_fp64_modes"] == 0
 
 
+@pytest.mark.parametrize("chunks", [8, 16, 32])
+def test_mixed_near_resonance_lists_every_chunking_and_k2_update(hs, chunks):
+    """The FP64 work lists exist for every chunking; a k^2 update rebuilds
+    them, including to none (Re k^2 < 0 leaves no mode near resonance) and
+    back, where the solve repeats bit for bit."""
+    rng = np.random.default_rng(31 + chunks)
+    p = W.random_problem(63, 47, 64, 4, rng, pml_x=5)
+    p = p.with_k2(np.array([1.5 + 0.002j, 2.0 + 0.001j, 1.2 + 0.004j, 1.8 + 0.003j]))
+    f = W.complex_normal(rng, (1,) + p.shape)
+    fd = dev(f)
+    plan = hs.Plan(p, "mixed", z_chunks=chunks)
+    assert plan.info()["z_chunks"] == chunks and plan.info()["n_fp64_modes"] > 0
+    u1 = plan.solve(fd).cpu().numpy()
+    assert per_rhs_err(u1, separable.solve(p, f)) < TOL64R
+    k2n = np.array([-0.5 + 0.01j, -0.2 + 0.02j, -0.4 + 0.005j, -0.3 + 0.01j])
+    plan.set_k2(k2n)
+    assert plan.info()["n_fp64_modes"] == 0
+    un = plan.solve(fd).cpu().numpy()
+    assert per_rhs_err(un, separable.solve(p.with_k2(k2n), f)) < TOL64R
+    plan.set_k2(p.k2)
+    assert np.array_equal(plan.solve(fd).cpu().numpy(), u1)
+
+
 def test_mixed_precision_decomposed(hs):
     p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=40, nlayers=6)
     rng = np.random.default_rng(13)
