@@ -15,7 +15,8 @@ timed on the host.  The same line carries two more workloads, each in
 complex128 and in mixed precision: 64 independent blocks of uneven sizes with
 8 right-hand sides each as one captured graph per solve ("batched_c3"), and
 the large 575 x 575 x 256 grid with 16 point sources at 4 frequencies
-("large_c5").
+("large_c5"); and the time of one adjoint gradient with respect to the layer
+values of k^2 on the 128 x 128 x 160 grid ("adjoint_c4").
 """
 from __future__ import annotations
 
@@ -334,6 +335,58 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
     return out
 
 
+def bench_c4(steps, with_oracle):
+    """Adjoint workload: gradient of 0.5 |P u - d|^2 with respect to the 40
+    layer values of k^2 on the 128 x 128 x 160 grid (P samples the z-index-9
+    plane, d comes from a perturbed k^2).  One gradient = forward solve,
+    adjoint source, adjoint solve, layer sums; timed through the autograd
+    wrapper (as a training loop calls it) and as the bare sequence of C-ABI
+    calls; the gradient is compared with the oracle's."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    p, f, k2_true, plane = W.c4_adjoint()
+    plan = hs.Plan(p, "c128")
+    fd = hs.to_device(f)
+    plan.set_k2(k2_true)
+    d = plan.solve(fd)[0, plane].clone()
+    plan.set_k2(p.k2)
+    k2 = torch.tensor(p.k2, dtype=torch.complex128, requires_grad=True)
+
+    def autograd_step():
+        u = hs.helmholtz_solve(k2, fd, plan)
+        J = 0.5 * (u[0, plane] - d).abs().pow(2).sum()
+        k2.grad = None
+        J.backward()
+        return J
+
+    def abi_step():
+        u = plan.solve(fd)
+        g = torch.zeros_like(u)
+        g[0, plane] = u[0, plane] - d
+        a = plan.solve_adjoint(g)
+        return plan.grad_k2(u, a)
+
+    out = {"workload": f"c4_adjoint {p.nx}x{p.ny}x{p.nz}, {p.nlayers} layers, gradient of a plane misfit "
+                       f"w.r.t. layer k^2, complex128", "unknowns": p.unknowns}
+    for name, fn in (("autograd", autograd_step), ("abi", abi_step)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        out[f"ms_per_gradient_{name}"] = (time.perf_counter() - t0) / steps * 1e3
+    if with_oracle:
+        from oracle import adjoint
+        J = autograd_step()
+        _, g_ref, _, _ = adjoint.plane_misfit_grad(p, f[0], plane, d.cpu().numpy())
+        g = k2.grad.detach().numpy()
+        out["grad_rel_err_vs_oracle"] = float(np.abs(g - g_ref).max() / np.abs(g_ref).max())
+        out["misfit"] = float(J.detach())
+    return out
+
+
 def bench_c5(steps, refine_steps=1):
     """Large decomposed grid: core 512 + 32 PML cells per side (575 x 575
     interior nodes), n_z = 256 in 60 layers, 16 point sources off the
@@ -399,6 +452,7 @@ def main():
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
     ap.add_argument("--no-c5", action="store_true", help="skip the large 575x575x256 measurement")
+    ap.add_argument("--no-c4", action="store_true", help="skip the adjoint-gradient measurement")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--refine-steps", type=int, default=1,
                     help="FP64-residual refinement steps of the mixed-precision solves (-1: none)")
@@ -407,6 +461,7 @@ def main():
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
+    ap.add_argument("--c4-only", action="store_true", help="time only the adjoint gradient (128x128x160)")
     ap.add_argument("--c5-only", action="store_true",
                     help="time only the large 575x575x256 grid, 16 sources x 4 frequencies (c128 vs mixed)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
@@ -437,6 +492,9 @@ def main():
         return
     if args.counters:
         counters_run(args)
+        return
+    if args.c4_only:
+        print(json.dumps(bench_c4(max(1, args.steps), True)), flush=True)
         return
     if args.c5_only:
         print(json.dumps(bench_c5(max(1, min(args.steps, 3)), refine_steps=args.refine_steps)), flush=True)
@@ -491,6 +549,9 @@ def main():
         del plan
         torch.cuda.empty_cache()
         c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline, refine_steps=args.refine_steps)
+    c4 = None
+    if not args.no_c4:
+        c4 = bench_c4(10, not args.no_cpu_baseline)
     c5 = None
     if not args.no_c5:
         torch.cuda.empty_cache()
@@ -524,6 +585,7 @@ def main():
             "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"],
             "stages_ms_per_step": mixed["stages"]},
         "batched_c3": c3,
+        "adjoint_c4": c4,
         "large_c5": c5,
         "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
         "plan_seconds": info["plan_seconds"],

@@ -186,6 +186,7 @@ class Plan:
             _check(lib().hs_plan_create(ctypes.byref(grid), ctypes.byref(blocks), ctypes.byref(opts),
                                         ctypes.byref(handle)))
         self._h = handle
+        self._k2 = k2.copy()          # the plan's current k^2 (set_k2 skips an unchanged value)
         nbytes = lib().hs_plan_workspace_bytes(self._h, self.max_rhs)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
         _check(lib().hs_plan_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel()))
@@ -233,7 +234,10 @@ class Plan:
         k2 = np.ascontiguousarray(np.asarray(k2, np.complex128))
         if k2.shape != (self.nlayers,):
             raise ValueError("k2 must have one value per layer")
+        if np.array_equal(k2, self._k2):
+            return                    # tables and pivot scan already hold this k^2
         _check(lib().hs_set_k2(self._h, k2.ctypes.data))
+        self._k2 = k2.copy()
 
     def _nrhs(self, t):
         return 1 if t.dim() == 3 else int(np.prod(t.shape[:-3]))
