@@ -3,8 +3,8 @@
 Oracle code: test infrastructure only.
 
 Per axis with n interior nodes and steps h[0..n] (node i between h[i] and
-h[i+1]), the control-volume edge is hhat_i = (h[i] + h[i+1]) / 2 (eq. (2),
-"lengths of the edges of the control volume").  The 1D stiffness matrix is
+h[i+1]), the control-volume edge of node i is hhat_i = (h[i] + h[i+1]) / 2, the
+mean of its two steps (eq. (2)).  The 1D stiffness matrix is
 
     (K u)_i = (u_i - u_{i-1}) / h[i] - (u_{i+1} - u_i) / h[i+1],
 

@@ -114,6 +114,51 @@ def test_pml_generalized_eigen_relation():
     assert lam.imag.max() < 1e-10
 
 
+@pytest.mark.parametrize("core,pml", [(256, 16), (512, 32)])
+def test_global_pml_axis_tables(core, pml):
+    """The global axes of the decomposed workloads (287 and 575 interior
+    nodes): mirror-symmetric PML axes whose eigenvalues come in pairs that
+    agree to about 1e-15.  The oracle's LAPACK eigenvectors with an explicit
+    inverse must still satisfy the generalized eigen relation and invert W,
+    and the eigenvalues must match a second LAPACK route (the standard
+    eigenproblem of M^{-1} K, eigenvalues only)."""
+    h = W.pml_steps(core, pml)
+    n = len(h) - 1
+    lam, Wm, Wi = separable.axis_eig(h)
+    K = operator.axis_K(h)
+    M = np.diag(operator.hhat(h))
+    res = np.linalg.norm(K @ Wm - M @ Wm @ np.diag(lam)) / (np.linalg.norm(K) * np.linalg.norm(Wm))
+    assert res < 1e-13
+    assert np.abs(Wi @ Wm - np.eye(n)).max() < 1e-11
+    assert np.abs(Wm @ Wi - np.eye(n)).max() < 1e-11
+    lam2 = sla.eigvals(np.linalg.solve(M, K))
+    scale = np.abs(lam).max()
+    # every eigenvalue has a partner in the other route's spectrum and back
+    assert np.abs(lam[:, None] - lam2[None, :]).min(axis=1).max() < 1e-9 * scale
+    assert np.abs(lam[:, None] - lam2[None, :]).min(axis=0).max() < 1e-9 * scale
+    assert lam.imag.max() < 1e-10
+
+
+@pytest.mark.parametrize("core,pml,along", [(256, 16, "x"), (512, 32, "x"), (512, 32, "y")])
+def test_manufactured_solution_on_global_pml_axis(core, pml, along):
+    """Manufactured u* on a grid with one full global PML axis (287 or 575
+    nodes) and short other axes, k^2 of the large workload's highest
+    frequency (omega = 3): f = A u* by the independent stencil, and the
+    separable oracle must return u*."""
+    rng = _rng(20)
+    long = W.pml_steps(core, pml)
+    short = W.stretched_ends_steps(6, 2)
+    hz = rng.uniform(0.7, 1.3, size=5)
+    k2 = 9.0 * W.draw_k2(rng, 2)
+    hx, hy = (long, short) if along == "x" else (short, long)
+    p = W.Problem(hx, hy, hz, W.layer_map(4, 2), k2)
+    ustar = W.complex_normal(rng, (2,) + p.shape)
+    f = operator.apply_A(p, ustar)
+    u = separable.solve(p, f)
+    assert operator.rel_err(u, ustar) < 1e-11
+    assert np.abs(u - ustar).max() < 1e-11 * np.abs(ustar).max()
+
+
 # ---------------------------------------------------------------- z solves
 
 def test_thomas_matches_lapack_banded():
