@@ -91,12 +91,18 @@ typedef struct {
 
 typedef struct {
   hs_precision prec;
-  int32_t refine_steps;   /* HS_C64_REFINE: correction steps (default 2 when 0;
-                             a negative value: none, one complex64 pass)       */
+  int32_t refine_steps;   /* HS_C64_REFINE: correction steps, at most 16 (default 2
+                             when 0; a negative value: none, one complex64 pass) */
   int32_t max_rhs;        /* largest nrhs a solve will be called with (>= 1)       */
   int32_t flags;          /* bit 0: force the dense transform on uniform axes;
                              bits 1-2: z-line chunks per mode (0 auto, 1: 8, 2: 16,
                              3: 32; must hold nz within 16 rows per chunk)        */
+  double tol;             /* > 0: every solve ends with the FP64 residual of the u
+                             it returns (one more read of f and u, nothing written)
+                             and hs_get_info reports HS_ERR_NOCONV when
+                             |f - A u| / |f| exceeds tol for some right-hand side;
+                             0: no final check (residuals are still recorded for
+                             the iterates a refinement step corrects)          */
 } hs_options;
 
 typedef struct {
@@ -118,6 +124,19 @@ typedef struct {
   int32_t n_split_fp16;     /* HS_C64_REFINE: axes whose dense tables run on fp16
                                matrix cores as two-term splits (n <= 256, or
                                n <= 512 for real sine tables)                */
+  /* Convergence record of the last solve (read after its stream has been
+   * synchronized).  Every FP64 residual r = f - A u that a solve evaluates
+   * (the one each refinement step corrects, and the final one when tol > 0)
+   * also yields |r|, |f| and |u| per right-hand side, reduced on the device
+   * in a fixed order into the plan workspace. */
+  double tol;               /* the plan's hs_options.tol                        */
+  double resid_first;       /* max over RHS of |f - A u_0| / |f| for the first
+                               pass u_0 (-1: not evaluated)                   */
+  double resid_final;       /* the same for the returned u (-1: not evaluated,
+                               i.e. tol == 0)                                 */
+  int32_t resid_evals;      /* residuals recorded by the last solve            */
+  int32_t converged;        /* 1: resid_final <= tol; 0: not (hs_get_info then
+                               returns HS_ERR_NOCONV); -1: not checked         */
 } hs_info;
 
 /* Build a plan: validates the grid and blocks (HS_ERR_ARG), computes the 1D
@@ -142,7 +161,9 @@ hs_status hs_plan_bind_workspace(hs_plan plan, void* dev_ptr, size_t bytes);
 hs_status hs_set_k2(hs_plan plan, const double* k2);
 
 /* u = A^{-1} f for nrhs right-hand sides (Sec. 2, the seven-step algorithm,
- * or eq. (5) for one block).  u may alias f. */
+ * or eq. (5) for one block).  u may alias f in both precisions (the mixed
+ * path then first copies f into the workspace, since its residuals read f
+ * after u has been written). */
 hs_status hs_solve(hs_plan plan, const void* f, void* u, int32_t nrhs, void* stream);
 
 /* a = A^{-H} g.  Uses the symmetry of the finite-volume matrix M A of eq. (3):
@@ -163,7 +184,19 @@ hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r,
 /* out = A u in FP64 by the same stencil (eqs. (2)-(3)). */
 hs_status hs_apply(hs_plan plan, const void* u, void* out, int32_t nrhs, void* stream);
 
+/* Plan statistics and the convergence record of the last solve.  Reads the
+ * record from the workspace (synchronous copy; call after the solve's stream
+ * has been synchronized).  Returns HS_ERR_NOCONV, with *info filled, when the
+ * last solve's final residual exceeded a positive tol. */
 hs_status hs_get_info(hs_plan plan, hs_info* info);
+
+/* The relative residuals |f - A u_k| / |f| recorded by the last solve, as
+ * rel[k * nrhs + r] for evaluation k (k = 0: the first pass; k = refine
+ * steps: the returned u, when tol > 0) and right-hand side r.  max_entries
+ * bounds what is written; *n_evals and *nrhs receive the counts.
+ * HS_ERR_STATE when no solve has recorded residuals.  Synchronous copy. */
+hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32_t* n_evals,
+                           int32_t* nrhs);
 
 /* Autotune the plan's launch shapes for nrhs right-hand sides: every usable
  * pair of (z-line chunks per mode in {8, 16, 32}, sine-transform lines per

@@ -45,7 +45,7 @@ class _Blocks(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("max_rhs", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("max_rhs", ctypes.c_int32), ("flags", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
                 ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32),
-                ("n_split_fp16", ctypes.c_int32)]
+                ("n_split_fp16", ctypes.c_int32), ("tol", ctypes.c_double), ("resid_first", ctypes.c_double),
+                ("resid_final", ctypes.c_double), ("resid_evals", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -78,6 +79,8 @@ EXPORTS = {
     "hs_residual": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_apply": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "hs_get_residuals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "hs_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "hs_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
     "hs_batch_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
@@ -135,6 +138,21 @@ def _check_array(t, shape, name):
         raise ValueError(f"{name}: trailing shape {tuple(t.shape[-3:])} != {tuple(shape)}")
 
 
+def _nrhs_of(t) -> int:
+    """Right-hand sides held by an array of shape [..., nz, ny, nx]."""
+    return 1 if t.dim() == 3 else int(np.prod(t.shape[:-3]))
+
+
+def same_nrhs(first, second, names) -> int:
+    """The right-hand-side count shared by two arrays of one call; raises
+    ValueError (before anything is launched) when they differ, so a short
+    output or second input is never written or read past its end."""
+    n1, n2 = _nrhs_of(first), _nrhs_of(second)
+    if n1 != n2:
+        raise ValueError(f"{names[0]} holds {n1} right-hand sides but {names[1]} holds {n2}")
+    return n1
+
+
 def axis_eig(h: np.ndarray):
     """Host-only generalized eigenpairs of one axis (the plan's own eigensolver).
 
@@ -157,7 +175,8 @@ class Plan:
     layer_of_z, k2 and optional sep_x, sep_y (numpy arrays)."""
 
     def __init__(self, problem, precision: str = "c128", max_rhs: int = 1, refine_steps: int = 0,
-                 force_dense: bool = False, z_chunks: int = 0, device=None):
+                 force_dense: bool = False, z_chunks: int = 0, tol: float = 0.0, device=None,
+                 workspace=None):
         import torch
         self.problem = problem
         self.nx = len(problem.hx) - 1
@@ -180,7 +199,7 @@ class Plan:
         blocks = _Blocks(len(sx), sx.ctypes.data if len(sx) else None, len(sy), sy.ctypes.data if len(sy) else None)
         prec = {"c128": HS_C128, "c64": HS_C64_REFINE, "mixed": HS_C64_REFINE}[precision]
         chunk_bits = {0: 0, 8: 1, 16: 2, 32: 3}[int(z_chunks)] << 1
-        opts = _Options(prec, int(refine_steps), self.max_rhs, (1 if force_dense else 0) | chunk_bits)
+        opts = _Options(prec, int(refine_steps), self.max_rhs, (1 if force_dense else 0) | chunk_bits, float(tol))
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().hs_plan_create(ctypes.byref(grid), ctypes.byref(blocks), ctypes.byref(opts),
@@ -188,7 +207,12 @@ class Plan:
         self._h = handle
         self._k2 = k2.copy()          # the plan's current k^2 (set_k2 skips an unchanged value)
         nbytes = lib().hs_plan_workspace_bytes(self._h, self.max_rhs)
-        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        elif workspace.dtype != torch.uint8 or not workspace.is_cuda or workspace.numel() < nbytes:
+            raise ValueError(f"workspace must be a CUDA uint8 tensor of at least {nbytes} bytes")
+        # plans used one after another on one stream may share a workspace
+        self.workspace = workspace
         _check(lib().hs_plan_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel()))
 
     def __del__(self):
@@ -205,9 +229,29 @@ class Plan:
         return self._h
 
     def info(self) -> dict:
+        """Plan statistics and the last solve's convergence record (a missed
+        tolerance shows as converged == 0 here; check() raises for it)."""
+        inf = Info()
+        st = lib().hs_get_info(self._h, ctypes.byref(inf))
+        if st not in (HS_OK, HS_ERR_NOCONV):
+            _check(st)
+        return inf.as_dict()
+
+    def check(self):
+        """Raise HSError(HS_ERR_NOCONV) when the last solve missed its
+        tolerance (synchronize the solve's stream first)."""
         inf = Info()
         _check(lib().hs_get_info(self._h, ctypes.byref(inf)))
-        return inf.as_dict()
+
+    def residuals(self) -> np.ndarray:
+        """Relative residuals |f - A u_k| / |f| of the last solve, [eval][rhs]."""
+        n_ev = ctypes.c_int32()
+        nr = ctypes.c_int32()
+        st = lib().hs_get_residuals(self._h, None, 0, ctypes.byref(n_ev), ctypes.byref(nr))
+        _check(st)
+        out = np.zeros(n_ev.value * nr.value, np.float64)
+        _check(lib().hs_get_residuals(self._h, out.ctypes.data, out.size, ctypes.byref(n_ev), ctypes.byref(nr)))
+        return out.reshape(n_ev.value, nr.value)
 
     def tune(self, nrhs: int = 1, cache: Optional[str] = None, stream=None):
         """Autotune launch shapes (z chunking, sine lines per workgroup) on this plan."""
@@ -240,14 +284,15 @@ class Plan:
         self._k2 = k2.copy()
 
     def _nrhs(self, t):
-        return 1 if t.dim() == 3 else int(np.prod(t.shape[:-3]))
+        return _nrhs_of(t)
 
     def solve(self, f, out=None, stream=None):
         import torch
         _check_array(f, self.shape, "f")
         u = out if out is not None else torch.empty_like(f)
         _check_array(u, self.shape, "u")
-        _check(lib().hs_solve(self._h, _ptr(f), _ptr(u), self._nrhs(f), _stream(stream)))
+        n = same_nrhs(f, u, ("f", "u"))
+        _check(lib().hs_solve(self._h, _ptr(f), _ptr(u), n, _stream(stream)))
         return u
 
     def solve_adjoint(self, g, out=None, stream=None):
@@ -255,14 +300,15 @@ class Plan:
         _check_array(g, self.shape, "g")
         a = out if out is not None else torch.empty_like(g)
         _check_array(a, self.shape, "a")
-        _check(lib().hs_solve_adjoint(self._h, _ptr(g), _ptr(a), self._nrhs(g), _stream(stream)))
+        n = same_nrhs(g, a, ("g", "a"))
+        _check(lib().hs_solve_adjoint(self._h, _ptr(g), _ptr(a), n, _stream(stream)))
         return a
 
     def grad_k2(self, u, a, stream=None):
         import torch
         _check_array(u, self.shape, "u")
         _check_array(a, self.shape, "a")
-        n = self._nrhs(u)
+        n = same_nrhs(u, a, ("u", "a"))
         grad = torch.empty((n, self.nlayers), dtype=torch.complex128, device=u.device)
         _check(lib().hs_grad_k2(self._h, _ptr(u), _ptr(a), _ptr(grad), n, _stream(stream)))
         return grad
@@ -271,8 +317,9 @@ class Plan:
         import torch
         _check_array(f, self.shape, "f")
         _check_array(u, self.shape, "u")
+        n = same_nrhs(f, u, ("f", "u"))
         r = torch.empty_like(f)
-        _check(lib().hs_residual(self._h, _ptr(f), _ptr(u), _ptr(r), self._nrhs(f), _stream(stream)))
+        _check(lib().hs_residual(self._h, _ptr(f), _ptr(u), _ptr(r), n, _stream(stream)))
         return r
 
     def apply(self, u, stream=None):

@@ -3,6 +3,8 @@
 // returns an hs_status and records a thread-local error text.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
@@ -135,6 +137,47 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   info->sine_lines = p.tune_lt;
   for (auto& a : p.axes)
     if (a.hfwd >= 0) ++info->n_split_fp16;
+  info->tol = p.tol;
+  info->resid_first = -1;
+  info->resid_final = -1;
+  info->converged = -1;
+  if (p.last_evals > 0) {
+    std::vector<double> rel;
+    int evals = 0, nrhs = 0;
+    std::string err;
+    hs_status s = p.residuals(rel, evals, nrhs, err);
+    if (s != HS_OK) return ret(s, err);
+    info->resid_evals = evals;
+    double first = 0, last = 0;
+    for (int r = 0; r < nrhs; ++r) {
+      first = std::max(first, rel[r]);
+      last = std::max(last, rel[size_t(evals - 1) * nrhs + r]);
+    }
+    info->resid_first = first;
+    if (p.last_final) {
+      info->resid_final = last;
+      info->converged = last <= p.tol ? 1 : 0;
+      if (!info->converged) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "last solve: relative residual %.3e above tol %.3e", last, p.tol);
+        return ret(HS_ERR_NOCONV, buf);
+      }
+    }
+  }
+  return ret(HS_OK, "");
+}
+
+hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32_t* n_evals, int32_t* nrhs) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  if (max_entries < 0 || (max_entries > 0 && !rel)) return ret(HS_ERR_ARG, "rel is NULL");
+  std::vector<double> v;
+  int evals = 0, nr = 0;
+  std::string err;
+  hs_status s = plan->p.residuals(v, evals, nr, err);
+  if (n_evals) *n_evals = evals;
+  if (nrhs) *nrhs = nr;
+  if (s != HS_OK) return ret(s, err);
+  for (size_t i = 0; i < v.size() && i < size_t(max_entries); ++i) rel[i] = v[i];
   return ret(HS_OK, "");
 }
 

@@ -115,6 +115,7 @@ struct DstDesc {
 //  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) I) x = rhs,   out(r,z,b,a) = x
 // element (r,z,b,a) of data / out sits at base + r*_r + (z*nb + b)*na + a.
 constexpr int kMaxTerms = 4;
+constexpr int kMaxRefine = 16;   // refinement steps of the complex64 path
 struct SweepDesc {
   int32_t na, nb, nz, dense_in;
   int32_t nxt, nyt, pad0_, pad1_;

@@ -1043,45 +1043,104 @@ __global__ __launch_bounds__(256) void k_sigma_scatter(SigmaGeom g, const cplx<R
 // which drops the boundary terms; the terms are summed in the order centre,
 // x-1, x+1, y-1, y+1, z-1, z+1.
 constexpr int RZ_TX = 64, RZ_TY = 4, RZ_ZC = 32;
+// part (may be NULL): per workgroup, the sums of |r|^2, |f|^2 and |u|^2 over
+// its points (three doubles at part + 3 * workgroup index, workgroups
+// numbered x fastest, then z chunk, then right-hand side); write_out = 0
+// evaluates those sums without storing r.
 template <typename CO>
 __global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const double2* __restrict__ f,
                                                             const double2* __restrict__ u, CO* __restrict__ out,
-                                                            int negate_f) {
+                                                            int negate_f, double* __restrict__ part,
+                                                            int write_out) {
   const int tx = threadIdx.x & (RZ_TX - 1), ty = threadIdx.x / RZ_TX;
   const int xt = (g.nx + RZ_TX - 1) / RZ_TX;
   const int x = (blockIdx.x % xt) * RZ_TX + tx, y = (blockIdx.x / xt) * RZ_TY + ty;
-  if (x >= g.nx || y >= g.ny) return;
-  const int z0 = blockIdx.y * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
-  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const double2* uc0 = u + (int64_t)blockIdx.z * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
-  const int64_t col = uc0 - u;
-  const double2 zero = mk<double>(0, 0);
-  const double2 cxd = g.xd[x], cyd = g.yd[y];
-  const double2 cxl = g.xl[x], cxu = g.xu[x], cyl = g.yl[y], cyu = g.yu[y];
-  const bool hx0 = x > 0, hx1 = x + 1 < g.nx, hy0 = y > 0, hy1 = y + 1 < g.ny;
-  double2 um = z0 > 0 ? uc0[(int64_t)(z0 - 1) * sz] : zero;
-  double2 uc = uc0[(int64_t)z0 * sz];
+  double rr = 0, ff = 0, uu = 0;
+  if (x < g.nx && y < g.ny) {
+    const int z0 = blockIdx.y * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    const double2* uc0 = u + (int64_t)blockIdx.z * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
+    const int64_t col = uc0 - u;
+    const double2 zero = mk<double>(0, 0);
+    const double2 cxd = g.xd[x], cyd = g.yd[y];
+    const double2 cxl = g.xl[x], cxu = g.xu[x], cyl = g.yl[y], cyu = g.yu[y];
+    const bool hx0 = x > 0, hx1 = x + 1 < g.nx, hy0 = y > 0, hy1 = y + 1 < g.ny;
+    double2 um = z0 > 0 ? uc0[(int64_t)(z0 - 1) * sz] : zero;
+    double2 uc = uc0[(int64_t)z0 * sz];
 #pragma unroll 4
-  for (int z = z0; z < z1; ++z) {
-    const double2* pz = uc0 + (int64_t)z * sz;
-    const double2 up = z + 1 < g.nz ? pz[sz] : zero;
-    const double2 vxl = hx0 ? pz[-1] : zero, vxu = hx1 ? pz[1] : zero;
-    const double2 vyl = hy0 ? pz[-sy] : zero, vyu = hy1 ? pz[sy] : zero;
-    double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
-    au = cfma(cxl, vxl, au);
-    au = cfma(cxu, vxu, au);
-    au = cfma(cyl, vyl, au);
-    au = cfma(cyu, vyu, au);
-    au = cfma(g.zl[z], um, au);
-    au = cfma(g.zu[z], up, au);
-    const int64_t e = col + (int64_t)z * sz;
-    if (negate_f)
-      out[e] = cvt<CO>(au);
-    else
-      out[e] = cvt<CO>(csub(f[e], au));
-    um = uc;
-    uc = up;
+    for (int z = z0; z < z1; ++z) {
+      const double2* pz = uc0 + (int64_t)z * sz;
+      const double2 up = z + 1 < g.nz ? pz[sz] : zero;
+      const double2 vxl = hx0 ? pz[-1] : zero, vxu = hx1 ? pz[1] : zero;
+      const double2 vyl = hy0 ? pz[-sy] : zero, vyu = hy1 ? pz[sy] : zero;
+      double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
+      au = cfma(cxl, vxl, au);
+      au = cfma(cxu, vxu, au);
+      au = cfma(cyl, vyl, au);
+      au = cfma(cyu, vyu, au);
+      au = cfma(g.zl[z], um, au);
+      au = cfma(g.zu[z], up, au);
+      const int64_t e = col + (int64_t)z * sz;
+      if (negate_f) {
+        if (write_out) out[e] = cvt<CO>(au);
+      } else {
+        const double2 fe = f[e];
+        const double2 r = csub(fe, au);
+        if (write_out) out[e] = cvt<CO>(r);
+        if (part) {
+          rr = fma(r.x, r.x, fma(r.y, r.y, rr));
+          ff = fma(fe.x, fe.x, fma(fe.y, fe.y, ff));
+          uu = fma(uc.x, uc.x, fma(uc.y, uc.y, uu));
+        }
+      }
+      um = uc;
+      uc = up;
+    }
   }
+  if (!part) return;
+  // workgroup sums in a fixed order: butterfly within each wave, then the
+  // four wave sums in order
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+    rr += __shfl_xor(rr, m, 64);
+    ff += __shfl_xor(ff, m, 64);
+    uu += __shfl_xor(uu, m, 64);
+  }
+  __shared__ double red[3][RZ_TX * RZ_TY / 64];
+  const int wave = threadIdx.x / 64;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wave] = rr;
+    red[1][wave] = ff;
+    red[2][wave] = uu;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0;
+    for (int w = 0; w < RZ_TX * RZ_TY / 64; ++w) s += red[threadIdx.x][w];
+    const int64_t wg = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[3 * wg + threadIdx.x] = s;
+  }
+}
+
+// Per right-hand side r, the sums of the residual kernel's workgroup partials
+// (nwg of them per right-hand side) in a fixed order: out[3 r + {0, 1, 2}] =
+// |r|^2, |f|^2, |u|^2.
+__global__ __launch_bounds__(256) void k_norm_finish(const double* __restrict__ part, int64_t nwg,
+                                                     double* __restrict__ out) {
+  const int r = blockIdx.x;
+  const double* p = part + 3 * (int64_t)r * nwg;
+  double acc[3] = {0, 0, 0};
+  for (int64_t i = threadIdx.x; i < nwg; i += 256)
+    for (int c = 0; c < 3; ++c) acc[c] += p[3 * i + c];
+  __shared__ double red[3][256];
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) out[3 * r + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Adjoint pre/post scaling with the mass matrix M = Mx (x) My (x) Mz of eq. (3):
@@ -1470,18 +1529,31 @@ void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* 
                        g, (const float2*)ws, (double2*)u);
 }
 
+static dim3 residual_grid(const StencilGeom& g, int nrhs) {
+  return dim3(unsigned(((g.nx + RZ_TX - 1) / RZ_TX) * ((g.ny + RZ_TY - 1) / RZ_TY)),
+              unsigned((g.nz + RZ_ZC - 1) / RZ_ZC), unsigned(nrhs));
+}
+
+int64_t residual_workgroups(const StencilGeom& g) {
+  const dim3 gr = residual_grid(g, 1);
+  return (int64_t)gr.x * gr.y;
+}
+
 void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,
-              int nrhs, hipStream_t st) {
+              int nrhs, hipStream_t st, double* part, double* norms, int write_out) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
   if (n == 0 || nrhs == 0) return;
-  const dim3 grid(unsigned(((g.nx + RZ_TX - 1) / RZ_TX) * ((g.ny + RZ_TY - 1) / RZ_TY)),
-                  unsigned((g.nz + RZ_ZC - 1) / RZ_ZC), unsigned(nrhs));
+  if (apply_only) part = nullptr;
+  const dim3 grid = residual_grid(g, nrhs);
   if (out64)
     hipLaunchKernelGGL((k_residual<double2>), grid, dim3(RZ_TX * RZ_TY), 0, st, g, (const double2*)f,
-                       (const double2*)u, (double2*)out, apply_only);
+                       (const double2*)u, (double2*)out, apply_only, part, write_out);
   else
     hipLaunchKernelGGL((k_residual<float2>), grid, dim3(RZ_TX * RZ_TY), 0, st, g, (const double2*)f,
-                       (const double2*)u, (float2*)out, apply_only);
+                       (const double2*)u, (float2*)out, apply_only, part, write_out);
+  if (part && norms)
+    hipLaunchKernelGGL(k_norm_finish, dim3(unsigned(nrhs)), dim3(256), 0, st, (const double*)part,
+                       (int64_t)grid.x * grid.y, norms);
 }
 
 void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st) {

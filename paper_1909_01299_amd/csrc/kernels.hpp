@@ -178,8 +178,12 @@ void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* 
           hipStream_t st);
 void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* u, int nrhs, hipStream_t st);
 
+// part (may be NULL): 3 * residual_workgroups(g) * nrhs doubles of workgroup
+// sums; norms (with part): 3 * nrhs doubles, per right-hand side |r|^2,
+// |f|^2, |u|^2 summed in a fixed order; write_out = 0 stores no r.
+int64_t residual_workgroups(const StencilGeom& g);
 void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,
-              int nrhs, hipStream_t st);
+              int nrhs, hipStream_t st, double* part = nullptr, double* norms = nullptr, int write_out = 1);
 void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st);
 void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
                  void* plane_sums, void* grad, int nrhs, hipStream_t st);

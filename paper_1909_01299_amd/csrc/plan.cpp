@@ -107,11 +107,14 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
     err = "at most 4 separators per axis are supported";
     return HS_ERR_ARG;
   }
-  hs_options def{HS_C128, 0, 1, 0};
+  hs_options def{HS_C128, 0, 1, 0, 0.0};
   const hs_options& op = o ? *o : def;
   if (op.prec != HS_C128 && op.prec != HS_C64_REFINE) { err = "unknown precision"; return HS_ERR_ARG; }
   prec = op.prec == HS_C128 ? 0 : 1;
+  if (op.refine_steps > kMaxRefine) { err = "refine_steps > 16"; return HS_ERR_ARG; }
   refine_steps = prec ? (op.refine_steps > 0 ? op.refine_steps : (op.refine_steps < 0 ? 0 : 2)) : 0;
+  if (!(op.tol >= 0) || !std::isfinite(op.tol)) { err = "tol must be finite and >= 0"; return HS_ERR_ARG; }
+  tol = op.tol;
   if (op.max_rhs < 0 || op.max_rhs > 4096) { err = "max_rhs out of range"; return HS_ERR_ARG; }
   max_rhs = op.max_rhs > 0 ? op.max_rhs : 1;
   flags = op.flags;
@@ -440,6 +443,16 @@ void Plan::layout_workspace() {
   bytes += align_up(int64_t(R * NZ * 16), 256);       // plane sums of the gradient
   off_res = bytes;
   if (prec == 1) bytes += align_up(int64_t(R * N * 8), 256);   // complex64 residual
+  // residual norms: workgroup sums of the residual kernel, then per
+  // evaluation (first pass, each refinement step, the final check) and
+  // right-hand side |r|^2, |f|^2, |u|^2
+  StencilGeom gdims{};
+  gdims.nx = NX; gdims.ny = NY; gdims.nz = NZ;
+  n_rwg = residual_workgroups(gdims);
+  off_npart = bytes;
+  bytes += align_up(int64_t(R * n_rwg * 3 * 8), 256);
+  off_norms = bytes;
+  bytes += align_up(int64_t((kMaxRefine + 1) * R * 3 * 8), 256);
   ws_bytes = bytes;
 }
 
@@ -1058,25 +1071,68 @@ hs_status Plan::solve(const void* f, void* u, int nrhs, hipStream_t st, std::str
   if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
   if (!f || !u) { err = "f and u must be non-NULL"; return HS_ERR_ARG; }
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  double* npart = (double*)((unsigned char*)ws + off_npart);
+  double* norms = (double*)((unsigned char*)ws + off_norms);
+  const double N = double(NX) * NY * NZ;
+  int evals = 0;
+  if (f == u && (prec == 1 || tol > 0)) {
+    // residuals read f after a pass has overwritten u: keep a copy of f in
+    // the complex128 scratch region (a single pass reads all of f before it
+    // writes u, so it runs in place)
+    void* fcopy = (unsigned char*)ws + off_d64;
+    if (hipMemcpyAsync(fcopy, f, size_t(nrhs) * size_t(N) * 16, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      err = "hipMemcpyAsync failed";
+      return HS_ERR_DEVICE;
+    }
+    f = fcopy;
+  }
   if (prec == 0) {
     solve_pass(f, 1, u, 0, nrhs, st);
   } else {
     // complex64 solve, then fixed-count refinement on the FP64 residual
     void* rbuf = (unsigned char*)ws + off_res;
-    if (f == u) {
-      err = "the mixed-precision solve needs u distinct from f";
-      return HS_ERR_ARG;
-    }
     solve_pass(f, 1, u, 0, nrhs, st);
-    const double N = double(NX) * NY * NZ;
     for (int it = 0; it < refine_steps; ++it) {
       stage_begin("residual_fp64", double(nrhs) * N * 40.0, double(nrhs) * N * 62.0, st);
-      hs::residual(sten, f, u, rbuf, 0, 0, nrhs, st);
+      hs::residual(sten, f, u, rbuf, 0, 0, nrhs, st, npart, norms + size_t(evals) * 3 * nrhs, 1);
       stage_end();
+      ++evals;
       solve_pass(rbuf, 0, u, 1, nrhs, st);
     }
   }
+  last_final = false;
+  if (tol > 0) {
+    // residual of the returned u: norms only, nothing stored
+    stage_begin("residual_check", double(nrhs) * N * 32.0, double(nrhs) * N * 62.0, st);
+    hs::residual(sten, f, u, nullptr, 1, 0, nrhs, st, npart, norms + size_t(evals) * 3 * nrhs, 0);
+    stage_end();
+    ++evals;
+    last_final = true;
+  }
+  last_nrhs = nrhs;
+  last_evals = evals;
   if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+hs_status Plan::residuals(std::vector<double>& rel, int& evals, int& nrhs, std::string& err) const {
+  evals = last_evals;
+  nrhs = last_nrhs;
+  rel.clear();
+  if (!ws || last_evals == 0) { err = "no solve has recorded residuals"; return HS_ERR_STATE; }
+  std::vector<double> raw(size_t(last_evals) * 3 * last_nrhs);
+  if (hipSetDevice(device) != hipSuccess ||
+      hipMemcpy(raw.data(), (const unsigned char*)ws + off_norms, raw.size() * sizeof(double),
+                hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipGetLastError();
+    err = "hipMemcpy of the residual norms failed";
+    return HS_ERR_DEVICE;
+  }
+  rel.resize(size_t(last_evals) * last_nrhs);
+  for (size_t i = 0; i < rel.size(); ++i) {
+    const double rr = raw[3 * i], ff = raw[3 * i + 1];
+    rel[i] = ff > 0 ? std::sqrt(rr / ff) : (rr > 0 ? INFINITY : 0.0);
+  }
   return HS_OK;
 }
 

@@ -81,6 +81,7 @@ struct Plan {
   std::vector<int32_t> sepx, sepy;
   int prec = 0;          // 0 = complex128, 1 = complex64 + FP64 refinement
   int refine_steps = 0;
+  double tol = 0;        // > 0: every solve checks the residual of its result
   int max_rhs = 1;
   int flags = 0;
   int device = 0;
@@ -117,6 +118,12 @@ struct Plan {
   size_t ws_bytes = 0;
   size_t off_d64 = 0;            // byte offset of the FP64 region
   size_t off_res = 0;            // byte offset of the complex64 residual (mixed)
+  size_t off_npart = 0;          // byte offset of the residual kernel's workgroup sums
+  size_t off_norms = 0;          // byte offset of the residual norms [eval][r][3]
+  int64_t n_rwg = 0;             // residual workgroups per right-hand side
+  // convergence record of the last solve (host side: what the workspace holds)
+  int last_nrhs = 0, last_evals = 0;
+  bool last_final = false;       // the last evaluation is of the returned u
   void* ws = nullptr;
   int NF = 0;
   int64_t w_face = 0, w_vface = 0, w_gface = 0, w_Gface = 0;
@@ -174,6 +181,8 @@ struct Plan {
   hs_status residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
                      std::string& err);
   hs_status tune(int nrhs, const char* cache_path, hipStream_t st, std::string& err);
+  // relative residuals of the last solve, [eval][r] (synchronous copy)
+  hs_status residuals(std::vector<double>& rel, int& evals, int& nrhs, std::string& err) const;
 
   // one pass of the block (or decomposed) solver in compute precision
   void solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipStream_t st);

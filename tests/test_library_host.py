@@ -129,6 +129,9 @@ def test_argument_errors_before_device(hs):
     hx[3] = 0
     assert _create(hs, W.Problem(hx, p.hy, p.hz, p.layer_of_z, p.k2))[0] == hs.HS_ERR_ARG
     assert _create(hs, p, opts=hs._Options(7, 0, 1, 0))[0] == hs.HS_ERR_ARG   # unknown precision
+    assert _create(hs, p, opts=hs._Options(1, 17, 1, 0))[0] == hs.HS_ERR_ARG  # too many refinement steps
+    assert _create(hs, p, opts=hs._Options(1, 1, 1, 0, -1e-8))[0] == hs.HS_ERR_ARG   # negative tolerance
+    assert _create(hs, p, opts=hs._Options(1, 1, 1, 0, float("nan")))[0] == hs.HS_ERR_ARG
     # an x-y plane beyond 2^28 nodes (step arrays of the right lengths, nz = 1)
     big = W.Problem(np.ones(16386), np.ones(16386), np.ones(2), np.zeros(1, np.int32), p.k2[:1])
     st, msg = _create(hs, big)
@@ -150,3 +153,18 @@ def test_null_and_status_strings(hs):
     assert L.hs_plan_workspace_bytes(None, 1) == 0
     assert L.hs_profile_only(None, b"zsweep_block") == hs.HS_ERR_ARG
     assert L.hs_profile_enable(None, 1) == hs.HS_ERR_ARG
+    assert L.hs_get_residuals(None, None, 0, None, None) == hs.HS_ERR_ARG
+
+
+def test_binding_rejects_mismatched_rhs_counts(hs):
+    """Two arrays of one call must hold the same number of right-hand sides;
+    the binding raises before anything reaches the library."""
+    import torch
+    a = torch.zeros((3, 4, 5, 6), dtype=torch.complex128)
+    b = torch.zeros((2, 4, 5, 6), dtype=torch.complex128)
+    assert hs.same_nrhs(a, a.clone(), ("f", "u")) == 3
+    assert hs.same_nrhs(a[0], a[1], ("f", "u")) == 1
+    with pytest.raises(ValueError, match="u holds 2"):
+        hs.same_nrhs(a, b, ("f", "u"))
+    with pytest.raises(ValueError):
+        hs.same_nrhs(a, a[0], ("u", "a"))
