@@ -9,6 +9,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <functional>
 
 namespace hs {
@@ -1160,14 +1161,20 @@ __global__ __launch_bounds__(256) void k_conj_mass(StencilGeom g, const double2*
   out[r * n + e] = inverse ? cmul(crcp(w), cconj(v)) : cconj(cmul(w, v));
 }
 
-// Layer gradient: plane sums of a * conj(u), then per-layer sums.
-__global__ __launch_bounds__(256) void k_plane_dot(int64_t plane, int nz, const double2* __restrict__ a,
-                                                   const double2* __restrict__ u, double2* __restrict__ out) {
-  const int z = blockIdx.x, r = blockIdx.z;
+// Layer gradient: partial sums of a * conj(u) over slices of each z plane,
+// then per-layer sums of the partials.  Workgroup (z, s) of right-hand side r
+// sums slice s of plane z (elements [s*chunk, (s+1)*chunk)) into
+// part[(r * nz + z) * S + s]; the slices of a plane and the tree within a
+// workgroup are summed in a fixed order, so results repeat bit for bit.
+__global__ __launch_bounds__(256) void k_plane_dot(int64_t plane, int nz, int S, const double2* __restrict__ a,
+                                                   const double2* __restrict__ u, double2* __restrict__ part) {
+  const int z = blockIdx.x / S, sl = blockIdx.x % S, r = blockIdx.z;
+  const int64_t chunk = (plane + S - 1) / S;
+  const int64_t i0 = (int64_t)sl * chunk, i1 = min(plane, i0 + chunk);
   const double2* ap = a + ((int64_t)r * nz + z) * plane;
   const double2* up = u + ((int64_t)r * nz + z) * plane;
   double2 acc = mk<double>(0, 0);
-  for (int64_t i = threadIdx.x; i < plane; i += 256) acc = cfma(ap[i], cconj(up[i]), acc);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc = cfma(ap[i], cconj(up[i]), acc);
   __shared__ double2 red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -1175,17 +1182,18 @@ __global__ __launch_bounds__(256) void k_plane_dot(int64_t plane, int nz, const 
     if (threadIdx.x < w) red[threadIdx.x] = cadd(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[(int64_t)r * nz + z] = red[0];
+  if (threadIdx.x == 0) part[((int64_t)r * nz + z) * S + sl] = red[0];
 }
 
-__global__ void k_layer_sum(int nz, int nlayers, const int* __restrict__ layer_of_z,
-                            const double2* __restrict__ plane_sums, double2* __restrict__ grad) {
+__global__ __launch_bounds__(64) void k_layer_sum(int nz, int S, int nlayers, const int* __restrict__ layer_of_z,
+                                                  const double2* __restrict__ part, double2* __restrict__ grad) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.z;
   if (l >= nlayers) return;
   double2 acc = mk<double>(0, 0);
   for (int z = 0; z < nz; ++z)
-    if (layer_of_z[z] == l) acc = cadd(acc, plane_sums[(int64_t)r * nz + z]);
+    if (layer_of_z[z] == l)
+      for (int sl = 0; sl < S; ++sl) acc = cadd(acc, part[((int64_t)r * nz + z) * S + sl]);
   grad[(int64_t)r * nlayers + l] = acc;
 }
 
@@ -1563,12 +1571,25 @@ void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int
                      (double2*)out, inverse);
 }
 
+int grad_slices(int64_t plane, int nz, int nrhs) {
+  // about 2048 workgroups in all, each summing at least 2048 elements
+  int64_t S = 2048 / std::max<int64_t>(1, (int64_t)nz * nrhs);
+  S = std::min<int64_t>(S, std::max<int64_t>(1, plane / 2048));
+  return int(std::max<int64_t>(1, std::min<int64_t>(S, 64)));
+}
+
+int64_t grad_partials(int64_t plane, int nz, int nrhs) {
+  return (int64_t)nrhs * nz * grad_slices(plane, nz, nrhs);
+}
+
 void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
-                 void* plane_sums, void* grad, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_plane_dot, dim3(nz, 1, nrhs), dim3(256), 0, st, plane, nz, (const double2*)a,
-                     (const double2*)u, (double2*)plane_sums);
-  hipLaunchKernelGGL(k_layer_sum, dim3((nlayers + 63) / 64, 1, nrhs), dim3(64), 0, st, nz, nlayers,
-                     layer_of_z, (const double2*)plane_sums, (double2*)grad);
+                 void* part, void* grad, int nrhs, hipStream_t st) {
+  if (nz == 0 || nrhs == 0) return;
+  const int S = grad_slices(plane, nz, nrhs);
+  hipLaunchKernelGGL(k_plane_dot, dim3(unsigned(nz * S), 1, nrhs), dim3(256), 0, st, plane, nz, S,
+                     (const double2*)a, (const double2*)u, (double2*)part);
+  hipLaunchKernelGGL(k_layer_sum, dim3((nlayers + 63) / 64, 1, nrhs), dim3(64), 0, st, nz, S, nlayers,
+                     layer_of_z, (const double2*)part, (double2*)grad);
 }
 
 }  // namespace hs

@@ -185,7 +185,12 @@ int64_t residual_workgroups(const StencilGeom& g);
 void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,
               int nrhs, hipStream_t st, double* part = nullptr, double* norms = nullptr, int write_out = 1);
 void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int nrhs, hipStream_t st);
+// Layer gradient grad[r][l] = sum over layer l of a * conj(u): slice partials
+// of every z plane into `part` (grad_partials(plane, nz, nrhs) complex128
+// values, all overwritten), then per-layer sums in a fixed order.
+int grad_slices(int64_t plane, int nz, int nrhs);
+int64_t grad_partials(int64_t plane, int nz, int nrhs);
 void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
-                 void* plane_sums, void* grad, int nrhs, hipStream_t st);
+                 void* part, void* grad, int nrhs, hipStream_t st);
 
 }  // namespace hs

@@ -440,7 +440,10 @@ void Plan::layout_workspace() {
   off_d64 = bytes;
   const size_t N = size_t(NX) * NY * NZ;
   bytes += align_up(int64_t(R * N * 16), 256);        // adjoint scratch (complex128)
-  bytes += align_up(int64_t(R * NZ * 16), 256);       // plane sums of the gradient
+  off_gpart = bytes;                                   // slice sums of the gradient
+  int64_t gmax = 0;
+  for (int r = 1; r <= R; ++r) gmax = std::max(gmax, grad_partials((int64_t)NX * NY, NZ, r));
+  bytes += align_up(gmax * 16, 256);
   off_res = bytes;
   if (prec == 1) bytes += align_up(int64_t(R * N * 8), 256);   // complex64 residual
   // residual norms: workgroup sums of the residual kernel, then per
@@ -1161,7 +1164,7 @@ hs_status Plan::grad_k2(const void* u, const void* a, void* grad, int nrhs, hipS
   if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
   if (!u || !a || !grad) { err = "u, a and grad must be non-NULL"; return HS_ERR_ARG; }
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
-  void* sums = (unsigned char*)ws + off_d64 + align_up(int64_t(max_rhs) * NX * NY * NZ * 16, 256);
+  void* sums = (unsigned char*)ws + off_gpart;
   grad_layers((int64_t)NX * NY, NZ, nlayers, dint + i_layer, a, u, sums, grad, nrhs, st);
   if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
   return HS_OK;

@@ -118,6 +118,7 @@ struct Plan {
   size_t ws_bytes = 0;
   size_t off_d64 = 0;            // byte offset of the FP64 region
   size_t off_res = 0;            // byte offset of the complex64 residual (mixed)
+  size_t off_gpart = 0;          // byte offset of the gradient's slice sums
   size_t off_npart = 0;          // byte offset of the residual kernel's workgroup sums
   size_t off_norms = 0;          // byte offset of the residual norms [eval][r][3]
   int64_t n_rwg = 0;             // residual workgroups per right-hand side
