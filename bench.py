@@ -1,22 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the separable Helmholtz solver on one MI355X.
 
-Workload (one step = one full solve of the decomposed grid):
-  uniform core 256 x 256 (h = 1) + 16 PML cells per side (steps 1.2^k (1+0.5i)),
-  287 x 287 interior nodes, nz = 200 in 20 layers, 4 x 4 blocks (separators at
-  15, 143, 271 on x and y) solved by the two-level interface reduction;
-  unit point source at the grid centre; complex128.  Inputs are resident in
-  HBM before the timed region.
+Headline workload (one step = every frequency's solve of every source):
+  uniform core 512 x 512 (h = 1) + 32 PML cells per side (steps
+  1.2^k (1+0.5i)), 575 x 575 interior nodes, n_z = 256 in 60 layers, 4 x 4
+  blocks (separators at 31, 287, 543 on x and y) solved by the two-level
+  interface reduction; 16 unit point sources off the separators; k^2 scaled
+  by omega^2 for omega in (1, 1.5, 2, 3).  One plan per frequency (the plans
+  share one workspace); a step solves the 16 right-hand sides at once with
+  each plan in turn.  complex128.  Inputs are resident in HBM before the
+  timed region.
 
-Prints one JSON line: unknowns*RHS/s of the complex128 solve, the mixed
-complex64 + FP64-refinement solve beside it, the roofline of the dominant
-kernel from hipEvents recorded on the solve's stream, and the FP64 CPU oracle
-timed on the host.  The same line carries two more workloads, each in
-complex128 and in mixed precision: 64 independent blocks of uneven sizes with
-8 right-hand sides each as one captured graph per solve ("batched_c3"), and
-the large 575 x 575 x 256 grid with 16 point sources at 4 frequencies
-("large_c5"); and the time of one adjoint gradient with respect to the layer
-values of k^2 on the 128 x 128 x 160 grid ("adjoint_c4").
+Prints one JSON line: unknowns*RHS/s of the complex128 solves, the mixed
+complex64 + FP64-refinement solves of the same workload beside them, the
+roofline of the dominant kernel from hipEvents recorded on the solve's
+stream inside the timed region, oracle errors on sampled sources, and the
+FP64 CPU oracle timed on the host on one source.  The same line carries three
+more workloads: the 287 x 287 x 200 decomposed grid with one centre point
+source ("decomposed_c2"), 64 independent blocks of uneven sizes with 8
+right-hand sides each as one captured graph per solve ("batched_c3"), and the
+time of one adjoint gradient with respect to the layer values of k^2 on the
+128 x 128 x 160 grid ("adjoint_c4").
 """
 from __future__ import annotations
 
@@ -44,41 +48,6 @@ def kernel_source_hash() -> str:
             h.update(name.encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def time_solves(plan, f, u, steps, warmup, profile=True):
-    """Wall time of `steps` solves.  With profile: an untimed run of as many
-    solves with hipEvents around every stage (on the solve's stream) gives the
-    stage table and the dominant stage; in the timed run only that stage is
-    bracketed by events (two per solve), so its kernel time is measured over
-    the timed region itself.  Returns (seconds, stage table, dominant stage
-    record from the timed region)."""
-    import torch
-    for _ in range(warmup):
-        plan.solve(f, out=u)
-    torch.cuda.synchronize()
-    stages, dom = [], None
-    if profile:
-        plan.profile(True)
-        plan.profile_read()          # reset accumulators
-        for _ in range(steps):
-            plan.solve(f, out=u)
-        torch.cuda.synchronize()
-        stages = plan.profile_read()
-        top = max(stages, key=lambda s: s["ms"])["name"]
-        plan.profile(True, only=top)
-        plan.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.solve(f, out=u)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    if profile:
-        rec = [s for s in plan.profile_read() if s["launches"] > 0]
-        dom = rec[0] if rec else None
-        plan.profile(False)
-    return dt, stages, dom
 
 
 def roofline(top, prec):
@@ -122,21 +91,38 @@ def copy_run():
 
 
 def counters_run(args):
-    """Three solves of the decomposed workload (complex128, default tiling);
-    per solve the stage kernels are dispatched in a fixed order."""
+    """Complex128 solves for the counter runs, per solve the stage kernels
+    dispatched in a fixed order: the headline workload (575 x 575 x 256, 16
+    sources, omega = 1; two solves) or, with --counters-workload c2, the
+    287 x 287 x 200 grid (three solves)."""
     import torch
     import paper_1909_01299_amd as hs
     import workloads as W
     torch.cuda.set_device(0)
-    p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
-    f = hs.to_device(f_np)
+    if args.counters_workload == "c2":
+        p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
+        f = hs.to_device(f_np)
+        solves = 3
+    else:
+        p, srcs, _ = W.c5_multi_rhs()
+        f = point_sources_device(p, srcs)
+        solves = 2
     u = torch.empty_like(f)
-    plan = hs.Plan(p, "c128", max_rhs=1)
-    for _ in range(3):
+    plan = hs.Plan(p, "c128", max_rhs=f.shape[0])
+    for _ in range(solves):
         plan.solve(f, out=u)
     torch.cuda.synchronize()
     info = plan.info()
-    print(json.dumps({"solves": 3, "z_chunks": info["z_chunks"]}), flush=True)
+    print(json.dumps({"workload": args.counters_workload, "solves": solves, "z_chunks": info["z_chunks"]}),
+          flush=True)
+
+
+def point_sources_device(p, srcs):
+    import torch
+    f = torch.zeros((len(srcs),) + p.shape, dtype=torch.complex128, device="cuda")
+    for r, (x, y, z) in enumerate(srcs):
+        f[r, z, y, x] = 1.0
+    return f
 
 
 def _counter_rows(folder, counter):
@@ -256,15 +242,43 @@ def traffic_for(kernel_stage: str):
     return None if rec is None else rec.get("bytes_per_launch")
 
 
-def cpu_baseline(problem, f, repeat_budget_s=20.0):
-    """The FP64 oracle (undecomposed generalized-eigen separable solve) on the
-    host: plan (eigendecomposition) excluded, solve timed."""
-    from oracle import separable
+def host_description():
+    """CPU model, thread count and numerical library versions of the host."""
+    import platform
+    import scipy
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
     try:
         from threadpoolctl import threadpool_info
-        cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count()])
+        for i in threadpool_info():
+            blas.append(f"{i.get('internal_api')} {i.get('version')} ({i.get('num_threads')} threads)")
     except Exception:
-        cores = os.cpu_count()
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "numpy": np.__version__,
+            "scipy": scipy.__version__, "blas": blas}
+
+
+def oracle_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        return os.cpu_count()
+
+
+def cpu_baseline(problem, f, unknowns_per_rhs, repeat_budget_s=20.0, sample=""):
+    """The FP64 oracle (undecomposed generalized-eigen separable solve) on the
+    host: plan (eigendecomposition) excluded, solves of f timed (median of at
+    most 3, within the budget).  Returns (oracle solution, baseline record)."""
+    from oracle import separable
     t0 = time.perf_counter()
     solver = separable.SeparableSolver(problem)
     t_plan = time.perf_counter() - t0
@@ -277,9 +291,28 @@ def cpu_baseline(problem, f, repeat_budget_s=20.0):
         if sum(times) > repeat_budget_s / 2 or len(times) >= 3:
             break
     t = float(np.median(times))
-    return u, {"value": problem.unknowns * f.shape[0] / t, "unit": "unknowns*RHS/s", "cores": cores,
-               "kind": "oracle", "sample": f"full workload, {f.shape[0]} RHS, median of {len(times)} solves "
-                                         f"({t:.2f} s each; eigen tables {t_plan:.2f} s excluded)"}
+    nrhs = 1 if f.ndim == 3 else f.shape[0]
+    return u, {"value": unknowns_per_rhs * nrhs / t, "unit": "unknowns*RHS/s", "cores": oracle_threads(),
+               "kind": "oracle",
+               "sample": f"{sample}: {nrhs} RHS, median of {len(times)} solves ({t:.2f} s each; eigen tables "
+                         f"{t_plan:.2f} s excluded)",
+               "host": host_description()}
+
+
+def errors_vs(u, ref, problem=None):
+    """Relative 2-norm error, largest pointwise error over the largest
+    reference value, and (decomposed grids) the relative error on the
+    separator planes."""
+    d = u - ref
+    out = {"rel2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
+           "relmax": float(np.abs(d).max() / np.abs(ref).max())}
+    if problem is not None and (len(problem.sep_x) or len(problem.sep_y)):
+        m = np.zeros(problem.shape[1:], dtype=bool)
+        m[:, problem.sep_x] = True
+        m[problem.sep_y, :] = True
+        ds, rs = d[:, m], ref[:, m]
+        out["rel2_sigma"] = float(np.linalg.norm(ds) / np.linalg.norm(rs))
+    return out
 
 
 def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c128", "mixed"), refine_steps=1):
@@ -324,8 +357,9 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
                 f1 = W.c3_rhs(i, pb, nrhs)[:1]
                 ref = separable.solve(pb, f1)
                 got = us[i][:1].cpu().numpy()
-                errs.append(float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
-            rec["rel_err_vs_oracle_max"] = max(errs)
+                errs.append(errors_vs(got, ref))
+            rec["rel_err_vs_oracle_max"] = max(e["rel2"] for e in errs)
+            rec["relmax_err_vs_oracle_max"] = max(e["relmax"] for e in errs)
             rec["oracle_sample"] = f"blocks {list(sample_blocks)}, RHS 0"
         out[prec] = rec
         del batch, plans
@@ -387,83 +421,186 @@ def bench_c4(steps, with_oracle):
     return out
 
 
-def bench_c5(steps, refine_steps=1):
-    """Large decomposed grid: core 512 + 32 PML cells per side (575 x 575
-    interior nodes), n_z = 256 in 60 layers, 16 point sources off the
-    separators, k^2 scaled by omega^2 for omega in (1, 1.5, 2, 3).  One plan
-    per precision; each frequency is one k^2 update (hs_set_k2, not timed)
-    followed by solves of all 16 right-hand sides at once.  The relative
-    residual |f - A u| / |f| of the last solve (FP64 stencil on the GPU) is
-    reported per frequency; parity with the oracle at this size is a test."""
+def merge_stage_tables(tables):
+    """Sum the per-stage records of several plans (same stage names)."""
+    out = {}
+    for tab in tables:
+        for rec in tab:
+            m = out.setdefault(rec["name"], dict(rec, ms=0.0, launches=0))
+            m["ms"] += rec["ms"]
+            m["launches"] += rec["launches"]
+    return list(out.values())
+
+
+def time_plans(plans, f, u, steps, warmup):
+    """Wall time of `steps` steps, a step being one solve of f with every plan
+    in turn.  An untimed step with hipEvents around every stage gives the
+    stage table and the dominant stage; in the timed steps only that stage is
+    bracketed by events (two per solve, on the solve's stream), so its kernel
+    time comes from the timed region itself.  Returns (seconds, stage table
+    per step, dominant stage record from the timed region)."""
+    import torch
+
+    def step():
+        for pl in plans:
+            pl.solve(f, out=u)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    for pl in plans:
+        pl.profile(True)
+        pl.profile_read()
+    step()
+    torch.cuda.synchronize()
+    stages = merge_stage_tables([pl.profile_read() for pl in plans])
+    top = max(stages, key=lambda r: r["ms"])["name"]
+    for pl in plans:
+        pl.profile(True, only=top)
+        pl.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = [r for r in merge_stage_tables([pl.profile_read() for pl in plans]) if r["launches"] > 0]
+    for pl in plans:
+        pl.profile(False)
+    return dt, stages, (rec[0] if rec else None)
+
+
+def bench_c5(steps, warmup, refine_steps=1, with_oracle=True, precs=("c128", "mixed"), profile_only=False):
+    """Headline workload: 575 x 575 x 256, 4 x 4 blocks + interface reduction,
+    16 point sources x 4 frequencies.  Returns the record of each precision
+    (throughput, roofline of the dominant stage, stage table) and, with the
+    oracle, errors on sampled sources and the oracle's own throughput."""
     import torch
     import paper_1909_01299_amd as hs
     import workloads as W
+    torch.cuda.set_device(0)
     p, srcs, omegas = W.c5_multi_rhs()
     nrhs = len(srcs)
-    f = torch.zeros((nrhs,) + p.shape, dtype=torch.complex128, device="cuda")
-    for r, (x, y, z) in enumerate(srcs):
-        f[r, z, y, x] = 1.0
+    f = point_sources_device(p, srcs)
     u = torch.empty_like(f)
+    per_step = p.unknowns * nrhs * len(omegas)
     out = {"workload": f"c5_large {p.nx}x{p.ny}x{p.nz}, 4x4 blocks + interface reduction, PML 32/side, "
-                       f"60 layers, {nrhs} point sources x {len(omegas)} frequencies",
-           "unknowns": p.unknowns, "nrhs": nrhs, "omegas": list(omegas)}
-    fnorm = float(torch.linalg.vector_norm(f[0]))
-    for prec in ("c128", "mixed"):
+                       f"60 layers, {nrhs} point sources x {len(omegas)} frequencies (omega in {list(omegas)})",
+           "unknowns": p.unknowns, "nrhs": nrhs, "omegas": list(omegas), "unknowns_rhs_per_step": per_step}
+    # oracle samples: (frequency index, source index)
+    samples = ((0, 0), (3, 1))
+    for prec in precs:
         t0 = time.perf_counter()
-        plan = hs.Plan(p, prec, max_rhs=nrhs, refine_steps=refine_steps if prec == "mixed" else 0)
-        t_plan = time.perf_counter() - t0
-        total = 0.0
-        resid = []
+        plans, ws = [], None
         for om in omegas:
-            plan.set_k2(p.k2 * om ** 2)
-            plan.solve(f, out=u)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                plan.solve(f, out=u)
-            torch.cuda.synchronize()
-            total += (time.perf_counter() - t0) / steps
-            r = plan.residual(f[:1], u[:1])
-            resid.append(float(torch.linalg.vector_norm(r)) / fnorm)
-            del r
-        rec = {"value": p.unknowns * nrhs * len(omegas) / total, "unit": "unknowns*RHS/s",
-               "ms_per_frequency": total / len(omegas) * 1e3, "plan_seconds": t_plan,
-               "rel_residual_rhs0_per_omega": resid}
+            pl = hs.Plan(p.with_k2(p.k2 * om ** 2), prec, max_rhs=nrhs,
+                         refine_steps=refine_steps if prec == "mixed" else 0, workspace=ws)
+            ws = pl.workspace
+            plans.append(pl)
+        t_plan = time.perf_counter() - t0
+        dt, stages, dom = time_plans(plans, f, u, steps, warmup)
+        rec = {"value": per_step * steps / dt, "unit": "unknowns*RHS/s", "ms_per_step": dt / steps * 1e3,
+               "ms_per_frequency": dt / steps / len(omegas) * 1e3, "plan_seconds_4_plans": t_plan,
+               "roofline": roofline(dom, prec),
+               "stages_ms_per_step": {r["name"]: round(r["ms"], 3) for r in stages}}
         if prec == "mixed":
-            rec["refine_steps"] = plan.info()["refine_steps"]
+            rec["refine_steps"] = plans[0].info()["refine_steps"]
+        if not profile_only:
+            # sampled results for the oracle, and the FP64 residual of each
+            # frequency's first source (GPU stencil), outside the timed region
+            rec["sampled"] = {}
+            resid = []
+            fnorm = float(torch.linalg.vector_norm(f[0]))
+            for k, pl in enumerate(plans):
+                pl.solve(f, out=u)
+                r = pl.residual(f[:1], u[:1])
+                resid.append(float(torch.linalg.vector_norm(r)) / fnorm)
+                del r
+                for (kk, src) in samples:
+                    if kk == k:
+                        rec["sampled"][(kk, src)] = u[src].cpu().numpy()
+            rec["rel_residual_rhs0_per_omega"] = resid
         out[prec] = rec
-        del plan
+        del plans, ws
         torch.cuda.empty_cache()
+    if "mixed" in out and "c128" in out:
+        out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    if with_oracle and not profile_only:
+        from oracle import separable
+        fs0 = W.point_source_batch(p, srcs[:1])[0]
+        u_ref0, cpu = cpu_baseline(p.with_k2(p.k2 * omegas[0] ** 2), fs0, p.unknowns,
+                                   sample=f"the headline grid at omega = {omegas[0]}, source 0 (of 16)")
+        out["cpu_baseline"] = cpu
+        refs = {samples[0]: u_ref0}
+        for (kk, src) in samples[1:]:
+            fs = W.point_source_batch(p, [srcs[src]])[0]
+            refs[(kk, src)] = separable.solve(p.with_k2(p.k2 * omegas[kk] ** 2), fs)
+        for prec in precs:
+            errs = {f"omega={omegas[kk]} source {src}": errors_vs(out[prec]["sampled"][(kk, src)], refs[(kk, src)], p)
+                    for (kk, src) in samples}
+            out[prec]["rel_err_vs_oracle"] = errs
+            out[prec]["rel_err_vs_oracle_max"] = max(e["rel2"] for e in errs.values())
+            out[prec]["relmax_err_vs_oracle_max"] = max(e["relmax"] for e in errs.values())
+    for prec in precs:
+        out[prec].pop("sampled", None)
+    return out
+
+
+def bench_c2(steps, warmup, args, with_oracle):
+    """The 287 x 287 x 200 decomposed grid (one centre point source): tuned
+    complex128 and mixed plans, stage tables, oracle errors."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
+    nrhs = f_np.shape[0]
+    f = hs.to_device(f_np)
+    out = {"workload": f"c2_decomposed {p.nx}x{p.ny}x{p.nz}, 4x4 blocks + interface reduction, "
+                       f"PML {args.pml}/side, {args.layers} layers, centre point source",
+           "unknowns": p.unknowns, "nrhs": nrhs}
+    us = {}
+    for prec in ("c128", "mixed"):
+        plan = hs.Plan(p, prec, max_rhs=nrhs, refine_steps=args.refine_steps if prec == "mixed" else 0)
+        tuned = plan.tune(nrhs)
+        u = torch.empty_like(f)
+        dt, stages, dom = time_plans([plan], f, u, steps, warmup)
+        us[prec] = u.cpu().numpy()
+        out[prec] = {"value": p.unknowns * nrhs * steps / dt, "ms_per_step": dt / steps * 1e3, "tuned": tuned,
+                     "roofline": roofline(dom, prec),
+                     "stages_ms_per_step": {r["name"]: round(r["ms"], 4) for r in stages}}
+        del plan
     out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    if with_oracle:
+        from oracle import separable
+        ref = separable.solve(p, f_np)
+        for prec in ("c128", "mixed"):
+            out[prec]["rel_err_vs_oracle"] = errors_vs(us[prec][0], ref[0], p)
     return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--mixed-only", action="store_true", help="time only the mixed-precision solve (profiling)")
-    ap.add_argument("--core", type=int, default=256, help="uniform core cells per axis")
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (baseline and errors)")
+    ap.add_argument("--core", type=int, default=256, help="decomposed_c2: uniform core cells per axis")
     ap.add_argument("--pml", type=int, default=16)
     ap.add_argument("--nz", type=int, default=200)
     ap.add_argument("--layers", type=int, default=20)
-    ap.add_argument("--no-c3", action="store_true", help="skip the batched 64-block measurement")
-    ap.add_argument("--no-c5", action="store_true", help="skip the large 575x575x256 measurement")
-    ap.add_argument("--no-c4", action="store_true", help="skip the adjoint-gradient measurement")
+    ap.add_argument("--no-extras", action="store_true", help="headline only (no c2, c3, c4 workloads)")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--refine-steps", type=int, default=1,
                     help="FP64-residual refinement steps of the mixed-precision solves (-1: none)")
     ap.add_argument("--copy", action="store_true", help="counter calibration: a plain 1 GiB copy")
-    ap.add_argument("--counters", action="store_true", help="three complex128 solves for counter runs")
+    ap.add_argument("--counters", action="store_true", help="complex128 solves for counter runs")
+    ap.add_argument("--counters-workload", choices=["c5", "c2"], default="c5")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
     ap.add_argument("--c4-only", action="store_true", help="time only the adjoint gradient (128x128x160)")
-    ap.add_argument("--c5-only", action="store_true",
-                    help="time only the large 575x575x256 grid, 16 sources x 4 frequencies (c128 vs mixed)")
+    ap.add_argument("--c5-only", choices=["c128", "mixed", "both"],
+                    help="time only the headline workload (no oracle): for kernel traces")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
     ap.add_argument("--stage-labels", action="store_true",
@@ -486,111 +623,74 @@ def main():
     if args.copy:
         copy_run()
         return
+    if args.counters:
+        counters_run(args)
+        return
     if args.c3_only:
         precs = ("c128", "mixed") if args.c3_only == "both" else (args.c3_only,)
         print(json.dumps(bench_c3(args.c3_steps, 1, False, precs=precs, refine_steps=args.refine_steps)), flush=True)
-        return
-    if args.counters:
-        counters_run(args)
         return
     if args.c4_only:
         print(json.dumps(bench_c4(max(1, args.steps), True)), flush=True)
         return
     if args.c5_only:
-        print(json.dumps(bench_c5(max(1, min(args.steps, 3)), refine_steps=args.refine_steps)), flush=True)
+        precs = ("c128", "mixed") if args.c5_only == "both" else (args.c5_only,)
+        print(json.dumps(bench_c5(args.steps, args.warmup, args.refine_steps, with_oracle=False, precs=precs,
+                                  profile_only=True)), flush=True)
         return
 
     import torch
-    import paper_1909_01299_amd as hs
-    import workloads as W
-
     torch.cuda.set_device(0)
-    p, f_np = W.c2_decomposed(core_cells=args.core, pml_cells=args.pml, nz=args.nz, nlayers=args.layers)
-    nrhs = f_np.shape[0]
-    f = hs.to_device(f_np)
-    u = torch.empty_like(f)
-
-    if args.mixed_only:
-        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
-        um = torch.empty_like(f)
-        dtm, _, _ = time_solves(plan_m, f, um, args.steps, args.warmup, profile=False)
-        print(json.dumps({"mixed_ms_per_step": dtm / args.steps * 1e3}), flush=True)
-        return
-    plan = hs.Plan(p, "c128", max_rhs=nrhs)
-    tuned = plan.tune(nrhs)
-    info = plan.info()
-    dt, stages, dom = time_solves(plan, f, u, args.steps, args.warmup)
-    ms = dt / args.steps * 1e3
-    value = p.unknowns * nrhs / (dt / args.steps)
-    u_gpu = u.cpu().numpy()
-
-    mixed = None
-    if not args.no_mixed:
-        plan_m = hs.Plan(p, "mixed", max_rhs=nrhs, refine_steps=args.refine_steps)
-        plan_m.tune(nrhs)
-        um = torch.empty_like(f)
-        dtm, stages_m, dom_m = time_solves(plan_m, f, um, args.steps, args.warmup)
-        mixed = {"value": p.unknowns * nrhs / (dtm / args.steps), "ms_per_step": dtm / args.steps * 1e3,
-                 "refine_steps": plan_m.info()["refine_steps"], "u": um.cpu().numpy(),
-                 "roofline": roofline(dom_m, "c64"),
-                 "stages": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages_m}}
-        del plan_m
-
-    cpu = None
-    rel_err = rel_err_mixed = None
-    if not args.no_cpu_baseline:
-        u_ref, cpu = cpu_baseline(p, f_np)
-        rel_err = float(np.linalg.norm(u_gpu - u_ref) / np.linalg.norm(u_ref))
-        if mixed is not None:
-            rel_err_mixed = float(np.linalg.norm(mixed["u"] - u_ref) / np.linalg.norm(u_ref))
-
-    c3 = None
-    if not args.no_c3:
-        del plan
+    with_oracle = not args.no_cpu_baseline
+    c5 = bench_c5(args.steps, args.warmup, args.refine_steps, with_oracle=with_oracle)
+    print(json.dumps({"progress": "headline done", "c128_ms_per_step": c5["c128"]["ms_per_step"]}),
+          file=sys.stderr, flush=True)
+    extras = {}
+    if not args.no_extras:
         torch.cuda.empty_cache()
-        c3 = bench_c3(args.c3_steps, 1, not args.no_cpu_baseline, refine_steps=args.refine_steps)
-    c4 = None
-    if not args.no_c4:
-        c4 = bench_c4(10, not args.no_cpu_baseline)
-    c5 = None
-    if not args.no_c5:
+        extras["decomposed_c2"] = bench_c2(20, 3, args, with_oracle)
+        print(json.dumps({"progress": "c2 done"}), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
-        c5 = bench_c5(2, refine_steps=args.refine_steps)
+        extras["batched_c3"] = bench_c3(args.c3_steps, 1, with_oracle, refine_steps=args.refine_steps)
+        print(json.dumps({"progress": "c3 done"}), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["adjoint_c4"] = bench_c4(10, with_oracle)
 
-    rf = roofline(dom, "c128")
+    c128 = c5["c128"]
+    rf = c128["roofline"]
     if rf is not None:
         rf["traffic"] = traffic_for(rf["kernel"])
+    mixed = c5.get("mixed")
     line = {
         "metric": "unknowns*RHS/s (decomposed 3D Helmholtz solve, complex128)",
-        "value": value,
+        "value": c128["value"],
         "unit": "unknowns*RHS/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": c128["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"c2_decomposed {p.nx}x{p.ny}x{p.nz}, 4x4 blocks + interface reduction, "
-                               f"PML {args.pml}/side, {args.layers} layers, centre point source",
-                   "unknowns": p.unknowns, "nrhs": nrhs, "blocks": info["nblocks"]},
-        "rel_err_vs_oracle": rel_err,
+        "config": {"workload": c5["workload"], "unknowns": c5["unknowns"], "nrhs": c5["nrhs"],
+                   "omegas": c5["omegas"], "unknowns_rhs_per_step": c5["unknowns_rhs_per_step"],
+                   "blocks": 16},
+        "rel_err_vs_oracle": c128.get("rel_err_vs_oracle"),
         "roofline": rf,
-        "cpu_baseline": cpu,
-        "mixed_c64_refine": None if mixed is None else {
+        "cpu_baseline": c5.get("cpu_baseline"),
+        "stages_ms_per_step": c128["stages_ms_per_step"],
+        "rel_residual_rhs0_per_omega": c128.get("rel_residual_rhs0_per_omega"),
+        "plan_seconds_4_plans": c128["plan_seconds_4_plans"],
+        "mixed_c64_refine": mixed and {
             "value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
-            "refine_steps": mixed["refine_steps"], "rel_err_vs_oracle": rel_err_mixed,
-            "speedup_vs_c128": mixed["value"] / value, "roofline": mixed["roofline"],
-            "stages_ms_per_step": mixed["stages"]},
-        "batched_c3": c3,
-        "adjoint_c4": c4,
-        "large_c5": c5,
-        "stages_ms_per_step": {s["name"]: round(s["ms"] / args.steps, 4) for s in stages},
-        "plan_seconds": info["plan_seconds"],
-        "tuned": tuned,
+            "refine_steps": mixed.get("refine_steps"), "speedup_vs_c128": c5.get("mixed_speedup_vs_c128"),
+            "rel_err_vs_oracle": mixed.get("rel_err_vs_oracle"), "roofline": mixed["roofline"],
+            "stages_ms_per_step": mixed["stages_ms_per_step"],
+            "rel_residual_rhs0_per_omega": mixed.get("rel_residual_rhs0_per_omega")},
     }
+    line.update(extras)
     print(json.dumps(line), flush=True)
 
 

@@ -1,16 +1,21 @@
 """GPU parity at the full sizes of every workload, in the launch configuration
 the benchmark times, against the FP64 oracle (through the C ABI).
 
-Where the oracle cannot afford every output (the 64-block batch), it checks a
-sample of blocks and right-hand sides one by one; elsewhere it solves the full
-problem.  Tolerances as in test_gpu_parity: 1e-10 (complex128) and 1e-8
-(complex64 + FP64 refinement) relative 2-norm error per right-hand side.
+Where the oracle cannot afford every output (the 64-block batch, the 16
+sources of the large grid), it checks a sample of blocks and right-hand sides
+one by one; elsewhere it solves the full problem.  Tolerances 1e-10
+(complex128) and 1e-8 (complex64 + FP64 refinement), each applied to the
+relative 2-norm error, the largest pointwise error relative to the largest
+reference value, and on decomposed grids the relative error on the
+separator planes alone (tests/parity.py).
 """
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import adjoint, operator, separable
+
+from parity import check
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +44,7 @@ def test_decomposed_287x287x200_full_vs_oracle(hs, prec):
     plan.tune(1)
     u = plan.solve(dev(f)).cpu().numpy()
     ref = separable.solve(p, f[0])
-    assert rel(u[0], ref) < TOL[prec]
+    check(u[0], ref, TOL[prec], p, f"287^2 {prec}")
 
 
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
@@ -71,7 +76,7 @@ def test_batched_64_blocks_x8_rhs_sampled_vs_oracle(hs, prec):
         solver = separable.SeparableSolver(pb)
         for r in rhs:
             ref = solver.solve(f_np[r])
-            assert rel(us[i][r].cpu().numpy(), ref) < TOL[prec], (i, r)
+            check(us[i][r].cpu().numpy(), ref, TOL[prec], None, f"block {i} rhs {r} {prec}")
 
 
 def test_adjoint_128x128x160_gradient_full_vs_oracle_and_differences(hs):
@@ -114,18 +119,30 @@ def test_adjoint_128x128x160_gradient_full_vs_oracle_and_differences(hs):
     plan.set_k2(p.k2)
 
 
-@pytest.mark.parametrize("omega", [1.0, 3.0])
-def test_large_575x575x256_two_sources_vs_oracle(hs, omega):
+@pytest.mark.parametrize("omega", [1.0, 1.5, 2.0, 3.0])
+def test_large_575x575x256_sources_vs_oracle(hs, omega):
     """Core 512 + 32 PML cells per side, n_z = 256 in 60 layers, k^2 scaled by
-    omega^2; the first two of the 16 point sources, complex128 and mixed."""
-    p, srcs, _ = W.c5_multi_rhs()
+    omega^2, every frequency the benchmark times.  The plans are those of the
+    benchmark (16 right-hand sides, one FP64 refinement step for the mixed
+    solve); all 16 sources are solved and two of them, a different pair per
+    frequency, are compared with the oracle."""
+    import torch
+    p, srcs, omegas = W.c5_multi_rhs()
+    assert omega in omegas
     p = p.with_k2(p.k2 * omega ** 2)
-    f = W.point_source_batch(p, srcs[:2])
+    f = W.point_source_batch(p, srcs)
+    k = omegas.index(omega)
+    pick = (2 * k, 2 * k + 1)
     solver = separable.SeparableSolver(p)
-    refs = [solver.solve(f[r]) for r in range(2)]
+    refs = {r: solver.solve(f[r]) for r in pick}
+    fd = dev(f)
     for prec in ("c128", "mixed"):
-        plan = hs.Plan(p, prec, max_rhs=2)
-        u = plan.solve(dev(f)).cpu().numpy()
-        for r in range(2):
-            assert rel(u[r], refs[r]) < TOL[prec], (prec, r)
-        del plan
+        plan = hs.Plan(p, prec, max_rhs=len(srcs), refine_steps=REFINE[prec], tol=1e-9)
+        u = plan.solve(fd)
+        torch.cuda.synchronize()
+        info = plan.info()
+        assert info["converged"] == 1, (prec, info["resid_final"])
+        for r in pick:
+            check(u[r].cpu().numpy(), refs[r], TOL[prec], p, f"575^2 omega {omega} {prec} source {r}")
+        del plan, u
+        torch.cuda.empty_cache()
