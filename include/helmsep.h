@@ -207,6 +207,13 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
  * allocates and frees two scratch arrays; synchronizes the stream. */
 hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void* stream);
 
+/* Set the launch shapes directly (as hs_plan_tune would store them), e.g. to
+ * reuse one plan's tuning on another plan of the same shapes: z_chunks in
+ * {0 (default for nz), 8, 16, 32}, sine_lines in {0 (default), 4, 8, 16}.
+ * HS_ERR_ARG for a value outside these sets or one the plan cannot use (a z
+ * chunking that cannot hold nz, sine lines whose LDS does not fit). */
+hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines);
+
 /* Per-stage timing.  While enabled, every stage of a solve is bracketed by
  * hipEvents recorded on the solve's stream (events come from a pool created
  * here, so solves still allocate nothing).  hs_profile_read synchronizes on

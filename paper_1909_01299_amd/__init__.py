@@ -87,6 +87,7 @@ EXPORTS = {
     "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
+    "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hs_profile_only": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -258,6 +259,10 @@ class Plan:
         _check(lib().hs_plan_tune(self._h, int(nrhs), cache.encode() if cache else None, _stream(stream)))
         inf = self.info()
         return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"]}
+
+    def set_launch(self, shapes: dict):
+        """Apply launch shapes as returned by tune() (z_chunks, sine_lines)."""
+        _check(lib().hs_plan_set_launch(self._h, int(shapes.get("z_chunks", 0)), int(shapes.get("sine_lines", 0))))
 
     def profile(self, on: bool = True, only: Optional[str] = None):
         """Record hipEvents around every stage of subsequent solves, or only

@@ -150,7 +150,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         dx.n = B.nbx; dx.P = p->NZ; dx.Q = B.nby;
         dx.src = fo; dx.src_p = plane; dx.src_q = B.nbx; dx.src_i = 1;
         dx.dst = spec; dx.dst_p = plane; dx.dst_q = B.nbx; dx.dst_i = 1;
-        const int v = ilog2i(AX.dstV) - 1;
+        const int v = ilog2i(AX.dstV);
         s_fwdx.dst[v].push_back(dx);
         DstDesc dr = dx;
         dr.src = ro;
@@ -176,7 +176,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         dy.n = B.nby; dy.P = p->NZ; dy.Q = B.nbx;
         dy.src = spec; dy.src_p = plane; dy.src_q = 1; dy.src_i = B.nbx;
         dy.dst = spec; dy.dst_p = plane; dy.dst_q = 1; dy.dst_i = B.nbx;
-        const int v = ilog2i(AY.dstV) - 1;
+        const int v = ilog2i(AY.dstV);
         s_fwdy.dst[v].push_back(dy);
         s_invy.dst[v].push_back(dy);
       } else {
@@ -266,7 +266,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
-      dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
+      dst_lines(prec, in64, out64, acc, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
                 dst, 1, st, plans[0]->tune_lt);
 }
 
@@ -277,7 +277,7 @@ void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
   const void* tw = (const unsigned char*)T + size_t(tab_off[0] + plans[0]->twid) * esz;
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
-      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st,
+      dst_lines(prec, 0, 0, 0, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st,
                 plans[0]->tune_lt);
 }
 

@@ -187,6 +187,21 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
   return ret(plan->p.tune(nrhs, cache_path, (hipStream_t)stream, err), err);
 }
 
+hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  hs::Plan& p = plan->p;
+  if (z_chunks != 0 && !hs::sweep_chunks_ok(z_chunks, p.NZ)) return ret(HS_ERR_ARG, "z chunking cannot hold nz");
+  if (sine_lines != 0) {
+    for (auto& a : p.axes)
+      if (a.dstV && !hs::dst_lt_ok(p.prec, a.dstV, sine_lines))
+        return ret(HS_ERR_ARG, "sine lines per workgroup not usable on this plan");
+    if (sine_lines != 4 && sine_lines != 8 && sine_lines != 16) return ret(HS_ERR_ARG, "sine lines not in {4, 8, 16}");
+  }
+  p.tune_chunks = z_chunks;
+  p.tune_lt = sine_lines;
+  return ret(HS_OK, "");
+}
+
 hs_status hs_profile_enable(hs_plan plan, int32_t on) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
   std::string err;

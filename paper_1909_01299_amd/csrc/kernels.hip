@@ -77,16 +77,24 @@ __global__ __launch_bounds__(256) void k_xform_y(const XformYDesc* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Orthonormal DST-I of length n = N - 1 (N = 8 V a power of two) through the
-// complex FFT of the odd extension y (y_0 = y_N = 0, y_j = x_j, y_{2N-j} = -x_j):
-// Y_m = -2i sum_j x_j sin(pi j m / N), so X_m = sqrt(2/N) (i/2) Y_m.
-// The length L = 2N = 16 V FFT is split 16 x V: each of 16 lanes per line
-// runs a V-point FFT in registers over y[t + 16 v], applies the twiddles
-// W_L^{t k2}, exchanges through a padded LDS row, and finishes with 16-point
-// FFTs over t.  A workgroup stages whole lines in LDS, so the same kernel
-// serves contiguous x lines and strided y lines (and runs in place).
+// Orthonormal DST-I of lines of n = N - 1 points (N = 16 V a power of two,
+// 16 <= N <= 512) by one complex FFT of length N.  With x_0 = x_N = 0,
+//   y_j = sin(pi j / N) (x_j + x_{N-j}) + (x_j - x_{N-j}) / 2,   Z = FFT_N(y),
+// the sums S_k = sum_j x_j sin(pi j k / N) are
+//   S_{2m}   = i (Z_m - Z_{N-m}) / 2                           m = 1 .. N/2-1
+//   S_{2m+1} = Z_0 / 2 + sum_{m' = 1 .. m} (Z_m' + Z_{N-m'}) / 2   m = 0 .. N/2-1
+// (the part of y symmetric about N/2 carries the odd sums, the antisymmetric
+// part the even ones; complex x by linearity), and the transform is
+// sqrt(2 / N) S_k.  The FFT is split 16 x V: each of 16 lanes per line runs a
+// V-point FFT in registers over y[t + 16 v], applies the twiddles W_N^{t k2},
+// exchanges through a padded LDS row and finishes with 16-point FFTs over t.
+// Lane t then forms the terms of N/32 consecutive m (running sums within the
+// lane, the totals of the lanes before it through LDS) and writes S into the
+// LDS slots it alone read; the lines are stored from there.  A workgroup
+// stages whole lines, so the same kernel serves contiguous x lines and
+// strided y lines, in place.
 // ---------------------------------------------------------------------------
-constexpr int TW_N = 512;   // tw[k] = exp(-2 pi i k / 512)
+constexpr int TW_N = 1024;   // tw[k] = exp(-2 pi i k / 1024)
 
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 __host__ __device__ constexpr int bitrevc(int i, int lg) {
@@ -136,22 +144,20 @@ template <typename R, typename CI, typename CO, bool ACC, int V, int LT>
 __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ descs, const cplx<R>* __restrict__ tw,
                                                  const CI* __restrict__ src, CO* __restrict__ dst) {
   using C = cplx<R>;
-  constexpr int L = 16 * V;
-  constexpr int N = L / 2;
+  constexpr int N = 16 * V;
   constexpr int n = N - 1;
-  constexpr int XS = 17 * V + 1;   // LDS row of one line: 17 slots per 16 values, odd pad
-  // complex exchange in one pass where it fits in 64 KB (the register array
-  // of the first stage dies before the second is filled); otherwise real and
-  // imaginary parts are exchanged in turn
-  constexpr bool CX = size_t(LT) * XS * 2 * sizeof(R) <= 65536;
-  __shared__ R xbuf[CX ? 2 * LT * XS : LT * XS];
+  constexpr int XS = 17 * V + 1;               // LDS row of a line: entry (k2, k1) at slot 17 k2 + k1
+  constexpr int MPL = N >= 32 ? N / 32 : 1;    // terms m per lane in the sums
+  constexpr int PL = (N / 2) / MPL;            // lanes holding terms (16; 8 for N = 16)
+  __shared__ C row[LT * XS];
+  __shared__ C tot[LT * 16];
   const DstDesc d = descs[blockIdx.y];
   const int lines = d.P * d.Q;
   const int l0 = blockIdx.x * LT;
   if (l0 >= lines) return;
   const int r = blockIdx.z;
   // lanes run along a line for contiguous lines (x) and across lines for
-  // strided ones (y), so that each 16-lane group touches consecutive addresses
+  // strided ones (y), so that each group of lanes touches consecutive addresses
   const bool along = d.src_i == 1;
   const int li = along ? int(threadIdx.x >> 4) : int(threadIdx.x % LT);
   const int t = along ? int(threadIdx.x & 15) : int(threadIdx.x / LT);
@@ -160,94 +166,98 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   const int gc = ok ? g : lines - 1;   // a valid line for lanes past the end
   const int p = gc / d.Q, q = gc % d.Q;
   const CI* sl = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
-  // odd extension y_j, j = t + 16 v: y_j = x_{j-1} (0 < j < N), -x_{2N-j-1} (j > N), 0 else.
-  // Every lane loads from a valid (clamped) address; sign and zeros are applied
-  // afterwards, so all loads are in flight together.
+  // y_j, j = t + 16 v, from x_j (element j - 1) and x_{N-j} (element N - j - 1);
+  // j = 0 loads element 0 and is zeroed, so all loads are in flight together
   C a[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) {
     const int j = t + 16 * v;
-    int e = j < N ? j - 1 : 2 * N - j - 1;
-    e = e < 0 ? 0 : (e > n - 1 ? n - 1 : e);
-    a[v] = cvt<C>(sl[(int64_t)e * d.src_i]);
-  }
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const int j = t + 16 * v;
-    const R fac = (!ok || j == 0 || j == N) ? R(0) : (j < N ? R(1) : R(-1));
-    a[v].x *= fac;
-    a[v].y *= fac;
+    const int e1 = j >= 1 ? j - 1 : 0, e2 = j >= 1 ? N - j - 1 : 0;
+    const C x1 = cvt<C>(sl[(int64_t)e1 * d.src_i]);
+    const C x2 = cvt<C>(sl[(int64_t)e2 * d.src_i]);
+    const R sn = -tw[j * (TW_N / (2 * N))].y;   // sin(pi j / N)
+    const R on = (ok && j >= 1) ? R(1) : R(0);
+    a[v].x = on * fma(sn, x1.x + x2.x, R(0.5) * (x1.x - x2.x));
+    a[v].y = on * fma(sn, x1.y + x2.y, R(0.5) * (x1.y - x2.y));
   }
   fft_reg<C, V>(a, tw);
 #pragma unroll
-  for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % L) * (TW_N / L)]);
+  for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % N) * (TW_N / N)]);
+  C* crow = row + li * XS;
+#pragma unroll
+  for (int k2 = 0; k2 < V; ++k2) crow[k2 * 17 + t] = a[k2];
+  __syncthreads();
+  // 16-point FFTs over t; Z_{k2 + V k1} goes back to the slots just read
   constexpr int G = V >= 16 ? V / 16 : 1;
-  C b[G][16];
-  if constexpr (CX) {
-    C* crow = reinterpret_cast<C*>(xbuf) + li * XS;
 #pragma unroll
-    for (int k2 = 0; k2 < V; ++k2) crow[k2 * 17 + t] = a[k2];
-    __syncthreads();
+  for (int gg = 0; gg < G; ++gg) {
+    const int k2 = t + 16 * gg;
+    if (k2 < V) {
+      C b[16];
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-      const int k2 = t + 16 * gg;
-      if (k2 < V) {
+      for (int k1 = 0; k1 < 16; ++k1) b[k1] = crow[k2 * 17 + k1];
+      fft_reg<C, 16>(b, tw);
 #pragma unroll
-        for (int tt = 0; tt < 16; ++tt) b[gg][tt] = crow[k2 * 17 + tt];
-        fft_reg<C, 16>(b[gg], tw);
+      for (int k1 = 0; k1 < 16; ++k1) crow[k2 * 17 + k1] = b[k1];
+    }
+  }
+  __syncthreads();
+  auto zslot = [](int m) { return (m % V) * 17 + m / V; };
+  // terms of m = t MPL .. t MPL + MPL - 1: running sums of the odd outputs;
+  // the even outputs S_{2m} go straight to the slot of Z_{N-m} (read by this
+  // lane only)
+  C cs[MPL];
+  C run = mk<R>(0, 0);
+  if (t < PL) {
+#pragma unroll
+    for (int i = 0; i < MPL; ++i) {
+      const int m = t * MPL + i;
+      const C zm = crow[zslot(m)];
+      C c;
+      if (m == 0) {
+        c.x = R(0.5) * zm.x;
+        c.y = R(0.5) * zm.y;
+      } else {
+        const C zn = crow[zslot(N - m)];
+        c.x = R(0.5) * (zm.x + zn.x);
+        c.y = R(0.5) * (zm.y + zn.y);
+        C e;
+        e.x = R(0.5) * (zn.y - zm.y);
+        e.y = R(0.5) * (zm.x - zn.x);
+        crow[zslot(N - m)] = e;
       }
-    }
-  } else {
-  R* wrow = xbuf + li * XS;
-#pragma unroll
-  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2].x;
-  __syncthreads();
-#pragma unroll
-  for (int gg = 0; gg < G; ++gg) {
-    const int k2 = t + 16 * gg;
-    if (k2 < V) {
-#pragma unroll
-      for (int tt = 0; tt < 16; ++tt) b[gg][tt].x = wrow[k2 * 17 + tt];
+      run = cadd(run, c);
+      cs[i] = run;
     }
   }
+  tot[li * 16 + t] = t < PL ? run : mk<R>(0, 0);
   __syncthreads();
+  if (t < PL) {
+    C off = mk<R>(0, 0);
+    for (int u = 0; u < t; ++u) off = cadd(off, tot[li * 16 + u]);
 #pragma unroll
-  for (int k2 = 0; k2 < V; ++k2) wrow[k2 * 17 + t] = a[k2].y;
+    for (int i = 0; i < MPL; ++i) crow[zslot(t * MPL + i)] = cadd(cs[i], off);
+  }
   __syncthreads();
-#pragma unroll
-  for (int gg = 0; gg < G; ++gg) {
-    const int k2 = t + 16 * gg;
-    if (k2 < V) {
-#pragma unroll
-      for (int tt = 0; tt < 16; ++tt) b[gg][tt].y = wrow[k2 * 17 + tt];
-      fft_reg<C, 16>(b[gg], tw);
-    }
-  }
-  }
   if (!ok) return;
-  const R sc = R(0.5) * R(sqrt(2.0 / double(N)));
+  const R sc = R(sqrt(2.0 / double(N)));
   CO* dl = dst + d.dst + (int64_t)r * d.dst_r + (int64_t)p * d.dst_p + (int64_t)q * d.dst_q;
 #pragma unroll
-  for (int gg = 0; gg < G; ++gg) {
-    const int k2 = t + 16 * gg;
-    if (k2 < V) {
-#pragma unroll
-      for (int k1 = 0; k1 < 16; ++k1) {
-        const int m = k2 + V * k1;
-        if (m >= 1 && m <= n) {
-          C o;
-          o.x = -sc * b[gg][k1].y;
-          o.y = sc * b[gg][k1].x;
-          CO* ptr = dl + (int64_t)(m - 1) * d.dst_i;
-          if (ACC) {
-            CO pv = *ptr;
-            pv.x += o.x;
-            pv.y += o.y;
-            *ptr = pv;
-          } else {
-            *ptr = cvt<CO>(o);
-          }
-        }
+  for (int c = 0; c < V; ++c) {
+    const int k = t + 16 * c;
+    if (k >= 1 && k <= n) {
+      const C v = crow[(k & 1) ? zslot(k >> 1) : zslot(N - (k >> 1))];
+      C o;
+      o.x = sc * v.x;
+      o.y = sc * v.y;
+      CO* ptr = dl + (int64_t)(k - 1) * d.dst_i;
+      if (ACC) {
+        CO pv = *ptr;
+        pv.x += o.x;
+        pv.y += o.y;
+        *ptr = pv;
+      } else {
+        *ptr = cvt<CO>(o);
       }
     }
   }
@@ -1206,17 +1216,21 @@ inline unsigned grid1(int64_t n) { return unsigned((n + 255) / 256); }
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------- sine transform
+// LDS of one workgroup of lt lines (rows of 17 V + 1 complex values and the
+// lanes' partial sums)
+static size_t dst_lds_bytes(int prec, int V, int lt) {
+  const size_t csz = prec == 0 ? 16 : 8;
+  return size_t(lt) * (17 * V + 1 + 16) * csz;
+}
+
 int dst_lines_per_wg(int prec, int V) {
-  // exchange rows of 17 V + 1 real values, at most 40 KB of LDS per workgroup
-  const int rsz = prec == 0 ? 8 : 4;
   int lt = 16;
-  while (lt > 4 && (17 * V + 1) * rsz * lt > 40960) lt /= 2;
+  while (lt > 4 && dst_lds_bytes(prec, V, lt) > 40960) lt /= 2;
   return lt;
 }
 
 bool dst_lt_ok(int prec, int V, int lt) {
-  const int rsz = prec == 0 ? 8 : 4;
-  return (lt == 4 || lt == 8 || lt == 16) && (17 * V + 1) * rsz * lt <= 65536;
+  return (lt == 4 || lt == 8 || lt == 16) && dst_lds_bytes(prec, V, lt) <= 65536;
 }
 
 template <typename R, typename CI, typename CO, bool ACC>
@@ -1228,10 +1242,14 @@ static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, cons
   const cplx<R>* T = (const cplx<R>*)tw;
 #define HS_DST_CASE(VV, LL)                                                                                    \
   if (V == VV && lt == LL) {                                                                                   \
-    hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV, LL>), grid, dim3(16 * LL), 0, st, d, T, (const CI*)src,       \
-                       (CO*)dst);                                                                              \
+    if constexpr ((17 * VV + 17) * LL * sizeof(cplx<R>) <= 65536)                                              \
+      hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV, LL>), grid, dim3(16 * LL), 0, st, d, T, (const CI*)src,     \
+                         (CO*)dst);                                                                            \
     return;                                                                                                    \
   }
+  HS_DST_CASE(1, 16)
+  HS_DST_CASE(1, 8)
+  HS_DST_CASE(1, 4)
   HS_DST_CASE(2, 16)
   HS_DST_CASE(2, 8)
   HS_DST_CASE(2, 4)

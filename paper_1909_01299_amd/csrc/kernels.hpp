@@ -98,8 +98,8 @@ void xform_lines_h3(int in64, int out64, int acc, const XformDesc* dev, const Xf
 void xform_y_h3(const XformYDesc* dev, const XformYDesc* host, int ndesc, const void* htab, void* ws, int nrhs,
                 hipStream_t st);
 
-// Sine transform of lines of n = 8 V - 1 points (V in {2, 4, 8, 16, 32}).
-constexpr int kTwiddleN = 512;
+// Sine transform of lines of n = 16 V - 1 points (V in {1, 2, 4, 8, 16, 32}).
+constexpr int kTwiddleN = 1024;
 // lt: lines per workgroup (4, 8 or 16; 0 or an unusable value = default)
 void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, int ndesc, int max_lines,
                const void* tw, const void* src, void* dst, int nrhs, hipStream_t st, int lt = 0);

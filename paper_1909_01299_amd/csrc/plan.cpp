@@ -169,7 +169,7 @@ hs_status Plan::build_tables(std::string& err) {
     a.sine = axis_is_uniform(n, h) && !(flags & 1);
     a.real_tables = axis_is_uniform(n, h);
     const int N = n + 1;
-    if (a.sine && N >= 16 && N <= 256 && (N & (N - 1)) == 0) a.dstV = N / 8;
+    if (a.sine && N >= 16 && N <= 512 && (N & (N - 1)) == 0) a.dstV = N / 16;
     if (axis_is_uniform(n, h)) {
       axis_eig_uniform(n, h[0], a.e);
     } else {
@@ -491,7 +491,7 @@ void Plan::build_descriptors() {
     const Axis& AY = axes[B.ay];
     const int64_t plane = (int64_t)B.nbx * B.nby;
     const int64_t spec_r = plane * NZ;
-    auto vidx = [](int V) { return ilog2i(V) - 1; };
+    auto vidx = [](int V) { return ilog2i(V); };
     if (AX.dstV) {
       DstDesc dx{};
       dx.n = B.nbx; dx.P = NZ; dx.Q = B.nby;
@@ -942,7 +942,7 @@ void Plan::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, c
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
-      dst_lines(prec, in64, out64, acc, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
+      dst_lines(prec, in64, out64, acc, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
                 dst, nrhs, st, tune_lt);
 }
 
@@ -953,7 +953,7 @@ void Plan::run_y(const StageList<XformYDesc>& sl, int nrhs, hipStream_t st) {
   const void* tw = (const unsigned char*)T + size_t(twid) * esz;
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
-      dst_lines(prec, 0, 0, 0, 2 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, nrhs,
+      dst_lines(prec, 0, 0, 0, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, nrhs,
                 st, tune_lt);
 }
 
@@ -961,9 +961,11 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   const void* T = tab();
   void* W = ws;
   const int nb = int(blocks.size());
+  // x-type terms staged in LDS: only solves with a dense input stage them
   auto xterms = [](const std::vector<SweepDesc>& v) {
     int m = 0;
-    for (auto& d : v) m = std::max(m, d.nxt);
+    for (auto& d : v)
+      if (d.dense_in) m = std::max(m, d.nxt);
     return m;
   };
   auto modes = [](const std::vector<SweepDesc>& v) { return sweep_modes(v); };
@@ -972,11 +974,12 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   const double R = nrhs;
   const double esz = prec == 0 ? 16.0 : 8.0;
   const double esz_in = in64 ? 16.0 : 8.0;
-  // dense pass: 8 n flops per complex output; sine FFT pass: 5 L log2(L) / n per output
+  // dense pass: 8 n flops per complex output; sine pass: a length N = n + 1
+  // complex FFT (5 N log2 N) and about 16 N of pre- and post-processing
   auto pass_flops = [](const Axis& a) {
     if (a.dstV) {
-      const double L = 2.0 * (a.n + 1);
-      return 5.0 * L * std::log2(L) / a.n;
+      const double L = double(a.n + 1);
+      return (5.0 * L * std::log2(L) + 16.0 * L) / a.n;
     }
     return 8.0 * a.n;
   };

@@ -18,7 +18,7 @@ namespace hs {
 struct Axis {
   int n = 0;
   bool sine = false;
-  int dstV = 0;                        // > 0: sine transform by FFT with V = (n + 1) / 8
+  int dstV = 0;                        // > 0: sine transform by FFT with V = (n + 1) / 16
   bool real_tables = false;            // uniform axis: W and W^{-1} are real sine matrices
   AxisEig e;
   int64_t fwd = 0, inv = 0, lam = 0;   // table offsets (complex elements)
@@ -54,7 +54,7 @@ struct Block {
 };
 
 // One transform stage: dense-table descriptors plus sine-FFT descriptors per V.
-constexpr int kNumV = 5;   // V = 2, 4, 8, 16, 32
+constexpr int kNumV = 6;   // V = 1, 2, 4, 8, 16, 32
 template <typename DenseDesc>
 struct StageList {
   std::vector<DenseDesc> dense;

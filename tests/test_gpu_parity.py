@@ -69,9 +69,11 @@ def test_dense_path_on_uniform_axes_matches_sine_path(hs):
     assert per_rhs_err(u1, u2) < TOL128
 
 
-@pytest.mark.parametrize("shape", [(15, 31, 12), (63, 127, 9), (255, 15, 6), (127, 127, 20)])
+@pytest.mark.parametrize("shape", [(15, 31, 12), (63, 127, 9), (255, 15, 6), (127, 127, 20), (511, 17, 5),
+                                   (31, 511, 4), (255, 255, 3)])
 def test_sine_fft_path_vs_oracle_and_dense(hs, shape):
-    """Uniform axes with n + 1 a power of two take the FFT sine transform."""
+    """Uniform axes with n + 1 a power of two (16 .. 512) take the FFT sine
+    transform, along x (contiguous lines) and along y (strided lines)."""
     nx, ny, nz = shape
     rng = np.random.default_rng(nx + 7 * ny)
     p = W.uniform_problem(nx, ny, nz, 3, rng)
