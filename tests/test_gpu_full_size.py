@@ -136,8 +136,10 @@ def test_large_575x575x256_sources_vs_oracle(hs, omega):
     solver = separable.SeparableSolver(p)
     refs = {r: solver.solve(f[r]) for r in pick}
     fd = dev(f)
+    # the plans check the relative residual of their result on the device
+    resid_tol = {"c128": 1e-12, "mixed": 1e-8}
     for prec in ("c128", "mixed"):
-        plan = hs.Plan(p, prec, max_rhs=len(srcs), refine_steps=REFINE[prec], tol=1e-9)
+        plan = hs.Plan(p, prec, max_rhs=len(srcs), refine_steps=REFINE[prec], tol=resid_tol[prec])
         u = plan.solve(fd)
         torch.cuda.synchronize()
         info = plan.info()
