@@ -29,7 +29,7 @@ def solve_adjoint(problem, g: np.ndarray, solver: SeparableSolver = None) -> np.
     if single:
         g = g[None]
     s = solver or SeparableSolver(problem)
-    lower, zdiag, upper = z_tridiag(problem.hz, k2_nodes(problem))
+    lower, zdiag, upper = z_tridiag(problem.hz, k2_nodes(problem), problem.sig_step)
     # (Dz - k^2)^H: transpose swaps lower and upper (shifted by one row), conj
     lo_h = np.zeros_like(lower)
     up_h = np.zeros_like(upper)
@@ -42,7 +42,7 @@ def solve_adjoint(problem, g: np.ndarray, solver: SeparableSolver = None) -> np.
     WxiH = s.Wxi.conj().T
     WyiH = s.Wyi.conj().T
     gh = transform_y(WyH, transform_x(WxH, g))
-    diag = d_h[:, None, None] + shift[None]
+    diag = d_h[:, None, None] + problem.sig_node[:, None, None] * shift[None]
     ah = np.empty_like(gh)
     for r in range(gh.shape[0]):
         ah[r] = thomas(lo_h, diag, up_h, gh[r])

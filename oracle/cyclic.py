@@ -38,7 +38,8 @@ def block_ranges(n: int, seps) -> list:
 def sub_problem(problem, x0, x1, y0, y1):
     from workloads import Problem
     return Problem(problem.hx[x0:x1 + 2], problem.hy[y0:y1 + 2], problem.hz,
-                   problem.layer_of_z, problem.k2)
+                   problem.layer_of_z, problem.k2, sigma_node=problem.sigma_node,
+                   sigma_step=problem.sigma_step)
 
 
 def _block_solve_all(problem, rhs):

@@ -14,8 +14,15 @@ tridiag(-1, 2, -1) / h^2.  The 3D operator in the D-form used throughout is
 
     A = Dx (x) I (x) I + I (x) Dy (x) I + I (x) I (x) (Dz - diag k^2(z)),
 
-which is minus eq. (3) divided by the mass matrices, with sigma = 1 and the
-constant lambda replaced by the layered k^2(z).  Arrays are ordered
+which is minus eq. (3) divided by the mass matrices, with the constant
+lambda replaced by the layered k^2(z).  With the coefficient sigma(z) of
+eqs. (1)-(2) the x and y terms of row k carry sigma at node k, and the z term
+is the flux form with sigma at the two z steps of the node:
+
+    A = diag(sigma_node) (Dx (+) Dy) + Dz^sigma - diag k^2,
+    (K_z^sigma u)_k = s[k] (u_k - u_{k-1}) / h[k] - s[k+1] (u_{k+1} - u_k) / h[k+1]
+
+(s = sigma at the steps; without sigma both are 1).  Arrays are ordered
 [z][y][x] (x fastest); a right-hand-side batch is [r][z][y][x].
 """
 from __future__ import annotations
@@ -30,35 +37,38 @@ def hhat(h: np.ndarray) -> np.ndarray:
     return 0.5 * (h[:-1] + h[1:])
 
 
-def axis_K(h: np.ndarray) -> np.ndarray:
-    """Dense n x n stiffness matrix K of one axis (complex symmetric)."""
+def axis_K(h: np.ndarray, w: np.ndarray = None) -> np.ndarray:
+    """Dense n x n stiffness matrix K of one axis (complex symmetric); w
+    (n + 1 values, default 1) weights each step's flux (sigma at the steps)."""
     h = np.asarray(h, dtype=np.complex128)
     n = h.shape[0] - 1
+    w = np.ones(n + 1) if w is None else np.asarray(w)
     K = np.zeros((n, n), dtype=np.complex128)
     for i in range(n):
-        K[i, i] = 1.0 / h[i] + 1.0 / h[i + 1]
+        K[i, i] = w[i] / h[i] + w[i + 1] / h[i + 1]
         if i > 0:
-            K[i, i - 1] = -1.0 / h[i]
+            K[i, i - 1] = -w[i] / h[i]
         if i + 1 < n:
-            K[i, i + 1] = -1.0 / h[i + 1]
+            K[i, i + 1] = -w[i + 1] / h[i + 1]
     return K
 
 
-def axis_D(h: np.ndarray) -> np.ndarray:
+def axis_D(h: np.ndarray, w: np.ndarray = None) -> np.ndarray:
     """Dense D = M^{-1} K of one axis."""
-    return axis_K(h) / hhat(np.asarray(h, dtype=np.complex128))[:, None]
+    return axis_K(h, w) / hhat(np.asarray(h, dtype=np.complex128))[:, None]
 
 
-def z_tridiag(hz: np.ndarray, k2_nodes: np.ndarray):
-    """Diagonals (lower, diag, upper) of Dz - diag(k^2) along z.
+def z_tridiag(hz: np.ndarray, k2_nodes: np.ndarray, sig_step: np.ndarray = None):
+    """Diagonals (lower, diag, upper) of Dz^sigma - diag(k^2) along z.
 
     lower[k] multiplies u_{k-1}, upper[k] multiplies u_{k+1}; lower[0] and
-    upper[nz-1] are zero."""
+    upper[nz-1] are zero.  sig_step: sigma at the nz + 1 steps (default 1)."""
     hz = np.asarray(hz, dtype=np.complex128)
+    w = np.ones(hz.shape[0]) if sig_step is None else np.asarray(sig_step, np.float64)
     hh = hhat(hz)
-    lower = -1.0 / (hh * hz[:-1])
-    upper = -1.0 / (hh * hz[1:])
-    diag = (1.0 / hz[:-1] + 1.0 / hz[1:]) / hh - np.asarray(k2_nodes, np.complex128)
+    lower = -w[:-1] / (hh * hz[:-1])
+    upper = -w[1:] / (hh * hz[1:])
+    diag = (w[:-1] / hz[:-1] + w[1:] / hz[1:]) / hh - np.asarray(k2_nodes, np.complex128)
     lower = lower.copy()
     upper = upper.copy()
     lower[0] = 0.0
@@ -81,33 +91,36 @@ def apply_A(problem, u: np.ndarray) -> np.ndarray:
     up = np.pad(u, pad)
     c = up[..., 1:-1, 1:-1, 1:-1]
 
-    def second_diff(h, lo, hi, axis_len, shape_axis):
+    def second_diff(h, lo, hi, axis_len, shape_axis, w=None):
         hl = np.asarray(h, np.complex128)[:-1]
         hr = np.asarray(h, np.complex128)[1:]
         hh = 0.5 * (hl + hr)
+        wl = np.ones(axis_len) if w is None else np.asarray(w)[:-1]
+        wr = np.ones(axis_len) if w is None else np.asarray(w)[1:]
         shp = [1, 1, 1]
         shp[shape_axis] = axis_len
-        hl = hl.reshape(shp)
-        hr = hr.reshape(shp)
-        hh = hh.reshape(shp)
-        return ((c - lo) / hl - (hi - c) / hr) / hh
+        hl, hr, hh = hl.reshape(shp), hr.reshape(shp), hh.reshape(shp)
+        wl, wr = wl.reshape(shp), wr.reshape(shp)
+        return (wl * (c - lo) / hl - wr * (hi - c) / hr) / hh
 
     dx = second_diff(problem.hx, up[..., 1:-1, 1:-1, :-2], up[..., 1:-1, 1:-1, 2:], nx, 2)
     dy = second_diff(problem.hy, up[..., 1:-1, :-2, 1:-1], up[..., 1:-1, 2:, 1:-1], ny, 1)
-    dz = second_diff(problem.hz, up[..., :-2, 1:-1, 1:-1], up[..., 2:, 1:-1, 1:-1], nz, 0)
+    dz = second_diff(problem.hz, up[..., :-2, 1:-1, 1:-1], up[..., 2:, 1:-1, 1:-1], nz, 0,
+                     problem.sig_step)
     k2 = k2_nodes(problem).reshape(nz, 1, 1)
-    return dx + dy + dz - k2 * c
+    sig = problem.sig_node.reshape(nz, 1, 1)
+    return sig * (dx + dy) + dz - k2 * c
 
 
 def assemble_A(problem) -> sp.csr_matrix:
     """Sparse A as a Kronecker sum, index = (z * ny + y) * nx + x."""
     Dx = sp.csr_matrix(axis_D(problem.hx))
     Dy = sp.csr_matrix(axis_D(problem.hy))
-    Dz = sp.csr_matrix(axis_D(problem.hz)) - sp.diags(k2_nodes(problem))
+    Dz = sp.csr_matrix(axis_D(problem.hz, problem.sig_step)) - sp.diags(k2_nodes(problem))
+    Sz = sp.diags(problem.sig_node.astype(np.complex128))
     Ix = sp.identity(problem.nx, dtype=np.complex128, format="csr")
     Iy = sp.identity(problem.ny, dtype=np.complex128, format="csr")
-    Iz = sp.identity(problem.nz, dtype=np.complex128, format="csr")
-    A = (sp.kron(Iz, sp.kron(Iy, Dx)) + sp.kron(Iz, sp.kron(Dy, Ix))
+    A = (sp.kron(Sz, sp.kron(Iy, Dx)) + sp.kron(Sz, sp.kron(Dy, Ix))
          + sp.kron(Dz, sp.kron(Iy, Ix)))
     return sp.csr_matrix(A)
 

@@ -9,10 +9,12 @@ steps the correct forward transform is W^{-1} (W^* = W^{-1} only for a
 unitary W), which is the reading used here.  After the transform the 3D
 system splits into one tridiagonal system in z per mode (a, b):
 
-    (Dz - diag k^2 + (lambda_a + mu_b) I) u_hat(a, b, :) = f_hat(a, b, :),
+    (Dz - diag k^2 + (lambda_a + mu_b) diag sigma) u_hat(a, b, :) = f_hat(a, b, :),
 
 solved by the Thomas algorithm (Gaussian elimination without pivoting, the
 O(N_z) solve of eq. (5)), vectorised over all modes and right-hand sides.
+With sigma(z) of eq. (1), Dz is the flux form with sigma at the z steps and
+the modal shift is scaled by sigma at each node (sigma = 1 when absent).
 """
 from __future__ import annotations
 
@@ -74,12 +76,13 @@ class SeparableSolver:
         self.problem = problem
         self.lam_x, self.Wx, self.Wxi = axis_eig(problem.hx)
         self.lam_y, self.Wy, self.Wyi = axis_eig(problem.hy)
-        self.lower, self.zdiag, self.upper = z_tridiag(problem.hz, k2_nodes(problem))
+        self.lower, self.zdiag, self.upper = z_tridiag(problem.hz, k2_nodes(problem), problem.sig_step)
+        self.sig = problem.sig_node
 
     def solve_spectral(self, fh: np.ndarray) -> np.ndarray:
         """z solves for every mode: fh is (R, nz, ny, nx) in mode space."""
         shift = self.lam_y[:, None] + self.lam_x[None, :]          # (b, a)
-        diag = self.zdiag[:, None, None] + shift[None]               # (nz, b, a)
+        diag = self.zdiag[:, None, None] + self.sig[:, None, None] * shift[None]   # (nz, b, a)
         out = np.empty_like(fh)
         for r in range(fh.shape[0]):
             out[r] = thomas(self.lower, diag, self.upper, fh[r])

@@ -19,6 +19,12 @@ geometrically growing, complex-stretched PML ends):
 * Complex normal entries are (N(0,1) + i N(0,1)) / sqrt(2).
 * Generator: numpy PCG64, ``default_rng(190901299 + config_id)``; draw order
   k^2 real parts, k^2 imaginary parts, block sizes, right-hand sides.
+* The coefficient sigma(z) of eq. (1) is optional (absent = 1).  Where it is
+  drawn it is piecewise constant over the same layers, sigma ~ U(0.5, 2); the
+  scheme of eq. (2) takes sigma at the nodes (x and y terms) and at the
+  midpoints of the z steps (z term); a step joining two layers takes the
+  harmonic mean of their values (two half-steps of the two materials in
+  series), a step to a wall the value of its node's layer.
 """
 from __future__ import annotations
 
@@ -50,6 +56,10 @@ class Problem:
     sep_x: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     sep_y: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     name: str = ""
+    # sigma(z) of eq. (1): real positive values at the nz nodes and at the
+    # nz + 1 z steps (step k joins node k - 1 and node k); None = 1
+    sigma_node: Optional[np.ndarray] = None
+    sigma_step: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.hx = np.ascontiguousarray(self.hx, dtype=np.complex128)
@@ -59,6 +69,26 @@ class Problem:
         self.k2 = np.ascontiguousarray(self.k2, dtype=np.complex128)
         self.sep_x = np.ascontiguousarray(self.sep_x, dtype=np.int32)
         self.sep_y = np.ascontiguousarray(self.sep_y, dtype=np.int32)
+        if (self.sigma_node is None) != (self.sigma_step is None):
+            raise ValueError("sigma_node and sigma_step are given together")
+        if self.sigma_node is not None:
+            self.sigma_node = np.ascontiguousarray(self.sigma_node, dtype=np.float64)
+            self.sigma_step = np.ascontiguousarray(self.sigma_step, dtype=np.float64)
+            assert self.sigma_node.shape == (self.nz,) and self.sigma_step.shape == (self.nz + 1,)
+
+    @property
+    def has_sigma(self) -> bool:
+        return self.sigma_node is not None
+
+    @property
+    def sig_node(self) -> np.ndarray:
+        """sigma at the z nodes (ones when absent)."""
+        return self.sigma_node if self.sigma_node is not None else np.ones(self.nz)
+
+    @property
+    def sig_step(self) -> np.ndarray:
+        """sigma at the z steps (ones when absent)."""
+        return self.sigma_step if self.sigma_step is not None else np.ones(self.nz + 1)
 
     @property
     def nx(self) -> int:
@@ -130,6 +160,31 @@ def draw_k2(rng: np.random.Generator, nlayers: int) -> np.ndarray:
     re = rng.uniform(0.05, 0.5, size=nlayers)
     im = rng.uniform(0.001, 0.05, size=nlayers)
     return re + 1j * im
+
+
+def draw_sigma(rng: np.random.Generator, nlayers: int) -> np.ndarray:
+    return rng.uniform(0.5, 2.0, size=nlayers)
+
+
+def layered_sigma(layer_of_z: np.ndarray, sig_layers: np.ndarray):
+    """(sigma_node, sigma_step) of a piecewise constant sigma: node k takes its
+    layer's value; a z step between nodes of two layers the harmonic mean of
+    the two, a step to a wall its node's value."""
+    lz = np.asarray(layer_of_z)
+    sl = np.asarray(sig_layers, dtype=np.float64)
+    node = sl[lz]
+    nz = lz.shape[0]
+    step = np.empty(nz + 1)
+    step[0] = node[0]
+    step[nz] = node[nz - 1]
+    a, b = node[:-1], node[1:]
+    step[1:nz] = 2.0 * a * b / (a + b)
+    return node, step
+
+
+def with_sigma(problem: "Problem", sig_layers: np.ndarray) -> "Problem":
+    node, step = layered_sigma(problem.layer_of_z, sig_layers)
+    return replace(problem, sigma_node=node, sigma_step=step)
 
 
 def complex_normal(rng: np.random.Generator, shape) -> np.ndarray:
