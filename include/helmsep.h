@@ -4,12 +4,13 @@
  * Druskin & Zaslavsky, "Fast finite-difference convolution for 3D problems in
  * layered media" (arXiv:1909.01299), Sec. 2.  The library solves
  *
- *     A u = f,   A = Dx (x) I (x) I + I (x) Dy (x) I + I (x) I (x) (Dz - diag k^2(z)),
+ *     A u = f,   A = S (Dx (x) I (x) I + I (x) Dy (x) I) + I (x) I (x) (Dz - diag k^2(z)),
  *
  * the 7-point finite-volume operator of eqs. (2)-(3) divided by its diagonal
  * mass matrices and with the sign chosen so that D_d = M_d^{-1} K_d is positive
- * on a uniform grid (sigma = 1, the constant lambda replaced by a layered
- * k^2(z)).  Per axis d with n interior nodes and steps h[0..n] (complex in a
+ * on a uniform grid, the constant lambda replaced by a layered k^2(z), S =
+ * diag(sigma(z)) at the nodes and Dz the flux form with sigma(z) at the z
+ * steps (sigma = 1 unless given).  Per axis d with n interior nodes and steps h[0..n] (complex in a
  * PML), node i lies between h[i] and h[i+1], hhat_i = (h[i] + h[i+1]) / 2 and
  * (K u)_i = (u_i - u_{i-1}) / h[i] - (u_{i+1} - u_i) / h[i+1]; the walls carry
  * homogeneous Dirichlet data.
@@ -67,7 +68,12 @@ typedef struct hs_batch_s* hs_batch;
 /* Grid description (paper Sec. 2: tensor grid with per-axis steps).
  * hx: 2*(nx+1) doubles, complex steps (re, im) h_0..h_nx; likewise hy.
  * hz: nz+1 real steps.  layer_of_z: nz entries in [0, nlayers).
- * k2: 2*nlayers doubles, complex k^2 per layer.  All host pointers. */
+ * k2: 2*nlayers doubles, complex k^2 per layer.
+ * sigma_node, sigma_step: the coefficient sigma(z) of eqs. (1)-(2), real and
+ * positive, at the nz nodes (it scales the x and y terms of row k) and at
+ * the nz+1 z steps (step k joins node k-1 and node k; the z term is the
+ * difference of the fluxes sigma u_z through the two steps of a node); both
+ * NULL for sigma = 1, both or neither given.  All host pointers. */
 typedef struct {
   int32_t nx, ny, nz;
   const double* hx;
@@ -76,6 +82,8 @@ typedef struct {
   int32_t nlayers;
   const int32_t* layer_of_z;
   const double* k2;
+  const double* sigma_node;
+  const double* sigma_step;
 } hs_grid;
 
 /* Separator planes (0-based interior indices, strictly increasing, at least
@@ -121,6 +129,8 @@ typedef struct {
                                FP64 with the workgroup that holds them        */
   int32_t z_chunks;         /* z-line chunks per mode in use (hs_plan_tune)   */
   int32_t sine_lines;       /* sine-transform lines per workgroup (0 = default) */
+  int32_t z_fixed_rows;     /* 1: z solves in instances with a fixed row count
+                               per chunk (chosen by hs_plan_tune)            */
   int32_t n_split_fp16;     /* HS_C64_REFINE: axes whose dense tables run on fp16
                                matrix cores as two-term splits (n <= 256, or
                                n <= 512 for real sine tables)                */
@@ -199,8 +209,9 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
                            int32_t* nrhs);
 
 /* Autotune the plan's launch shapes for nrhs right-hand sides: every usable
- * pair of (z-line chunks per mode in {8, 16, 32}, sine-transform lines per
- * workgroup in {4, 8, 16}) is timed with hipEvents on `stream` over 3 solves
+ * combination of z-line chunks per mode in {8, 16, 32}, sine-transform lines
+ * per workgroup in {4, 8, 16} and (where nz fills the chunks exactly) z-solve
+ * instances with a fixed row count per chunk or not is timed with hipEvents on `stream` over 3 solves
  * of scratch data and the fastest is kept in the plan.  cache_path (may be
  * NULL) names a JSON-lines file keyed by device architecture and plan shape:
  * a hit skips the timing, a miss appends the result.  Needs a bound workspace;
@@ -209,10 +220,11 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
 
 /* Set the launch shapes directly (as hs_plan_tune would store them), e.g. to
  * reuse one plan's tuning on another plan of the same shapes: z_chunks in
- * {0 (default for nz), 8, 16, 32}, sine_lines in {0 (default), 4, 8, 16}.
+ * {0 (default for nz), 8, 16, 32}, sine_lines in {0 (default), 4, 8, 16},
+ * z_fixed_rows in {0, 1} (1 is used only where nz fills the chunks exactly).
  * HS_ERR_ARG for a value outside these sets or one the plan cannot use (a z
  * chunking that cannot hold nz, sine lines whose LDS does not fit). */
-hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines);
+hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows);
 
 /* Per-stage timing.  While enabled, every stage of a solve is bracketed by
  * hipEvents recorded on the solve's stream (events come from a pool created

@@ -35,7 +35,8 @@ _STATUS = {0: "HS_OK", 1: "HS_ERR_ARG", 2: "HS_ERR_ALLOC", 3: "HS_ERR_DEVICE",
 class _Grid(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("hx", ctypes.c_void_p), ("hy", ctypes.c_void_p), ("hz", ctypes.c_void_p),
-                ("nlayers", ctypes.c_int32), ("layer_of_z", ctypes.c_void_p), ("k2", ctypes.c_void_p)]
+                ("nlayers", ctypes.c_int32), ("layer_of_z", ctypes.c_void_p), ("k2", ctypes.c_void_p),
+                ("sigma_node", ctypes.c_void_p), ("sigma_step", ctypes.c_void_p)]
 
 
 class _Blocks(ctypes.Structure):
@@ -55,7 +56,7 @@ class Info(ctypes.Structure):
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
                 ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32),
-                ("n_split_fp16", ctypes.c_int32), ("tol", ctypes.c_double), ("resid_first", ctypes.c_double),
+                ("z_fixed_rows", ctypes.c_int32), ("n_split_fp16", ctypes.c_int32), ("tol", ctypes.c_double), ("resid_first", ctypes.c_double),
                 ("resid_final", ctypes.c_double), ("resid_evals", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
     def as_dict(self):
@@ -87,7 +88,7 @@ EXPORTS = {
     "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
-    "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hs_profile_only": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -195,8 +196,13 @@ class Plan:
         k2 = np.ascontiguousarray(np.asarray(problem.k2, np.complex128))
         sx = np.ascontiguousarray(np.asarray(getattr(problem, "sep_x", []), np.int32))
         sy = np.ascontiguousarray(np.asarray(getattr(problem, "sep_y", []), np.int32))
+        sn = getattr(problem, "sigma_node", None)
+        ss = getattr(problem, "sigma_step", None)
+        sn = None if sn is None else np.ascontiguousarray(np.asarray(sn, np.float64))
+        ss = None if ss is None else np.ascontiguousarray(np.asarray(ss, np.float64))
         grid = _Grid(self.nx, self.ny, self.nz, hx.ctypes.data, hy.ctypes.data, hz.ctypes.data,
-                     self.nlayers, lz.ctypes.data, k2.ctypes.data)
+                     self.nlayers, lz.ctypes.data, k2.ctypes.data,
+                     None if sn is None else sn.ctypes.data, None if ss is None else ss.ctypes.data)
         blocks = _Blocks(len(sx), sx.ctypes.data if len(sx) else None, len(sy), sy.ctypes.data if len(sy) else None)
         prec = {"c128": HS_C128, "c64": HS_C64_REFINE, "mixed": HS_C64_REFINE}[precision]
         chunk_bits = {0: 0, 8: 1, 16: 2, 32: 3}[int(z_chunks)] << 1
@@ -255,14 +261,16 @@ class Plan:
         return out.reshape(n_ev.value, nr.value)
 
     def tune(self, nrhs: int = 1, cache: Optional[str] = None, stream=None):
-        """Autotune launch shapes (z chunking, sine lines per workgroup) on this plan."""
+        """Autotune launch shapes (z chunking, sine lines per workgroup, fixed
+        z-solve rows) on this plan."""
         _check(lib().hs_plan_tune(self._h, int(nrhs), cache.encode() if cache else None, _stream(stream)))
         inf = self.info()
-        return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"]}
+        return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"], "z_fixed_rows": inf["z_fixed_rows"]}
 
     def set_launch(self, shapes: dict):
         """Apply launch shapes as returned by tune() (z_chunks, sine_lines)."""
-        _check(lib().hs_plan_set_launch(self._h, int(shapes.get("z_chunks", 0)), int(shapes.get("sine_lines", 0))))
+        _check(lib().hs_plan_set_launch(self._h, int(shapes.get("z_chunks", 0)), int(shapes.get("sine_lines", 0)),
+                                        int(shapes.get("z_fixed_rows", 0))))
 
     def profile(self, on: bool = True, only: Optional[str] = None):
         """Record hipEvents around every stage of subsequent solves, or only

@@ -94,6 +94,7 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
     spec_off.push_back(off);
     off = align_up(off + int64_t(nrhs[i]) * p->NX * p->NY * p->NZ, 64);
     max_nz = std::max(max_nz, p->NZ);
+    common_nz = (i == 0 || common_nz == p->NZ) ? p->NZ : -1;
     max_modes = std::max<int64_t>(max_modes, sweep_modes_bound(p->NX, p->NY));
   }
   ws_elems = size_t(off);
@@ -191,7 +192,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
       SweepDesc s{};
       s.na = B.nbx; s.nb = B.nby; s.nz = p->NZ; s.dense_in = 1;
       s.lam_x = T0 + AX.lam; s.lam_y = T0 + AY.lam;
-      s.zlo = T0 + p->zlo; s.zdiag = T0 + p->zdiag; s.zup = T0 + p->zup;
+      s.zlo = T0 + p->zlo; s.zdiag = T0 + p->zdiag; s.zup = T0 + p->zup; s.zsig = T0 + p->zsig;
       s.data = spec; s.out = spec;
       s.fp64_below = p->fp64_below;
       d_sweep.push_back(s);
@@ -286,7 +287,7 @@ void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
     sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks,
-          prec == 1 ? sel_dev : nullptr, &side);
+          prec == 1 ? sel_dev : nullptr, &side, plans[0]->tune_full ? common_nz : 0);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };

@@ -31,6 +31,7 @@ struct Batch {
   size_t ws_elems = 0, ws_bytes = 0;
   void* ws = nullptr;
   int max_nz = 0;
+  int common_nz = 0;   // the plans' nz when they all share one, else 0
   int64_t max_modes = 0;
   // descriptors rebuilt when the caller's pointers change
   std::vector<const void*> last_f;

@@ -112,7 +112,7 @@ struct DstDesc {
 // One batched z sweep over the (a, b) modes of a block.
 //  rhs(a,b,z,r) = [dense_in ? data(r,z,b,a) : 0]
 //               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)
-//  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) I) x = rhs,   out(r,z,b,a) = x
+//  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) diag sigma) x = rhs,   out(r,z,b,a) = x
 // element (r,z,b,a) of data / out sits at base + r*_r + (z*nb + b)*na + a.
 constexpr int kMaxTerms = 4;
 constexpr int kMaxRefine = 16;   // refinement steps of the complex64 path
@@ -122,6 +122,7 @@ struct SweepDesc {
   double fp64_below;              // complex64 path: modes with Re(lam_x + lam_y) <= this solve in FP64
   int64_t lam_x, lam_y;           // table offsets (complex, length na / nb)
   int64_t zlo, zdiag, zup;        // table offsets (complex, length nz)
+  int64_t zsig;                   // table offset of sigma at the z nodes (real parts), scaling the shift
   int64_t data, data_r;           // workspace offsets
   int64_t out, out_r;
   int64_t colx[kMaxTerms]; int32_t colx_stride[kMaxTerms];   // table offsets

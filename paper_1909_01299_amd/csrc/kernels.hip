@@ -393,7 +393,10 @@ __host__ __device__ __forceinline__ bool psweep_mode(const SweepDesc& d, const S
 //  2. one lane per mode solves the reduced system on the chunk end values;
 //  3. every chunk is solved again with its neighbours' end values moved to the
 //     right-hand side, with the stored pivots (no divisions).
-template <typename RS, typename R, int P, int MW, int L>
+// FULL: every chunk has exactly L rows (known at compile time, so the row
+// loops have no bounds to test and the scheduler can overlap the rows'
+// independent work); otherwise Lc <= L rows from nz.
+template <typename RS, typename R, int P, int MW, int L, bool FULL>
 __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* __restrict__ tab,
                                             cplx<RS>* __restrict__ ws, unsigned char* smem_raw, int xcap,
                                             const SweepTile& tile) {
@@ -402,10 +405,11 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   using Q = typename quad_of<R>::type;
   const int na = d.na, nb = d.nb, nz = d.nz;
   const int64_t plane = (int64_t)na * nb;
-  const int Lc = psweep_rows(nz, P);
+  const int Lc = FULL ? L : psweep_rows(nz, P);
   const int nzp = P * Lc;
   Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z, padded to nzp rows
-  C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nzp) * sizeof(Q) + 255) / 256) * 256);   // [P][6][MW]
+  R* zs = reinterpret_cast<R*>(smem_raw + size_t(nzp) * sizeof(Q));   // sigma per z (scales the shift)
+  C* xch = reinterpret_cast<C*>(smem_raw + ((size_t(nzp) * (sizeof(Q) + sizeof(R)) + 255) / 256) * 256);   // [P][6][MW]
   C* gxs = xch + 6 * P * MW;                 // x-type term lines [t][2 rows b][nzp]
   for (int k = threadIdx.x; k < nzp; k += 256) {
     Q q;
@@ -422,6 +426,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
       q.w = R(0);
     }
     zt[k] = q;
+    zs[k] = k < nz ? tab[d.zsig + k].x : R(0);
   }
   // The x-type low-rank terms G_t(b, z) are shared by every mode of a row b;
   // consecutive modes lie on at most two rows when na >= MW, whose lines are
@@ -513,9 +518,10 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     for (int kk = 0; kk < L; ++kk) {
       if (kk < Lc) {
         const Q q = zt[k0 + kk];
+        const R sg = zs[k0 + kk];
         C piv;
-        piv.x = q.x + s.x - q.z * cp.x;
-        piv.y = q.y + s.y - q.z * cp.y;
+        piv.x = fma(sg, s.x, q.x) - q.z * cp.x;
+        piv.y = fma(sg, s.y, q.y) - q.z * cp.y;
         const C ipk = crcp_fast(piv);
         ip[kk] = ipk;
         C t;
@@ -535,9 +541,10 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
     for (int kk = L - 1; kk >= 0; --kk) {
       if (kk < Lc) {
         const Q q = zt[k0 + kk];
+        const R sg = zs[k0 + kk];
         C piv;
-        piv.x = q.x + s.x - q.w * cn.x;
-        piv.y = q.y + s.y - q.w * cn.y;
+        piv.x = fma(sg, s.x, q.x) - q.w * cn.x;
+        piv.y = fma(sg, s.y, q.y) - q.w * cn.y;
         const C ipk = crcp_fast(piv);
         C t;
         t.x = rb[kk].x - q.w * yf.x;
@@ -691,7 +698,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
 // workgroups whose bit is set and solve the others in FP32.  Every workgroup
 // thus runs in exactly one of them, and each kernel gets its own register
 // allocation.
-template <typename R, int P, int MW, int L, bool FP64SEL>
+template <typename R, int P, int MW, int L, bool FP64SEL, bool FULL>
 __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ descs,
                                                 const cplx<R>* __restrict__ tab,
                                                 const double2* __restrict__ tab64,
@@ -711,9 +718,9 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
   if ((int64_t)wg >= tiles) return;
   const SweepTile tile = psweep_tile(d, MW, int(tiles), wg);
   if constexpr (sizeof(R) == 8 || !FP64SEL)
-    psweep_body<R, R, P, MW, L>(d, tab, ws, smem_raw, xcap, tile);
+    psweep_body<R, R, P, MW, L, FULL>(d, tab, ws, smem_raw, xcap, tile);
   else
-    psweep_body<R, double, P, MW, L>(d, tab64, ws, smem_raw, xcap, tile);
+    psweep_body<R, double, P, MW, L, FULL>(d, tab64, ws, smem_raw, xcap, tile);
 }
 
 
@@ -949,8 +956,9 @@ __global__ __launch_bounds__(256) void k_sigma_resid(SigmaGeom g, const CI* __re
       const int br = jb * g.nbx_blocks + si + 1;
       const C vl = ws[g.face + (((int64_t)bl * g.rmax + r) * 4 + 1) * g.face_f + (int64_t)z * g.NF + yl];
       const C vr = ws[g.face + (((int64_t)br * g.rmax + r) * 4 + 0) * g.face_f + (int64_t)z * g.NF + yl];
-      v = cfma(coef[g.cx_lo + si], vl, v);
-      v = cfma(coef[g.cx_hi + si], vr, v);
+      const R sg = coef[g.zsig + z].x;
+      v = cfma(cscale(coef[g.cx_lo + si], sg), vl, v);
+      v = cfma(cscale(coef[g.cx_hi + si], sg), vr, v);
     }
     ws[g.rx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + y] = v;
   } else if (e < nline_x + nline_y) {
@@ -968,8 +976,9 @@ __global__ __launch_bounds__(256) void k_sigma_resid(SigmaGeom g, const CI* __re
       const int bt = (ti + 1) * g.nbx_blocks + ib;  // block above, its bottom face
       const C vb = ws[g.face + (((int64_t)bb * g.rmax + r) * 4 + 3) * g.face_f + (int64_t)z * g.NF + xl];
       const C vt = ws[g.face + (((int64_t)bt * g.rmax + r) * 4 + 2) * g.face_f + (int64_t)z * g.NF + xl];
-      v = cfma(coef[g.cy_lo + ti], vb, v);
-      v = cfma(coef[g.cy_hi + ti], vt, v);
+      const R sg = coef[g.zsig + z].x;
+      v = cfma(cscale(coef[g.cy_lo + ti], sg), vb, v);
+      v = cfma(cscale(coef[g.cy_hi + ti], sg), vt, v);
     }
     ws[g.ry + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + x] = v;
   }
@@ -991,14 +1000,17 @@ __global__ __launch_bounds__(256) void k_lift(SigmaGeom g, const LiftBlock* __re
     const int z = int((e % per_face) / g.NF);
     const int i = int(e % g.NF);
     C v = mk<R>(0, 0);
+    const R sg = coef[g.zsig + z].x;   // sigma of the plane scales the x / y couplings
     if (face < 2) {
       const int si = face == 0 ? B.sep_lo_x : B.sep_hi_x;
       if (si >= 0 && i < B.nby)
-        v = cmul(coef[B.cfx[face]], ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + B.y0 + i]);
+        v = cmul(cscale(coef[B.cfx[face]], sg),
+                 ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + B.y0 + i]);
     } else {
       const int ti = face == 2 ? B.sep_lo_y : B.sep_hi_y;
       if (ti >= 0 && i < B.nbx)
-        v = cmul(coef[B.cfy[face - 2]], ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + B.x0 + i]);
+        v = cmul(cscale(coef[B.cfy[face - 2]], sg),
+                 ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + B.x0 + i]);
     }
     ws[g.gface + (((int64_t)blockIdx.y * g.rmax + r) * 4 + face) * g.face_f + (int64_t)z * g.NF + i] = v;
   }
@@ -1078,17 +1090,20 @@ __global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const
     const bool hx0 = x > 0, hx1 = x + 1 < g.nx, hy0 = y > 0, hy1 = y + 1 < g.ny;
     double2 um = z0 > 0 ? uc0[(int64_t)(z0 - 1) * sz] : zero;
     double2 uc = uc0[(int64_t)z0 * sz];
+    const double2 cxy = cadd(cxd, cyd);
 #pragma unroll 4
     for (int z = z0; z < z1; ++z) {
       const double2* pz = uc0 + (int64_t)z * sz;
       const double2 up = z + 1 < g.nz ? pz[sz] : zero;
       const double2 vxl = hx0 ? pz[-1] : zero, vxu = hx1 ? pz[1] : zero;
       const double2 vyl = hy0 ? pz[-sy] : zero, vyu = hy1 ? pz[sy] : zero;
-      double2 au = cmul(cadd(cxd, cadd(cyd, g.zd[z])), uc);
-      au = cfma(cxl, vxl, au);
-      au = cfma(cxu, vxu, au);
-      au = cfma(cyl, vyl, au);
-      au = cfma(cyu, vyu, au);
+      // sigma of the plane scales its x and y terms (exact when it is 1)
+      const double sg = g.sg[z].x;
+      double2 au = cmul(cadd(cscale(cxy, sg), g.zd[z]), uc);
+      au = cfma(cscale(cxl, sg), vxl, au);
+      au = cfma(cscale(cxu, sg), vxu, au);
+      au = cfma(cscale(cyl, sg), vyl, au);
+      au = cfma(cscale(cyu, sg), vyu, au);
       au = cfma(g.zl[z], um, au);
       au = cfma(g.zu[z], up, au);
       const int64_t e = col + (int64_t)z * sz;
@@ -1326,7 +1341,14 @@ size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms) {
   // arith_bytes: 8 for FP64 arithmetic, 4 for FP32
   const size_t rows = size_t(chunks) * psweep_rows(nz, chunks);
   const size_t cs = 2 * size_t(arith_bytes);   // one complex value
-  return (rows * 2 * cs + 255) / 256 * 256 + 6 * 256 * cs + size_t(sweep_stage_cap(nz, chunks, max_xterms)) * cs;
+  return (rows * (2 * cs + size_t(arith_bytes)) + 255) / 256 * 256 + 6 * 256 * cs +
+         size_t(sweep_stage_cap(nz, chunks, max_xterms)) * cs;
+}
+
+bool sweep_rows_fixed(int chunks, int nz) {
+  if (!sweep_chunks_ok(chunks, nz)) return false;
+  const int rows = psweep_rows(nz, chunks);
+  return rows == psweep_regrows(rows);
 }
 
 int sweep_default_chunks(int nz) { return nz > 16 * PS_LMAX ? 32 : 16; }
@@ -1390,7 +1412,7 @@ void sweep_select(const SweepDesc* d, int ndesc, int64_t max_modes, int chunks,
 
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
            const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, const SweepSel* sel,
-           const SideStream* side) {
+           const SideStream* side, int full_nz) {
   if (ndesc == 0 || nrhs == 0 || max_modes == 0) return;
   chunks = sweep_effective_chunks(chunks, max_nz);
   size_t lds = sweep_lds_bytes(prec == 0 ? 8 : 4, max_nz, chunks, max_xterms);
@@ -1400,15 +1422,25 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
   SweepSel sc{};
   if (prec != 0 && sel) sc = sel[chunks == 8 ? 0 : chunks == 16 ? 1 : 2];
   if (sc.n == 0) sc.bits = nullptr;   // nothing selected: no bit to test
-  const bool short_rows = psweep_regrows(psweep_rows(max_nz, chunks)) == 8;
+  const int rows = psweep_rows(max_nz, chunks);
+  const bool short_rows = psweep_regrows(rows) == 8;
+  // full chunks: every descriptor's z line fills its chunks' register rows
+  const bool full = full_nz == max_nz && rows == psweep_regrows(rows);
+#define HS_PSWEEP_L(RR, CC, PP, MM, LL, SEL, STREAM, LDS, GRID)                                          \
+  do {                                                                                                     \
+    if (full)                                                                                              \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, LL, SEL, true>), GRID, dim3(256), LDS, STREAM, d,           \
+                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap, sc);                        \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_psweep<RR, PP, MM, LL, SEL, false>), GRID, dim3(256), LDS, STREAM, d,          \
+                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap, sc);                        \
+  } while (0)
 #define HS_PSWEEP(RR, CC, PP, MM, SEL, STREAM, LDS, GRID)                                                 \
   do {                                                                                                     \
     if (short_rows)                                                                                        \
-      hipLaunchKernelGGL((k_psweep<RR, PP, MM, 8, SEL>), GRID, dim3(256), LDS, STREAM, d, (const CC*)tab,  \
-                         (const double2*)tab64, (CC*)ws, xcap, sc);                                        \
+      HS_PSWEEP_L(RR, CC, PP, MM, 8, SEL, STREAM, LDS, GRID);                                              \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_psweep<RR, PP, MM, PS_LMAX, SEL>), GRID, dim3(256), LDS, STREAM, d,            \
-                         (const CC*)tab, (const double2*)tab64, (CC*)ws, xcap, sc);                        \
+      HS_PSWEEP_L(RR, CC, PP, MM, PS_LMAX, SEL, STREAM, LDS, GRID);                                        \
   } while (0)
   if (prec == 0) {
     if (chunks == 32) HS_PSWEEP(double, double2, 32, 8, false, st, lds, grid);
@@ -1438,6 +1470,7 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
     }
   }
 #undef HS_PSWEEP
+#undef HS_PSWEEP_L
 }
 
 void contract_split(ContractDesc& d) {

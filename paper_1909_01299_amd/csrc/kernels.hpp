@@ -31,6 +31,7 @@ struct SigmaGeom {
   const int32_t* yloc;
   const void* coef;
   int64_t cx_lo, cx_hi, cy_lo, cy_hi;   // coefficient offsets per separator
+  int64_t zsig;                         // offset of sigma at the z nodes (scales the x / y couplings)
 };
 
 struct LiftBlock {
@@ -45,6 +46,7 @@ struct StencilGeom {
   const double2 *yd, *yl, *yu;
   const double2 *zd, *zl, *zu;
   const double2 *mx, *my, *mz;
+  const double2* sg;   // sigma at the z nodes (real parts): scales the x and y terms of a plane
 };
 
 // Dense transforms (xform_mfma.hip): matrix cores for long lines in numbers
@@ -149,9 +151,11 @@ void sweep_select(const SweepDesc* d, int ndesc, int64_t max_modes, int chunks,
                   const std::function<double(int64_t)>& lam_re, SweepSelHost& out);
 // sel: complex64 only, three selections (chunk counts 8, 16, 32) or NULL (no
 // mode in FP64)
+// full_nz: the common nz of every descriptor (0 when they differ); when it
+// fills the chunks' register rows exactly, the kernel takes fixed-length rows
 void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_nz, int max_xterms, const void* tab,
            const void* tab64, void* ws, int nrhs, hipStream_t st, int chunks, const SweepSel* sel,
-           const SideStream* side = nullptr);
+           const SideStream* side = nullptr, int full_nz = 0);
 // creates / destroys a SideStream on the current device (false on failure)
 bool side_stream_create(SideStream& s);
 void side_stream_destroy(SideStream& s);
@@ -159,6 +163,8 @@ int sweep_default_chunks(int nz);
 // modes a launch provisions for one descriptor of na x nb modes
 inline int64_t sweep_modes_bound(int na, int nb) { return (int64_t)nb * ((na + 31) / 32 * 32); }
 bool sweep_chunks_ok(int chunks, int nz);
+// true when nz fills `chunks` chunks of a fixed register row count exactly
+bool sweep_rows_fixed(int chunks, int nz);
 
 // Fused two-axis contractions of spectral arrays (each array read once).
 // contract_split chooses the row slabs of a descriptor (nslab, rows) from its

@@ -88,6 +88,20 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
     if (std::abs(hx[i] + hx[i + 1]) == 0) { err = "hx: zero control volume"; return HS_ERR_ARG; }
   for (int i = 0; i < NY; ++i)
     if (std::abs(hy[i] + hy[i + 1]) == 0) { err = "hy: zero control volume"; return HS_ERR_ARG; }
+  if ((g->sigma_node == nullptr) != (g->sigma_step == nullptr)) {
+    err = "sigma_node and sigma_step are given together or not at all";
+    return HS_ERR_ARG;
+  }
+  sig_node.assign(NZ, 1.0);
+  sig_step.assign(NZ + 1, 1.0);
+  if (g->sigma_node) {
+    sig_node.assign(g->sigma_node, g->sigma_node + NZ);
+    sig_step.assign(g->sigma_step, g->sigma_step + NZ + 1);
+    for (double v : sig_node)
+      if (!(v > 0) || !std::isfinite(v)) { err = "sigma_node must be positive and finite"; return HS_ERR_ARG; }
+    for (double v : sig_step)
+      if (!(v > 0) || !std::isfinite(v)) { err = "sigma_step must be positive and finite"; return HS_ERR_ARG; }
+  }
   layer.assign(g->layer_of_z, g->layer_of_z + NZ);
   for (int v : layer)
     if (v < 0 || v >= nlayers) { err = "layer_of_z entry out of range"; return HS_ERR_ARG; }
@@ -272,6 +286,11 @@ hs_status Plan::build_tables(std::string& err) {
   zlo = push(std::vector<cd>(NZ));
   zdiag = push(std::vector<cd>(NZ));
   zup = push(std::vector<cd>(NZ));
+  {
+    std::vector<cd> sv(NZ);
+    for (int k = 0; k < NZ; ++k) sv[k] = cd(sig_node[k], 0.0);
+    zsig = push(sv);
+  }
   build_z_tables();
   // interface coefficients: r(s) = f(s) + v(s-1)/(hhat_s h_s) + v(s+1)/(hhat_s h_{s+1})
   std::vector<cd> c;
@@ -302,12 +321,15 @@ hs_status Plan::build_tables(std::string& err) {
   return HS_OK;
 }
 
+// z tables of Dz^sigma - diag k^2: the flux form of eq. (2) with sigma at the
+// two steps of node k (step k joins node k - 1 and node k)
 void Plan::build_z_tables() {
   for (int k = 0; k < NZ; ++k) {
     const double hh = 0.5 * (hz[k] + hz[k + 1]);
-    htab[zlo + k] = k > 0 ? cd(-1.0 / (hh * hz[k])) : cd(0.0);
-    htab[zup + k] = k + 1 < NZ ? cd(-1.0 / (hh * hz[k + 1])) : cd(0.0);
-    htab[zdiag + k] = (1.0 / hz[k] + 1.0 / hz[k + 1]) / hh - k2[layer[k]];
+    const double wl = sig_step[k] / hz[k], wu = sig_step[k + 1] / hz[k + 1];
+    htab[zlo + k] = k > 0 ? cd(-wl / hh) : cd(0.0);
+    htab[zup + k] = k + 1 < NZ ? cd(-wu / hh) : cd(0.0);
+    htab[zdiag + k] = (wl + wu) / hh - k2[layer[k]];
   }
 }
 
@@ -335,14 +357,16 @@ void Plan::build_stencil_host(std::vector<double2>& out) {
   for (int i = 0; i < NX; ++i) put(0.5 * (hx[i] + hx[i + 1]));
   for (int i = 0; i < NY; ++i) put(0.5 * (hy[i] + hy[i + 1]));
   for (int k = 0; k < NZ; ++k) put(cd(0.5 * (hz[k] + hz[k + 1])));
+  for (int k = 0; k < NZ; ++k) put(cd(sig_node[k]));
 }
 
 // Near resonance a mode's z pivots lose digits to cancellation; in the
 // complex64 path every workgroup holding a mode with
 // Re(lam_x + lam_y) <= 1.25 max_z Re k^2(z) solves its z systems in FP64.
 void Plan::set_fp64_threshold() {
+  // resonance where sigma_k (lam_x + lam_y) meets k^2_k for some z
   double kmax = -1e300;
-  for (int k = 0; k < NZ; ++k) kmax = std::max(kmax, k2[layer[k]].real());
+  for (int k = 0; k < NZ; ++k) kmax = std::max(kmax, k2[layer[k]].real() / sig_node[k]);
   fp64_below = prec == 1 ? 1.25 * kmax : -1e300;
   auto patch = [&](std::vector<SweepDesc>& v) {
     for (auto& d : v) d.fp64_below = fp64_below;
@@ -361,7 +385,7 @@ hs_status Plan::scan_pivots(std::string& err) {
         const cd s = ax.e.lam[a] + ay.e.lam[b];
         cd c = 0.0;
         for (int k = 0; k < NZ; ++k) {
-          cd piv = htab[zdiag + k] + s - htab[zlo + k] * c;
+          cd piv = htab[zdiag + k] + sig_node[k] * s - htab[zlo + k] * c;
           mn = std::min(mn, std::abs(piv));
           c = htab[zup + k] / piv;
         }
@@ -535,7 +559,7 @@ void Plan::build_descriptors() {
     SweepDesc s{};
     s.na = B.nbx; s.nb = B.nby; s.nz = NZ;
     s.lam_x = AX.lam; s.lam_y = AY.lam;
-    s.zlo = zlo; s.zdiag = zdiag; s.zup = zup;
+    s.zlo = zlo; s.zdiag = zdiag; s.zup = zup; s.zsig = zsig;
     s.data = B.spec; s.data_r = spec_r;
     s.out = B.spec; s.out_r = spec_r;
     s.dense_in = 1;
@@ -630,7 +654,7 @@ void Plan::build_descriptors() {
     SweepDesc g{};
     g.na = NX; g.nb = NY; g.nz = NZ;
     g.lam_x = GX.lam; g.lam_y = GY.lam;
-    g.zlo = zlo; g.zdiag = zdiag; g.zup = zup;
+    g.zlo = zlo; g.zdiag = zdiag; g.zup = zup; g.zsig = zsig;
     g.dense_in = 0;
     g.out = w_gspec; g.out_r = (int64_t)NX * NY * NZ;
     g.nxt = nsx; g.nyt = nsy;
@@ -663,6 +687,7 @@ void Plan::build_descriptors() {
     sg.f_r = f_r; sg.face = w_vface; sg.face_f = face_f; sg.gface = w_gface;
     sg.rx = w_rx; sg.ry = w_ry; sg.wx = w_wx; sg.wy = w_wy;
     sg.cx_lo = cx_lo; sg.cx_hi = cx_hi; sg.cy_lo = cy_lo; sg.cy_hi = cy_hi;
+    sg.zsig = zsig;
   }
   cl_face = contract_launch(d_face.data(), int(d_face.size()), prec);
   cl_sig = contract_launch(d_sig.data(), int(d_sig.size()), prec);
@@ -727,6 +752,7 @@ hs_status Plan::upload(std::string& err) {
   sten.yd = p; p += NY; sten.yl = p; p += NY; sten.yu = p; p += NY;
   sten.zd = p; p += NZ; sten.zl = p; p += NZ; sten.zu = p; p += NZ;
   sten.mx = p; p += NX; sten.my = p; p += NY; sten.mz = p; p += NZ;
+  sten.sg = p; p += NZ;
   return upload_descs(err);
 }
 
@@ -1003,7 +1029,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
   if (!decomposed) {
     stage_begin("zsweep_block", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweep, nb, modes(d_sweep), NZ, xterms(d_sweep), T, dtab64, W, nrhs, st, tune_chunks, sel(0),
-          &side);
+          &side, tune_full ? NZ : 0);
     stage_end();
   } else {
     const double nsx = double(sepx.size()), nsy = double(sepy.size());
@@ -1012,7 +1038,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     // steps 2-3: block sweeps, v on the lines next to the separators
     stage_begin("zsweep_blocks_v", R * nblk * 2 * esz, R * nblk * thomas, st);
     sweep(prec, p_sweepB, nb, modes(d_sweepB), NZ, xterms(d_sweepB), T, dtab64, W, nrhs, st, tune_chunks,
-          sel(1), &side);
+          sel(1), &side, tune_full ? NZ : 0);
     stage_end();
     stage_begin("face_contract", R * (nblk + nface) * esz, R * nblk * 4 * 8, st);
     contract(prec, p_face, cl_face, T, W, nrhs, st);
@@ -1035,7 +1061,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
-          sel(3), &side);
+          sel(3), &side, tune_full ? NZ : 0);
     stage_end();
     stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
     contract(prec, p_sig, cl_sig, T, W, nrhs, st);
@@ -1052,7 +1078,7 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_end();
     stage_begin("zsweep_blocks_u", R * (2 * nblk + nface) * esz, R * nblk * (thomas + 32), st);
     sweep(prec, p_sweepC, nb, modes(d_sweepC), NZ, xterms(d_sweepC), T, dtab64, W, nrhs, st, tune_chunks,
-          sel(2), &side);
+          sel(2), &side, tune_full ? NZ : 0);
     stage_end();
   }
   // step 7: inverse transforms into u
@@ -1212,13 +1238,16 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
     while (std::getline(in, line)) {
       const std::string tag = "\"key\": \"" + k + "\"";
       if (line.find(tag) == std::string::npos) continue;
-      int c = 0, l = 0;
-      const size_t pc = line.find("\"chunks\": "), pl = line.find("\"lines\": ");
+      int c = 0, l = 0, fr = 0;
+      const size_t pc = line.find("\"chunks\": "), pl = line.find("\"lines\": "),
+                   pf = line.find("\"fixed_rows\": ");
       if (pc != std::string::npos && pl != std::string::npos) {
         c = std::atoi(line.c_str() + pc + 10);
         l = std::atoi(line.c_str() + pl + 9);
+        if (pf != std::string::npos) fr = std::atoi(line.c_str() + pf + 14);
         tune_chunks = c;
         tune_lt = l;
+        tune_full = fr;
         return HS_OK;
       }
     }
@@ -1248,33 +1277,36 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   float best = 1e30f;
-  int bc = 0, bl = 0;
+  int bc = 0, bl = 0, bf = 0;
   const bool was_on = prof_on;
   prof_on = false;
   for (int c : chunks)
-    for (int l : lts) {
-      tune_chunks = c;
-      tune_lt = l;
-      std::string e2;
-      if (solve(f, u, nrhs, st, e2) != HS_OK) continue;
-      (void)hipEventRecord(e0, st);
-      for (int rep = 0; rep < 3; ++rep) (void)solve(f, u, nrhs, st, e2);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) { best = ms; bc = c; bl = l; }
-    }
+    for (int l : lts)
+      for (int fr = 0; fr < (sweep_rows_fixed(c, NZ) ? 2 : 1); ++fr) {
+        tune_chunks = c;
+        tune_lt = l;
+        tune_full = fr;
+        std::string e2;
+        if (solve(f, u, nrhs, st, e2) != HS_OK) continue;
+        (void)hipEventRecord(e0, st);
+        for (int rep = 0; rep < 3; ++rep) (void)solve(f, u, nrhs, st, e2);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bc = c; bl = l; bf = fr; }
+      }
   prof_on = was_on;
   tune_chunks = bc;
   tune_lt = bl;
+  tune_full = bf;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(f);
   (void)hipFree(u);
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl
+    out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl << ", \"fixed_rows\": " << bf
         << ", \"ms_per_solve\": " << best / 3 << "}\n";
   }
   return HS_OK;

@@ -78,6 +78,7 @@ struct Plan {
   std::vector<double> hz;
   std::vector<int32_t> layer;
   std::vector<cd> k2;
+  std::vector<double> sig_node, sig_step;   // sigma(z) at the z nodes and steps (ones when not given)
   std::vector<int32_t> sepx, sepy;
   int prec = 0;          // 0 = complex128, 1 = complex64 + FP64 refinement
   int refine_steps = 0;
@@ -95,7 +96,7 @@ struct Plan {
   bool decomposed = false;
   std::vector<cd> htab;          // host FP64 table image
   std::vector<_Float16> h16;     // complex64 path: split-fp16 fragment image (8 halves per unit)
-  int64_t zlo = 0, zdiag = 0, zup = 0;
+  int64_t zlo = 0, zdiag = 0, zup = 0, zsig = 0;
   int64_t cx_lo = 0, cx_hi = 0, cy_lo = 0, cy_hi = 0;
   std::vector<int64_t> lift_cf;  // per block 4 coefficient offsets
   void* dtab64 = nullptr;
@@ -109,6 +110,7 @@ struct Plan {
   double min_pivot = 0;
   int tune_chunks = 0;           // z-line chunks per mode (0 = default for NZ)
   int tune_lt = 0;               // sine-transform lines per workgroup (0 = default)
+  int tune_full = 0;             // 1: z solves with chunks of a fixed row count where nz fills them
   double fp64_below = -1e300;    // complex64 path: z solves of modes with Re(lam_x + lam_y) <= this in FP64
   SideStream side;               // complex64 path: stream of the FP64 z solves
   int64_t n_fp64_modes = 0;

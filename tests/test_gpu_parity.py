@@ -180,6 +180,27 @@ def test_every_z_chunking_vs_oracle(hs, chunks, prec):
     assert per_rhs_err(u, separable.solve(p, f)) < (TOL128 if prec == "c128" else TOL64R)
 
 
+@pytest.mark.parametrize("chunks,nz", [(16, 256), (32, 256), (16, 128), (8, 64)])
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_fixed_row_z_solves_vs_oracle(hs, chunks, nz, prec):
+    """nz filling the chunks exactly: the fixed-row instances (straight-line
+    row loops) against the oracle, on a decomposed grid so the dense-input,
+    low-rank and global solves all take them, and to rounding against the
+    instances with a run-time row count."""
+    rng = np.random.default_rng(nz + chunks)
+    p = W.random_problem(36, 30, nz, 4, rng, sep_x=[8, 20], sep_y=[14], pml_x=4, pml_y=3)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    plan = hs.Plan(p, prec, max_rhs=2, z_chunks=chunks, refine_steps=1 if prec == "mixed" else 0)
+    fd = dev(f)
+    plan.set_launch({"z_chunks": chunks, "sine_lines": 0, "z_fixed_rows": 1})
+    assert plan.info()["z_fixed_rows"] == 1
+    u1 = plan.solve(fd).cpu().numpy()
+    plan.set_launch({"z_chunks": chunks, "sine_lines": 0, "z_fixed_rows": 0})
+    u0 = plan.solve(fd).cpu().numpy()
+    assert per_rhs_err(u1, separable.solve(p, f)) < (TOL128 if prec == "c128" else TOL64R)
+    assert per_rhs_err(u1, u0) < 1e-13
+
+
 # ------------------------------------------------------------------ decomposition
 
 DECOMP = [

@@ -132,6 +132,17 @@ def test_argument_errors_before_device(hs):
     assert _create(hs, p, opts=hs._Options(1, 17, 1, 0))[0] == hs.HS_ERR_ARG  # too many refinement steps
     assert _create(hs, p, opts=hs._Options(1, 1, 1, 0, -1e-8))[0] == hs.HS_ERR_ARG   # negative tolerance
     assert _create(hs, p, opts=hs._Options(1, 1, 1, 0, float("nan")))[0] == hs.HS_ERR_ARG
+    # sigma(z): both arrays or neither, positive values
+    sn = np.ones(p.nz)
+    ss = np.ones(p.nz + 1)
+    g, b, keep = _grid_args(hs, p)
+    g.sigma_node = sn.ctypes.data
+    h = ctypes.c_void_p()
+    assert hs.lib().hs_plan_create(ctypes.byref(g), ctypes.byref(b), None, ctypes.byref(h)) == hs.HS_ERR_ARG
+    g.sigma_step = ss.ctypes.data
+    sn[2] = -1.0
+    assert hs.lib().hs_plan_create(ctypes.byref(g), ctypes.byref(b), None, ctypes.byref(h)) == hs.HS_ERR_ARG
+    assert b"sigma" in hs.lib().hs_last_error()
     # an x-y plane beyond 2^28 nodes (step arrays of the right lengths, nz = 1)
     big = W.Problem(np.ones(16386), np.ones(16386), np.ones(2), np.zeros(1, np.int32), p.k2[:1])
     st, msg = _create(hs, big)
