@@ -187,6 +187,17 @@ hs_status hs_solve_adjoint(hs_plan plan, const void* g, void* a, int32_t nrhs, v
 hs_status hs_grad_k2(hs_plan plan, const void* u, const void* a, void* grad,
                      int32_t nrhs, void* stream);
 
+/* hs_grad_k2 for callers that cannot allocate device memory at the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same result, bit for bit, with no bound workspace; the
+ * partial sums live in a static device array of the library (65536 complex128
+ * values, 1 MiB per device, held until the process ends), so nrhs * nz must
+ * not exceed 65536 (HS_ERR_ARG otherwise).  Every call on one device shares
+ * that array: calls that overlap on one device (different streams, or other
+ * threads) race and must be serialized by the caller. */
+hs_status hs_grad_k2_noalloc(hs_plan plan, const void* u, const void* a, void* grad, int32_t nrhs,
+                             void* stream);
+
 /* r = f - A u in FP64 by the 7-point stencil on the whole grid (eq. (2)). */
 hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r,
                       int32_t nrhs, void* stream);

@@ -77,6 +77,7 @@ EXPORTS = {
     "hs_solve": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_solve_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_grad_k2": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
+    "hs_grad_k2_noalloc": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_residual": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_apply": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_int32, ctypes.c_void_p]),
     "hs_get_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -324,6 +325,22 @@ class Plan:
         n = same_nrhs(u, a, ("u", "a"))
         grad = torch.empty((n, self.nlayers), dtype=torch.complex128, device=u.device)
         _check(lib().hs_grad_k2(self._h, _ptr(u), _ptr(a), _ptr(grad), n, _stream(stream)))
+        return grad
+
+    def grad_k2_noalloc(self, u, a, grad=None, stream=None):
+        """grad_k2 through the allocation-free entry point (static device
+        scratch; no workspace).  `grad` may be a preallocated (nrhs, nlayers)
+        complex128 CUDA tensor."""
+        import torch
+        _check_array(u, self.shape, "u")
+        _check_array(a, self.shape, "a")
+        n = same_nrhs(u, a, ("u", "a"))
+        if grad is None:
+            grad = torch.empty((n, self.nlayers), dtype=torch.complex128, device=u.device)
+        elif (grad.dtype != torch.complex128 or not grad.is_cuda or not grad.is_contiguous()
+              or grad.numel() < n * self.nlayers):
+            raise ValueError("grad must be a contiguous complex128 CUDA tensor of nrhs * nlayers values")
+        _check(lib().hs_grad_k2_noalloc(self._h, _ptr(u), _ptr(a), _ptr(grad), n, _stream(stream)))
         return grad
 
     def residual(self, f, u, stream=None):

@@ -105,6 +105,12 @@ hs_status hs_grad_k2(hs_plan plan, const void* u, const void* a, void* grad, int
   return ret(plan->p.grad_k2(u, a, grad, nrhs, (hipStream_t)stream, err), err);
 }
 
+hs_status hs_grad_k2_noalloc(hs_plan plan, const void* u, const void* a, void* grad, int32_t nrhs, void* stream) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  std::string err;
+  return ret(plan->p.grad_k2_noalloc(u, a, grad, nrhs, (hipStream_t)stream, err), err);
+}
+
 hs_status hs_residual(hs_plan plan, const void* f, const void* u, void* r, int32_t nrhs, void* stream) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
   std::string err;

@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <functional>
+#include <mutex>
+#include <string>
 
 namespace hs {
 
@@ -1620,6 +1622,41 @@ void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int
   if (n == 0 || nrhs == 0) return;
   hipLaunchKernelGGL(k_conj_mass, dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const double2*)in,
                      (double2*)out, inverse);
+}
+
+// Static scratch of the allocation-free gradient entry point: the slice
+// partials of one call (kGradScratchElems complex128 values, 1 MiB per device,
+// held until the process ends).  In host code `scratch` only names the
+// symbol: kernels take the device address that grad_scratch_init looked up.
+__device__ __align__(256) double2 scratch[kGradScratchElems];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+bool grad_scratch_init(int device, std::string& err) {
+  if (device < 0 || device >= kMaxDevices) {
+    err = "device index beyond the static scratch table";
+    return false;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return true;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+    return false;
+  }
+  g_scratch_ptr[device] = ptr;
+  return true;
+}
+
+void* grad_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 int grad_slices(int64_t plane, int nz, int nrhs) {

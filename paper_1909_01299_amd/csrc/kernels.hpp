@@ -6,6 +6,7 @@
 
 #include <complex>
 #include <functional>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -195,6 +196,14 @@ void conj_mass(const StencilGeom& g, const void* in, void* out, int inverse, int
 // of every z plane into `part` (grad_partials(plane, nz, nrhs) complex128
 // values, all overwritten), then per-layer sums in a fixed order.
 int grad_slices(int64_t plane, int nz, int nrhs);
+// The allocation-free gradient keeps its partials in a static device array of
+// kGradScratchElems complex128 values; grad_scratch_init (current device =
+// `device`, once per device, at plan creation) looks up its device address,
+// grad_scratch_ptr returns it (NULL before init).
+constexpr int64_t kGradScratchElems = 65536;
+constexpr int kMaxDevices = 64;
+bool grad_scratch_init(int device, std::string& err);
+void* grad_scratch_ptr(int device);
 int64_t grad_partials(int64_t plane, int nz, int nrhs);
 void grad_layers(int64_t plane, int nz, int nlayers, const int* layer_of_z, const void* a, const void* u,
                  void* part, void* grad, int nrhs, hipStream_t st);

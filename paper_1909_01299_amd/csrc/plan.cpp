@@ -161,6 +161,7 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
   build_descriptors();
   set_fp64_threshold();
   st = upload(err);
+  if (st == HS_OK && !grad_scratch_init(device, err)) st = HS_ERR_DEVICE;
   if (st == HS_OK && prec == 1 && !side_stream_create(side)) {
     (void)hipGetLastError();
     err = "stream creation failed";
@@ -1195,6 +1196,24 @@ hs_status Plan::grad_k2(const void* u, const void* a, void* grad, int nrhs, hipS
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
   void* sums = (unsigned char*)ws + off_gpart;
   grad_layers((int64_t)NX * NY, NZ, nlayers, dint + i_layer, a, u, sums, grad, nrhs, st);
+  if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
+  return HS_OK;
+}
+
+hs_status Plan::grad_k2_noalloc(const void* u, const void* a, void* grad, int nrhs, hipStream_t st,
+                                std::string& err) {
+  if (nrhs < 1) { err = "nrhs must be >= 1"; return HS_ERR_ARG; }
+  if (!u || !a || !grad) { err = "u, a and grad must be non-NULL"; return HS_ERR_ARG; }
+  const int64_t need = grad_partials((int64_t)NX * NY, NZ, nrhs);
+  if (need > kGradScratchElems) {
+    err = "nrhs * nz = " + std::to_string((int64_t)nrhs * NZ) + " exceeds the static scratch (" +
+          std::to_string(kGradScratchElems) + " partial sums)";
+    return HS_ERR_ARG;
+  }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  void* part = grad_scratch_ptr(device);
+  if (!part) { err = "static scratch not set up on this device"; return HS_ERR_STATE; }
+  grad_layers((int64_t)NX * NY, NZ, nlayers, dint + i_layer, a, u, part, grad, nrhs, st);
   if (hipGetLastError() != hipSuccess) { err = "kernel launch failed"; return HS_ERR_DEVICE; }
   return HS_OK;
 }

@@ -181,6 +181,8 @@ struct Plan {
   hs_status solve(const void* f, void* u, int nrhs, hipStream_t st, std::string& err);
   hs_status solve_adjoint(const void* g, void* a, int nrhs, hipStream_t st, std::string& err);
   hs_status grad_k2(const void* u, const void* a, void* grad, int nrhs, hipStream_t st, std::string& err);
+  // the same with the partial sums in the library's static device scratch
+  hs_status grad_k2_noalloc(const void* u, const void* a, void* grad, int nrhs, hipStream_t st, std::string& err);
   hs_status residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
                      std::string& err);
   hs_status tune(int nrhs, const char* cache_path, hipStream_t st, std::string& err);
