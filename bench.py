@@ -109,6 +109,8 @@ def counters_run(args):
         solves = 2
     u = torch.empty_like(f)
     plan = hs.Plan(p, "c128", max_rhs=f.shape[0])
+    if TUNE_CACHE:
+        plan.tune(f.shape[0], cache=TUNE_CACHE)
     for _ in range(solves):
         plan.solve(f, out=u)
     torch.cuda.synchronize()
@@ -421,6 +423,9 @@ def bench_c4(steps, with_oracle):
     return out
 
 
+TUNE_CACHE = None   # JSON-lines file of tuned launch shapes (--tune-cache)
+
+
 def merge_stage_tables(tables):
     """Sum the per-stage records of several plans (same stage names)."""
     out = {}
@@ -498,9 +503,10 @@ def bench_c5(steps, warmup, refine_steps=1, with_oracle=True, precs=("c128", "mi
             ws = pl.workspace
             plans.append(pl)
         t_plan = time.perf_counter() - t0
-        # launch shapes tuned once on the first frequency (same shapes for all)
+        # launch shapes tuned once on the first frequency (same shapes for all);
+        # a cache file (--tune-cache) lets a profiled run reuse them untuned
         t0 = time.perf_counter()
-        tuned = plans[0].tune(nrhs)
+        tuned = plans[0].tune(nrhs, cache=TUNE_CACHE)
         for pl in plans[1:]:
             pl.set_launch(tuned)
         t_tune = time.perf_counter() - t0
@@ -608,11 +614,14 @@ def main():
     ap.add_argument("--c4-only", action="store_true", help="time only the adjoint gradient (128x128x160)")
     ap.add_argument("--c5-only", choices=["c128", "mixed", "both"],
                     help="time only the headline workload (no oracle): for kernel traces")
+    ap.add_argument("--tune-cache", help="JSON-lines cache of tuned launch shapes (read, else written)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
     ap.add_argument("--stage-labels", action="store_true",
                     help="with --stats-summary: list the z sweeps of decomposed solves by stage")
     args = ap.parse_args()
+    global TUNE_CACHE
+    TUNE_CACHE = args.tune_cache
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary)
         return

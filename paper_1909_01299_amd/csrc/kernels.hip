@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <functional>
+#include <vector>
 #include <mutex>
 #include <string>
 
@@ -151,8 +152,9 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   constexpr int XS = 17 * V + 1;               // LDS row of a line: entry (k2, k1) at slot 17 k2 + k1
   constexpr int MPL = N >= 32 ? N / 32 : 1;    // terms m per lane in the sums
   constexpr int PL = (N / 2) / MPL;            // lanes holding terms (16; 8 for N = 16)
-  __shared__ C row[LT * XS];
-  __shared__ C tot[LT * 16];
+  extern __shared__ unsigned char dst_smem[];   // row[LT * XS], then tot[LT * 16]
+  C* row = reinterpret_cast<C*>(dst_smem);
+  C* tot = row + LT * XS;
   const DstDesc d = descs[blockIdx.y];
   const int lines = d.P * d.Q;
   const int l0 = blockIdx.x * LT;
@@ -1233,6 +1235,18 @@ inline unsigned grid1(int64_t n) { return unsigned((n + 255) / 256); }
 // ---------------------------------------------------------------------------
 
 // ---------------------------------------------------------------- sine transform
+// Kernels whose dynamic LDS exceeds 64 KiB ask for it once (gfx950 has 160 KiB
+// per workgroup).
+static void allow_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::vector<std::pair<const void*, size_t>> done;
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& e : done)
+    if (e.first == fn && e.second >= bytes) return;
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  done.push_back({fn, bytes});
+}
+
 // LDS of one workgroup of lt lines (rows of 17 V + 1 complex values and the
 // lanes' partial sums)
 static size_t dst_lds_bytes(int prec, int V, int lt) {
@@ -1247,7 +1261,7 @@ int dst_lines_per_wg(int prec, int V) {
 }
 
 bool dst_lt_ok(int prec, int V, int lt) {
-  return (lt == 4 || lt == 8 || lt == 16) && dst_lds_bytes(prec, V, lt) <= 65536;
+  return (lt == 4 || lt == 8 || lt == 16) && dst_lds_bytes(prec, V, lt) <= kMaxLdsBytes;
 }
 
 template <typename R, typename CI, typename CO, bool ACC>
@@ -1257,11 +1271,12 @@ static void launch_dst_t(int V, const DstDesc* d, int ndesc, int max_lines, cons
   if (!dst_lt_ok(prec, V, lt)) lt = dst_lines_per_wg(prec, V);
   const dim3 grid((max_lines + lt - 1) / lt, ndesc, nrhs);
   const cplx<R>* T = (const cplx<R>*)tw;
+  const size_t lds = dst_lds_bytes(prec, V, lt);
 #define HS_DST_CASE(VV, LL)                                                                                    \
   if (V == VV && lt == LL) {                                                                                   \
-    if constexpr ((17 * VV + 17) * LL * sizeof(cplx<R>) <= 65536)                                              \
-      hipLaunchKernelGGL((k_dst<R, CI, CO, ACC, VV, LL>), grid, dim3(16 * LL), 0, st, d, T, (const CI*)src,     \
-                         (CO*)dst);                                                                            \
+    auto kfn = k_dst<R, CI, CO, ACC, VV, LL>;                                                                  \
+    if (lds > 65536) allow_lds(reinterpret_cast<const void*>(kfn), lds);                                       \
+    hipLaunchKernelGGL(kfn, grid, dim3(16 * LL), lds, st, d, T, (const CI*)src, (CO*)dst);                     \
     return;                                                                                                    \
   }
   HS_DST_CASE(1, 16)

@@ -101,6 +101,7 @@ void xform_lines_h3(int in64, int out64, int acc, const XformDesc* dev, const Xf
 void xform_y_h3(const XformYDesc* dev, const XformYDesc* host, int ndesc, const void* htab, void* ws, int nrhs,
                 hipStream_t st);
 
+constexpr size_t kMaxLdsBytes = 163840;   // LDS of one workgroup on gfx950
 // Sine transform of lines of n = 16 V - 1 points (V in {1, 2, 4, 8, 16, 32}).
 constexpr int kTwiddleN = 1024;
 // lt: lines per workgroup (4, 8 or 16; 0 or an unusable value = default)
