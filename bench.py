@@ -339,6 +339,9 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
                  for b in blocks]
         batch = hs.Batch(plans, [nrhs] * len(plans))
         t_plan = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        batch.tune(fs, us, cache=TUNE_CACHE)
+        t_tune = time.perf_counter() - t0
         for _ in range(warmup):
             batch.solve(fs, us)
         torch.cuda.synchronize()
@@ -348,7 +351,7 @@ def bench_c3(steps, warmup, with_oracle, sample_blocks=(0, 5, 40, 63), precs=("c
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         rec = {"value": unknowns * nrhs / dt, "unit": "unknowns*RHS/s", "ms_per_step": dt * 1e3,
-               "plan_seconds": t_plan}
+               "plan_seconds": t_plan, "tune_seconds": t_tune}
         if prec == "mixed":
             rec["refine_steps"] = plans[0].info()["refine_steps"]
         if with_oracle:

@@ -266,15 +266,25 @@ hs_status hs_profile_read(hs_plan plan, hs_stage_time* out, int32_t max_out, int
  * nrhs[i] right-hand sides for plans[i]; the plans must outlive the batch and
  * share one precision.  The batch copies the plans' tables when it is created:
  * later hs_set_k2 calls on a plan do not reach it (create a new batch).  Its
- * launch shapes (z chunking, sine lines per workgroup) are those of plans[0]
- * when the graph is captured (first solve, or new array pointers).  Errors: HS_ERR_ARG (decomposed plans, mixed precisions or devices,
+ * launch shapes start as those of plans[0] and are the batch's own after
+ * hs_batch_tune.  Errors: HS_ERR_ARG (decomposed plans, mixed precisions or devices,
  * nrhs outside [1, 4096]), HS_ERR_ALLOC, HS_ERR_DEVICE. */
 hs_status hs_batch_create(const hs_plan* plans, int32_t nplans, const int32_t* nrhs,
                           hs_batch* out);
 size_t hs_batch_workspace_bytes(hs_batch batch);
 hs_status hs_batch_bind_workspace(hs_batch batch, void* dev_ptr, size_t bytes);
-/* f[i], u[i]: device arrays of plans[i] with nrhs[i] right-hand sides. */
+/* f[i], u[i]: device arrays of plans[i] with nrhs[i] right-hand sides.  New
+ * array pointers make the batch capture its graph again (after waiting for
+ * the device, since the previous graph's descriptors are rewritten).  The
+ * complex64 path needs u[i] distinct from f[i]. */
 hs_status hs_batch_solve(hs_batch batch, const void* const* f, void* const* u, void* stream);
+/* Autotune the batch's own launch shapes (z-line chunks, sine lines per
+ * workgroup, fixed z-solve rows; as hs_plan_tune, but timed on the whole
+ * captured graph of the batch) with the caller's arrays: u is overwritten.
+ * cache_path (may be NULL): JSON-lines cache keyed by device, precision and
+ * the plans' shapes.  Synchronizes the stream. */
+hs_status hs_batch_tune(hs_batch batch, const void* const* f, void* const* u, const char* cache_path,
+                        void* stream);
 void hs_batch_destroy(hs_batch batch);
 
 /* Host-only 1D generalized eigensolver used by the plan (no device needed):

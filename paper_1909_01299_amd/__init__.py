@@ -88,6 +88,7 @@ EXPORTS = {
     "hs_batch_bind_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "hs_batch_solve": (ctypes.c_int, [ctypes.c_void_p] * 4),
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
+    "hs_batch_tune": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_char_p, ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
     "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -389,12 +390,7 @@ class Batch:
                 pass
             self._h = None
 
-    def solve(self, fs, us=None, stream=None):
-        import torch
-        if len(fs) != len(self.plans):
-            raise ValueError("one f per plan")
-        if us is None:
-            us = [torch.empty_like(f) for f in fs]
+    def _arrays(self, fs, us):
         for p, r, f, u in zip(self.plans, self.nrhs, fs, us):
             _check_array(f, p.shape, "f")
             _check_array(u, p.shape, "u")
@@ -402,6 +398,24 @@ class Batch:
                 raise ValueError("right-hand side count differs from the batch's")
         fa = (ctypes.c_void_p * len(fs))(*[_ptr(f) for f in fs])
         ua = (ctypes.c_void_p * len(us))(*[_ptr(u) for u in us])
+        return fa, ua
+
+    def tune(self, fs, us, cache: Optional[str] = None, stream=None):
+        """Autotune the batch's launch shapes on its whole graph (us is overwritten)."""
+        if len(fs) != len(self.plans) or len(us) != len(self.plans):
+            raise ValueError("one f and one u per plan")
+        fa, ua = self._arrays(fs, us)
+        _check(lib().hs_batch_tune(self._h, fa, ua, cache.encode() if cache else None, _stream(stream)))
+
+    def solve(self, fs, us=None, stream=None):
+        import torch
+        if len(fs) != len(self.plans):
+            raise ValueError("one f per plan")
+        if us is None:
+            us = [torch.empty_like(f) for f in fs]
+        if len(us) != len(self.plans):
+            raise ValueError("one u per plan")
+        fa, ua = self._arrays(fs, us)
         _check(lib().hs_batch_solve(self._h, fa, ua, _stream(stream)))
         return us
 

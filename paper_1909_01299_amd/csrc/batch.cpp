@@ -11,6 +11,9 @@
 
 #include <algorithm>
 #include <cstring>
+#include <fstream>
+#include <functional>
+#include <sstream>
 
 namespace hs {
 
@@ -40,6 +43,9 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
   prec = plans[0]->prec;
   refine_steps = plans[0]->refine_steps;
   device = plans[0]->device;
+  tune_chunks = plans[0]->tune_chunks;
+  tune_lt = plans[0]->tune_lt;
+  tune_full = plans[0]->tune_full;
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
     if (p->decomposed) { err = "batched plans must be single blocks (no separators)"; return HS_ERR_ARG; }
@@ -129,6 +135,7 @@ hs_status Batch::bind(void* p, size_t bytes, std::string& err) {
 hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err) {
   s_fwdx = {}; s_fwdx_res = {}; s_invx = {}; s_fwdy = {}; s_invy = {};
   d_sweep.clear();
+  d_resid.clear();
   const char* f0 = (const char*)f[0];
   const char* u0 = (const char*)u[0];
   for (size_t i = 0; i < plans.size(); ++i) {
@@ -142,6 +149,15 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
     const int64_t H0 = h16_off[i];
     const int64_t plane = (int64_t)B.nbx * B.nby;
     const int64_t N = plane * p->NZ;
+    {
+      ResidualItem ri{};
+      ri.g = p->sten;
+      ri.f = df / 16;
+      ri.u = du / 16;
+      ri.r = int64_t(res_off[i] / 8);
+      ri.nrhs = nrhs[i];
+      d_resid.push_back(ri);
+    }
     for (int r = 0; r < nrhs[i]; ++r) {
       const int64_t spec = spec_off[i] + r * N;
       const int64_t fo = df / 16 + r * N, uo = du / 16 + r * N;
@@ -223,6 +239,8 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
   partition_y(prec, s_fwdy.dense); partition_y(prec, s_invy.dense);
   reg_stage(s_fwdx); reg_stage(s_fwdx_res); reg_stage(s_invx); reg_stage(s_fwdy); reg_stage(s_invy);
   reg(d_sweep, &p_sweep);
+  resid_wg = residual_list_items(d_resid);
+  reg(d_resid, &p_resid);
   // near-resonance selections: every descriptor reads its own plan's FP64 table
   for (int c = 0; c < 3; ++c) {
     sel_dev[c] = SweepSel{};
@@ -268,7 +286,7 @@ void Batch::run_x(const StageList<XformDesc>& sl, int in64, int out64, int acc, 
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
       dst_lines(prec, in64, out64, acc, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, src,
-                dst, 1, st, plans[0]->tune_lt);
+                dst, 1, st, tune_lt);
 }
 
 void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
@@ -279,27 +297,22 @@ void Batch::run_y(const StageList<XformYDesc>& sl, hipStream_t st) {
   for (int v = 0; v < kNumV; ++v)
     if (!sl.dst[v].empty())
       dst_lines(prec, 0, 0, 0, 1 << v, sl.p_dst[v], int(sl.dst[v].size()), sl.max_lines[v], tw, ws, ws, 1, st,
-                plans[0]->tune_lt);
+                tune_lt);
 }
 
 void Batch::enqueue(const void* f0, void* u0, hipStream_t st) {
   auto pass = [&](const StageList<XformDesc>& fwd, const void* src, int in64, int acc) {
     run_x(fwd, in64, 0, 0, src, ws, st);
     run_y(s_fwdy, st);
-    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, plans[0]->tune_chunks,
-          prec == 1 ? sel_dev : nullptr, &side, plans[0]->tune_full ? common_nz : 0);
+    sweep(prec, p_sweep, int(d_sweep.size()), max_modes, max_nz, 0, tab(), dtab64, ws, 1, st, tune_chunks,
+          prec == 1 ? sel_dev : nullptr, &side, tune_full ? common_nz : 0);
     run_y(s_invy, st);
     run_x(s_invx, 0, 1, acc, ws, u0, st);
   };
   pass(s_fwdx, f0, 1, 0);
   for (int it = 0; it < refine_steps; ++it) {
-    for (size_t i = 0; i < plans.size(); ++i) {
-      const Plan* p = plans[i];
-      // r = f - A u of plan i (FP64 stencil, complex64 output); f, u of plan i are
-      // recovered from the offsets relative to f0 / u0 recorded at capture
-      hs::residual(p->sten, (const char*)f0 + foff[i], (char*)u0 + uoff[i], (char*)ws + res_off[i], 0, 0,
-                   nrhs[i], st);
-    }
+    // r = f - A u of every plan (FP64 stencils, complex64 output) in one launch
+    residual_list(p_resid, int(d_resid.size()), resid_wg, f0, u0, ws, st);
     pass(s_fwdx_res, ws, 0, 1);
   }
 }
@@ -316,6 +329,13 @@ hs_status Batch::solve(const void* const* f, void* const* u, hipStream_t st, std
   bool same = last_f.size() == plans.size();
   for (size_t i = 0; same && i < plans.size(); ++i) same = last_f[i] == f[i] && last_u[i] == u[i];
   if (!same) {
+    // a replay of the previous graph may still read the descriptor buffer
+    // that rebuild() rewrites
+    if (exec && hipDeviceSynchronize() != hipSuccess) {
+      (void)hipGetLastError();
+      err = "hipDeviceSynchronize failed";
+      return HS_ERR_DEVICE;
+    }
     hs_status s = rebuild(f, u, err);
     if (s != HS_OK) return s;
     foff.assign(plans.size(), 0);
@@ -324,6 +344,9 @@ hs_status Batch::solve(const void* const* f, void* const* u, hipStream_t st, std
       foff[i] = (const char*)f[i] - (const char*)f[0];
       uoff[i] = (const char*)u[i] - (const char*)u[0];
     }
+  }
+  if (!same || recapture) {
+    recapture = false;
     if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
     if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
     if (hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
@@ -344,6 +367,91 @@ hs_status Batch::solve(const void* const* f, void* const* u, hipStream_t st, std
     (void)hipGetLastError();
     err = "graph launch failed";
     return HS_ERR_DEVICE;
+  }
+  return HS_OK;
+}
+
+hs_status Batch::tune(const void* const* f, void* const* u, const char* cache_path, hipStream_t st,
+                      std::string& err) {
+  if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { err = "hipGetDeviceProperties failed"; return HS_ERR_DEVICE; }
+  // cache key: device, precision and every plan's shape and right-hand sides
+  std::ostringstream shapes;
+  for (size_t i = 0; i < plans.size(); ++i) {
+    const Plan* p = plans[i];
+    shapes << p->NX << "x" << p->NY << "x" << p->NZ << "r" << nrhs[i];
+    for (auto& a : p->axes) shapes << (a.dstV ? "s" : "d");
+    shapes << ";";
+  }
+  std::ostringstream key;
+  key << prop.gcnArchName << "|batch|p" << prec << "|n" << plans.size() << "|h"
+      << std::hex << std::hash<std::string>{}(shapes.str());
+  const std::string k = key.str();
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    const std::string tag = "\"key\": \"" + k + "\"";
+    while (std::getline(in, line)) {
+      if (line.find(tag) == std::string::npos) continue;
+      const size_t pc = line.find("\"chunks\": "), pl = line.find("\"lines\": "), pf = line.find("\"fixed_rows\": ");
+      if (pc == std::string::npos || pl == std::string::npos || pf == std::string::npos) continue;
+      tune_chunks = std::atoi(line.c_str() + pc + 10);
+      tune_lt = std::atoi(line.c_str() + pl + 9);
+      tune_full = std::atoi(line.c_str() + pf + 14);
+      recapture = true;   // capture again with these shapes
+      return HS_OK;
+    }
+  }
+  std::vector<int> chunks, lts;
+  for (int c : {8, 16, 32})
+    if (sweep_chunks_ok(c, max_nz)) chunks.push_back(c);
+  bool any_dst = false;
+  for (const Plan* p : plans)
+    for (auto& a : p->axes) any_dst |= a.dstV != 0;
+  for (int l : {4, 8, 16}) {
+    bool ok = any_dst;
+    for (const Plan* p : plans)
+      for (auto& a : p->axes)
+        if (a.dstV) ok = ok && dst_lt_ok(prec, a.dstV, l);
+    if (ok) lts.push_back(l);
+  }
+  if (lts.empty()) lts.push_back(0);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    err = "hipEventCreate failed";
+    return HS_ERR_DEVICE;
+  }
+  float best = 1e30f;
+  int bc = tune_chunks, bl = tune_lt, bf = tune_full;
+  for (int c : chunks)
+    for (int l : lts)
+      for (int fr = 0; fr < (common_nz > 0 && sweep_rows_fixed(c, common_nz) ? 2 : 1); ++fr) {
+        tune_chunks = c;
+        tune_lt = l;
+        tune_full = fr;
+        recapture = true;
+        std::string e2;
+        if (solve(f, u, st, e2) != HS_OK) continue;   // captures this shape's graph
+        (void)hipEventRecord(e0, st);
+        for (int rep = 0; rep < 2; ++rep) (void)solve(f, u, st, e2);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bc = c; bl = l; bf = fr; }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  tune_chunks = bc;
+  tune_lt = bl;
+  tune_full = bf;
+  recapture = true;
+  if (cache_path && *cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl << ", \"fixed_rows\": " << bf
+        << ", \"ms_per_solve\": " << best / 2 << "}\n";
   }
   return HS_OK;
 }

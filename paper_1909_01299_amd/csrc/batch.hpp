@@ -41,6 +41,13 @@ struct Batch {
   StageList<XformYDesc> s_fwdy, s_invy;
   std::vector<SweepDesc> d_sweep;
   const SweepDesc* p_sweep = nullptr;
+  // complex64 path: every plan's FP64 residual in one flat launch
+  std::vector<ResidualItem> d_resid;
+  const ResidualItem* p_resid = nullptr;
+  int64_t resid_wg = 0;
+  // launch shapes of the batch (those of plans[0] until hs_batch_tune)
+  int tune_chunks = 0, tune_lt = 0, tune_full = 0;
+  bool recapture = false;         // launch shapes changed: capture the graph again
   // complex64: near-resonance selection of d_sweep for chunk counts 8, 16, 32
   SweepSelHost sel_host[3];
   SweepSel sel_dev[3];
@@ -56,6 +63,9 @@ struct Batch {
   hs_status build(const std::vector<const Plan*>& ps, const std::vector<int>& rs, std::string& err);
   hs_status bind(void* p, size_t bytes, std::string& err);
   hs_status solve(const void* const* f, void* const* u, hipStream_t st, std::string& err);
+  // time the usable launch shapes on the whole captured graph with the
+  // caller's arrays (u is overwritten) and keep the fastest
+  hs_status tune(const void* const* f, void* const* u, const char* cache_path, hipStream_t st, std::string& err);
 
  private:
   hs_status rebuild(const void* const* f, void* const* u, std::string& err);

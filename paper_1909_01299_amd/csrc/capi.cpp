@@ -303,6 +303,13 @@ hs_status hs_batch_solve(hs_batch batch, const void* const* f, void* const* u, v
   return ret(batch->b.solve(f, u, (hipStream_t)stream, err), err);
 }
 
+hs_status hs_batch_tune(hs_batch batch, const void* const* f, void* const* u, const char* cache_path, void* stream) {
+  if (!batch) return ret(HS_ERR_ARG, "batch is NULL");
+  if (!f || !u) return ret(HS_ERR_ARG, "f and u must be non-NULL");
+  std::string err;
+  return ret(batch->b.tune(f, u, cache_path, (hipStream_t)stream, err), err);
+}
+
 void hs_batch_destroy(hs_batch batch) { delete batch; }
 
 }  // extern "C"

@@ -1074,19 +1074,21 @@ constexpr int RZ_TX = 64, RZ_TY = 4, RZ_ZC = 32;
 // its points (three doubles at part + 3 * workgroup index, workgroups
 // numbered x fastest, then z chunk, then right-hand side); write_out = 0
 // evaluates those sums without storing r.
+// Workgroup (bx, by, bz) of a grid (gx, gy, nrhs): column tile bx, z chunk by,
+// right-hand side bz.
 template <typename CO>
-__global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const double2* __restrict__ f,
-                                                            const double2* __restrict__ u, CO* __restrict__ out,
-                                                            int negate_f, double* __restrict__ part,
-                                                            int write_out) {
+__device__ __forceinline__ void residual_body(const StencilGeom& g, const double2* __restrict__ f,
+                                              const double2* __restrict__ u, CO* __restrict__ out, int negate_f,
+                                              double* __restrict__ part, int write_out, int bx, int by, int bz,
+                                              int gx, int gy) {
   const int tx = threadIdx.x & (RZ_TX - 1), ty = threadIdx.x / RZ_TX;
   const int xt = (g.nx + RZ_TX - 1) / RZ_TX;
-  const int x = (blockIdx.x % xt) * RZ_TX + tx, y = (blockIdx.x / xt) * RZ_TY + ty;
+  const int x = (bx % xt) * RZ_TX + tx, y = (bx / xt) * RZ_TY + ty;
   double rr = 0, ff = 0, uu = 0;
   if (x < g.nx && y < g.ny) {
-    const int z0 = blockIdx.y * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
+    const int z0 = by * RZ_ZC, z1 = min(g.nz, z0 + RZ_ZC);
     const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-    const double2* uc0 = u + (int64_t)blockIdx.z * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
+    const double2* uc0 = u + (int64_t)bz * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
     const int64_t col = uc0 - u;
     const double2 zero = mk<double>(0, 0);
     const double2 cxd = g.xd[x], cyd = g.yd[y];
@@ -1147,9 +1149,38 @@ __global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const
   if (threadIdx.x < 3) {
     double s = 0;
     for (int w = 0; w < RZ_TX * RZ_TY / 64; ++w) s += red[threadIdx.x][w];
-    const int64_t wg = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    const int64_t wg = ((int64_t)bz * gy + by) * gx + bx;
     part[3 * wg + threadIdx.x] = s;
   }
+}
+
+template <typename CO>
+__global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual(StencilGeom g, const double2* __restrict__ f,
+                                                            const double2* __restrict__ u, CO* __restrict__ out,
+                                                            int negate_f, double* __restrict__ part,
+                                                            int write_out) {
+  residual_body<CO>(g, f, u, out, negate_f, part, write_out, int(blockIdx.x), int(blockIdx.y), int(blockIdx.z),
+                    int(gridDim.x), int(gridDim.y));
+}
+
+// Residuals r = f - A u (complex64 output) of many plans in one launch: the
+// workgroups of plan i (its column tiles x z chunks x right-hand sides) are
+// the contiguous range [l[i].wg0, l[i + 1].wg0) of a flat grid, found by a
+// binary search over the list.
+__global__ __launch_bounds__(RZ_TX * RZ_TY) void k_residual_list(const ResidualItem* __restrict__ l, int n,
+                                                                 const double2* __restrict__ f0,
+                                                                 const double2* __restrict__ u0,
+                                                                 float2* __restrict__ r0) {
+  const int64_t wg = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (l[mid].wg0 <= wg) lo = mid; else hi = mid - 1;
+  }
+  const ResidualItem& it = l[lo];
+  const int64_t loc = wg - it.wg0;
+  const int bx = int(loc % it.gx), by = int((loc / it.gx) % it.gy), bz = int(loc / ((int64_t)it.gx * it.gy));
+  residual_body<float2>(it.g, f0 + it.f, u0 + it.u, r0 + it.r, 0, nullptr, 1, bx, by, bz, it.gx, it.gy);
 }
 
 // Per right-hand side r, the sums of the residual kernel's workgroup partials
@@ -1613,6 +1644,25 @@ static dim3 residual_grid(const StencilGeom& g, int nrhs) {
 int64_t residual_workgroups(const StencilGeom& g) {
   const dim3 gr = residual_grid(g, 1);
   return (int64_t)gr.x * gr.y;
+}
+
+int64_t residual_list_items(std::vector<ResidualItem>& items) {
+  int64_t wg = 0;
+  for (auto& it : items) {
+    const dim3 gr = residual_grid(it.g, it.nrhs);
+    it.gx = int(gr.x);
+    it.gy = int(gr.y);
+    it.wg0 = wg;
+    wg += (int64_t)gr.x * gr.y * gr.z;
+  }
+  return wg;
+}
+
+void residual_list(const ResidualItem* dev, int n, int64_t total_wg, const void* f0, const void* u0, void* r0,
+                   hipStream_t st) {
+  if (n == 0 || total_wg == 0) return;
+  hipLaunchKernelGGL(k_residual_list, dim3(unsigned(total_wg)), dim3(RZ_TX * RZ_TY), 0, st, dev, n,
+                     (const double2*)f0, (const double2*)u0, (float2*)r0);
 }
 
 void residual(const StencilGeom& g, const void* f, const void* u, void* out, int out64, int apply_only,

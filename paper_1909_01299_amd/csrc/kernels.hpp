@@ -186,6 +186,19 @@ void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* 
           hipStream_t st);
 void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* u, int nrhs, hipStream_t st);
 
+// One plan's residual in a batched launch: its stencil, the element offsets of
+// its f, u (complex128) and r (complex64) from the launch's base pointers, its
+// right-hand sides; gx, gy, wg0 are filled by residual_list_items.
+struct ResidualItem {
+  StencilGeom g;
+  int64_t f, u, r;
+  int32_t nrhs, gx, gy, pad_;
+  int64_t wg0;
+};
+// sets gx, gy, wg0 of every item; returns the total number of workgroups
+int64_t residual_list_items(std::vector<ResidualItem>& items);
+void residual_list(const ResidualItem* dev, int n, int64_t total_wg, const void* f0, const void* u0, void* r0,
+                   hipStream_t st);
 // part (may be NULL): 3 * residual_workgroups(g) * nrhs doubles of workgroup
 // sums; norms (with part): 3 * nrhs doubles, per right-hand side |r|^2,
 // |f|^2, |u|^2 summed in a fixed order; write_out = 0 stores no r.

@@ -84,3 +84,57 @@ def test_batch_rejects_decomposed_plans(hs):
     plan = hs.Plan(p, "c128")
     with pytest.raises(hs.HSError):
         hs.Batch([plan], [1])
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("mixed", 1e-8)])
+def test_batch_tuner_keeps_parity_and_caches(hs, prec, tol, tmp_path):
+    """The batch's own autotuner times its launch shapes on the whole graph;
+    the tuned batch still matches the oracle, and a second batch of the same
+    shapes takes the shapes from the cache file."""
+    import torch
+    probs = _blocks(6, 16, 40, 12, 48, seed=21)
+    nrhs = [2, 1, 1, 2, 1, 2]
+    rng = np.random.default_rng(22)
+    plans = [hs.Plan(p, prec, max_rhs=r, refine_steps=1 if prec == "mixed" else 0) for p, r in zip(probs, nrhs)]
+    fs_np = [W.complex_normal(rng, (r,) + p.shape) for p, r in zip(probs, nrhs)]
+    fs = [hs.to_device(f) for f in fs_np]
+    us = [torch.empty_like(f) for f in fs]
+    cache = str(tmp_path / "batch_tune.jsonl")
+    batch = hs.Batch(plans, nrhs)
+    batch.tune(fs, us, cache=cache)
+    us = batch.solve(fs, us)
+    torch.cuda.synchronize()
+    for p, f_np, u in zip(probs, fs_np, us):
+        ref = separable.solve(p, f_np)
+        got = u.cpu().numpy()
+        for r in range(f_np.shape[0]):
+            assert _rel(got[r], ref[r]) < tol
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"fixed_rows"' in lines[0]
+    batch2 = hs.Batch(plans, nrhs)
+    batch2.tune(fs, [torch.empty_like(f) for f in fs], cache=cache)
+    assert len(open(cache).read().strip().splitlines()) == 1
+
+
+def test_batch_new_pointers_back_to_back(hs):
+    """Solves with new array pointers issued back to back, with no
+    synchronization between them: each capture waits for the previous graph
+    before its descriptors are rewritten, so every result is right."""
+    import torch
+    probs = _blocks(5, 12, 36, 8, 30, seed=31)
+    nrhs = [1, 2, 1, 1, 2]
+    rng = np.random.default_rng(32)
+    plans = [hs.Plan(p, "mixed", max_rhs=r, refine_steps=1) for p, r in zip(probs, nrhs)]
+    batch = hs.Batch(plans, nrhs)
+    sets = []
+    for _ in range(3):
+        fs_np = [W.complex_normal(rng, (r,) + p.shape) for p, r in zip(probs, nrhs)]
+        fs = [hs.to_device(f) for f in fs_np]
+        sets.append((fs_np, fs, batch.solve(fs)))
+    torch.cuda.synchronize()
+    for fs_np, fs, us in sets:
+        for p, f_np, u in zip(probs, fs_np, us):
+            ref = separable.solve(p, f_np)
+            got = u.cpu().numpy()
+            for r in range(f_np.shape[0]):
+                assert _rel(got[r], ref[r]) < 1e-8
