@@ -177,10 +177,12 @@ def traffic_summary(fdir, wdir, cfdir, cwdir):
             rec = stages.setdefault(lab, {"fetch_kib": [], "write_kib": []})
             rec[key + "_kib"].append(r[3])
     run = "cd /tmp && export TMPDIR=/tmp && timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 $R/bench.py {a}"
+    rel = lambda d: d if os.path.isabs(d) else "$R/" + d   # noqa: E731
+    ctr = "--counters" + (f" --tune-cache {rel(TUNE_CACHE)}" if TUNE_CACHE else "")
     out = {"source_hash": kernel_source_hash(),
            "commands (R = repository root)": [
-               run.format(c="FETCH_SIZE", d=fdir, a="--counters"), run.format(c="WRITE_SIZE", d=wdir, a="--counters"),
-               run.format(c="FETCH_SIZE", d=cfdir, a="--copy"), run.format(c="WRITE_SIZE", d=cwdir, a="--copy"),
+               run.format(c="FETCH_SIZE", d=rel(fdir), a=ctr), run.format(c="WRITE_SIZE", d=rel(wdir), a=ctr),
+               run.format(c="FETCH_SIZE", d=rel(cfdir), a="--copy"), run.format(c="WRITE_SIZE", d=rel(cwdir), a="--copy"),
                f"python3 $R/bench.py --traffic-summary {fdir} {wdir} {cfdir} {cwdir}"],
            "copy_scale": scale, "stages": {}}
     for lab, rec in stages.items():
