@@ -89,7 +89,12 @@ typedef struct {
 /* Separator planes (0-based interior indices, strictly increasing, at least
  * one node between neighbours and between a separator and a wall).  A block
  * is a maximal run of nodes between separators (Sec. 2, eq. (4)).  Zero
- * separators = one block. */
+ * separators = one block.  Any count: the second gridding of Sec. 2 (about
+ * sqrt(n) blocks of about sqrt(n) nodes per axis) is the intended use of
+ * many.  Up to 4 separators per axis enter the global z solve as low-rank
+ * terms; with more, their lines are first expanded into a dense spectral
+ * right-hand side (one more write and read of the global grid).  A block
+ * side may not exceed 512 nodes. */
 typedef struct {
   int32_t nsep_x;
   const int32_t* sep_x;
@@ -104,7 +109,10 @@ typedef struct {
   int32_t max_rhs;        /* largest nrhs a solve will be called with (>= 1)       */
   int32_t flags;          /* bit 0: force the dense transform on uniform axes;
                              bits 1-2: z-line chunks per mode (0 auto, 1: 8, 2: 16,
-                             3: 32; must hold nz within 16 rows per chunk)        */
+                             3: 32; must hold nz within 16 rows per chunk);
+                             bit 3: expand the right-hand side of the global
+                             interface solve densely (the path taken anyway
+                             with more than 4 separators on an axis)            */
   double tol;             /* > 0: every solve ends with the FP64 residual of the u
                              it returns (one more read of f and u, nothing written)
                              and hs_get_info reports HS_ERR_NOCONV when

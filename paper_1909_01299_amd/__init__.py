@@ -180,7 +180,7 @@ class Plan:
 
     def __init__(self, problem, precision: str = "c128", max_rhs: int = 1, refine_steps: int = 0,
                  force_dense: bool = False, z_chunks: int = 0, tol: float = 0.0, device=None,
-                 workspace=None):
+                 workspace=None, dense_global: bool = False):
         import torch
         self.problem = problem
         self.nx = len(problem.hx) - 1
@@ -208,7 +208,8 @@ class Plan:
         blocks = _Blocks(len(sx), sx.ctypes.data if len(sx) else None, len(sy), sy.ctypes.data if len(sy) else None)
         prec = {"c128": HS_C128, "c64": HS_C64_REFINE, "mixed": HS_C64_REFINE}[precision]
         chunk_bits = {0: 0, 8: 1, 16: 2, 32: 3}[int(z_chunks)] << 1
-        opts = _Options(prec, int(refine_steps), self.max_rhs, (1 if force_dense else 0) | chunk_bits, float(tol))
+        opts = _Options(prec, int(refine_steps), self.max_rhs, (1 if force_dense else 0) | chunk_bits | (8 if dense_global else 0),
+                        float(tol))
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(lib().hs_plan_create(ctypes.byref(grid), ctypes.byref(blocks), ctypes.byref(opts),

@@ -154,4 +154,17 @@ struct ContractDesc {
   int64_t xpart, xpart_s, xpart_t, xpart_r, xpart_z;
 };
 
+// Dense spectral right-hand side of the global interface solve, for
+// separator counts above kMaxTerms (too many to add inside the z solve):
+//   out(r,z,b,a) = sum_i cx[i*na + a] gx_i(r,z,b) + sum_j cy[j*nb + b] gy_j(r,z,a)
+// with gx_i(r,z,b) at gx + r*gx_r + i*gx_t + z*gx_z + b (gy_j likewise with a),
+// out(r,z,b,a) at out + r*out_r + (z*nb + b)*na + a; cx, cy are table offsets.
+struct ExpandDesc {
+  int32_t na, nb, nz, nxt, nyt, pad_;
+  int64_t cx, cy;
+  int64_t gx, gx_t, gx_r, gx_z;
+  int64_t gy, gy_t, gy_r, gy_z;
+  int64_t out, out_r;
+};
+
 }  // namespace hs

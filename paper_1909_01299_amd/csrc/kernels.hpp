@@ -181,6 +181,7 @@ ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec);
 void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
               hipStream_t st);
 
+void expand(int prec, const ExpandDesc& e, const void* tab, void* ws, int nrhs, hipStream_t st);
 void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws, int nrhs, hipStream_t st);
 void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,
           hipStream_t st);

@@ -117,10 +117,6 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
     sepy.assign(b->sep_y, b->sep_y + b->nsep_y);
   }
   if (!check_seps(NX, sepx, err, "sep_x") || !check_seps(NY, sepy, err, "sep_y")) return HS_ERR_ARG;
-  if ((int)sepx.size() > kMaxTerms || (int)sepy.size() > kMaxTerms) {
-    err = "at most 4 separators per axis are supported";
-    return HS_ERR_ARG;
-  }
   hs_options def{HS_C128, 0, 1, 0, 0.0};
   const hs_options& op = o ? *o : def;
   if (op.prec != HS_C128 && op.prec != HS_C64_REFINE) { err = "unknown precision"; return HS_ERR_ARG; }
@@ -140,6 +136,7 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
     }
   }
   decomposed = !sepx.empty() || !sepy.empty();
+  dense_glob = (int)sepx.size() > kMaxTerms || (int)sepy.size() > kMaxTerms || (flags & 8) != 0;
   for (auto& rx : runs(NX, sepx)) max_block_n = std::max(max_block_n, rx.second - rx.first + 1);
   for (auto& ry : runs(NY, sepy)) max_block_n = std::max(max_block_n, ry.second - ry.first + 1);
   if (max_block_n > 512) { err = "block side > 512 is not supported; add separators"; return HS_ERR_ARG; }
@@ -306,6 +303,20 @@ hs_status Plan::build_tables(std::string& err) {
   c.clear();
   for (int t : sepy) c.push_back(1.0 / (0.5 * (hy[t] + hy[t + 1]) * hy[t + 1]));
   cy_hi = push(c);
+  // many separators: the columns of W^{-1} at the separators, one contiguous
+  // vector per separator, expanded into a dense global right-hand side
+  if (decomposed && dense_glob) {
+    const Axis& GX = axes[gax];
+    const Axis& GY = axes[gay];
+    c.assign(sepx.size() * size_t(NX), cd(0, 0));
+    for (size_t i = 0; i < sepx.size(); ++i)
+      for (int a = 0; a < NX; ++a) c[i * NX + a] = GX.e.Winv[(size_t)a * NX + sepx[i]];
+    ex_cx = push(c);
+    c.assign(sepy.size() * size_t(NY), cd(0, 0));
+    for (size_t j = 0; j < sepy.size(); ++j)
+      for (int b = 0; b < NY; ++b) c[j * NY + b] = GY.e.Winv[(size_t)b * NY + sepy[j]];
+    ex_cy = push(c);
+  }
   // lift coefficients: first interior line x0 couples to its separator by
   // -1/(hhat_{x0} h_{x0}), last line x1 by -1/(hhat_{x1} h_{x1+1})
   lift_cf.clear();
@@ -456,7 +467,10 @@ void Plan::layout_workspace() {
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
     w_gspec = take(R * NZ * (int64_t)NX * NY);
-    const int64_t np = part_elems(NX, NY, nsx, nsy);
+    // the interface contraction in groups of kMaxTerms separators per axis
+    int64_t np = 0;
+    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms)
+      np += part_elems(NX, NY, std::clamp(nsx - g0, 0, kMaxTerms), std::clamp(nsy - g0, 0, kMaxTerms));
     w_cpart = np > 0 ? take(np) : 0;
   }
   ws_elems = size_t(off);
@@ -656,31 +670,52 @@ void Plan::build_descriptors() {
     g.na = NX; g.nb = NY; g.nz = NZ;
     g.lam_x = GX.lam; g.lam_y = GY.lam;
     g.zlo = zlo; g.zdiag = zdiag; g.zup = zup; g.zsig = zsig;
-    g.dense_in = 0;
     g.out = w_gspec; g.out_r = (int64_t)NX * NY * NZ;
-    g.nxt = nsx; g.nyt = nsy;
-    for (int i = 0; i < nsx; ++i) {
-      g.colx[i] = GX.fwd + sepx[i]; g.colx_stride[i] = NX;        // W_x^{-1}[a][s_i]
-      g.gx[i] = w_Rx + (int64_t)i * NZ * NY;
-    }
-    for (int j = 0; j < nsy; ++j) {
-      g.coly[j] = GY.fwd + sepy[j]; g.coly_stride[j] = NY;
-      g.gy[j] = w_Ry + (int64_t)j * NZ * NX;
-    }
     g.gx_r = (int64_t)nsx * NZ * NY; g.gy_r = (int64_t)nsy * NZ * NX;
     g.gx_z = NY; g.gy_z = NX;
+    ex = ExpandDesc{};
+    if (!dense_glob) {
+      // the separator lines enter the z solve as low-rank terms
+      g.dense_in = 0;
+      g.nxt = nsx; g.nyt = nsy;
+      for (int i = 0; i < nsx; ++i) {
+        g.colx[i] = GX.fwd + sepx[i]; g.colx_stride[i] = NX;        // W_x^{-1}[a][s_i]
+        g.gx[i] = w_Rx + (int64_t)i * NZ * NY;
+      }
+      for (int j = 0; j < nsy; ++j) {
+        g.coly[j] = GY.fwd + sepy[j]; g.coly_stride[j] = NY;
+        g.gy[j] = w_Ry + (int64_t)j * NZ * NX;
+      }
+    } else {
+      // expanded first into a dense spectral right-hand side, solved in place
+      ex.na = NX; ex.nb = NY; ex.nz = NZ; ex.nxt = nsx; ex.nyt = nsy;
+      ex.cx = ex_cx; ex.cy = ex_cy;
+      ex.gx = w_Rx; ex.gx_t = (int64_t)NZ * NY; ex.gx_r = g.gx_r; ex.gx_z = NY;
+      ex.gy = w_Ry; ex.gy_t = (int64_t)NZ * NX; ex.gy_r = g.gy_r; ex.gy_z = NX;
+      ex.out = w_gspec; ex.out_r = g.out_r;
+      g.dense_in = 1;
+      g.data = w_gspec; g.data_r = g.out_r;
+      g.nxt = 0; g.nyt = 0;
+    }
     d_sweepG.push_back(g);
-    // w~ contracted with the rows of W at the separators: Q_x[s](b) = sum_a W_x[s][a] w~(a,b)
-    if (nsx + nsy > 0) {
+    // w~ contracted with the rows of W at the separators: Q_x[s](b) = sum_a W_x[s][a] w~(a,b),
+    // kMaxTerms separators of each axis per descriptor
+    int64_t part_off = w_cpart;
+    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms) {
       ContractDesc c{};
-      c.na = NX; c.nb = NY; c.nz = NZ; c.nxt = nsx; c.nyt = nsy;
+      c.na = NX; c.nb = NY; c.nz = NZ;
+      c.nxt = std::clamp(nsx - g0, 0, kMaxTerms);
+      c.nyt = std::clamp(nsy - g0, 0, kMaxTerms);
       c.src = w_gspec; c.src_r = g.out_r;
-      for (int i = 0; i < nsx; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[i] * NX; c.cx_stride[i] = 1; }
-      for (int j = 0; j < nsy; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[j] * NY; c.cy_stride[j] = 1; }
-      c.dx = w_Qx; c.dx_t = (int64_t)NZ * NY; c.dx_r = (int64_t)nsx * NZ * NY; c.dx_z = NY;
-      c.dy = w_Qy; c.dy_t = (int64_t)NZ * NX; c.dy_r = (int64_t)nsy * NZ * NX; c.dy_z = NX;
+      for (int i = 0; i < c.nxt; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[g0 + i] * NX; c.cx_stride[i] = 1; }
+      for (int j = 0; j < c.nyt; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[g0 + j] * NY; c.cy_stride[j] = 1; }
+      c.dx_t = (int64_t)NZ * NY; c.dx_r = (int64_t)nsx * NZ * NY; c.dx_z = NY;
+      c.dx = w_Qx + (c.nxt > 0 ? g0 * c.dx_t : 0);
+      c.dy_t = (int64_t)NZ * NX; c.dy_r = (int64_t)nsy * NZ * NX; c.dy_z = NX;
+      c.dy = w_Qy + (c.nyt > 0 ? g0 * c.dy_t : 0);
       contract_split(c);
-      set_part(c, w_cpart);
+      set_part(c, part_off);
+      part_off += (c.nslab > 1 ? max_rhs * c.part_r : 0) + (c.ncs > 1 ? max_rhs * c.xpart_r : 0);
       d_sig.push_back(c);
     }
     sg.NX = NX; sg.NY = NY; sg.nz = NZ; sg.nsx = nsx; sg.nsy = nsy; sg.NF = NF;
@@ -1060,7 +1095,14 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
     run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, dtab16, W, W, nrhs, st);
     stage_end();
-    stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
+    if (dense_glob) {
+      stage_begin("sigma_expand", R * (nsig + nglob) * esz, R * nglob * 8 * (nsx + nsy), st);
+      expand(prec, ex, T, W, nrhs, st);
+      stage_end();
+      stage_begin("zsweep_global", R * 2 * nglob * esz, R * nglob * thomas, st);
+    } else {
+      stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
+    }
     sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
           sel(3), &side, tune_full ? NZ : 0);
     stage_end();

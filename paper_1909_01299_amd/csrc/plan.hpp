@@ -94,10 +94,12 @@ struct Plan {
   std::vector<Block> blocks;
   int nbx_blocks = 1, nby_blocks = 1;
   bool decomposed = false;
+  bool dense_glob = false;        // more than kMaxTerms separators on an axis: dense global right-hand side
   std::vector<cd> htab;          // host FP64 table image
   std::vector<_Float16> h16;     // complex64 path: split-fp16 fragment image (8 halves per unit)
   int64_t zlo = 0, zdiag = 0, zup = 0, zsig = 0;
   int64_t cx_lo = 0, cx_hi = 0, cy_lo = 0, cy_hi = 0;
+  int64_t ex_cx = 0, ex_cy = 0;  // dense_glob: W_x^{-1}[a][s_i] as [i][a], W_y^{-1}[b][t_j] as [j][b]
   std::vector<int64_t> lift_cf;  // per block 4 coefficient offsets
   void* dtab64 = nullptr;
   void* dtab32 = nullptr;
@@ -133,6 +135,7 @@ struct Plan {
   int64_t w_rx = 0, w_ry = 0, w_Rx = 0, w_Ry = 0, w_Qx = 0, w_Qy = 0, w_wx = 0, w_wy = 0;
   int64_t w_gspec = 0;           // global spectral solution w~ of the interface solve
   int64_t w_cpart = 0;           // slab partial sums of the interface contraction (split plane only)
+  ExpandDesc ex{};               // dense_glob: dense spectral right-hand side of the global solve
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;

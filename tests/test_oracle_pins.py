@@ -260,6 +260,18 @@ def test_seven_step_matches_sparse_lu(cfg):
     assert np.allclose(inter["w_sigma"][:, on], ref[:, on] - inter["v"][:, on], atol=1e-12)
 
 
+def test_seven_step_gridding_b_matches_sparse_lu():
+    """About sqrt(n) x sqrt(n) blocks on general non-uniform x and y steps
+    with stretched ends (the second gridding of Sec. 2): 5 x 4 separators."""
+    rng = _rng(19)
+    p = W.gridding_b_problem(36, 25, 5, 3, rng, pml=3)
+    assert len(p.sep_x) == 5 and len(p.sep_y) == 4
+    assert len(np.unique(np.diff(np.concatenate([[-1], p.sep_x, [p.nx]])))) <= 2
+    f = W.complex_normal(rng, (2,) + p.shape)
+    u, _ = cyclic.seven_step(p, f)
+    assert operator.rel_err(u, direct.solve_splu(p, f)) < 1e-12
+
+
 def test_block_ranges():
     assert cyclic.block_ranges(10, []) == [(0, 9)]
     assert cyclic.block_ranges(10, [3, 6]) == [(0, 2), (4, 5), (7, 9)]

@@ -150,6 +150,36 @@ def stretched_ends_steps(n: int, p: int, ratio: float = 1.2,
     return h
 
 
+def graded_steps(n: int, rng: np.random.Generator, spread: float = 0.4, pml: int = 0,
+                 ratio: float = 1.2, stretch: complex = 1 + 0.5j) -> np.ndarray:
+    """n interior nodes on a general non-uniform grid: real steps
+    exp(spread * s_k) with s a random sequence smoothed over five steps, so
+    that no two blocks of a split share a step vector; the outermost ``pml``
+    steps at each end are then stretched as in ``stretched_ends_steps``."""
+    s = rng.standard_normal(n + 5)
+    s = np.convolve(s, np.ones(5) / np.sqrt(5.0), mode="valid")[: n + 1]
+    h = np.exp(spread * s).astype(np.complex128)
+    for k in range(1, pml + 1):
+        h[pml - k] *= ratio ** k * stretch
+        h[n - pml + k] *= ratio ** k * stretch
+    return h
+
+
+def gridding_b_separators(n: int) -> np.ndarray:
+    """Separators of an axis of n interior nodes split into about sqrt(n)
+    blocks of about sqrt(n) nodes each (the second gridding of Sec. 2):
+    round(sqrt(n)) - 1 separators, the remaining nodes shared out evenly,
+    larger blocks first."""
+    nsep = max(int(round(np.sqrt(n))) - 1, 0)
+    nodes, nblk = n - nsep, nsep + 1
+    sizes = [nodes // nblk + (1 if i < nodes % nblk else 0) for i in range(nblk)]
+    seps, pos = [], -1
+    for i in range(nsep):
+        pos += sizes[i] + 1
+        seps.append(pos)
+    return np.asarray(seps, np.int32)
+
+
 def layer_map(nz: int, nlayers: int) -> np.ndarray:
     """layer(k) = floor(k * L / nz) for 0-based z node k."""
     k = np.arange(nz, dtype=np.int64)
@@ -243,6 +273,20 @@ def random_problem(nx: int, ny: int, nz: int, nlayers: int, rng: np.random.Gener
     k2 = draw_k2(rng, nlayers)
     return Problem(hx, hy, hz, layer_map(nz, nlayers), k2,
                    np.asarray(sep_x, np.int32), np.asarray(sep_y, np.int32), name=name)
+
+
+def gridding_b_problem(nx: int, ny: int, nz: int, nlayers: int, rng: np.random.Generator,
+                       pml: int = 0, spread: float = 0.4, name: str = "") -> Problem:
+    """General non-uniform x and y steps (``graded_steps``, stretched ends of
+    ``pml`` steps) split into about sqrt(n) x sqrt(n) blocks of about sqrt(n)
+    nodes per side (``gridding_b_separators``); random real z steps in
+    [0.7, 1.3] and layer k^2 as in ``random_problem``."""
+    hx = graded_steps(nx, rng, spread, pml)
+    hy = graded_steps(ny, rng, spread, pml)
+    hz = rng.uniform(0.7, 1.3, size=nz + 1)
+    k2 = draw_k2(rng, nlayers)
+    return Problem(hx, hy, hz, layer_map(nz, nlayers), k2,
+                   gridding_b_separators(nx), gridding_b_separators(ny), name=name)
 
 
 # ----------------------------------------------------------------------------
