@@ -113,7 +113,9 @@ struct DstDesc {
 //  rhs(a,b,z,r) = [dense_in ? data(r,z,b,a) : 0]
 //               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)
 //  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) diag sigma) x = rhs,   out(r,z,b,a) = x
-// element (r,z,b,a) of data / out sits at base + r*_r + (z*nb + b)*na + a.
+// element (r,z,b,a) of data / out sits at base + r*_r + z*plane + b*na + a
+// (plane >= na*nb: z planes may be padded so that mode tiles start on whole
+// cache lines).
 constexpr int kMaxTerms = 4;
 constexpr int kMaxRefine = 16;   // refinement steps of the complex64 path
 struct SweepDesc {
@@ -130,9 +132,10 @@ struct SweepDesc {
   int64_t coly[kMaxTerms]; int32_t coly_stride[kMaxTerms];
   int64_t gy[kMaxTerms];
   int64_t gx_r, gy_r, gx_z, gy_z;   // gx(r,z,b) = gx + r*gx_r + z*gx_z + b
+  int64_t plane;                    // z-plane stride of data and out
 };
 
-// Contraction of a spectral array X(r,z,b,a) = src + r*src_r + (z*nb + b)*na + a
+// Contraction of a spectral array X(r,z,b,a) = src + r*src_r + z*plane + b*na + a
 // along both axes in one read, with up to kMaxTerms coefficient vectors each:
 //   out_x,t(r,z,b) = sum_a cx_t[a] X(r,z,b,a)   at dx + t*dx_t + r*dx_r + z*dx_z + b
 //   out_y,t(r,z,a) = sum_b cy_t[b] X(r,z,b,a)   at dy + t*dy_t + r*dy_r + z*dy_z + a
@@ -152,19 +155,20 @@ struct ContractDesc {
   int64_t dy, dy_t, dy_r, dy_z;
   int64_t part, part_s, part_t, part_r, part_z;
   int64_t xpart, xpart_s, xpart_t, xpart_r, xpart_z;
+  int64_t plane;                  // z-plane stride of X (>= na*nb)
 };
 
 // Dense spectral right-hand side of the global interface solve, for
 // separator counts above kMaxTerms (too many to add inside the z solve):
 //   out(r,z,b,a) = sum_i cx[i*na + a] gx_i(r,z,b) + sum_j cy[j*nb + b] gy_j(r,z,a)
 // with gx_i(r,z,b) at gx + r*gx_r + i*gx_t + z*gx_z + b (gy_j likewise with a),
-// out(r,z,b,a) at out + r*out_r + (z*nb + b)*na + a; cx, cy are table offsets.
+// out(r,z,b,a) at out + r*out_r + z*plane + b*na + a; cx, cy are table offsets.
 struct ExpandDesc {
   int32_t na, nb, nz, nxt, nyt, pad_;
   int64_t cx, cy;
   int64_t gx, gx_t, gx_r, gx_z;
   int64_t gy, gy_t, gy_r, gy_z;
-  int64_t out, out_r;
+  int64_t out, out_r, plane;
 };
 
 }  // namespace hs

@@ -408,7 +408,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   using CS = cplx<RS>;
   using Q = typename quad_of<R>::type;
   const int na = d.na, nb = d.nb, nz = d.nz;
-  const int64_t plane = (int64_t)na * nb;
+  const int64_t plane = d.plane;
   const int Lc = FULL ? L : psweep_rows(nz, P);
   const int nzp = P * Lc;
   Q* zt = reinterpret_cast<Q*>(smem_raw);   // (dg.x, dg.y, lo, up) per z, padded to nzp rows
@@ -777,7 +777,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   for (int s = 0; s < SMAX; ++s)
 #pragma unroll
     for (int t = 0; t < kMaxTerms; ++t) yacc[s][t] = mk<R>(0, 0);
-  const C* xp = ws + d.src + (int64_t)r * d.src_r + ((int64_t)z * d.nb + b0) * d.na + c0;
+  const C* xp = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.plane + (int64_t)b0 * d.na + c0;
   int col[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) col[s] = min(la + s * L, na - 1);
@@ -947,7 +947,7 @@ __global__ __launch_bounds__(256) void k_expand(ExpandDesc e, const cplx<R>* __r
   const bool aok = a0 + lane < e.na;
   const C* gx = ws + e.gx + (int64_t)r * e.gx_r + (int64_t)z * e.gx_z;
   const C* gy = ws + e.gy + (int64_t)r * e.gy_r + (int64_t)z * e.gy_z;
-  C* out = ws + e.out + (int64_t)r * e.out_r + (int64_t)z * e.na * e.nb;
+  C* out = ws + e.out + (int64_t)r * e.out_r + (int64_t)z * e.plane;
   const int nch = (max(e.nxt, e.nyt) + TC - 1) / TC;
   for (int ch = 0; ch < nch; ++ch) {
     const int t0 = ch * TC;

@@ -117,6 +117,17 @@ int xform_y_tiles(const XformYDesc& d, int ct);
 // z solves: LDS of one workgroup (z tables + chunk-end exchange), and the
 // batched launch over descriptors (max_modes = largest sweep_modes_bound(na, nb)).
 size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms);
+// z-plane stride of a spectral array of n = na*nb modes: planes of 1024
+// modes or more are padded to an odd multiple of 16 elements, so that the z
+// solves' tiles of 16 consecutive modes start on whole 128-byte lines in both
+// precisions and consecutive planes do not map to one memory channel; smaller
+// planes stay dense (their padding would cost more than it saves).
+inline int64_t spectral_plane(int64_t n) {
+  if (n < 1024) return n;
+  int64_t q = (n + 15) / 16;
+  if ((q & 1) == 0) ++q;
+  return 16 * q;
+}
 constexpr int kMaxNz = 512;    // 32 chunks of 16 rows; keeps the LDS within 64 KiB
 // chunks: z-line chunks per mode (8, 16 or 32, each at most 16 rows; 256 / chunks
 // modes per workgroup); 0 or an unusable value = default for max_nz

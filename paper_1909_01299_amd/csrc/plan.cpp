@@ -442,9 +442,10 @@ void Plan::layout_workspace() {
   };
   NF = 0;
   for (auto& B : blocks) NF = std::max(NF, std::max(B.nbx, B.nby));
-  for (auto& B : blocks) B.spec = take(R * NZ * B.nbx * B.nby);
+  for (auto& B : blocks) B.pplane = spectral_plane((int64_t)B.nbx * B.nby);
+  for (auto& B : blocks) B.spec = take(R * NZ * B.pplane);
   if (decomposed) {
-    for (auto& B : blocks) B.vt = take(R * NZ * B.nbx * B.nby);
+    for (auto& B : blocks) B.vt = take(R * NZ * B.pplane);
     // slab partial sums of contractions over planes too large for one workgroup
     auto part_elems = [&](int na, int nb, int nxt, int nyt) -> int64_t {
       ContractDesc c{};
@@ -466,7 +467,8 @@ void Plan::layout_workspace() {
     const int64_t lx = R * nsx * NZ * (int64_t)NY, ly = R * nsy * NZ * (int64_t)NX;
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
-    w_gspec = take(R * NZ * (int64_t)NX * NY);
+    gpplane = spectral_plane((int64_t)NX * NY);
+    w_gspec = take(R * NZ * gpplane);
     // the interface contraction in groups of kMaxTerms separators per axis
     int64_t np = 0;
     for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms)
@@ -528,7 +530,7 @@ void Plan::build_descriptors() {
     const Block& B = blocks[bi];
     const Axis& AX = axes[B.ax];
     const Axis& AY = axes[B.ay];
-    const int64_t plane = (int64_t)B.nbx * B.nby;
+    const int64_t plane = B.pplane;
     const int64_t spec_r = plane * NZ;
     auto vidx = [](int V) { return ilog2i(V); };
     if (AX.dstV) {
@@ -577,6 +579,7 @@ void Plan::build_descriptors() {
     s.zlo = zlo; s.zdiag = zdiag; s.zup = zup; s.zsig = zsig;
     s.data = B.spec; s.data_r = spec_r;
     s.out = B.spec; s.out_r = spec_r;
+    s.plane = plane;
     s.dense_in = 1;
     if (!decomposed) {
       d_sweep.push_back(s);
@@ -589,7 +592,7 @@ void Plan::build_descriptors() {
     const int64_t fbase = w_face + (int64_t)bi * R * 4 * face_f;
     ContractDesc c{};
     c.na = B.nbx; c.nb = B.nby; c.nz = NZ; c.nxt = 2; c.nyt = 2;
-    c.src = B.vt; c.src_r = spec_r;
+    c.src = B.vt; c.src_r = spec_r; c.plane = plane;
     c.cx[0] = AX.inv; c.cx_stride[0] = 1;                                // W_x[0][a]
     c.cx[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; c.cx_stride[1] = 1;  // W_x[n-1][a]
     c.cy[0] = AY.inv; c.cy_stride[0] = 1;                                // W_y[0][b]
@@ -670,7 +673,7 @@ void Plan::build_descriptors() {
     g.na = NX; g.nb = NY; g.nz = NZ;
     g.lam_x = GX.lam; g.lam_y = GY.lam;
     g.zlo = zlo; g.zdiag = zdiag; g.zup = zup; g.zsig = zsig;
-    g.out = w_gspec; g.out_r = (int64_t)NX * NY * NZ;
+    g.out = w_gspec; g.out_r = gpplane * NZ; g.plane = gpplane;
     g.gx_r = (int64_t)nsx * NZ * NY; g.gy_r = (int64_t)nsy * NZ * NX;
     g.gx_z = NY; g.gy_z = NX;
     ex = ExpandDesc{};
@@ -692,7 +695,7 @@ void Plan::build_descriptors() {
       ex.cx = ex_cx; ex.cy = ex_cy;
       ex.gx = w_Rx; ex.gx_t = (int64_t)NZ * NY; ex.gx_r = g.gx_r; ex.gx_z = NY;
       ex.gy = w_Ry; ex.gy_t = (int64_t)NZ * NX; ex.gy_r = g.gy_r; ex.gy_z = NX;
-      ex.out = w_gspec; ex.out_r = g.out_r;
+      ex.out = w_gspec; ex.out_r = g.out_r; ex.plane = gpplane;
       g.dense_in = 1;
       g.data = w_gspec; g.data_r = g.out_r;
       g.nxt = 0; g.nyt = 0;
@@ -706,7 +709,7 @@ void Plan::build_descriptors() {
       c.na = NX; c.nb = NY; c.nz = NZ;
       c.nxt = std::clamp(nsx - g0, 0, kMaxTerms);
       c.nyt = std::clamp(nsy - g0, 0, kMaxTerms);
-      c.src = w_gspec; c.src_r = g.out_r;
+      c.src = w_gspec; c.src_r = g.out_r; c.plane = gpplane;
       for (int i = 0; i < c.nxt; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[g0 + i] * NX; c.cx_stride[i] = 1; }
       for (int j = 0; j < c.nyt; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[g0 + j] * NY; c.cy_stride[j] = 1; }
       c.dx_t = (int64_t)NZ * NY; c.dx_r = (int64_t)nsx * NZ * NY; c.dx_z = NY;
