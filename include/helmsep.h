@@ -139,6 +139,10 @@ typedef struct {
   int32_t sine_lines;       /* sine-transform lines per workgroup (0 = default) */
   int32_t z_fixed_rows;     /* 1: z solves in instances with a fixed row count
                                per chunk (chosen by hs_plan_tune)            */
+  int32_t global_dense;     /* decomposed grids: 1 when the global interface
+                               solve's right-hand side is expanded densely
+                               before its z solve, 0 when its separator lines
+                               enter the z solve as low-rank terms          */
   int32_t n_split_fp16;     /* HS_C64_REFINE: axes whose dense tables run on fp16
                                matrix cores as two-term splits (n <= 256, or
                                n <= 512 for real sine tables)                */
@@ -174,8 +178,9 @@ size_t hs_plan_workspace_bytes(hs_plan plan, int32_t nrhs);
  * max_rhs) bytes, 256-byte aligned.  The plan keeps the pointer, not a copy. */
 hs_status hs_plan_bind_workspace(hs_plan plan, void* dev_ptr, size_t bytes);
 
-/* Replace the layer values k^2 (2*nlayers host doubles).  Rebuilds the z
- * tables and re-scans the pivots; synchronous. */
+/* Replace the layer values k^2 (2*nlayers host doubles).  Waits for all work
+ * on the device (solves in flight read the tables), rebuilds the z tables and
+ * re-scans the pivots; synchronous. */
 hs_status hs_set_k2(hs_plan plan, const double* k2);
 
 /* u = A^{-1} f for nrhs right-hand sides (Sec. 2, the seven-step algorithm,
@@ -229,9 +234,11 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
 
 /* Autotune the plan's launch shapes for nrhs right-hand sides: every usable
  * combination of z-line chunks per mode in {8, 16, 32}, sine-transform lines
- * per workgroup in {4, 8, 16} and (where nz fills the chunks exactly) z-solve
- * instances with a fixed row count per chunk or not is timed with hipEvents on `stream` over 3 solves
- * of scratch data and the fastest is kept in the plan.  cache_path (may be
+ * per workgroup in {4, 8, 16}, (where nz fills the chunks exactly) z-solve
+ * instances with a fixed row count per chunk or not, and (decomposed grids
+ * with at most 4 separators per axis) the global right-hand side expanded
+ * densely or as low-rank terms is timed with hipEvents on `stream` over 3
+ * solves of scratch data and the fastest is kept in the plan.  cache_path (may be
  * NULL) names a JSON-lines file keyed by device architecture and plan shape:
  * a hit skips the timing, a miss appends the result.  Needs a bound workspace;
  * allocates and frees two scratch arrays; synchronizes the stream. */
@@ -240,10 +247,15 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
 /* Set the launch shapes directly (as hs_plan_tune would store them), e.g. to
  * reuse one plan's tuning on another plan of the same shapes: z_chunks in
  * {0 (default for nz), 8, 16, 32}, sine_lines in {0 (default), 4, 8, 16},
- * z_fixed_rows in {0, 1} (1 is used only where nz fills the chunks exactly).
- * HS_ERR_ARG for a value outside these sets or one the plan cannot use (a z
- * chunking that cannot hold nz, sine lines whose LDS does not fit). */
-hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows);
+ * z_fixed_rows in {0, 1} (1 is used only where nz fills the chunks exactly),
+ * global_dense in {-1 (keep), 0, 1} (ignored on a single block; 0 is refused
+ * where more than 4 separators on an axis, or flag bit 3, require the dense
+ * expansion).  Changing global_dense waits for the device and rewrites the
+ * plan's descriptors.  HS_ERR_ARG for a value outside these sets or one the
+ * plan cannot use (a z chunking that cannot hold nz, sine lines whose LDS
+ * does not fit). */
+hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows,
+                             int32_t global_dense);
 
 /* Per-stage timing.  While enabled, every stage of a solve is bracketed by
  * hipEvents recorded on the solve's stream (events come from a pool created

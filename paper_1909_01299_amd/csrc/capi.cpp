@@ -142,6 +142,7 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   info->z_chunks = hs::sweep_chunks_ok(p.tune_chunks, p.NZ) ? p.tune_chunks : hs::sweep_default_chunks(p.NZ);
   info->sine_lines = p.tune_lt;
   info->z_fixed_rows = p.tune_full;
+  info->global_dense = p.dense_glob ? 1 : 0;
   for (auto& a : p.axes)
     if (a.hfwd >= 0) ++info->n_split_fp16;
   info->tol = p.tol;
@@ -194,7 +195,8 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
   return ret(plan->p.tune(nrhs, cache_path, (hipStream_t)stream, err), err);
 }
 
-hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows) {
+hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows,
+                             int32_t global_dense) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
   hs::Plan& p = plan->p;
   if (z_chunks != 0 && !hs::sweep_chunks_ok(z_chunks, p.NZ)) return ret(HS_ERR_ARG, "z chunking cannot hold nz");
@@ -205,6 +207,14 @@ hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines,
     if (sine_lines != 4 && sine_lines != 8 && sine_lines != 16) return ret(HS_ERR_ARG, "sine lines not in {4, 8, 16}");
   }
   if (z_fixed_rows != 0 && z_fixed_rows != 1) return ret(HS_ERR_ARG, "z_fixed_rows not in {0, 1}");
+  if (global_dense < -1 || global_dense > 1) return ret(HS_ERR_ARG, "global_dense not in {-1, 0, 1}");
+  if (global_dense == 0 && p.decomposed && p.glob_forced)
+    return ret(HS_ERR_ARG, "more than 4 separators on an axis (or flag bit 3): the global right-hand side is dense");
+  if (global_dense >= 0) {
+    std::string err;
+    const hs_status st = p.set_global_dense(global_dense == 1, err);
+    if (st != HS_OK) return ret(st, err);
+  }
   p.tune_chunks = z_chunks;
   p.tune_lt = sine_lines;
   p.tune_full = z_fixed_rows;

@@ -136,7 +136,8 @@ hs_status Plan::build(const hs_grid* g, const hs_blocks* b, const hs_options* o,
     }
   }
   decomposed = !sepx.empty() || !sepy.empty();
-  dense_glob = (int)sepx.size() > kMaxTerms || (int)sepy.size() > kMaxTerms || (flags & 8) != 0;
+  glob_forced = (int)sepx.size() > kMaxTerms || (int)sepy.size() > kMaxTerms || (flags & 8) != 0;
+  dense_glob = glob_forced;
   for (auto& rx : runs(NX, sepx)) max_block_n = std::max(max_block_n, rx.second - rx.first + 1);
   for (auto& ry : runs(NY, sepy)) max_block_n = std::max(max_block_n, ry.second - ry.first + 1);
   if (max_block_n > 512) { err = "block side > 512 is not supported; add separators"; return HS_ERR_ARG; }
@@ -303,9 +304,9 @@ hs_status Plan::build_tables(std::string& err) {
   c.clear();
   for (int t : sepy) c.push_back(1.0 / (0.5 * (hy[t] + hy[t + 1]) * hy[t + 1]));
   cy_hi = push(c);
-  // many separators: the columns of W^{-1} at the separators, one contiguous
-  // vector per separator, expanded into a dense global right-hand side
-  if (decomposed && dense_glob) {
+  // the columns of W^{-1} at the separators, one contiguous vector per
+  // separator, for the dense expansion of the global right-hand side
+  if (decomposed) {
     const Axis& GX = axes[gax];
     const Axis& GY = axes[gay];
     c.assign(sepx.size() * size_t(NX), cd(0, 0));
@@ -869,8 +870,24 @@ int64_t Plan::sweep_modes(const std::vector<SweepDesc>& v) {
   return m;
 }
 
+hs_status Plan::set_global_dense(bool dense, std::string& err) {
+  if (!decomposed || dense == dense_glob) return HS_OK;
+  if (!dense && glob_forced) {
+    err = "more than 4 separators on an axis (or flag bit 3): the global right-hand side is expanded densely";
+    return HS_ERR_ARG;
+  }
+  // solves in flight read the descriptors being replaced
+  if (hipDeviceSynchronize() != hipSuccess) { err = "hipDeviceSynchronize failed"; return HS_ERR_DEVICE; }
+  dense_glob = dense;
+  build_descriptors();
+  set_fp64_threshold();
+  return upload_descs(err);
+}
+
 hs_status Plan::set_k2(const double* k2v, std::string& err) {
   if (!k2v) { err = "k2 is NULL"; return HS_ERR_ARG; }
+  // solves in flight read the tables and descriptors being replaced
+  if (hipDeviceSynchronize() != hipSuccess) { err = "hipDeviceSynchronize failed"; return HS_ERR_DEVICE; }
   std::vector<cd> old = k2;
   for (int l = 0; l < nlayers; ++l) {
     k2[l] = cd(k2v[2 * l], k2v[2 * l + 1]);
@@ -1302,17 +1319,18 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
     while (std::getline(in, line)) {
       const std::string tag = "\"key\": \"" + k + "\"";
       if (line.find(tag) == std::string::npos) continue;
-      int c = 0, l = 0, fr = 0;
+      int c = 0, l = 0, fr = 0, gd = dense_glob ? 1 : 0;
       const size_t pc = line.find("\"chunks\": "), pl = line.find("\"lines\": "),
-                   pf = line.find("\"fixed_rows\": ");
+                   pf = line.find("\"fixed_rows\": "), pg = line.find("\"global_dense\": ");
       if (pc != std::string::npos && pl != std::string::npos) {
         c = std::atoi(line.c_str() + pc + 10);
         l = std::atoi(line.c_str() + pl + 9);
         if (pf != std::string::npos) fr = std::atoi(line.c_str() + pf + 14);
+        if (pg != std::string::npos) gd = std::atoi(line.c_str() + pg + 16);
         tune_chunks = c;
         tune_lt = l;
         tune_full = fr;
-        return HS_OK;
+        return set_global_dense(gd != 0 || glob_forced, err);
       }
     }
   }
@@ -1341,37 +1359,47 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   float best = 1e30f;
-  int bc = 0, bl = 0, bf = 0;
+  int bc = 0, bl = 0, bf = 0, bg = dense_glob ? 1 : 0;
   const bool was_on = prof_on;
   prof_on = false;
-  for (int c : chunks)
-    for (int l : lts)
-      for (int fr = 0; fr < (sweep_rows_fixed(c, NZ) ? 2 : 1); ++fr) {
-        tune_chunks = c;
-        tune_lt = l;
-        tune_full = fr;
-        std::string e2;
-        if (solve(f, u, nrhs, st, e2) != HS_OK) continue;
-        (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 3; ++rep) (void)solve(f, u, nrhs, st, e2);
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; bc = c; bl = l; bf = fr; }
-      }
+  // the global right-hand side's form: both where the separators allow it
+  std::vector<int> gds;
+  if (decomposed && !glob_forced) gds = {0, 1};
+  else gds = {dense_glob ? 1 : 0};
+  hs_status gst = HS_OK;
+  for (int gd : gds) {
+    if ((gst = set_global_dense(gd != 0, err)) != HS_OK) break;
+    for (int c : chunks)
+      for (int l : lts)
+        for (int fr = 0; fr < (sweep_rows_fixed(c, NZ) ? 2 : 1); ++fr) {
+          tune_chunks = c;
+          tune_lt = l;
+          tune_full = fr;
+          std::string e2;
+          if (solve(f, u, nrhs, st, e2) != HS_OK) continue;
+          (void)hipEventRecord(e0, st);
+          for (int rep = 0; rep < 3; ++rep) (void)solve(f, u, nrhs, st, e2);
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) { best = ms; bc = c; bl = l; bf = fr; bg = gd; }
+        }
+  }
   prof_on = was_on;
   tune_chunks = bc;
   tune_lt = bl;
   tune_full = bf;
+  if (gst == HS_OK) gst = set_global_dense(bg != 0, err);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(f);
   (void)hipFree(u);
+  if (gst != HS_OK) return gst;
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl << ", \"fixed_rows\": " << bf
-        << ", \"ms_per_solve\": " << best / 3 << "}\n";
+        << ", \"global_dense\": " << bg << ", \"ms_per_solve\": " << best / 3 << "}\n";
   }
   return HS_OK;
 }

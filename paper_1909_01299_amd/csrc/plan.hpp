@@ -95,7 +95,8 @@ struct Plan {
   std::vector<Block> blocks;
   int nbx_blocks = 1, nby_blocks = 1;
   bool decomposed = false;
-  bool dense_glob = false;        // more than kMaxTerms separators on an axis: dense global right-hand side
+  bool dense_glob = false;        // the global right-hand side is expanded densely (else low-rank terms in the z solve)
+  bool glob_forced = false;       // dense expansion required: more than kMaxTerms separators on an axis, or flag bit 3
   std::vector<cd> htab;          // host FP64 table image
   std::vector<_Float16> h16;     // complex64 path: split-fp16 fragment image (8 halves per unit)
   int64_t zlo = 0, zdiag = 0, zup = 0, zsig = 0;
@@ -191,6 +192,9 @@ struct Plan {
   hs_status residual(const void* f, const void* u, void* r, int apply_only, int nrhs, hipStream_t st,
                      std::string& err);
   hs_status tune(int nrhs, const char* cache_path, hipStream_t st, std::string& err);
+  // form of the global interface solve's right-hand side (decomposed grids):
+  // dense expansion or low-rank terms; waits for the device, rebuilds descriptors
+  hs_status set_global_dense(bool dense, std::string& err);
   // relative residuals of the last solve, [eval][r] (synchronous copy)
   hs_status residuals(std::vector<double>& rel, int& evals, int& nrhs, std::string& err) const;
 

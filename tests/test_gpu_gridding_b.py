@@ -4,7 +4,7 @@ general non-uniform x and y steps with stretched ends, against the oracle in
 both precisions.  With more than 4 separators on an axis the right-hand side
 of the global interface solve is expanded densely before the z solve; the
 tests cover ragged column and row tiles of that expansion, more than one
-chunk of 16 separators, axes whose counts differ (groups of the interface
+chunk of 8 separators, axes whose counts differ (groups of the interface
 contraction with no terms on one axis), the forced dense path against the
 low-rank one, the adjoint and the layer gradient."""
 import numpy as np
@@ -41,7 +41,7 @@ def solve(hs, p, f, prec, **kw):
 @pytest.mark.parametrize("cfg", [
     dict(nx=64, ny=49, nz=40, pml=5),     # 7 x 6 separators, blocks of 7-8 nodes
     dict(nx=100, ny=16, nz=33, pml=4),    # 9 x 3: the later contraction groups hold x terms only
-    dict(nx=20, ny=324, nz=10, pml=3),    # 3 x 17: two chunks of y terms in the expansion
+    dict(nx=20, ny=324, nz=10, pml=3),    # 3 x 17: three chunks of y terms in the expansion
 ])
 def test_gridding_b_vs_oracle(hs, prec, tol, cfg):
     rng = np.random.default_rng(cfg["nx"] * 7 + cfg["ny"])
@@ -108,3 +108,36 @@ def test_gridding_b_adjoint_and_gradient(hs):
     gk = plan.grad_k2(u, lam).cpu().numpy()[0]
     torch.cuda.synchronize()
     assert np.abs(gk - g_ref).max() < 1e-8 * np.abs(g_ref).max()
+
+
+def test_global_form_as_launch_shape(hs, tmp_path):
+    """With at most 4 separators per axis the global right-hand side's form is
+    a launch shape: both forms agree with each other and the oracle, the tuner
+    picks one and caches it, and a grid with more separators refuses the
+    low-rank form."""
+    import torch
+    p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=24, nlayers=4)
+    plan = hs.Plan(p, "c128")
+    assert plan.info()["global_dense"] == 0
+    u_lr = plan.solve(dev(f)).cpu().numpy()
+    plan.set_launch({"z_chunks": 0, "sine_lines": 0, "z_fixed_rows": 0, "global_dense": 1})
+    assert plan.info()["global_dense"] == 1
+    u_dn = plan.solve(dev(f)).cpu().numpy()
+    check(u_dn, u_lr, 1e-12)
+    check(u_dn, separable.solve(p, f), TOL128, p)
+    cache = str(tmp_path / "tune.jsonl")
+    shapes = plan.tune(1, cache=cache)
+    assert shapes["global_dense"] in (0, 1)
+    assert '"global_dense": ' in open(cache).read()
+    plan2 = hs.Plan(p, "c128")
+    assert plan2.tune(1, cache=cache) == shapes
+    u2 = plan2.solve(dev(f)).cpu().numpy()
+    torch.cuda.synchronize()
+    check(u2, separable.solve(p, f), TOL128, p)
+    rng = np.random.default_rng(4)
+    q = W.gridding_b_problem(36, 25, 6, 3, rng, pml=3)
+    wide = hs.Plan(q, "c128")
+    assert wide.info()["global_dense"] == 1
+    with pytest.raises(hs.HSError) as e:
+        wide.set_launch({"global_dense": 0})
+    assert e.value.status == hs.HS_ERR_ARG
