@@ -98,10 +98,10 @@ hs_status Batch::build(const std::vector<const Plan*>& ps, const std::vector<int
   for (size_t i = 0; i < plans.size(); ++i) {
     const Plan* p = plans[i];
     spec_off.push_back(off);
-    off = align_up(off + int64_t(nrhs[i]) * spectral_plane((int64_t)p->NX * p->NY) * p->NZ, 64);
+    off = align_up(off + int64_t(nrhs[i]) * p->blocks[0].pplane * p->NZ, 64);
     max_nz = std::max(max_nz, p->NZ);
     common_nz = (i == 0 || common_nz == p->NZ) ? p->NZ : -1;
-    max_modes = std::max<int64_t>(max_modes, sweep_modes_bound(p->NX, p->NY));
+    max_modes = std::max<int64_t>(max_modes, sweep_modes_bound(p->blocks[0].rs, p->NY));
   }
   ws_elems = size_t(off);
   const size_t esz = prec == 0 ? 16 : 8;
@@ -150,6 +150,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
     const int64_t plane = (int64_t)B.nbx * B.nby;    // physical arrays (f, u, residual)
     const int64_t N = plane * p->NZ;
     const int64_t splane = B.pplane;                   // spectral arrays
+    const int srs = B.rs;
     const int64_t Ns = splane * p->NZ;
     {
       ResidualItem ri{};
@@ -168,41 +169,41 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
         DstDesc dx{};
         dx.n = B.nbx; dx.P = p->NZ; dx.Q = B.nby;
         dx.src = fo; dx.src_p = plane; dx.src_q = B.nbx; dx.src_i = 1;
-        dx.dst = spec; dx.dst_p = splane; dx.dst_q = B.nbx; dx.dst_i = 1;
+        dx.dst = spec; dx.dst_p = splane; dx.dst_q = srs; dx.dst_i = 1;
         const int v = ilog2i(AX.dstV);
         s_fwdx.dst[v].push_back(dx);
         DstDesc dr = dx;
         dr.src = ro;
         s_fwdx_res.dst[v].push_back(dr);
         DstDesc ix = dx;
-        ix.src = spec; ix.src_p = splane; ix.dst = uo; ix.dst_p = plane;
+        ix.src = spec; ix.src_p = splane; ix.src_q = srs; ix.dst = uo; ix.dst_p = plane; ix.dst_q = B.nbx;
         s_invx.dst[v].push_back(ix);
       } else {
         XformDesc fx{};
         fx.tab = T0 + AX.fwd; set_frag(fx, AX, true, T0, H0); fx.n_in = fx.n_out = B.nbx; fx.P = p->NZ; fx.Q = B.nby;
         fx.src = fo; fx.src_p = plane; fx.src_q = B.nbx;
-        fx.dst = spec; fx.dst_p = splane; fx.dst_q = B.nbx;
+        fx.dst = spec; fx.dst_p = splane; fx.dst_q = srs;
         s_fwdx.dense.push_back(fx);
         XformDesc fr = fx;
         fr.src = ro;
         s_fwdx_res.dense.push_back(fr);
         XformDesc ix = fx;
         ix.tab = T0 + AX.inv; set_frag(ix, AX, false, T0, H0);
-        ix.src = spec; ix.src_p = splane; ix.dst = uo; ix.dst_p = plane;
+        ix.src = spec; ix.src_p = splane; ix.src_q = srs; ix.dst = uo; ix.dst_p = plane; ix.dst_q = B.nbx;
         s_invx.dense.push_back(ix);
       }
       if (AY.dstV) {
         DstDesc dy{};
-        dy.n = B.nby; dy.P = p->NZ; dy.Q = B.nbx;
-        dy.src = spec; dy.src_p = splane; dy.src_q = 1; dy.src_i = B.nbx;
-        dy.dst = spec; dy.dst_p = splane; dy.dst_q = 1; dy.dst_i = B.nbx;
+        dy.n = B.nby; dy.P = p->NZ; dy.Q = srs;
+        dy.src = spec; dy.src_p = splane; dy.src_q = 1; dy.src_i = srs;
+        dy.dst = spec; dy.dst_p = splane; dy.dst_q = 1; dy.dst_i = srs;
         const int v = ilog2i(AY.dstV);
         s_fwdy.dst[v].push_back(dy);
         s_invy.dst[v].push_back(dy);
       } else {
         XformYDesc fy{};
         fy.tab = T0 + AY.fwd; set_frag(fy, AY, true, T0, H0); fy.n = B.nby; fy.ncols = B.nbx; fy.P = p->NZ;
-        fy.data = spec; fy.s_p = splane; fy.s_k = B.nbx;
+        fy.data = spec; fy.s_p = splane; fy.s_k = srs;
         s_fwdy.dense.push_back(fy);
         XformYDesc iy = fy;
         iy.tab = T0 + AY.inv; set_frag(iy, AY, false, T0, H0);
@@ -212,7 +213,7 @@ hs_status Batch::rebuild(const void* const* f, void* const* u, std::string& err)
       s.na = B.nbx; s.nb = B.nby; s.nz = p->NZ; s.dense_in = 1;
       s.lam_x = T0 + AX.lam; s.lam_y = T0 + AY.lam;
       s.zlo = T0 + p->zlo; s.zdiag = T0 + p->zdiag; s.zup = T0 + p->zup; s.zsig = T0 + p->zsig;
-      s.data = spec; s.out = spec; s.plane = splane;
+      s.data = spec; s.out = spec; s.plane = splane; s.rs = srs;
       s.fp64_below = p->fp64_below;
       d_sweep.push_back(s);
     }

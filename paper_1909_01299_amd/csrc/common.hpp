@@ -113,14 +113,14 @@ struct DstDesc {
 //  rhs(a,b,z,r) = [dense_in ? data(r,z,b,a) : 0]
 //               + sum_i colx_i[a] * gx_i(r,z,b) + sum_j coly_j[b] * gy_j(r,z,a)
 //  (Dz - diag k^2 + (lam_x[a] + lam_y[b]) diag sigma) x = rhs,   out(r,z,b,a) = x
-// element (r,z,b,a) of data / out sits at base + r*_r + z*plane + b*na + a
-// (plane >= na*nb: z planes may be padded so that mode tiles start on whole
-// cache lines).
+// element (r,z,b,a) of data / out sits at base + r*_r + z*plane + b*rs + a
+// (rows and z planes may be padded, rs >= na and plane >= nb*rs, so that
+// tiles of modes start on whole cache lines).
 constexpr int kMaxTerms = 4;
 constexpr int kMaxRefine = 16;   // refinement steps of the complex64 path
 struct SweepDesc {
   int32_t na, nb, nz, dense_in;
-  int32_t nxt, nyt, pad0_, pad1_;
+  int32_t nxt, nyt, rs, pad1_;    // rs: row stride of data and out
   double fp64_below;              // complex64 path: modes with Re(lam_x + lam_y) <= this solve in FP64
   int64_t lam_x, lam_y;           // table offsets (complex, length na / nb)
   int64_t zlo, zdiag, zup;        // table offsets (complex, length nz)
@@ -135,7 +135,7 @@ struct SweepDesc {
   int64_t plane;                    // z-plane stride of data and out
 };
 
-// Contraction of a spectral array X(r,z,b,a) = src + r*src_r + z*plane + b*na + a
+// Contraction of a spectral array X(r,z,b,a) = src + r*src_r + z*plane + b*rs + a
 // along both axes in one read, with up to kMaxTerms coefficient vectors each:
 //   out_x,t(r,z,b) = sum_a cx_t[a] X(r,z,b,a)   at dx + t*dx_t + r*dx_r + z*dx_z + b
 //   out_y,t(r,z,a) = sum_b cy_t[b] X(r,z,b,a)   at dy + t*dy_t + r*dy_r + z*dy_z + a
@@ -147,7 +147,7 @@ struct SweepDesc {
 // and a second pass adds the slabs in order.
 struct ContractDesc {
   int32_t na, nb, nz, nxt, nyt, nslab, rows, ncs;
-  int32_t cols, pad;
+  int32_t cols, rs;               // rs: row stride of X (>= na)
   int64_t src, src_r;
   int64_t cx[kMaxTerms], cy[kMaxTerms];   // table offsets
   int32_t cx_stride[kMaxTerms], cy_stride[kMaxTerms];
@@ -162,9 +162,9 @@ struct ContractDesc {
 // separator counts above kMaxTerms (too many to add inside the z solve):
 //   out(r,z,b,a) = sum_i cx[i*na + a] gx_i(r,z,b) + sum_j cy[j*nb + b] gy_j(r,z,a)
 // with gx_i(r,z,b) at gx + r*gx_r + i*gx_t + z*gx_z + b (gy_j likewise with a),
-// out(r,z,b,a) at out + r*out_r + z*plane + b*na + a; cx, cy are table offsets.
+// out(r,z,b,a) at out + r*out_r + z*plane + b*rs + a; cx, cy are table offsets.
 struct ExpandDesc {
-  int32_t na, nb, nz, nxt, nyt, pad_;
+  int32_t na, nb, nz, nxt, nyt, rs;
   int64_t cx, cy;
   int64_t gx, gx_t, gx_r, gx_z;
   int64_t gy, gy_t, gy_r, gy_z;

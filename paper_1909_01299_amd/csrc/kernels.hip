@@ -359,7 +359,7 @@ __host__ __device__ __forceinline__ bool psweep_two_d(const SweepDesc& d, int mw
   return !d.dense_in && d.na >= mw;
 }
 __host__ __device__ __forceinline__ int64_t psweep_tiles(const SweepDesc& d, int mw) {
-  return psweep_two_d(d, mw) ? (int64_t)d.nb * ((d.na + mw - 1) / mw) : ((int64_t)d.na * d.nb + mw - 1) / mw;
+  return psweep_two_d(d, mw) ? (int64_t)d.nb * ((d.na + mw - 1) / mw) : ((int64_t)d.rs * d.nb + mw - 1) / mw;
 }
 // tile of workgroup wg < tiles
 __host__ __device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, int mw, int tiles, int wg) {
@@ -370,7 +370,7 @@ __host__ __device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, in
     const int t = xcd_linear(wg, tiles);
     st.a0 = (t / nb) * mw;
     st.b = t % nb;
-    st.m0 = (int64_t)st.b * na + st.a0;
+    st.m0 = (int64_t)st.b * d.rs + st.a0;
   } else {
     st.m0 = (int64_t)wg * mw;
     st.a0 = 0;
@@ -378,10 +378,12 @@ __host__ __device__ __forceinline__ SweepTile psweep_tile(const SweepDesc& d, in
   }
   return st;
 }
-// mode ml (< mw) of a tile: false past the row (tiles) or the plane
+// mode ml (< mw) of a tile, numbered m = b*rs + a (its offset in a plane):
+// false past the row (tiles), in a row's padding or past the plane
 __host__ __device__ __forceinline__ bool psweep_mode(const SweepDesc& d, const SweepTile& t, int ml, int64_t& m) {
-  const bool on = t.two_d ? t.a0 + ml < d.na : t.m0 + ml < (int64_t)d.na * d.nb;
-  m = on ? t.m0 + ml : 0;
+  const int64_t mm = t.m0 + ml;
+  const bool on = t.two_d ? t.a0 + ml < d.na : mm < (int64_t)d.rs * d.nb && int(mm % d.rs) < d.na;
+  m = on ? mm : 0;
   return on;
 }
 
@@ -438,7 +440,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   // where a dense right-hand side is read as well (its loads overlap); without
   // one the extra round trip costs more than it saves.
   const int r = blockIdx.z;
-  const int b_lo = int(tile.m0 / na);
+  const int b_lo = int(tile.m0 / d.rs);
   const bool xstage = d.dense_in && d.nxt > 0 && na >= MW && 2 * d.nxt * nzp <= xcap;
   if (xstage) {
 #pragma unroll
@@ -459,7 +461,7 @@ __device__ __forceinline__ void psweep_body(const SweepDesc& d, const cplx<R>* _
   // rows addressed in memory: kb .. kb + nv - 1 (clamped into the line)
   const int kb = k0 < nz ? k0 : nz - 1;
   const int nv = k0 < nz ? min(nz - k0, Lc) : 1;
-  const int a = int(m % na), b = int(m / na);
+  const int a = int(m % d.rs), b = int(m / d.rs);
   const C s = mact ? cadd(tab[d.lam_x + a], tab[d.lam_y + b]) : mk<R>(1, 0);
   auto X = [&](int f, int jj) -> C& { return xch[(jj * 6 + f) * MW + ml]; };
 
@@ -777,7 +779,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   for (int s = 0; s < SMAX; ++s)
 #pragma unroll
     for (int t = 0; t < kMaxTerms; ++t) yacc[s][t] = mk<R>(0, 0);
-  const C* xp = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.plane + (int64_t)b0 * d.na + c0;
+  const C* xp = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.plane + (int64_t)b0 * d.rs + c0;
   int col[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) col[s] = min(la + s * L, na - 1);
@@ -793,7 +795,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
     C xv[U][SMAX];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * d.na;
+      const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * d.rs;
 #pragma unroll
       for (int s = 0; s < SMAX; ++s) xv[u][s] = xp[row + col[s]];
     }
@@ -962,13 +964,13 @@ __global__ __launch_bounds__(256) void k_expand(ExpandDesc e, const cplx<R>* __r
     const C* cyc = tab + e.cy + (int64_t)t0 * e.nb;
 #pragma unroll 2
     for (int b = w; b < e.nb; b += 4) {
-      C acc = ch > 0 && aok ? out[(int64_t)b * e.na] : mk<R>(0, 0);
+      C acc = ch > 0 && aok ? out[(int64_t)b * e.rs] : mk<R>(0, 0);
 #pragma unroll
       for (int t = 0; t < TC; ++t) {
         if (t < nx) acc = cfma(cxa[t], gxc[(int64_t)t * e.gx_t + b], acc);
         if (t < ny) acc = cfma(cyc[(int64_t)t * e.nb + b], gya[t], acc);
       }
-      if (aok) out[(int64_t)b * e.na] = acc;
+      if (aok) out[(int64_t)b * e.rs] = acc;
     }
   }
 }
@@ -1492,7 +1494,7 @@ void sweep_select(const SweepDesc* d, int ndesc, int64_t max_modes, int chunks,
       for (int ml = 0; ml < mw && !low; ++ml) {
         int64_t m;
         if (!psweep_mode(s, t, ml, m)) continue;
-        const int a = int(m % s.na), b = int(m / s.na);
+        const int a = int(m % s.rs), b = int(m / s.rs);
         low = lam_re(s.lam_x + a) + lam_re(s.lam_y + b) <= s.fp64_below;
       }
       if (low) {

@@ -122,6 +122,12 @@ size_t sweep_lds_bytes(int arith_bytes, int nz, int chunks, int max_xterms);
 // solves' tiles of 16 consecutive modes start on whole 128-byte lines in both
 // precisions and consecutive planes do not map to one memory channel; smaller
 // planes stay dense (their padding would cost more than it saves).
+// row stride of a spectral array of rows of na modes: a multiple of 16
+// elements where that adds at most one element in eight, else na.
+inline int spectral_row(int na) {
+  const int r = (na + 15) / 16 * 16;
+  return (r - na) * 8 <= na ? r : na;
+}
 inline int64_t spectral_plane(int64_t n) {
   if (n < 1024) return n;
   int64_t q = (n + 15) / 16;
@@ -173,8 +179,8 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 bool side_stream_create(SideStream& s);
 void side_stream_destroy(SideStream& s);
 int sweep_default_chunks(int nz);
-// modes a launch provisions for one descriptor of na x nb modes
-inline int64_t sweep_modes_bound(int na, int nb) { return (int64_t)nb * ((na + 31) / 32 * 32); }
+// modes a launch provisions for one descriptor of nb rows of row stride rs (>= na)
+inline int64_t sweep_modes_bound(int rs, int nb) { return (int64_t)nb * ((rs + 31) / 32 * 32); }
 bool sweep_chunks_ok(int chunks, int nz);
 // true when nz fills `chunks` chunks of a fixed register row count exactly
 bool sweep_rows_fixed(int chunks, int nz);

@@ -443,7 +443,10 @@ void Plan::layout_workspace() {
   };
   NF = 0;
   for (auto& B : blocks) NF = std::max(NF, std::max(B.nbx, B.nby));
-  for (auto& B : blocks) B.pplane = spectral_plane((int64_t)B.nbx * B.nby);
+  for (auto& B : blocks) {
+    B.rs = spectral_row(B.nbx);
+    B.pplane = spectral_plane((int64_t)B.nby * B.rs);
+  }
   for (auto& B : blocks) B.spec = take(R * NZ * B.pplane);
   if (decomposed) {
     for (auto& B : blocks) B.vt = take(R * NZ * B.pplane);
@@ -468,7 +471,8 @@ void Plan::layout_workspace() {
     const int64_t lx = R * nsx * NZ * (int64_t)NY, ly = R * nsy * NZ * (int64_t)NX;
     w_rx = take(lx); w_Rx = take(lx); w_Qx = take(lx); w_wx = take(lx);
     w_ry = take(ly); w_Ry = take(ly); w_Qy = take(ly); w_wy = take(ly);
-    gpplane = spectral_plane((int64_t)NX * NY);
+    grs = spectral_row(NX);
+    gpplane = spectral_plane((int64_t)NY * grs);
     w_gspec = take(R * NZ * gpplane);
     // the interface contraction in groups of kMaxTerms separators per axis
     int64_t np = 0;
@@ -538,36 +542,38 @@ void Plan::build_descriptors() {
       DstDesc dx{};
       dx.n = B.nbx; dx.P = NZ; dx.Q = B.nby;
       dx.src = (int64_t)B.y0 * NX + B.x0; dx.src_r = f_r; dx.src_p = gplane; dx.src_q = NX; dx.src_i = 1;
-      dx.dst = B.spec; dx.dst_r = spec_r; dx.dst_p = plane; dx.dst_q = B.nbx; dx.dst_i = 1;
+      dx.dst = B.spec; dx.dst_r = spec_r; dx.dst_p = plane; dx.dst_q = B.rs; dx.dst_i = 1;
       s_fwdx.dst[vidx(AX.dstV)].push_back(dx);
       DstDesc ix = dx;
-      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
+      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.rs;
       ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
       s_invx.dst[vidx(AX.dstV)].push_back(ix);
     } else {
       XformDesc fx{};
       fx.tab = AX.fwd; set_frag(fx, AX, true); fx.n_in = fx.n_out = B.nbx; fx.P = NZ; fx.Q = B.nby;
       fx.src = (int64_t)B.y0 * NX + B.x0; fx.src_r = f_r; fx.src_p = gplane; fx.src_q = NX;
-      fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.nbx;
+      fx.dst = B.spec; fx.dst_r = spec_r; fx.dst_p = plane; fx.dst_q = B.rs;
       fx.sine = AX.sine;
       s_fwdx.dense.push_back(fx);
       XformDesc ix = fx;
       ix.tab = AX.inv; set_frag(ix, AX, false);
-      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.nbx;
+      ix.src = B.spec; ix.src_r = spec_r; ix.src_p = plane; ix.src_q = B.rs;
       ix.dst = (int64_t)B.y0 * NX + B.x0; ix.dst_r = f_r; ix.dst_p = gplane; ix.dst_q = NX;
       s_invx.dense.push_back(ix);
     }
     if (AY.dstV) {
       DstDesc dy{};
-      dy.n = B.nby; dy.P = NZ; dy.Q = B.nbx;
-      dy.src = B.spec; dy.src_r = spec_r; dy.src_p = plane; dy.src_q = 1; dy.src_i = B.nbx;
-      dy.dst = B.spec; dy.dst_r = spec_r; dy.dst_p = plane; dy.dst_q = 1; dy.dst_i = B.nbx;
+      // every column of a padded row (the padding ones too: tiles of lines
+      // then never straddle two planes)
+      dy.n = B.nby; dy.P = NZ; dy.Q = B.rs;
+      dy.src = B.spec; dy.src_r = spec_r; dy.src_p = plane; dy.src_q = 1; dy.src_i = B.rs;
+      dy.dst = B.spec; dy.dst_r = spec_r; dy.dst_p = plane; dy.dst_q = 1; dy.dst_i = B.rs;
       s_fwdy.dst[vidx(AY.dstV)].push_back(dy);
       s_invy.dst[vidx(AY.dstV)].push_back(dy);
     } else {
       XformYDesc fy{};
       fy.tab = AY.fwd; set_frag(fy, AY, true); fy.n = B.nby; fy.ncols = B.nbx; fy.P = NZ;
-      fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.nbx;
+      fy.data = B.spec; fy.s_r = spec_r; fy.s_p = plane; fy.s_k = B.rs;
       s_fwdy.dense.push_back(fy);
       XformYDesc iy = fy;
       iy.tab = AY.inv; set_frag(iy, AY, false);
@@ -580,7 +586,7 @@ void Plan::build_descriptors() {
     s.zlo = zlo; s.zdiag = zdiag; s.zup = zup; s.zsig = zsig;
     s.data = B.spec; s.data_r = spec_r;
     s.out = B.spec; s.out_r = spec_r;
-    s.plane = plane;
+    s.plane = plane; s.rs = B.rs;
     s.dense_in = 1;
     if (!decomposed) {
       d_sweep.push_back(s);
@@ -593,7 +599,7 @@ void Plan::build_descriptors() {
     const int64_t fbase = w_face + (int64_t)bi * R * 4 * face_f;
     ContractDesc c{};
     c.na = B.nbx; c.nb = B.nby; c.nz = NZ; c.nxt = 2; c.nyt = 2;
-    c.src = B.vt; c.src_r = spec_r; c.plane = plane;
+    c.src = B.vt; c.src_r = spec_r; c.plane = plane; c.rs = B.rs;
     c.cx[0] = AX.inv; c.cx_stride[0] = 1;                                // W_x[0][a]
     c.cx[1] = AX.inv + (int64_t)(B.nbx - 1) * B.nbx; c.cx_stride[1] = 1;  // W_x[n-1][a]
     c.cy[0] = AY.inv; c.cy_stride[0] = 1;                                // W_y[0][b]
@@ -674,7 +680,7 @@ void Plan::build_descriptors() {
     g.na = NX; g.nb = NY; g.nz = NZ;
     g.lam_x = GX.lam; g.lam_y = GY.lam;
     g.zlo = zlo; g.zdiag = zdiag; g.zup = zup; g.zsig = zsig;
-    g.out = w_gspec; g.out_r = gpplane * NZ; g.plane = gpplane;
+    g.out = w_gspec; g.out_r = gpplane * NZ; g.plane = gpplane; g.rs = grs;
     g.gx_r = (int64_t)nsx * NZ * NY; g.gy_r = (int64_t)nsy * NZ * NX;
     g.gx_z = NY; g.gy_z = NX;
     ex = ExpandDesc{};
@@ -696,7 +702,7 @@ void Plan::build_descriptors() {
       ex.cx = ex_cx; ex.cy = ex_cy;
       ex.gx = w_Rx; ex.gx_t = (int64_t)NZ * NY; ex.gx_r = g.gx_r; ex.gx_z = NY;
       ex.gy = w_Ry; ex.gy_t = (int64_t)NZ * NX; ex.gy_r = g.gy_r; ex.gy_z = NX;
-      ex.out = w_gspec; ex.out_r = g.out_r; ex.plane = gpplane;
+      ex.out = w_gspec; ex.out_r = g.out_r; ex.plane = gpplane; ex.rs = grs;
       g.dense_in = 1;
       g.data = w_gspec; g.data_r = g.out_r;
       g.nxt = 0; g.nyt = 0;
@@ -710,7 +716,7 @@ void Plan::build_descriptors() {
       c.na = NX; c.nb = NY; c.nz = NZ;
       c.nxt = std::clamp(nsx - g0, 0, kMaxTerms);
       c.nyt = std::clamp(nsy - g0, 0, kMaxTerms);
-      c.src = w_gspec; c.src_r = g.out_r; c.plane = gpplane;
+      c.src = w_gspec; c.src_r = g.out_r; c.plane = gpplane; c.rs = grs;
       for (int i = 0; i < c.nxt; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[g0 + i] * NX; c.cx_stride[i] = 1; }
       for (int j = 0; j < c.nyt; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[g0 + j] * NY; c.cy_stride[j] = 1; }
       c.dx_t = (int64_t)NZ * NY; c.dx_r = (int64_t)nsx * NZ * NY; c.dx_z = NY;
@@ -866,7 +872,7 @@ hs_status Plan::upload_descs(std::string& err) {
 
 int64_t Plan::sweep_modes(const std::vector<SweepDesc>& v) {
   int64_t m = 0;
-  for (auto& d : v) m = std::max<int64_t>(m, sweep_modes_bound(d.na, d.nb));
+  for (auto& d : v) m = std::max<int64_t>(m, sweep_modes_bound(d.rs, d.nb));
   return m;
 }
 

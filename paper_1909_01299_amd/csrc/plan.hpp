@@ -48,7 +48,8 @@ struct Block {
   int x0 = 0, nbx = 0, y0 = 0, nby = 0;
   int ax = -1, ay = -1;          // axis table indices
   int sep_lo_x = -1, sep_hi_x = -1, sep_lo_y = -1, sep_hi_y = -1;
-  int64_t pplane = 0;            // z-plane stride of its spectral arrays (spectral_plane(nbx*nby))
+  int rs = 0;                    // row stride of its spectral arrays (spectral_row(nbx))
+  int64_t pplane = 0;            // z-plane stride of its spectral arrays (spectral_plane(nby*rs))
   int64_t spec = 0;              // workspace offset of the block spectral array
   int64_t vt = 0;                // workspace offset of its spectral block solution v~ (steps 2-3)
   int64_t cpart = 0;             // slab partial sums of its face contraction (split planes only)
@@ -136,6 +137,7 @@ struct Plan {
   int64_t w_face = 0, w_vface = 0, w_gface = 0, w_Gface = 0;
   int64_t w_rx = 0, w_ry = 0, w_Rx = 0, w_Ry = 0, w_Qx = 0, w_Qy = 0, w_wx = 0, w_wy = 0;
   int64_t w_gspec = 0;           // global spectral solution w~ of the interface solve
+  int grs = 0;                   // its row stride
   int64_t gpplane = 0;           // its z-plane stride
   int64_t w_cpart = 0;           // slab partial sums of the interface contraction (split plane only)
   ExpandDesc ex{};               // dense_glob: dense spectral right-hand side of the global solve
