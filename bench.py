@@ -305,8 +305,9 @@ def cpu_baseline(problem, f, unknowns_per_rhs, repeat_budget_s=20.0, sample=""):
 
 def errors_vs(u, ref, problem=None):
     """Relative 2-norm error, largest pointwise error over the largest
-    reference value, and (decomposed grids) the relative error on the
-    separator planes."""
+    reference value, and (decomposed grids) the error on the separator planes
+    as an RMS per node over the RMS of the whole field, and relative to the
+    separator field itself."""
     d = u - ref
     out = {"rel2": float(np.linalg.norm(d) / np.linalg.norm(ref)),
            "relmax": float(np.abs(d).max() / np.abs(ref).max())}
@@ -315,6 +316,7 @@ def errors_vs(u, ref, problem=None):
         m[:, problem.sep_x] = True
         m[problem.sep_y, :] = True
         ds, rs = d[:, m], ref[:, m]
+        out["rms_sigma"] = float(np.linalg.norm(ds) / np.sqrt(ds.size) / (np.linalg.norm(ref) / np.sqrt(ref.size)))
         out["rel2_sigma"] = float(np.linalg.norm(ds) / np.linalg.norm(rs))
     return out
 
@@ -596,6 +598,45 @@ def bench_c2(steps, warmup, args, with_oracle):
     return out
 
 
+def bench_gridding_b(steps, warmup, with_oracle, refine_steps=1):
+    """The second gridding of Sec. 2 at the large grid's size: 575 x 575 x 256
+    on graded non-uniform x and y steps, 24 x 24 blocks of 23 nodes (dense
+    eigenvector transforms everywhere, 23 separators per axis, dense global
+    right-hand side), 4 point sources: tuned complex128 and mixed plans, stage
+    tables, the dominant stage's roofline, oracle error on the first source."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    p, srcs = W.gridding_b_large()
+    nrhs = len(srcs)
+    f = point_sources_device(p, srcs)
+    out = {"workload": f"gridding_b {p.nx}x{p.ny}x{p.nz}, graded non-uniform x/y steps, "
+                       f"{len(p.sep_x) + 1}x{len(p.sep_y) + 1} blocks, {nrhs} point sources",
+           "unknowns": p.unknowns, "nrhs": nrhs, "separators_per_axis": [len(p.sep_x), len(p.sep_y)]}
+    us = {}
+    for prec in ("c128", "mixed"):
+        t0 = time.perf_counter()
+        plan = hs.Plan(p, prec, max_rhs=nrhs, refine_steps=refine_steps if prec == "mixed" else 0)
+        t_plan = time.perf_counter() - t0
+        tuned = plan.tune(nrhs, cache=TUNE_CACHE)
+        u = torch.empty_like(f)
+        dt, stages, dom = time_plans([plan], f, u, steps, warmup)
+        us[prec] = u[0].cpu().numpy()
+        out[prec] = {"value": p.unknowns * nrhs * steps / dt, "unit": "unknowns*RHS/s",
+                     "ms_per_step": dt / steps * 1e3, "plan_seconds": t_plan, "tuned": tuned,
+                     "roofline": roofline(dom, prec),
+                     "stages_ms_per_step": {r["name"]: round(r["ms"], 3) for r in stages}}
+        del plan, u
+        torch.cuda.empty_cache()
+    out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    if with_oracle:
+        from oracle import separable
+        ref = separable.solve(p, W.point_source_batch(p, srcs[:1]))[0]
+        for prec in ("c128", "mixed"):
+            out[prec]["rel_err_vs_oracle_src0"] = errors_vs(us[prec], ref, p)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -617,6 +658,8 @@ def main():
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
     ap.add_argument("--c4-only", action="store_true", help="time only the adjoint gradient (128x128x160)")
+    ap.add_argument("--gridding-b-only", action="store_true",
+                    help="time only the 575x575x256 grid split 24x24 on graded steps")
     ap.add_argument("--c5-only", choices=["c128", "mixed", "both"],
                     help="time only the headline workload (no oracle): for kernel traces")
     ap.add_argument("--tune-cache", help="JSON-lines cache of tuned launch shapes (read, else written)")
@@ -654,6 +697,10 @@ def main():
     if args.c4_only:
         print(json.dumps(bench_c4(max(1, args.steps), True)), flush=True)
         return
+    if args.gridding_b_only:
+        print(json.dumps(bench_gridding_b(max(1, args.steps), args.warmup, not args.no_cpu_baseline,
+                                          refine_steps=args.refine_steps)), flush=True)
+        return
     if args.c5_only:
         precs = ("c128", "mixed") if args.c5_only == "both" else (args.c5_only,)
         print(json.dumps(bench_c5(args.steps, args.warmup, args.refine_steps, with_oracle=False, precs=precs,
@@ -676,6 +723,9 @@ def main():
         print(json.dumps({"progress": "c3 done"}), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         extras["adjoint_c4"] = bench_c4(10, with_oracle)
+        print(json.dumps({"progress": "c4 done"}), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["gridding_b"] = bench_gridding_b(3, 1, with_oracle, refine_steps=args.refine_steps)
 
     c128 = c5["c128"]
     rf = c128["roofline"]

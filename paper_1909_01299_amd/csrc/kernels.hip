@@ -931,46 +931,67 @@ __global__ __launch_bounds__(256) void k_contract_fin(const ContractDesc* __rest
 }
 
 // Dense spectral right-hand side of the global solve (ExpandDesc): a
-// workgroup owns 64 columns a of one z plane, each wave every fourth row b.
-// Terms are taken 8 at a time: the per-column factors (cx_i[a], gy_j(a)) of
-// a chunk sit in registers, the per-row factors (gx_i(b), cy_j[b]) are read
-// at wave-uniform addresses (one request per wave), so the rows need no
-// barrier and their stores stream.  A later chunk adds to what the same
-// thread stored for the element before.
+// workgroup owns 64 columns a of one z plane and walks its rows b in tiles
+// of 16, one row in four per wave.  Terms are taken 16 at a time; the
+// per-column factors (cx_i[a], gy_j(a)) and the per-row factors (gx_i(b),
+// cy_j[b]) of a chunk are staged in LDS, zero past the term counts.  A
+// later chunk adds to what the same thread stored for the element before.
 template <typename R>
 __global__ __launch_bounds__(256) void k_expand(ExpandDesc e, const cplx<R>* __restrict__ tab,
                                                 cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
-  constexpr int TC = 8;
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int TC = 16, TB = 16;
+  __shared__ C colf[2][TC][64];
+  __shared__ C rowf[2][TC][TB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int a0 = blockIdx.x * 64, z = blockIdx.y, r = blockIdx.z;
   const int a = min(a0 + lane, e.na - 1);
   const bool aok = a0 + lane < e.na;
   const C* gx = ws + e.gx + (int64_t)r * e.gx_r + (int64_t)z * e.gx_z;
   const C* gy = ws + e.gy + (int64_t)r * e.gy_r + (int64_t)z * e.gy_z;
-  C* out = ws + e.out + (int64_t)r * e.out_r + (int64_t)z * e.plane + a;
+  C* out = ws + e.out + (int64_t)r * e.out_r + (int64_t)z * e.plane;
   const int nch = (max(e.nxt, e.nyt) + TC - 1) / TC;
   for (int ch = 0; ch < nch; ++ch) {
     const int t0 = ch * TC;
     const int nx = min(max(e.nxt - t0, 0), TC), ny = min(max(e.nyt - t0, 0), TC);
-    C cxa[TC], gya[TC];
-#pragma unroll
-    for (int t = 0; t < TC; ++t) {
-      cxa[t] = t < nx ? tab[e.cx + (int64_t)(t0 + t) * e.na + a] : mk<R>(0, 0);
-      gya[t] = t < ny ? gy[(int64_t)(t0 + t) * e.gy_t + a] : mk<R>(0, 0);
+    const int nt = max(nx, ny);
+    __syncthreads();
+    for (int i = threadIdx.x; i < TC * 64; i += 256) {
+      const int t = i / 64, l = i % 64;
+      const int aa = min(a0 + l, e.na - 1);
+      colf[0][t][l] = t < nx ? tab[e.cx + (int64_t)(t0 + t) * e.na + aa] : mk<R>(0, 0);
+      colf[1][t][l] = t < ny ? gy[(int64_t)(t0 + t) * e.gy_t + aa] : mk<R>(0, 0);
     }
-    const C* gxc = gx + (int64_t)t0 * e.gx_t;
-    const C* cyc = tab + e.cy + (int64_t)t0 * e.nb;
-#pragma unroll 2
-    for (int b = w; b < e.nb; b += 4) {
-      C acc = ch > 0 && aok ? out[(int64_t)b * e.rs] : mk<R>(0, 0);
-#pragma unroll
-      for (int t = 0; t < TC; ++t) {
-        if (t < nx) acc = cfma(cxa[t], gxc[(int64_t)t * e.gx_t + b], acc);
-        if (t < ny) acc = cfma(cyc[(int64_t)t * e.nb + b], gya[t], acc);
+    for (int b0 = 0; b0 < e.nb; b0 += TB) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < 2 * TC * TB; i += 256) {
+        const int sd = i / (TC * TB), t = (i / TB) % TC, q = i % TB;
+        const int bb = min(b0 + q, e.nb - 1);
+        C v = mk<R>(0, 0);
+        if (sd == 0 && t < nx) v = gx[(int64_t)(t0 + t) * e.gx_t + bb];
+        if (sd == 1 && t < ny) v = tab[e.cy + (int64_t)(t0 + t) * e.nb + bb];
+        rowf[sd][t][q] = v;
       }
-      if (aok) out[(int64_t)b * e.rs] = acc;
+      __syncthreads();
+      C acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = b0 + w * 4 + q;
+        acc[q] = ch > 0 && aok && b < e.nb ? out[(int64_t)b * e.rs + a] : mk<R>(0, 0);
+      }
+      for (int t = 0; t < nt; ++t) {
+        const C cxv = colf[0][t][lane], gyv = colf[1][t][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          acc[q] = cfma(cxv, rowf[0][t][w * 4 + q], acc[q]);
+          acc[q] = cfma(rowf[1][t][w * 4 + q], gyv, acc[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = b0 + w * 4 + q;
+        if (aok && b < e.nb) out[(int64_t)b * e.rs + a] = acc[q];
+      }
     }
   }
 }

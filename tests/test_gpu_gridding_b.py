@@ -4,7 +4,7 @@ general non-uniform x and y steps with stretched ends, against the oracle in
 both precisions.  With more than 4 separators on an axis the right-hand side
 of the global interface solve is expanded densely before the z solve; the
 tests cover ragged column and row tiles of that expansion, more than one
-chunk of 8 separators, axes whose counts differ (groups of the interface
+chunk of 16 separators, axes whose counts differ (groups of the interface
 contraction with no terms on one axis), the forced dense path against the
 low-rank one, the adjoint and the layer gradient."""
 import numpy as np
@@ -41,7 +41,7 @@ def solve(hs, p, f, prec, **kw):
 @pytest.mark.parametrize("cfg", [
     dict(nx=64, ny=49, nz=40, pml=5),     # 7 x 6 separators, blocks of 7-8 nodes
     dict(nx=100, ny=16, nz=33, pml=4),    # 9 x 3: the later contraction groups hold x terms only
-    dict(nx=20, ny=324, nz=10, pml=3),    # 3 x 17: three chunks of y terms in the expansion
+    dict(nx=20, ny=324, nz=10, pml=3),    # 3 x 17: two chunks of y terms in the expansion
 ])
 def test_gridding_b_vs_oracle(hs, prec, tol, cfg):
     rng = np.random.default_rng(cfg["nx"] * 7 + cfg["ny"])

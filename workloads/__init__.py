@@ -382,6 +382,24 @@ def c5_multi_rhs(core_cells: int = 512, pml_cells: int = 32, nz: int = 256,
     return p, srcs, tuple(omegas)
 
 
+def gridding_b_large(n: int = 575, pml: int = 32, nz: int = 256, nlayers: int = 60, nsrc: int = 4):
+    """The second gridding of Sec. 2 at the large grid's size: n x n x nz with
+    graded non-uniform x and y steps (spread 0.4) and stretched ends of ``pml``
+    steps, split into about sqrt(n) x sqrt(n) blocks (24 x 24 of 23 nodes for
+    n = 575); nsrc random point sources off the separators."""
+    rng = rng_for(6)
+    p = gridding_b_problem(n, n, nz, nlayers, rng, pml=pml, name=f"gridding_b_{n}^2x{nz}")
+    srcs = []
+    while len(srcs) < nsrc:
+        x = int(rng.integers(pml, n - pml))
+        y = int(rng.integers(pml, n - pml))
+        z = int(rng.integers(0, nz))
+        if x in p.sep_x or y in p.sep_y:
+            continue
+        srcs.append((x, y, z))
+    return p, srcs
+
+
 def point_source_batch(problem: Problem, srcs) -> np.ndarray:
     f = np.zeros((len(srcs),) + problem.shape, dtype=np.complex128)
     for r, (x, y, z) in enumerate(srcs):
