@@ -237,8 +237,9 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
  * per workgroup in {4, 8, 16}, (where nz fills the chunks exactly) z-solve
  * instances with a fixed row count per chunk or not, and (decomposed grids
  * with at most 4 separators per axis) the global right-hand side expanded
- * densely or as low-rank terms is timed with hipEvents on `stream` over 3
- * solves of scratch data and the fastest is kept in the plan.  cache_path (may be
+ * densely or as low-rank terms is timed with hipEvents on `stream` on
+ * scratch data (each combination's time: its fastest single solve over two
+ * passes of three) and the fastest is kept in the plan.  cache_path (may be
  * NULL) names a JSON-lines file keyed by device architecture and plan shape:
  * a hit skips the timing, a miss appends the result.  Needs a bound workspace;
  * allocates and frees two scratch arrays; synchronizes the stream. */
@@ -300,7 +301,8 @@ hs_status hs_batch_bind_workspace(hs_batch batch, void* dev_ptr, size_t bytes);
 hs_status hs_batch_solve(hs_batch batch, const void* const* f, void* const* u, void* stream);
 /* Autotune the batch's own launch shapes (z-line chunks, sine lines per
  * workgroup, fixed z-solve rows; as hs_plan_tune, but timed on the whole
- * captured graph of the batch) with the caller's arrays: u is overwritten.
+ * captured graph of the batch, the fastest of two replays per combination)
+ * with the caller's arrays: u is overwritten.
  * cache_path (may be NULL): JSON-lines cache keyed by device, precision and
  * the plans' shapes.  Synchronizes the stream. */
 hs_status hs_batch_tune(hs_batch batch, const void* const* f, void* const* u, const char* cache_path,

@@ -438,13 +438,16 @@ hs_status Batch::tune(const void* const* f, void* const* u, const char* cache_pa
         recapture = true;
         std::string e2;
         if (solve(f, u, st, e2) != HS_OK) continue;   // captures this shape's graph
-        (void)hipEventRecord(e0, st);
-        for (int rep = 0; rep < 2; ++rep) (void)solve(f, u, st, e2);
-        (void)hipEventRecord(e1, st);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) { best = ms; bc = c; bl = l; bf = fr; }
+        // the fastest of two single replays
+        for (int rep = 0; rep < 2; ++rep) {
+          (void)hipEventRecord(e0, st);
+          (void)solve(f, u, st, e2);
+          (void)hipEventRecord(e1, st);
+          (void)hipEventSynchronize(e1);
+          float ms = 0;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (ms < best) { best = ms; bc = c; bl = l; bf = fr; }
+        }
       }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -455,7 +458,7 @@ hs_status Batch::tune(const void* const* f, void* const* u, const char* cache_pa
   if (cache_path && *cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << "{\"key\": \"" << k << "\", \"chunks\": " << bc << ", \"lines\": " << bl << ", \"fixed_rows\": " << bf
-        << ", \"ms_per_solve\": " << best / 2 << "}\n";
+        << ", \"ms_per_solve\": " << best << "}\n";
   }
   return HS_OK;
 }
