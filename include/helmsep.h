@@ -143,6 +143,10 @@ typedef struct {
                                solve's right-hand side is expanded densely
                                before its z solve, 0 when its separator lines
                                enter the z solve as low-rank terms          */
+  int32_t fp64_stream;      /* HS_C64_REFINE: 1 when the FP64 z solves of the
+                               near-resonance workgroups run on a second stream
+                               beside the FP32 launch, 0 when they run first on
+                               the solve's stream (chosen by hs_plan_tune)    */
   int32_t n_split_fp16;     /* HS_C64_REFINE: axes whose dense tables run on fp16
                                matrix cores as two-term splits (n <= 256, or
                                n <= 512 for real sine tables)                */
@@ -237,7 +241,8 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
  * per workgroup in {4, 8, 16}, (where nz fills the chunks exactly) z-solve
  * instances with a fixed row count per chunk or not, and (decomposed grids
  * with at most 4 separators per axis) the global right-hand side expanded
- * densely or as low-rank terms is timed with hipEvents on `stream` on
+ * densely or as low-rank terms, and (HS_C64_REFINE with near-resonance
+ * modes) the stream of the FP64 z solves is timed with hipEvents on `stream` on
  * scratch data (each combination's time: its fastest single solve over two
  * passes of three) and the fastest is kept in the plan.  cache_path (may be
  * NULL) names a JSON-lines file keyed by device architecture and plan shape:
@@ -251,12 +256,12 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
  * z_fixed_rows in {0, 1} (1 is used only where nz fills the chunks exactly),
  * global_dense in {-1 (keep), 0, 1} (ignored on a single block; 0 is refused
  * where more than 4 separators on an axis, or flag bit 3, require the dense
- * expansion).  Changing global_dense waits for the device and rewrites the
+ * expansion), fp64_stream in {-1 (keep), 0, 1} (see hs_info).  Changing global_dense waits for the device and rewrites the
  * plan's descriptors.  HS_ERR_ARG for a value outside these sets or one the
  * plan cannot use (a z chunking that cannot hold nz, sine lines whose LDS
  * does not fit). */
 hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows,
-                             int32_t global_dense);
+                             int32_t global_dense, int32_t fp64_stream);
 
 /* Per-stage timing.  While enabled, every stage of a solve is bracketed by
  * hipEvents recorded on the solve's stream (events come from a pool created

@@ -56,7 +56,7 @@ class Info(ctypes.Structure):
                 ("inv_resid_max", ctypes.c_double), ("min_pivot", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("table_bytes", ctypes.c_size_t),
                 ("n_fp64_modes", ctypes.c_int64), ("z_chunks", ctypes.c_int32), ("sine_lines", ctypes.c_int32),
-                ("z_fixed_rows", ctypes.c_int32), ("global_dense", ctypes.c_int32), ("n_split_fp16", ctypes.c_int32), ("tol", ctypes.c_double), ("resid_first", ctypes.c_double),
+                ("z_fixed_rows", ctypes.c_int32), ("global_dense", ctypes.c_int32), ("fp64_stream", ctypes.c_int32), ("n_split_fp16", ctypes.c_int32), ("tol", ctypes.c_double), ("resid_first", ctypes.c_double),
                 ("resid_final", ctypes.c_double), ("resid_evals", ctypes.c_int32), ("converged", ctypes.c_int32)]
 
     def as_dict(self):
@@ -90,7 +90,8 @@ EXPORTS = {
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
     "hs_batch_tune": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_char_p, ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
-    "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "hs_profile_only": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
     "hs_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
@@ -270,13 +271,15 @@ class Plan:
         _check(lib().hs_plan_tune(self._h, int(nrhs), cache.encode() if cache else None, _stream(stream)))
         inf = self.info()
         return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"], "z_fixed_rows": inf["z_fixed_rows"],
-                "global_dense": inf["global_dense"]}
+                "global_dense": inf["global_dense"], "fp64_stream": inf["fp64_stream"]}
 
     def set_launch(self, shapes: dict):
         """Apply launch shapes as returned by tune() (z_chunks, sine_lines,
-        z_fixed_rows, global_dense; a missing global_dense keeps the plan's)."""
+        z_fixed_rows, global_dense, fp64_stream; a missing global_dense or
+        fp64_stream keeps the plan's)."""
         _check(lib().hs_plan_set_launch(self._h, int(shapes.get("z_chunks", 0)), int(shapes.get("sine_lines", 0)),
-                                        int(shapes.get("z_fixed_rows", 0)), int(shapes.get("global_dense", -1))))
+                                        int(shapes.get("z_fixed_rows", 0)), int(shapes.get("global_dense", -1)),
+                                        int(shapes.get("fp64_stream", -1))))
 
     def profile(self, on: bool = True, only: Optional[str] = None):
         """Record hipEvents around every stage of subsequent solves, or only

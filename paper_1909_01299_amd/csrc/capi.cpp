@@ -143,6 +143,7 @@ hs_status hs_get_info(hs_plan plan, hs_info* info) {
   info->sine_lines = p.tune_lt;
   info->z_fixed_rows = p.tune_full;
   info->global_dense = p.dense_glob ? 1 : 0;
+  info->fp64_stream = p.tune_side;
   for (auto& a : p.axes)
     if (a.hfwd >= 0) ++info->n_split_fp16;
   info->tol = p.tol;
@@ -196,7 +197,7 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
 }
 
 hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows,
-                             int32_t global_dense) {
+                             int32_t global_dense, int32_t fp64_stream) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
   hs::Plan& p = plan->p;
   if (z_chunks != 0 && !hs::sweep_chunks_ok(z_chunks, p.NZ)) return ret(HS_ERR_ARG, "z chunking cannot hold nz");
@@ -208,6 +209,7 @@ hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines,
   }
   if (z_fixed_rows != 0 && z_fixed_rows != 1) return ret(HS_ERR_ARG, "z_fixed_rows not in {0, 1}");
   if (global_dense < -1 || global_dense > 1) return ret(HS_ERR_ARG, "global_dense not in {-1, 0, 1}");
+  if (fp64_stream < -1 || fp64_stream > 1) return ret(HS_ERR_ARG, "fp64_stream not in {-1, 0, 1}");
   if (global_dense == 0 && p.decomposed && p.glob_forced)
     return ret(HS_ERR_ARG, "more than 4 separators on an axis (or flag bit 3): the global right-hand side is dense");
   if (global_dense >= 0) {
@@ -218,6 +220,7 @@ hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines,
   p.tune_chunks = z_chunks;
   p.tune_lt = sine_lines;
   p.tune_full = z_fixed_rows;
+  if (fp64_stream >= 0) p.tune_side = fp64_stream;
   return ret(HS_OK, "");
 }
 

@@ -116,6 +116,7 @@ struct Plan {
   int tune_chunks = 0;           // z-line chunks per mode (0 = default for NZ)
   int tune_lt = 0;               // sine-transform lines per workgroup (0 = default)
   int tune_full = 0;             // 1: z solves with chunks of a fixed row count where nz fills them
+  int tune_side = 1;             // complex64: FP64 z solves on a second stream (1) or before the FP32 launch (0)
   double fp64_below = -1e300;    // complex64 path: z solves of modes with Re(lam_x + lam_y) <= this in FP64
   SideStream side;               // complex64 path: stream of the FP64 z solves
   int64_t n_fp64_modes = 0;

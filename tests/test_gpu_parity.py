@@ -377,6 +377,30 @@ def test_mixed_near_resonance_lists_every_chunking_and_k2_update(hs, chunks):
     assert np.array_equal(plan.solve(fd).cpu().numpy(), u1)
 
 
+def test_fp64_stream_choice_same_result(hs):
+    """The near-resonance FP64 z solves beside the FP32 launch on a second
+    stream or before it on the solve's stream: the same workgroups write the
+    same modes, so both give the same result bit for bit (decomposed grid)."""
+    import torch
+    p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=40, nlayers=6)
+    p = p.with_k2(p.k2 * 4.0)
+    rng = np.random.default_rng(17)
+    f = f + 0.1 * W.complex_normal(rng, f.shape)
+    fd = dev(f)
+    plan = hs.Plan(p, "mixed", refine_steps=1)
+    assert plan.info()["n_fp64_modes"] > 0 and plan.info()["fp64_stream"] == 1
+    u1 = plan.solve(fd).cpu().numpy()
+    plan.set_launch({"z_chunks": 0, "sine_lines": 0, "z_fixed_rows": 0, "fp64_stream": 0})
+    assert plan.info()["fp64_stream"] == 0
+    u0 = plan.solve(fd).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(u0, u1)
+    assert per_rhs_err(u0, separable.solve(p, f)) < TOL64R
+    shapes = plan.tune(1)
+    assert shapes["fp64_stream"] in (0, 1)
+    assert per_rhs_err(plan.solve(fd).cpu().numpy(), separable.solve(p, f)) < TOL64R
+
+
 def test_mixed_precision_decomposed(hs):
     p, f = W.c2_decomposed(core_cells=48, pml_cells=6, nz=40, nlayers=6)
     rng = np.random.default_rng(13)
