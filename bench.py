@@ -197,6 +197,52 @@ def traffic_summary(fdir, wdir, cfdir, cwdir):
     print(json.dumps(out), flush=True)
 
 
+SQ_SETS = ("SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+           "SQ_INSTS_VMEM_RD SQ_LDS_BANK_CONFLICT",
+           "SQ_INST_LEVEL_VMEM SQ_ACTIVE_INST_VMEM SQ_INSTS_LDS SQ_WAIT_ANY SQ_LEVEL_WAVES SQ_INSTS_VALU "
+           "SQ_INSTS_VMEM_WR SQ_BUSY_CU_CYCLES")
+
+
+def sq_summary(dir1, dir2):
+    """Per-kernel summary of two rocprofv3 --pmc runs over `bench.py
+    --counters` (the two counter sets of SQ_SETS): fractions of wave cycles
+    spent waiting (any) and issuing VALU / LDS instructions, vector-memory
+    instructions in flight per busy cycle, LDS bank-conflict cycles per LDS
+    instruction."""
+    import csv
+    import re
+    import collections
+
+    def load(folder):
+        agg = collections.OrderedDict()
+        with open(os.path.join(folder, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                m = re.search(r"(k_[a-z0-9_]+<[^(]*>)", r["Kernel_Name"])
+                name = (m.group(1) if m else r["Kernel_Name"][:30]) + "  grid=" + r["Grid_Size"]
+                a = agg.setdefault(name, collections.Counter())
+                a[r["Counter_Name"]] += float(r["Counter_Value"])
+        return agg
+    a1, a2 = load(dir1), load(dir2)
+    run = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 180 rocprofv3 --pmc {c} --output-format csv "
+           "-d {d} -o run -- python3 $R/bench.py --counters" + (f" --tune-cache {TUNE_CACHE}" if TUNE_CACHE else ""))
+    print("# rocprofv3 SQ counters per kernel: complex128 solves of the 575x575x256 grid (16 sources, omega = 1)")
+    for c, d in zip(SQ_SETS, (dir1, dir2)):
+        print("# command (R = repository root): " + run.format(c=c, d=d))
+    print(f"# summary: python3 $R/bench.py --sq-summary {dir1} {dir2}")
+    print("# columns: waves per dispatch, wait (any) / VALU busy / LDS busy as fractions of wave cycles, "
+          "VMEM instructions in flight per busy cycle, LDS bank-conflict cycles per LDS instruction, kernel")
+    for name, d in a1.items():
+        d = collections.Counter(d)
+        d.update(a2.get(name, {}))
+        if d.get("SQ_WAVES", 0) < 1000:
+            continue
+        wc = d.get("SQ_WAVE_CYCLES", 0) or 1
+        bc = d.get("SQ_BUSY_CYCLES", 0) or 1
+        print(f"{d['SQ_WAVES']:11.0f}  {d['SQ_WAIT_ANY'] / wc:5.2f}  {d['SQ_ACTIVE_INST_VALU'] / wc:5.2f}  "
+              f"{d['SQ_ACTIVE_INST_LDS'] / wc:5.2f}  {d['SQ_INST_LEVEL_VMEM'] / bc:5.1f}  "
+              f"{d['SQ_LDS_BANK_CONFLICT'] / max(d['SQ_INSTS_LDS'], 1):5.2f}  {name}")
+
+
 def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool = False):
     """Text summary of a rocprofv3 kernel trace: per kernel and grid, the
     number of dispatches, the average duration and the share of the total.
@@ -665,6 +711,8 @@ def main():
     ap.add_argument("--tune-cache", help="JSON-lines cache of tuned launch shapes (read, else written)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
+    ap.add_argument("--sq-summary", nargs=2, metavar=("SQ1", "SQ2"),
+                    help="print a per-kernel summary of two rocprofv3 --pmc runs of the SQ counter sets")
     ap.add_argument("--stage-labels", action="store_true",
                     help="with --stats-summary: list the z sweeps of decomposed solves by stage")
     args = ap.parse_args()
@@ -675,6 +723,9 @@ def main():
         return
     if args.stats_summary:
         stats_summary(*args.stats_summary, stage_labels=args.stage_labels)
+        return
+    if args.sq_summary:
+        sq_summary(*args.sq_summary)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

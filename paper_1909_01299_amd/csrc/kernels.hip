@@ -43,39 +43,46 @@ __device__ __forceinline__ CO cvt(CI v) {
 }
 
 // ---------------------------------------------------------------------------
-// Dense transform along a strided axis, in place: for plane p and columns
-// [c0, c0 + CT), data[o][c] = sum_k T[o][k] data[k][c].  The whole column
-// panel is staged in LDS before any output is written.
+// Dense transform along a strided axis, in place: for planes p0 .. p0 + ppw - 1
+// and columns [c0, c0 + CT), data[o][c] = sum_k T[o][k] data[k][c].  Every
+// column panel of the workgroup is staged in LDS before any output is
+// written; several planes per workgroup keep short axes (a few tens of rows)
+// from running as many tiny workgroups.
 // ---------------------------------------------------------------------------
 template <typename R, int CT>
 __global__ __launch_bounds__(256) void k_xform_y(const XformYDesc* __restrict__ descs,
                                                  const cplx<R>* __restrict__ tab,
-                                                 cplx<R>* __restrict__ ws) {
+                                                 cplx<R>* __restrict__ ws, int ppw) {
   using C = cplx<R>;
   extern __shared__ unsigned char smem_raw[];
-  C* panel = reinterpret_cast<C*>(smem_raw);
+  C* panel = reinterpret_cast<C*>(smem_raw);   // [ppw][n][CT]
   const XformYDesc d = descs[blockIdx.y];
   const int r = blockIdx.z;
   const int ntc = (d.ncols + CT - 1) / CT;
+  const int npg = (d.P + ppw - 1) / ppw;
   const int tile = blockIdx.x;
-  if (tile >= ntc * d.P) return;
-  const int p = tile / ntc, c0 = (tile % ntc) * CT;
-  C* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
+  if (tile >= ntc * npg) return;
+  const int p0 = (tile / ntc) * ppw, c0 = (tile % ntc) * CT;
+  const int np = min(ppw, d.P - p0);
+  C* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p0 * d.s_p;
   const int n = d.n;
-  for (int e = threadIdx.x; e < n * CT; e += 256) {
-    const int k = e / CT, c = e % CT;
-    panel[e] = (c0 + c < d.ncols) ? base[(int64_t)k * d.s_k + c0 + c] : mk<R>(0, 0);
+  const int pe = n * CT;   // elements of one plane's panel
+  for (int e = threadIdx.x; e < np * pe; e += 256) {
+    const int pp = e / pe, k = (e % pe) / CT, c = e % CT;
+    panel[e] = (c0 + c < d.ncols) ? base[(int64_t)pp * d.s_p + (int64_t)k * d.s_k + c0 + c] : mk<R>(0, 0);
   }
   __syncthreads();
   const C* T = tab + d.tab;
   constexpr int RG = 256 / CT;  // output rows handled in parallel
   const int c = threadIdx.x % CT, og = threadIdx.x / CT;
   if (c0 + c >= d.ncols) return;
-  for (int o = og; o < n; o += RG) {
+  for (int q = og; q < np * n; q += RG) {
+    const int pp = q / n, o = q % n;
     C acc = mk<R>(0, 0);
     const C* Trow = T + (int64_t)o * n;
-    for (int k = 0; k < n; ++k) acc = cfma(Trow[k], panel[k * CT + c], acc);
-    base[(int64_t)o * d.s_k + c0 + c] = acc;
+    const C* pc = panel + pp * pe + c;
+    for (int k = 0; k < n; ++k) acc = cfma(Trow[k], pc[k * CT], acc);
+    base[(int64_t)pp * d.s_p + (int64_t)o * d.s_k + c0 + c] = acc;
   }
 }
 
@@ -1418,32 +1425,43 @@ void dst_lines(int prec, int in64, int out64, int acc, int V, const DstDesc* d, 
   }
 }
 
+// planes per workgroup of the strided dense transform: panels of at most
+// 24 KiB in all (one plane where a panel alone is that large)
+int xform_y_ppw(int prec, int max_n, int ct) {
+  const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
+  const size_t one = size_t(std::max(max_n, 1)) * ct * esz;
+  return int(std::max<size_t>(1, std::min<size_t>(16, 24576 / one)));
+}
+
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st) {
   if (ndesc == 0 || nrhs == 0) return;
   const bool wide = max_n <= 256;
   const int CT = wide ? 16 : 8;
   const size_t esz = prec == 0 ? sizeof(double2) : sizeof(float2);
-  const size_t lds = size_t(max_n) * CT * esz;
+  const int ppw = xform_y_ppw(prec, max_n, CT);
+  const size_t lds = size_t(ppw) * max_n * CT * esz;
   const int tiles = wide ? max_tiles16 : max_tiles8;
   if (prec == 0) {
     if (wide)
       hipLaunchKernelGGL((k_xform_y<double, 16>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
-                         (const double2*)tab, (double2*)ws);
+                         (const double2*)tab, (double2*)ws, ppw);
     else
       hipLaunchKernelGGL((k_xform_y<double, 8>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
-                         (const double2*)tab, (double2*)ws);
+                         (const double2*)tab, (double2*)ws, ppw);
   } else {
     if (wide)
       hipLaunchKernelGGL((k_xform_y<float, 16>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
-                         (const float2*)tab, (float2*)ws);
+                         (const float2*)tab, (float2*)ws, ppw);
     else
       hipLaunchKernelGGL((k_xform_y<float, 8>), dim3(tiles, ndesc, nrhs), dim3(256), lds, st, d,
-                         (const float2*)tab, (float2*)ws);
+                         (const float2*)tab, (float2*)ws, ppw);
   }
 }
 
-int xform_y_tiles(const XformYDesc& d, int ct) { return ((d.ncols + ct - 1) / ct) * d.P; }
+int xform_y_tiles(const XformYDesc& d, int ct, int ppw) {
+  return ((d.ncols + ct - 1) / ct) * ((d.P + ppw - 1) / ppw);
+}
 
 // Staged x-type term lines: at most this many bytes of LDS.
 constexpr size_t kSweepStageBytes = 32768;

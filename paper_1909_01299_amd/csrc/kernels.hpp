@@ -112,7 +112,8 @@ bool dst_lt_ok(int prec, int V, int lt);
 
 void xform_y(int prec, const XformYDesc* d, int ndesc, int max_n, int max_tiles16, int max_tiles8,
              const void* tab, void* ws, int nrhs, hipStream_t st);
-int xform_y_tiles(const XformYDesc& d, int ct);
+int xform_y_ppw(int prec, int max_n, int ct);
+int xform_y_tiles(const XformYDesc& d, int ct, int ppw);
 
 // z solves: LDS of one workgroup (z tables + chunk-end exchange), and the
 // batched launch over descriptors (max_modes = largest sweep_modes_bound(na, nb)).

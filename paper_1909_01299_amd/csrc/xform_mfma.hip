@@ -786,7 +786,7 @@ void xform_lines(int prec, int in64, int out64, int acc, const XformDesc* d, int
   }
 }
 
-bool xform_y_use_mfma(int prec, int n) { return n >= 32 && n <= (prec == 0 ? 256 : 512); }
+bool xform_y_use_mfma(int prec, int n) { return n >= 16 && n <= (prec == 0 ? 256 : 512); }
 
 int xform_y_mfma_tiles(const XformYDesc& d) { return ((d.ncols + YM_NC - 1) / YM_NC) * d.P; }
 
@@ -873,11 +873,13 @@ void run_y_list(int prec, const XformYDesc* dev, const std::vector<XformYDesc>& 
     const int g = y_group(prec, host[b]);
     int e = b;
     int max_n = 0, t16 = 0, t8 = 0;
-    while (e < n && y_group(prec, host[e]) == g) {
-      max_n = std::max(max_n, host[e].n);
-      t16 = std::max(t16, xform_y_tiles(host[e], 16));
-      t8 = std::max(t8, xform_y_tiles(host[e], 8));
-      ++e;
+    while (e < n && y_group(prec, host[e]) == g) max_n = std::max(max_n, host[e].n), ++e;
+    // the small-tile kernel takes several planes per workgroup (as many as its
+    // launch will use for the group's longest axis)
+    const int pw16 = g >= 6 ? xform_y_ppw(prec, max_n, 16) : 1, pw8 = g >= 6 ? xform_y_ppw(prec, max_n, 8) : 1;
+    for (int i = b; i < e; ++i) {
+      t16 = std::max(t16, xform_y_tiles(host[i], 16, pw16));
+      t8 = std::max(t8, xform_y_tiles(host[i], 8, pw8));
     }
     if (g < 4)
       xform_y_h3(dev + b, host.data() + b, e - b, htab, ws, nrhs, st);
