@@ -649,7 +649,10 @@ def bench_gridding_b(steps, warmup, with_oracle, refine_steps=1):
     on graded non-uniform x and y steps, 24 x 24 blocks of 23 nodes (dense
     eigenvector transforms everywhere, 23 separators per axis, dense global
     right-hand side), 4 point sources: tuned complex128 and mixed plans, stage
-    tables, the dominant stage's roofline, oracle error on the first source."""
+    tables, the dominant stage's roofline, oracle error on the first source;
+    and the same grid with nested partitions (complex128): the interface
+    problem of the 24 x 24 blocks solved by the cyclic reduction of the 5 x 5
+    partition of every fifth separator."""
     import torch
     import paper_1909_01299_amd as hs
     import workloads as W
@@ -675,11 +678,30 @@ def bench_gridding_b(steps, warmup, with_oracle, refine_steps=1):
         del plan, u
         torch.cuda.empty_cache()
     out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    # nested partitions: the 24 x 24 blocks' interface problem solved by the
+    # cyclic reduction of the 5 x 5 partition made of every fifth separator
+    from dataclasses import replace
+    coarse_p = replace(p, sep_x=p.sep_x[4::5].copy(), sep_y=p.sep_y[4::5].copy())
+    fine = hs.Plan(p, "c128", max_rhs=nrhs)
+    coarse = hs.Plan(coarse_p, "c128", max_rhs=nrhs)
+    coarse.tune(nrhs, cache=TUNE_CACHE)
+    fine.set_coarse(coarse)
+    tuned = fine.tune(nrhs, cache=TUNE_CACHE)
+    u = torch.empty_like(f)
+    dt, stages, dom = time_plans([fine], f, u, steps, warmup)
+    us["nested"] = u[0].cpu().numpy()
+    out["nested_c128"] = {"value": p.unknowns * nrhs * steps / dt, "unit": "unknowns*RHS/s",
+                          "ms_per_step": dt / steps * 1e3, "tuned": tuned,
+                          "coarse_separators_per_axis": [len(coarse_p.sep_x), len(coarse_p.sep_y)],
+                          "stages_ms_per_step": {r["name"]: round(r["ms"], 3) for r in stages}}
+    del fine, coarse, u
+    torch.cuda.empty_cache()
     if with_oracle:
         from oracle import separable
         ref = separable.solve(p, W.point_source_batch(p, srcs[:1]))[0]
-        for prec in ("c128", "mixed"):
-            out[prec]["rel_err_vs_oracle_src0"] = errors_vs(us[prec], ref, p)
+        for prec in ("c128", "mixed", "nested"):
+            key = "nested_c128" if prec == "nested" else prec
+            out[key]["rel_err_vs_oracle_src0"] = errors_vs(us[prec], ref, p)
     return out
 
 

@@ -250,6 +250,24 @@ hs_status hs_get_residuals(hs_plan plan, double* rel, int32_t max_entries, int32
  * allocates and frees two scratch arrays; synchronizes the stream. */
 hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void* stream);
 
+/* Nested partitions (Sec. 2, the remark on multi-level cyclic reduction):
+ * the interface problem of `plan` (Alg. step 5: A w = r with r on its
+ * separator planes) is solved by the cyclic reduction of `coarse` instead of
+ * the global eigenvector basis.  coarse: a plan of the same grid (steps,
+ * layers, k^2, sigma), precision and device, with max_rhs at least plan's,
+ * whose separators are a subset of plan's (it may have none, or a coarser
+ * plan of its own: any depth).  The residual on the separators is scattered
+ * onto a grid array, solved by coarse's own pass (no refinement of its own)
+ * and read back on the separators; the rest of the solve is unchanged.  The
+ * plan keeps the pointer: coarse must outlive it, keep a bound workspace and
+ * not be used concurrently with it.  hs_set_k2 on plan also sets coarse's
+ * k^2.  NULL detaches.  Waits for the device; the workspace layout changes
+ * (hs_plan_workspace_bytes grows by two grid arrays per right-hand side) and
+ * the bound workspace is released: bind one again before solving.
+ * HS_ERR_ARG when coarse does not fit (another grid, precision or device, a
+ * separator not in plan's, max_rhs too small, a cycle, a single-block plan). */
+hs_status hs_plan_set_coarse(hs_plan plan, hs_plan coarse);
+
 /* Set the launch shapes directly (as hs_plan_tune would store them), e.g. to
  * reuse one plan's tuning on another plan of the same shapes: z_chunks in
  * {0 (default for nz), 8, 16, 32}, sine_lines in {0 (default), 4, 8, 16},

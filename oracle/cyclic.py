@@ -12,6 +12,10 @@ the local correction of eq. (7)), in the paper's order:
      boundary, i.e. A_II w_I = -A_{I,Sigma} w_Sigma;
 7.   u = v + w inside the blocks and u = w on Sigma.
 
+`nested` is the multi-level form of the remark that follows the cost
+estimate in Sec. 2: mutually embedded partitions, with step 5 of one level
+solved by the same seven steps on the next coarser partition.
+
 Blocks are the maximal runs of interior nodes between separator planes (a
 separator plane belongs to no block); A^ij is the principal sub-matrix of A
 on a block, so its steps include the ones reaching the separators.
@@ -52,8 +56,10 @@ def _block_solve_all(problem, rhs):
     return out
 
 
-def seven_step(problem, f: np.ndarray):
-    """Returns (u, intermediates) with intermediates v, r (full grid), w_sigma."""
+def seven_step(problem, f: np.ndarray, solve5=None):
+    """Returns (u, intermediates) with intermediates v, r (full grid), w_sigma.
+    solve5 (optional): the solver of step 5's A w = r on the whole grid
+    (default: the global eigen-transform)."""
     f = np.asarray(f, dtype=np.complex128)
     single = f.ndim == 3
     if single:
@@ -64,7 +70,8 @@ def seven_step(problem, f: np.ndarray):
     # steps 3-4
     r = f - apply_A(problem, v)
     # step 5
-    w_full = SeparableSolver(problem).solve(np.where(mask, r, 0.0))
+    rs = np.where(mask, r, 0.0)
+    w_full = SeparableSolver(problem).solve(rs) if solve5 is None else solve5(rs)
     w_sigma = np.where(mask, w_full, 0.0)
     # step 6
     lift = -apply_A(problem, w_sigma)
@@ -76,3 +83,25 @@ def seven_step(problem, f: np.ndarray):
         u = u[0]
         inter = {k: val[0] for k, val in inter.items()}
     return u, inter
+
+
+def nested(problem, f: np.ndarray, coarse_levels):
+    """Multi-level cyclic reduction: the seven steps on `problem`'s
+    separators, whose step 5 is the same method on the next coarser
+    partition coarse_levels[0] = (sep_x, sep_y), each list a subset of the
+    finer one, and so on; the coarsest level's step 5 is the global
+    eigen-transform.  Returns u."""
+    from dataclasses import replace
+    if not coarse_levels:
+        return seven_step(problem, f)[0]
+    sx, sy = (np.asarray(v, np.int32) for v in coarse_levels[0])
+    assert set(sx.tolist()) <= set(problem.sep_x.tolist()) and set(sy.tolist()) <= set(problem.sep_y.tolist())
+    coarser = replace(problem, sep_x=sx, sep_y=sy)
+    rest = coarse_levels[1:]
+    if len(sx) == 0 and len(sy) == 0:
+        solve5 = SeparableSolver(coarser).solve
+    else:
+        def solve5(rhs):
+            return nested(coarser, rhs, rest)
+    return seven_step(problem, f, solve5)[0]
+

@@ -90,6 +90,7 @@ EXPORTS = {
     "hs_batch_destroy": (None, [ctypes.c_void_p]),
     "hs_batch_tune": (ctypes.c_int, [ctypes.c_void_p] * 3 + [ctypes.c_char_p, ctypes.c_void_p]),
     "hs_plan_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_char_p, ctypes.c_void_p]),
+    "hs_plan_set_coarse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "hs_plan_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.c_int32]),
     "hs_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -273,6 +274,18 @@ class Plan:
         return {"z_chunks": inf["z_chunks"], "sine_lines": inf["sine_lines"], "z_fixed_rows": inf["z_fixed_rows"],
                 "global_dense": inf["global_dense"], "fp64_stream": inf["fp64_stream"]}
 
+    def set_coarse(self, coarse: Optional["Plan"]):
+        """Solve this plan's interface problem by the cyclic reduction of a
+        coarser plan on the same grid (its separators a subset of these), or
+        by the global basis again (None).  The workspace is laid out anew and
+        a new one is allocated and bound."""
+        import torch
+        _check(lib().hs_plan_set_coarse(self._h, coarse._h if coarse is not None else None))
+        self._coarse = coarse   # keeps the coarser plan alive as long as this one
+        nbytes = lib().hs_plan_workspace_bytes(self._h, self.max_rhs)
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().hs_plan_bind_workspace(self._h, _ptr(self.workspace), self.workspace.numel()))
+
     def set_launch(self, shapes: dict):
         """Apply launch shapes as returned by tune() (z_chunks, sine_lines,
         z_fixed_rows, global_dense, fp64_stream; a missing global_dense or
@@ -304,6 +317,10 @@ class Plan:
             return                    # tables and pivot scan already hold this k^2
         _check(lib().hs_set_k2(self._h, k2.ctypes.data))
         self._k2 = k2.copy()
+        q = getattr(self, "_coarse", None)
+        while q is not None:            # the library set the coarser plans' k^2 as well
+            q._k2 = k2.copy()
+            q = getattr(q, "_coarse", None)
 
     def _nrhs(self, t):
         return _nrhs_of(t)

@@ -196,6 +196,13 @@ hs_status hs_plan_tune(hs_plan plan, int32_t nrhs, const char* cache_path, void*
   return ret(plan->p.tune(nrhs, cache_path, (hipStream_t)stream, err), err);
 }
 
+hs_status hs_plan_set_coarse(hs_plan plan, hs_plan coarse) {
+  if (!plan) return ret(HS_ERR_ARG, "plan is NULL");
+  if (coarse == plan) return ret(HS_ERR_ARG, "a plan cannot be its own coarser plan");
+  std::string err;
+  return ret(plan->p.set_coarse(coarse ? &coarse->p : nullptr, err), err);
+}
+
 hs_status hs_plan_set_launch(hs_plan plan, int32_t z_chunks, int32_t sine_lines, int32_t z_fixed_rows,
                              int32_t global_dense, int32_t fp64_stream) {
   if (!plan) return ret(HS_ERR_ARG, "plan is NULL");

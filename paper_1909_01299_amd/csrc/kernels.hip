@@ -1004,6 +1004,64 @@ __global__ __launch_bounds__(256) void k_expand(ExpandDesc e, const cplx<R>* __r
 }
 
 // ---------------------------------------------------------------------------
+// Nested partitions (step 5 solved by a coarser plan): the residual on the
+// separator lines scattered onto a zeroed grid array F(r,z,y,x) (crossings
+// from the x lines, whose residual holds them), and the coarser plan's
+// solution W read back onto the lines.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_ml_zero(cplx<R>* __restrict__ F, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) F[i] = mk<R>(0, 0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_ml_scatter(SigmaGeom g, const cplx<R>* __restrict__ ws,
+                                                    cplx<R>* __restrict__ F) {
+  const int r = blockIdx.z;
+  const int64_t nline_x = (int64_t)g.nsx * g.nz * g.NY;
+  const int64_t nline_y = (int64_t)g.nsy * g.nz * g.NX;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  cplx<R>* Fr = F + (int64_t)r * g.f_r;
+  if (e < nline_x) {
+    const int y = int(e % g.NY);
+    const int z = int((e / g.NY) % g.nz);
+    const int si = int(e / ((int64_t)g.NY * g.nz));
+    Fr[((int64_t)z * g.NY + y) * g.NX + g.sep_x[si]] = ws[g.rx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + y];
+  } else if (e < nline_x + nline_y) {
+    const int64_t e2 = e - nline_x;
+    const int x = int(e2 % g.NX);
+    if (g.xblk[x] < 0) return;
+    const int z = int((e2 / g.NX) % g.nz);
+    const int ti = int(e2 / ((int64_t)g.NX * g.nz));
+    Fr[((int64_t)z * g.NY + g.sep_y[ti]) * g.NX + x] = ws[g.ry + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + x];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_ml_gather(SigmaGeom g, const double2* __restrict__ W,
+                                                   cplx<R>* __restrict__ ws) {
+  const int r = blockIdx.z;
+  const int64_t nline_x = (int64_t)g.nsx * g.nz * g.NY;
+  const int64_t nline_y = (int64_t)g.nsy * g.nz * g.NX;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double2* Wr = W + (int64_t)r * g.f_r;
+  if (e < nline_x) {
+    const int y = int(e % g.NY);
+    const int z = int((e / g.NY) % g.nz);
+    const int si = int(e / ((int64_t)g.NY * g.nz));
+    ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + y] =
+        cvt<cplx<R>>(Wr[((int64_t)z * g.NY + y) * g.NX + g.sep_x[si]]);
+  } else if (e < nline_x + nline_y) {
+    const int64_t e2 = e - nline_x;
+    const int x = int(e2 % g.NX);
+    const int z = int((e2 / g.NX) % g.nz);
+    const int ti = int(e2 / ((int64_t)g.NX * g.nz));
+    ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + x] =
+        cvt<cplx<R>>(Wr[((int64_t)z * g.NY + g.sep_y[ti]) * g.NX + x]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Interface kernels (steps 3-6 of the two-level reduction)
 // ---------------------------------------------------------------------------
 
@@ -1729,6 +1787,35 @@ void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* 
   else
     hipLaunchKernelGGL((k_sigma_scatter<float, double2, false>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st,
                        g, (const float2*)ws, (double2*)u);
+}
+
+void ml_scatter(int prec, const SigmaGeom& g, void* ws, int64_t f_off, int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nsx * g.nz * g.NY + (int64_t)g.nsy * g.nz * g.NX;
+  if (nrhs == 0) return;
+  const int64_t total = (int64_t)nrhs * g.f_r;
+  const unsigned zb = unsigned(std::min<int64_t>((total + 255) / 256, 65536));
+  if (prec == 0) {
+    double2* F = (double2*)ws + f_off;
+    hipLaunchKernelGGL((k_ml_zero<double>), dim3(zb), dim3(256), 0, st, F, total);
+    if (n > 0)
+      hipLaunchKernelGGL((k_ml_scatter<double>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const double2*)ws, F);
+  } else {
+    float2* F = (float2*)ws + f_off;
+    hipLaunchKernelGGL((k_ml_zero<float>), dim3(zb), dim3(256), 0, st, F, total);
+    if (n > 0)
+      hipLaunchKernelGGL((k_ml_scatter<float>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const float2*)ws, F);
+  }
+}
+
+void ml_gather(int prec, const SigmaGeom& g, const void* W, void* ws, int nrhs, hipStream_t st) {
+  const int64_t n = (int64_t)g.nsx * g.nz * g.NY + (int64_t)g.nsy * g.nz * g.NX;
+  if (n == 0 || nrhs == 0) return;
+  if (prec == 0)
+    hipLaunchKernelGGL((k_ml_gather<double>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const double2*)W,
+                       (double2*)ws);
+  else
+    hipLaunchKernelGGL((k_ml_gather<float>), dim3(grid1(n), 1, nrhs), dim3(256), 0, st, g, (const double2*)W,
+                       (float2*)ws);
 }
 
 static dim3 residual_grid(const StencilGeom& g, int nrhs) {

@@ -204,6 +204,11 @@ void sigma_resid(int prec, int in64, const SigmaGeom& g, const void* f, void* ws
 void lift(int prec, const SigmaGeom& g, const LiftBlock* lb, int nblocks, void* ws, int nrhs,
           hipStream_t st);
 void sigma_scatter(int prec, int acc, const SigmaGeom& g, const void* ws, void* u, int nrhs, hipStream_t st);
+// nested partitions: zero F (f_off elements into ws, nrhs grid arrays) and
+// scatter the separator residual onto it; read W (complex128) back onto the
+// separator lines wx / wy
+void ml_scatter(int prec, const SigmaGeom& g, void* ws, int64_t f_off, int nrhs, hipStream_t st);
+void ml_gather(int prec, const SigmaGeom& g, const void* W, void* ws, int nrhs, hipStream_t st);
 
 // One plan's residual in a batched launch: its stencil, the element offsets of
 // its f, u (complex128) and r (complex64) from the launch's base pointers, its

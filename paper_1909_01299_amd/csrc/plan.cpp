@@ -479,6 +479,7 @@ void Plan::layout_workspace() {
     for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms)
       np += part_elems(NX, NY, std::clamp(nsx - g0, 0, kMaxTerms), std::clamp(nsy - g0, 0, kMaxTerms));
     w_cpart = np > 0 ? take(np) : 0;
+    w_F = coarse ? take(R * (int64_t)NX * NY * NZ) : 0;
   }
   ws_elems = size_t(off);
   const size_t esz = prec == 0 ? 16 : 8;
@@ -502,6 +503,8 @@ void Plan::layout_workspace() {
   bytes += align_up(int64_t(R * n_rwg * 3 * 8), 256);
   off_norms = bytes;
   bytes += align_up(int64_t((kMaxRefine + 1) * R * 3 * 8), 256);
+  off_W = bytes;
+  if (coarse && decomposed) bytes += align_up(int64_t(R * N * 16), 256);   // the coarse solution
   ws_bytes = bytes;
 }
 
@@ -890,6 +893,38 @@ hs_status Plan::set_global_dense(bool dense, std::string& err) {
   return upload_descs(err);
 }
 
+hs_status Plan::set_coarse(Plan* c, std::string& err) {
+  if (c) {
+    if (!decomposed) { err = "a single block has no interface problem for a coarser plan"; return HS_ERR_ARG; }
+    for (const Plan* q = c; q; q = q->coarse)
+      if (q == this) { err = "the coarser plans would form a cycle"; return HS_ERR_ARG; }
+    if (c->prec != prec) { err = "the coarser plan has another precision"; return HS_ERR_ARG; }
+    if (c->device != device) { err = "the coarser plan lives on another device"; return HS_ERR_ARG; }
+    if (c->max_rhs < max_rhs) { err = "the coarser plan's max_rhs is smaller"; return HS_ERR_ARG; }
+    if (c->NX != NX || c->NY != NY || c->NZ != NZ || c->hx != hx || c->hy != hy || c->hz != hz ||
+        c->layer != layer || c->k2 != k2 || c->sig_node != sig_node || c->sig_step != sig_step) {
+      err = "the coarser plan is not on the same grid (steps, layers, k^2, sigma)";
+      return HS_ERR_ARG;
+    }
+    auto subset = [](const std::vector<int>& a, const std::vector<int>& b) {
+      return std::includes(b.begin(), b.end(), a.begin(), a.end());
+    };
+    if (!subset(c->sepx, sepx) || !subset(c->sepy, sepy)) {
+      err = "the coarser plan's separators must be a subset of this plan's (nested partitions)";
+      return HS_ERR_ARG;
+    }
+  }
+  if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
+  // solves in flight use the workspace being re-laid out
+  if (hipDeviceSynchronize() != hipSuccess) { err = "hipDeviceSynchronize failed"; return HS_ERR_DEVICE; }
+  coarse = c;
+  layout_workspace();
+  build_descriptors();
+  set_fp64_threshold();
+  ws = nullptr;   // the layout changed: a workspace of hs_plan_workspace_bytes must be bound again
+  return upload_descs(err);
+}
+
 hs_status Plan::set_k2(const double* k2v, std::string& err) {
   if (!k2v) { err = "k2 is NULL"; return HS_ERR_ARG; }
   // solves in flight read the tables and descriptors being replaced
@@ -937,7 +972,9 @@ hs_status Plan::set_k2(const double* k2v, std::string& err) {
     err = "hipMemcpy failed";
     return HS_ERR_DEVICE;
   }
-  return upload_descs(err);   // the FP64 threshold of the sweeps depends on k^2
+  st = upload_descs(err);   // the FP64 threshold of the sweeps depends on k^2
+  if (st == HS_OK && coarse) st = coarse->set_k2(k2v, err);
+  return st;
 }
 
 hs_status Plan::bind(void* p, size_t bytes, std::string& err) {
@@ -1116,28 +1153,43 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
     stage_begin("sigma_resid", R * nsig * (esz_in + 3 * esz), R * nsig * 16, st);
     sigma_resid(prec, in64, g, f, W, nrhs, st);
     stage_end();
-    // step 5: global interface solve, evaluated on the separators
-    const double gfl = double(NZ) * (nsx * double(NY) * NY + nsy * double(NX) * NX) * 8.0;
-    stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
-    run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, dtab16, W, W, nrhs, st);
-    stage_end();
-    if (dense_glob) {
-      stage_begin("sigma_expand", R * (nsig + nglob) * esz, R * nglob * 8 * (nsx + nsy), st);
-      expand(prec, ex, T, W, nrhs, st);
+    if (coarse) {
+      // step 5 by the next level: r on the separators scattered onto the grid,
+      // solved by the coarser plan's own cyclic reduction, read back on them
+      stage_begin("coarse_scatter", R * (nglob + nsig) * esz, 0, st);
+      ml_scatter(prec, g, W, w_F, nrhs, st);
       stage_end();
-      stage_begin("zsweep_global", R * 2 * nglob * esz, R * nglob * thomas, st);
+      stage_begin("coarse_solve", 0, 0, st);
+      coarse->solve_pass((const unsigned char*)W + size_t(w_F) * (prec == 0 ? 16 : 8), prec == 0 ? 1 : 0,
+                         (unsigned char*)W + off_W, 0, nrhs, st);
+      stage_end();
+      stage_begin("coarse_gather", R * nsig * (16 + esz), 0, st);
+      ml_gather(prec, g, (const unsigned char*)W + off_W, W, nrhs, st);
+      stage_end();
     } else {
-      stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
+      // step 5: global interface solve, evaluated on the separators
+      const double gfl = double(NZ) * (nsx * double(NY) * NY + nsy * double(NX) * NX) * 8.0;
+      stage_begin("sigma_xform_in", R * nsig * 2 * esz, R * gfl, st);
+      run_lines_list(prec, 0, 0, 0, p_glob_in, d_glob_in, T, dtab16, W, W, nrhs, st);
+      stage_end();
+      if (dense_glob) {
+        stage_begin("sigma_expand", R * (nsig + nglob) * esz, R * nglob * 8 * (nsx + nsy), st);
+        expand(prec, ex, T, W, nrhs, st);
+        stage_end();
+        stage_begin("zsweep_global", R * 2 * nglob * esz, R * nglob * thomas, st);
+      } else {
+        stage_begin("zsweep_global", R * (nsig + nglob) * esz, R * nglob * (thomas + 8 * (nsx + nsy)), st);
+      }
+      sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
+            sel(3), tune_side ? &side : nullptr, tune_full ? NZ : 0);
+      stage_end();
+      stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
+      contract(prec, p_sig, cl_sig, T, W, nrhs, st);
+      stage_end();
+      stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
+      run_lines_list(prec, 0, 0, 0, p_glob_out, d_glob_out, T, dtab16, W, W, nrhs, st);
+      stage_end();
     }
-    sweep(prec, p_sweepG, 1, modes(d_sweepG), NZ, xterms(d_sweepG), T, dtab64, W, nrhs, st, tune_chunks,
-          sel(3), tune_side ? &side : nullptr, tune_full ? NZ : 0);
-    stage_end();
-    stage_begin("sigma_contract", R * (nglob + nsig) * esz, R * nglob * (nsx + nsy) * 8, st);
-    contract(prec, p_sig, cl_sig, T, W, nrhs, st);
-    stage_end();
-    stage_begin("sigma_xform_out", R * nsig * 2 * esz, R * gfl, st);
-    run_lines_list(prec, 0, 0, 0, p_glob_out, d_glob_out, T, dtab16, W, W, nrhs, st);
-    stage_end();
     // step 6: lift the separator values into the blocks and sweep again
     stage_begin("lift", R * nface * 2 * esz, R * nface * 6, st);
     lift(prec, g, p_lift, nb, W, nrhs, st);
@@ -1169,6 +1221,8 @@ void Plan::solve_pass(const void* f, int in64, void* u, int acc, int nrhs, hipSt
 
 hs_status Plan::solve(const void* f, void* u, int nrhs, hipStream_t st, std::string& err) {
   if (!ws) { err = "no workspace bound"; return HS_ERR_STATE; }
+  for (const Plan* q = coarse; q; q = q->coarse)
+    if (!q->ws) { err = "a coarser plan has no workspace bound"; return HS_ERR_STATE; }
   if (nrhs < 1 || nrhs > max_rhs) { err = "nrhs out of range [1, max_rhs]"; return HS_ERR_ARG; }
   if (!f || !u) { err = "f and u must be non-NULL"; return HS_ERR_ARG; }
   if (hipSetDevice(device) != hipSuccess) { err = "hipSetDevice failed"; return HS_ERR_DEVICE; }
@@ -1318,6 +1372,7 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
   for (int v : sepy) key << v << ",";
   key << "|ax";
   for (auto& a : axes) key << a.n << (a.dstV ? "s" : "d") << ",";
+  for (const Plan* q = coarse; q; q = q->coarse) key << "|coarse" << q->sepx.size() << "x" << q->sepy.size();
   const std::string k = key.str();
   if (cache_path && *cache_path) {
     std::ifstream in(cache_path);

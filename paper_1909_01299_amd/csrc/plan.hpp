@@ -142,6 +142,11 @@ struct Plan {
   int64_t gpplane = 0;           // its z-plane stride
   int64_t w_cpart = 0;           // slab partial sums of the interface contraction (split plane only)
   ExpandDesc ex{};               // dense_glob: dense spectral right-hand side of the global solve
+  // nested partitions: the interface problem of Alg. step 5 solved by the
+  // cyclic reduction of a coarser plan (its separators a subset of these)
+  Plan* coarse = nullptr;
+  int64_t w_F = 0;               // coarse: the interface residual scattered onto the grid [R][nz][ny][nx]
+  size_t off_W = 0;              // coarse: byte offset of its solution (complex128, same layout)
 
   // ---------------- descriptors (device copies in one buffer)
   void* ddesc = nullptr;
@@ -198,6 +203,9 @@ struct Plan {
   // form of the global interface solve's right-hand side (decomposed grids):
   // dense expansion or low-rank terms; waits for the device, rebuilds descriptors
   hs_status set_global_dense(bool dense, std::string& err);
+  // attach (or detach with nullptr) the coarser plan of a nested partition;
+  // re-lays out the workspace and unbinds it
+  hs_status set_coarse(Plan* c, std::string& err);
   // relative residuals of the last solve, [eval][r] (synchronous copy)
   hs_status residuals(std::vector<double>& rel, int& evals, int& nrhs, std::string& err) const;
 

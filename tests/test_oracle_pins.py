@@ -272,6 +272,22 @@ def test_seven_step_gridding_b_matches_sparse_lu():
     assert operator.rel_err(u, direct.solve_splu(p, f)) < 1e-12
 
 
+def test_nested_partitions_match_sparse_lu():
+    """Multi-level cyclic reduction on mutually embedded partitions: three
+    levels (5 x 4 separators, then 2 x 2 of them, then one each) and two
+    levels ending in a single block reproduce the direct solve."""
+    rng = _rng(23)
+    p = W.gridding_b_problem(36, 25, 5, 3, rng, pml=3)
+    f = W.complex_normal(rng, (2,) + p.shape)
+    ref = direct.solve_splu(p, f)
+    sx, sy = p.sep_x.tolist(), p.sep_y.tolist()
+    levels = [([sx[1], sx[3]], [sy[0], sy[2]]), ([sx[3]], [sy[2]])]
+    assert operator.rel_err(cyclic.nested(p, f, levels), ref) < 1e-12
+    assert operator.rel_err(cyclic.nested(p, f, [([], [])]), ref) < 1e-12
+    with pytest.raises(AssertionError):
+        cyclic.nested(p, f, [([sx[0] + 1], [])])
+
+
 def test_block_ranges():
     assert cyclic.block_ranges(10, []) == [(0, 9)]
     assert cyclic.block_ranges(10, [3, 6]) == [(0, 2), (4, 5), (7, 9)]
