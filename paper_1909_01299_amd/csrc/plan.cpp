@@ -1429,7 +1429,7 @@ hs_status Plan::tune(int nrhs, const char* cache_path, hipStream_t st, std::stri
   struct Cand { int gd, c, l, fr, sd; float ms; };
   std::vector<Cand> cands;
   std::vector<int> gds;
-  if (decomposed && !glob_forced) gds = {0, 1};
+  if (decomposed && !glob_forced && !coarse) gds = {0, 1};   // with a coarser plan the global step is not run
   else gds = {dense_glob ? 1 : 0};
   for (int gd : gds)
     for (int c : chunks)
