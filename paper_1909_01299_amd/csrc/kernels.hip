@@ -748,12 +748,13 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 // With full-wave rows the x sums of the U rows are reduced together: the
 // first butterfly steps exchange half of the rows each (transposed
 // reduction), so 4 rows cost 7 exchanges instead of 24 (2 rows: 6, not 12).
-template <typename R, int SMAX>
+template <typename R, int SMAX, int NT, bool PF>
 __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict__ descs, int max_slab, int max_cs,
                                                   const cplx<R>* __restrict__ tab, cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
   constexpr int U = SMAX <= 2 ? 4 : 2;
   constexpr int SW = SMAX * 64;   // LDS stride of one x term
+  static_assert(NT <= kMaxTerms, "term count");
   extern __shared__ unsigned char smem_raw[];
   const ContractDesc d = descs[blockIdx.y];
   const int z = blockIdx.x / (max_slab * max_cs);
@@ -770,9 +771,9 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   const int b0 = slab * d.rows, nrow = min(d.nb, b0 + d.rows) - b0;
   C* cxs = reinterpret_cast<C*>(smem_raw);   // [nxt][SMAX*64], zero past na
   C* cys = cxs + d.nxt * SW;                 // [nyt][rows]
-  C* yb = cys + d.nyt * d.rows;              // [3][kMaxTerms][64]
+  C* yb = cys + d.nyt * d.rows;              // [3][NT][64]
 #pragma unroll
-  for (int t = 0; t < kMaxTerms; ++t) {
+  for (int t = 0; t < NT; ++t) {
     if (t < d.nxt)
       for (int i = threadIdx.x; i < SW; i += 256)
         cxs[t * SW + i] = i < na ? tab[d.cx[t] + (int64_t)(c0 + i) * d.cx_stride[t]] : mk<R>(0, 0);
@@ -781,11 +782,11 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   }
   __syncthreads();
 
-  C yacc[SMAX][kMaxTerms];
+  C yacc[SMAX][NT];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s)
 #pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) yacc[s][t] = mk<R>(0, 0);
+    for (int t = 0; t < NT; ++t) yacc[s][t] = mk<R>(0, 0);
   const C* xp = ws + d.src + (int64_t)r * d.src_r + (int64_t)z * d.plane + (int64_t)b0 * d.rs + c0;
   int col[SMAX];
 #pragma unroll
@@ -798,16 +799,36 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
                            (int64_t)z * d.xpart_z
                      : d.dx + t * d.dx_t + (int64_t)r * d.dx_r + (int64_t)z * d.dx_z;
   };
-  for (int i0 = rg; i0 < nrow; i0 += U * RG) {
-    C xv[U][SMAX];
+  // PF: the rows of the next group load while this group's sums are formed
+  C xn[PF ? U : 1][SMAX];
+  auto load_rows = [&](int i0, C (&x)[U][SMAX]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * d.rs;
 #pragma unroll
-      for (int s = 0; s < SMAX; ++s) xv[u][s] = xp[row + col[s]];
+      for (int s = 0; s < SMAX; ++s) x[u][s] = xp[row + col[s]];
+    }
+  };
+  if constexpr (PF)
+    if (rg < nrow) load_rows(rg, xn);
+  for (int i0 = rg; i0 < nrow; i0 += U * RG) {
+    C xv[U][SMAX];
+    if constexpr (PF) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) xv[u][s] = xn[u][s];
+      if (i0 + U * RG < nrow) load_rows(i0 + U * RG, xn);
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t row = (int64_t)min(i0 + u * RG, nrow - 1) * d.rs;
+#pragma unroll
+        for (int s = 0; s < SMAX; ++s) xv[u][s] = xp[row + col[s]];
+      }
     }
 #pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) {
+    for (int t = 0; t < NT; ++t) {
       if (t < d.nyt) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -871,7 +892,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
 #pragma unroll
       for (int s = 0; s < SMAX; ++s)
 #pragma unroll
-        for (int t = 0; t < kMaxTerms; ++t)
+        for (int t = 0; t < NT; ++t)
           if (t < d.nyt) yacc[s][t] = cadd(yacc[s][t], shfl_xor_c(yacc[s][t], m, 64));
     }
   }
@@ -881,18 +902,18 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
     if (s < S && d.nyt > 0) {
       if (w > 0 && lane < L)
 #pragma unroll
-        for (int t = 0; t < kMaxTerms; ++t)
-          if (t < d.nyt) yb[((w - 1) * kMaxTerms + t) * 64 + lane] = yacc[s][t];
+        for (int t = 0; t < NT; ++t)
+          if (t < d.nyt) yb[((w - 1) * NT + t) * 64 + lane] = yacc[s][t];
       __syncthreads();
       const int al = la + s * L;
       const int a = c0 + al;
       if (w == 0 && lane < L && al < na) {
 #pragma unroll
-        for (int t = 0; t < kMaxTerms; ++t) {
+        for (int t = 0; t < NT; ++t) {
           if (t < d.nyt) {
-            C v = cadd(yacc[s][t], yb[(0 * kMaxTerms + t) * 64 + lane]);
-            v = cadd(v, yb[(1 * kMaxTerms + t) * 64 + lane]);
-            v = cadd(v, yb[(2 * kMaxTerms + t) * 64 + lane]);
+            C v = cadd(yacc[s][t], yb[(0 * NT + t) * 64 + lane]);
+            v = cadd(v, yb[(1 * NT + t) * 64 + lane]);
+            v = cadd(v, yb[(2 * NT + t) * 64 + lane]);
             const int64_t o = split ? d.part + (int64_t)r * d.part_r + (int64_t)slab * d.part_s + t * d.part_t +
                                           (int64_t)z * d.part_z + a
                                     : d.dy + t * d.dy_t + (int64_t)r * d.dy_r + (int64_t)z * d.dy_z + a;
@@ -1128,6 +1149,8 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_lift(SigmaGeom g, const LiftBlock* __restrict__ lb,
                                               cplx<R>* __restrict__ ws) {
   using C = cplx<R>;
+  // B's two-entry arrays are read through selects below: a run-time index
+  // into them would place B in scratch memory
   const LiftBlock B = lb[blockIdx.y];
   const int r = blockIdx.z;
   const int64_t per_face = (int64_t)g.nz * g.NF;
@@ -1141,12 +1164,12 @@ __global__ __launch_bounds__(256) void k_lift(SigmaGeom g, const LiftBlock* __re
     if (face < 2) {
       const int si = face == 0 ? B.sep_lo_x : B.sep_hi_x;
       if (si >= 0 && i < B.nby)
-        v = cmul(cscale(coef[B.cfx[face]], sg),
+        v = cmul(cscale(coef[face == 0 ? B.cfx[0] : B.cfx[1]], sg),
                  ws[g.wx + (((int64_t)r * g.nsx + si) * g.nz + z) * g.NY + B.y0 + i]);
     } else {
       const int ti = face == 2 ? B.sep_lo_y : B.sep_hi_y;
       if (ti >= 0 && i < B.nbx)
-        v = cmul(cscale(coef[B.cfy[face - 2]], sg),
+        v = cmul(cscale(coef[face == 2 ? B.cfy[0] : B.cfy[1]], sg),
                  ws[g.wy + (((int64_t)r * g.nsy + ti) * g.nz + z) * g.NX + B.x0 + i]);
     }
     ws[g.gface + (((int64_t)blockIdx.y * g.rmax + r) * 4 + face) * g.face_f + (int64_t)z * g.NF + i] = v;
@@ -1203,6 +1226,16 @@ __global__ __launch_bounds__(256) void k_sigma_scatter(SigmaGeom g, const cplx<R
 // which drops the boundary terms; the terms are summed in the order centre,
 // x-1, x+1, y-1, y+1, z-1, z+1.
 constexpr int RZ_TX = 64, RZ_TY = 4, RZ_ZC = 32;
+
+// p[0] where c holds, else zero.  Returned by value: a conditional between
+// the load and a named zero would be an lvalue, which clang lowers to one
+// flat load from a select of the global address and a stack slot.
+__device__ __forceinline__ double2 load_or_zero(bool c, const double2* p) {
+  double2 v = mk<double>(0, 0);
+  if (c) v = *p;
+  return v;
+}
+
 // part (may be NULL): per workgroup, the sums of |r|^2, |f|^2 and |u|^2 over
 // its points (three doubles at part + 3 * workgroup index, workgroups
 // numbered x fastest, then z chunk, then right-hand side); write_out = 0
@@ -1223,19 +1256,18 @@ __device__ __forceinline__ void residual_body(const StencilGeom& g, const double
     const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
     const double2* uc0 = u + (int64_t)bz * sz * g.nz + (int64_t)y * sy + x;   // column (x, y)
     const int64_t col = uc0 - u;
-    const double2 zero = mk<double>(0, 0);
     const double2 cxd = g.xd[x], cyd = g.yd[y];
     const double2 cxl = g.xl[x], cxu = g.xu[x], cyl = g.yl[y], cyu = g.yu[y];
     const bool hx0 = x > 0, hx1 = x + 1 < g.nx, hy0 = y > 0, hy1 = y + 1 < g.ny;
-    double2 um = z0 > 0 ? uc0[(int64_t)(z0 - 1) * sz] : zero;
+    double2 um = load_or_zero(z0 > 0, uc0 + (int64_t)(z0 - 1) * sz);
     double2 uc = uc0[(int64_t)z0 * sz];
     const double2 cxy = cadd(cxd, cyd);
 #pragma unroll 4
     for (int z = z0; z < z1; ++z) {
       const double2* pz = uc0 + (int64_t)z * sz;
-      const double2 up = z + 1 < g.nz ? pz[sz] : zero;
-      const double2 vxl = hx0 ? pz[-1] : zero, vxu = hx1 ? pz[1] : zero;
-      const double2 vyl = hy0 ? pz[-sy] : zero, vyu = hy1 ? pz[sy] : zero;
+      const double2 up = load_or_zero(z + 1 < g.nz, pz + sz);
+      const double2 vxl = load_or_zero(hx0, pz - 1), vxu = load_or_zero(hx1, pz + 1);
+      const double2 vyl = load_or_zero(hy0, pz - sy), vyu = load_or_zero(hy1, pz + sy);
       // sigma of the plane scales its x and y terms (exact when it is 1)
       const double sg = g.sg[z].x;
       double2 au = cmul(cadd(cscale(cxy, sg), g.zd[z]), uc);
@@ -1699,37 +1731,48 @@ ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec) {
     L.fin_units = std::max<int64_t>(L.fin_units, fin);
     lds_elems = std::max<size_t>(lds_elems, size_t(d[i].nyt) * d[i].rows + 3 * kMaxTerms * 64);
     lds_x = std::max<size_t>(lds_x, size_t(d[i].nxt));
+    L.max_terms = std::max(L.max_terms, std::max(d[i].nxt, d[i].nyt));
   }
   L.smax = L.smax <= 1 ? 1 : L.smax <= 2 ? 2 : L.smax <= 4 ? 4 : L.smax <= 6 ? 6 : 8;
   L.lds = (lds_elems + lds_x * L.smax * 64) * (prec == 0 ? 16 : 8);
   return L;
 }
 
-template <typename R, int SMAX>
+template <typename R, int SMAX, int NT>
 static void launch_contract(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
                             hipStream_t st) {
   using C = cplx<R>;
   const dim3 grid(unsigned(L.max_nz * L.max_slab * L.max_cs), unsigned(L.ndesc), unsigned(nrhs));
-  hipLaunchKernelGGL((k_contract<R, SMAX>), grid, dim3(256), L.lds, st, d, L.max_slab, L.max_cs, (const C*)tab,
+  hipLaunchKernelGGL((k_contract<R, SMAX, NT, NT == 2 && SMAX <= 4>), grid, dim3(256), L.lds, st, d, L.max_slab, L.max_cs, (const C*)tab,
                      (C*)ws);
   if (L.fin_units > 0)
     hipLaunchKernelGGL((k_contract_fin<R>), dim3(unsigned((L.fin_units + 255) / 256), L.ndesc, nrhs), dim3(256), 0,
                        st, d, (C*)ws);
 }
 
+template <typename R, int NT>
+static void contract_nt(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
+                        hipStream_t st) {
+  if (L.smax <= 1)
+    launch_contract<R, 1, NT>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 2)
+    launch_contract<R, 2, NT>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 4)
+    launch_contract<R, 4, NT>(d, L, tab, ws, nrhs, st);
+  else if (L.smax <= 6)
+    launch_contract<R, 6, NT>(d, L, tab, ws, nrhs, st);
+  else
+    launch_contract<R, 8, NT>(d, L, tab, ws, nrhs, st);
+}
+
+// two-term sums (the four faces of a block) get their own, smaller kernels
 template <typename R>
 static void contract_r(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
                        hipStream_t st) {
-  if (L.smax <= 1)
-    launch_contract<R, 1>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 2)
-    launch_contract<R, 2>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 4)
-    launch_contract<R, 4>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 6)
-    launch_contract<R, 6>(d, L, tab, ws, nrhs, st);
+  if (L.max_terms <= 2)
+    contract_nt<R, 2>(d, L, tab, ws, nrhs, st);
   else
-    launch_contract<R, 8>(d, L, tab, ws, nrhs, st);
+    contract_nt<R, kMaxTerms>(d, L, tab, ws, nrhs, st);
 }
 
 void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,

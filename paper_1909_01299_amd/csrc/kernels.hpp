@@ -191,6 +191,7 @@ bool sweep_rows_fixed(int chunks, int nz);
 // plane size; contract_launch gathers the launch shape of a descriptor list.
 struct ContractLaunch {
   int ndesc = 0, max_slab = 1, max_cs = 1, smax = 1, max_nz = 0;
+  int max_terms = 0;       // most x or y terms of one descriptor
   int64_t fin_units = 0;   // largest count of slab sums of a split descriptor (0: none split)
   size_t lds = 0;          // dynamic LDS bytes
 };
