@@ -1698,10 +1698,11 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 }
 
 void contract_split(ContractDesc& d) {
-  // at most 512 columns per workgroup (8 per lane); about 16K elements per
-  // workgroup: whole planes for blocks, row slabs for the global plane so
-  // that there are enough workgroups to fill the chip
-  d.ncs = (d.na + 511) / 512;
+  // at most 256 columns per workgroup (4 per lane, which keeps the kernel at
+  // three waves per SIMD); about 16K elements per workgroup: whole planes for
+  // blocks, row slabs for the global plane so that there are enough
+  // workgroups to fill the chip
+  d.ncs = (d.na + 255) / 256;
   d.cols = (d.na + d.ncs - 1) / d.ncs;
   const int64_t elems = (int64_t)d.cols * d.nb;
   int nslab = int(std::max<int64_t>(1, std::min<int64_t>(d.nb, (elems + 16383) / 16384)));
