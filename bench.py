@@ -243,6 +243,78 @@ def sq_summary(dir1, dir2):
               f"{d['SQ_LDS_BANK_CONFLICT'] / max(d['SQ_INSTS_LDS'], 1):5.2f}  {name}")
 
 
+MFMA_COUNTERS = "SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F16 SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE"
+
+
+def mfma_summary(triples):
+    """Issued matrix-core rate of the dense transform kernels of the 64-block
+    batch: per precision P, a rocprofv3 --pmc run of MFMA_COUNTERS and a
+    kernel trace of the same command; per kernel and grid, 512 x the MFMA
+    MOPS count (FP64 for complex128, F16 for the split-fp16 mixed solves)
+    over the kernel-trace time, against the dense peak of that type."""
+    import csv
+    import re
+    import subprocess
+    import collections
+
+    def norm(name):
+        if name.startswith("_Z"):
+            try:
+                name = subprocess.run(["c++filt", name], capture_output=True, text=True).stdout.strip() or name
+            except OSError:
+                pass
+        name = name.replace("hs::(anonymous namespace)::", "").replace("void ", "")
+        name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", name)
+        return re.sub(r"\(.*", "", name)
+
+    print("# rocprofv3 MFMA counters: batched 64 blocks x 8 RHS (one warm-up + one timed solve), dense transform kernels")
+    print("# commands (R = repository root), per precision P in {c128, mixed}:")
+    print(f"#   cd /tmp && export TMPDIR=/tmp && timeout -s KILL 180 rocprofv3 --pmc {MFMA_COUNTERS} --output-format csv "
+          "-d $R/gpurun_out/mfma/c3_P -o run -- python3 $R/bench.py --c3-only P --c3-steps 1")
+    print("#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --output-format csv -d $R/gpurun_out/mfma/c3_P_kt "
+          "-o run -- python3 $R/bench.py --c3-only P --c3-steps 1")
+    print("# summary: python3 $R/bench.py --mfma-summary c128 gpurun_out/mfma/c3_c128 gpurun_out/mfma/c3_c128_kt "
+          "mixed gpurun_out/mfma/c3_mixed gpurun_out/mfma/c3_mixed_kt")
+    print("# issued matrix flop/s = 512 * SQ_INSTS_VALU_MFMA_MOPS_<type> / (kernel-trace duration); "
+          "peaks (dense): FP64 78.6, fp16 2500 TFLOP/s")
+    print("# split-fp16 kernels issue three fp16 products per FP32-class product")
+    print("# columns: precision, dispatches, total ms, issued TFLOP/s, fraction of the type's peak, kernel")
+    for i in range(0, len(triples), 3):
+        prec, pmc, kt = triples[i:i + 3]
+        ctr = "SQ_INSTS_VALU_MFMA_MOPS_F64" if prec == "c128" else "SQ_INSTS_VALU_MFMA_MOPS_F16"
+        peak = PEAK_F64 if prec == "c128" else 2.5e15
+        mops = collections.Counter()
+        for _, name, grid, v in _counter_rows(pmc, ctr):
+            mops[(norm(name), grid)] += v
+        dur = collections.Counter()
+        cnt = collections.Counter()
+        for path in glob_csv(kt, "*kernel_trace.csv"):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+                    key = (norm(r["Kernel_Name"]), g)
+                    dur[key] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+                    cnt[key] += 1
+        tot_f = tot_t = 0.0
+        for key, m in sorted(mops.items(), key=lambda kv: -dur.get(kv[0], 0)):
+            if m <= 0 or dur.get(key, 0) <= 0:
+                continue
+            fl = 512.0 * m
+            tot_f += fl
+            tot_t += dur[key]
+            print(f"{prec:6s} {cnt[key]:4d} {dur[key] * 1e3:9.2f} {fl / dur[key] / 1e12:8.1f} {fl / dur[key] / peak:6.3f}  "
+                  f"{key[0]}  grid={key[1]}")
+        if tot_t > 0:
+            kind = "F64" if prec == "c128" else "F16"
+            print(f"{prec:6s}  all {tot_t * 1e3:9.2f} {tot_f / tot_t / 1e12:8.1f} {tot_f / tot_t / peak:6.3f}  "
+                  f"(all {kind} matrix kernels)")
+
+
+def glob_csv(folder, pattern):
+    import glob
+    return glob.glob(os.path.join(folder, "**", pattern), recursive=True)
+
+
 def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool = False):
     """Text summary of a rocprofv3 kernel trace: per kernel and grid, the
     number of dispatches, the average duration and the share of the total.
@@ -612,7 +684,79 @@ def bench_c5(steps, warmup, refine_steps=1, with_oracle=True, precs=("c128", "mi
     return out
 
 
-def bench_c2(steps, warmup, args, with_oracle):
+def bench_c5_streams(steps, warmup):
+    """The headline workload (complex128) as two independent halves: the 16
+    sources split 8 + 8, each half with its own four plans and workspace on
+    its own stream, so the kernels of one half overlap those of the other
+    (the z solves are latency-bound and leave HBM bandwidth idle).  Same
+    memory as one 16-source plan set.  Timed like the headline (a step is
+    every frequency of both halves; synchronised on both sides of the timed
+    steps), against one stream of 16-source solves; the results of the two
+    schedules must agree bit for bit."""
+    import torch
+    import paper_1909_01299_amd as hs
+    import workloads as W
+    torch.cuda.set_device(0)
+    p, srcs, omegas = W.c5_multi_rhs()
+    nrhs = len(srcs)
+    f = point_sources_device(p, srcs)
+    u = torch.empty_like(f)
+    per_step = p.unknowns * nrhs * len(omegas)
+
+    def plan_set(n):
+        plans, ws = [], None
+        for om in omegas:
+            pl = hs.Plan(p.with_k2(p.k2 * om ** 2), "c128", max_rhs=n, workspace=ws)
+            ws = pl.workspace
+            plans.append(pl)
+        return plans
+
+    def timed(step):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    one = plan_set(nrhs)
+    tuned = one[0].tune(nrhs, cache=TUNE_CACHE)
+    for pl in one[1:]:
+        pl.set_launch(tuned)
+    t_one = timed(lambda: [pl.solve(f, out=u) for pl in one])
+    ref = u.clone()
+    del one
+    torch.cuda.empty_cache()
+    h = nrhs // 2
+    halves = [plan_set(h), plan_set(nrhs - h)]
+    for ps in halves:
+        for pl in ps:
+            pl.set_launch(tuned)
+    fs, us = [f[:h], f[h:]], [u[:h], u[h:]]
+    main = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def two():
+        for s in streams:
+            s.wait_stream(main)
+        for k in range(len(omegas)):
+            for i in range(2):
+                halves[i][k].solve(fs[i], out=us[i], stream=streams[i])
+        for s in streams:
+            main.wait_stream(s)
+
+    t_two = timed(two)
+    same = bool(torch.equal(u, ref))
+    return {"workload": f"c5_large {p.nx}x{p.ny}x{p.nz}, {nrhs} point sources x {len(omegas)} frequencies, c128",
+            "tuned": tuned,
+            "one_stream": {"value": per_step / t_one, "ms_per_step": t_one * 1e3},
+            "two_streams_8_plus_8": {"value": per_step / t_two, "ms_per_step": t_two * 1e3},
+            "speedup": t_one / t_two, "bitwise_equal": same}
+
+
+def bench_c2(steps, warmup, args, with_oracle, precs=("c128", "mixed")):
     """The 287 x 287 x 200 decomposed grid (one centre point source): tuned
     complex128 and mixed plans, stage tables, oracle errors."""
     import torch
@@ -625,9 +769,9 @@ def bench_c2(steps, warmup, args, with_oracle):
                        f"PML {args.pml}/side, {args.layers} layers, centre point source",
            "unknowns": p.unknowns, "nrhs": nrhs}
     us = {}
-    for prec in ("c128", "mixed"):
+    for prec in precs:
         plan = hs.Plan(p, prec, max_rhs=nrhs, refine_steps=args.refine_steps if prec == "mixed" else 0)
-        tuned = plan.tune(nrhs)
+        tuned = plan.tune(nrhs, cache=TUNE_CACHE)
         u = torch.empty_like(f)
         dt, stages, dom = time_plans([plan], f, u, steps, warmup)
         us[prec] = u.cpu().numpy()
@@ -635,11 +779,12 @@ def bench_c2(steps, warmup, args, with_oracle):
                      "roofline": roofline(dom, prec),
                      "stages_ms_per_step": {r["name"]: round(r["ms"], 4) for r in stages}}
         del plan
-    out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    if "mixed" in out and "c128" in out:
+        out["mixed_speedup_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
     if with_oracle:
         from oracle import separable
         ref = separable.solve(p, f_np)
-        for prec in ("c128", "mixed"):
+        for prec in precs:
             out[prec]["rel_err_vs_oracle"] = errors_vs(us[prec][0], ref[0], p)
     return out
 
@@ -724,17 +869,24 @@ def main():
     ap.add_argument("--counters-workload", choices=["c5", "c2"], default="c5")
     ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "CFETCH", "CWRITE"),
                     help="write profiles/pmc_traffic.json from four rocprofv3 --pmc output folders")
+    ap.add_argument("--c2-only", choices=["c128", "mixed", "both"],
+                    help="time only the 287x287x200 decomposed grid (no oracle): for kernel traces")
     ap.add_argument("--c3-only", choices=["c128", "mixed", "both"], help="time only the 64-block batch")
     ap.add_argument("--c4-only", action="store_true", help="time only the adjoint gradient (128x128x160)")
     ap.add_argument("--gridding-b-only", action="store_true",
                     help="time only the 575x575x256 grid split 24x24 on graded steps")
     ap.add_argument("--c5-only", choices=["c128", "mixed", "both"],
                     help="time only the headline workload (no oracle): for kernel traces")
+    ap.add_argument("--c5-streams", action="store_true",
+                    help="the headline workload (complex128) as two 8-source halves on two streams")
     ap.add_argument("--tune-cache", help="JSON-lines cache of tuned launch shapes (read, else written)")
     ap.add_argument("--stats-summary", nargs=3, metavar=("TRACE_CSV", "TITLE", "COMMAND"),
                     help="print a text summary of a rocprofv3 kernel trace")
     ap.add_argument("--sq-summary", nargs=2, metavar=("SQ1", "SQ2"),
                     help="print a per-kernel summary of two rocprofv3 --pmc runs of the SQ counter sets")
+    ap.add_argument("--mfma-summary", nargs="+", metavar="P PMC TRACE",
+                    help="print the issued matrix-core rate per kernel from (precision, --pmc folder, "
+                         "kernel-trace folder) triples")
     ap.add_argument("--stage-labels", action="store_true",
                     help="with --stats-summary: list the z sweeps of decomposed solves by stage")
     args = ap.parse_args()
@@ -748,6 +900,9 @@ def main():
         return
     if args.sq_summary:
         sq_summary(*args.sq_summary)
+        return
+    if args.mfma_summary:
+        mfma_summary(args.mfma_summary)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -763,6 +918,10 @@ def main():
     if args.counters:
         counters_run(args)
         return
+    if args.c2_only:
+        precs = ("c128", "mixed") if args.c2_only == "both" else (args.c2_only,)
+        print(json.dumps(bench_c2(max(1, args.steps), args.warmup, args, False, precs=precs)), flush=True)
+        return
     if args.c3_only:
         precs = ("c128", "mixed") if args.c3_only == "both" else (args.c3_only,)
         print(json.dumps(bench_c3(args.c3_steps, 1, False, precs=precs, refine_steps=args.refine_steps)), flush=True)
@@ -773,6 +932,9 @@ def main():
     if args.gridding_b_only:
         print(json.dumps(bench_gridding_b(max(1, args.steps), args.warmup, not args.no_cpu_baseline,
                                           refine_steps=args.refine_steps)), flush=True)
+        return
+    if args.c5_streams:
+        print(json.dumps(bench_c5_streams(max(1, args.steps), args.warmup)), flush=True)
         return
     if args.c5_only:
         precs = ("c128", "mixed") if args.c5_only == "both" else (args.c5_only,)
