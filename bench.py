@@ -243,6 +243,26 @@ def sq_summary(dir1, dir2):
               f"{d['SQ_LDS_BANK_CONFLICT'] / max(d['SQ_INSTS_LDS'], 1):5.2f}  {name}")
 
 
+def short_mangled(name):
+    """Kernel name and template arguments read from a mangled name that
+    c++filt leaves as it is (kernels over _Float16 vectors)."""
+    import re
+    m = re.search(r"\d+(k_[a-z0-9_]+)I(.*?)EEvP", name)
+    if not m:
+        return name
+    args = []
+    for t in re.finditer(r"Lb([01])E|Li(\d+)E|(?:\d+HIP_vector_type|S\d*_)I([fd])Lj2EE|S\d*_", m.group(2)):
+        if t.group(1) is not None:
+            args.append("true" if t.group(1) == "1" else "false")
+        elif t.group(2) is not None:
+            args.append(t.group(2))
+        elif t.group(3) is not None:
+            args.append("float2" if t.group(3) == "f" else "double2")
+        else:
+            args.append("same type")
+    return f"{m.group(1)}<{', '.join(args)}>"
+
+
 MFMA_COUNTERS = "SQ_VALU_MFMA_BUSY_CYCLES SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F16 SQ_BUSY_CU_CYCLES GRBM_GUI_ACTIVE"
 
 
@@ -260,21 +280,24 @@ def mfma_summary(triples):
     def norm(name):
         if name.startswith("_Z"):
             try:
-                name = subprocess.run(["c++filt", name], capture_output=True, text=True).stdout.strip() or name
+                dem = subprocess.run(["c++filt", name], capture_output=True, text=True).stdout.strip()
             except OSError:
-                pass
+                dem = ""
+            name = dem if dem and not dem.startswith("_Z") else short_mangled(name)
         name = name.replace("hs::(anonymous namespace)::", "").replace("void ", "")
         name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", name)
         return re.sub(r"\(.*", "", name)
 
+    tc = f" --tune-cache {TUNE_CACHE}" if TUNE_CACHE else ""
     print("# rocprofv3 MFMA counters: batched 64 blocks x 8 RHS (one warm-up + one timed solve), dense transform kernels")
-    print("# commands (R = repository root), per precision P in {c128, mixed}:")
-    print(f"#   cd /tmp && export TMPDIR=/tmp && timeout -s KILL 180 rocprofv3 --pmc {MFMA_COUNTERS} --output-format csv "
-          "-d $R/gpurun_out/mfma/c3_P -o run -- python3 $R/bench.py --c3-only P --c3-steps 1")
-    print("#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --output-format csv -d $R/gpurun_out/mfma/c3_P_kt "
-          "-o run -- python3 $R/bench.py --c3-only P --c3-steps 1")
-    print("# summary: python3 $R/bench.py --mfma-summary c128 gpurun_out/mfma/c3_c128 gpurun_out/mfma/c3_c128_kt "
-          "mixed gpurun_out/mfma/c3_mixed gpurun_out/mfma/c3_mixed_kt")
+    print("# commands (R = repository root), per precision:")
+    for i in range(0, len(triples), 3):
+        prec, pmc, kt = triples[i:i + 3]
+        print(f"#   cd /tmp && export TMPDIR=/tmp && timeout -s KILL 180 rocprofv3 --pmc {MFMA_COUNTERS} --output-format csv "
+              f"-d $R/{pmc} -o run -- python3 $R/bench.py --c3-only {prec} --c3-steps 1{tc}")
+        print(f"#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --output-format csv -d $R/{kt} "
+              f"-o run -- python3 $R/bench.py --c3-only {prec} --c3-steps 1{tc}")
+    print("# summary: python3 $R/bench.py" + tc + " --mfma-summary " + " ".join(triples))
     print("# issued matrix flop/s = 512 * SQ_INSTS_VALU_MFMA_MOPS_<type> / (kernel-trace duration); "
           "peaks (dense): FP64 78.6, fp16 2500 TFLOP/s")
     print("# split-fp16 kernels issue three fp16 products per FP32-class product")
@@ -328,7 +351,10 @@ def stats_summary(trace_csv: str, title: str, command: str, stage_labels: bool =
     with open(trace_csv) as fh:
         rows = sorted(csv.DictReader(fh), key=lambda r: int(r["Start_Timestamp"]))
         for r in rows:
-            name = r["Kernel_Name"].replace("hs::(anonymous namespace)::", "")
+            name = r["Kernel_Name"]
+            if name.startswith("_Z"):
+                name = short_mangled(name)
+            name = name.replace("hs::(anonymous namespace)::", "")
             name = re.sub(r"HIP_vector_type<(\w+), 2u>", r"\g<1>2", name)
             name = re.sub(r"\(hs::.*|\(.*", "", name).replace("void ", "")
             grid = "x".join(r["Grid_Size_" + a] for a in "XYZ")
