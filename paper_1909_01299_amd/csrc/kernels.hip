@@ -737,6 +737,28 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 }
 
 
+// v from the lane that DPP control CTRL names (quad permutes, row mirrors,
+// row broadcasts); rows outside ROWS get zero.
+template <int CTRL, int ROWS, typename R>
+__device__ __forceinline__ R dpp_take(R v) {
+  return __builtin_amdgcn_update_dpp(R(0), v, CTRL, ROWS, 0xf, false);
+}
+// Sum of v over aligned groups of L lanes (L a power of two, at most 64; a
+// wave-uniform value): pairs, quads, half-rows and rows of 16 by lane
+// permutations (every lane of a group of up to 16 then holds its sum), then
+// the broadcasts of lane 15 into the next row and of lane 31 into rows 2 and
+// 3.  The sum is in the group's last lane in every case.
+template <typename C>
+__device__ __forceinline__ C group_sum_dpp(C v, int L) {
+  if (L > 1) { v.x += dpp_take<0xB1, 0xf>(v.x); v.y += dpp_take<0xB1, 0xf>(v.y); }     // lane ^ 1
+  if (L > 2) { v.x += dpp_take<0x4E, 0xf>(v.x); v.y += dpp_take<0x4E, 0xf>(v.y); }     // lane ^ 2
+  if (L > 4) { v.x += dpp_take<0x141, 0xf>(v.x); v.y += dpp_take<0x141, 0xf>(v.y); }   // 7 - lane in 8
+  if (L > 8) { v.x += dpp_take<0x140, 0xf>(v.x); v.y += dpp_take<0x140, 0xf>(v.y); }   // 15 - lane in 16
+  if (L > 16) { v.x += dpp_take<0x142, 0xa>(v.x); v.y += dpp_take<0x142, 0xa>(v.y); }  // lane 15 -> next row
+  if (L > 32) { v.x += dpp_take<0x143, 0xc>(v.x); v.y += dpp_take<0x143, 0xc>(v.y); }  // lane 31 -> rows 2, 3
+  return v;
+}
+
 // Fused contraction over both axes of a plane X(r,z,b,a) (a contiguous): one
 // workgroup reads the rows b of one slab of one z plane once and forms
 //   out_x,t(b) = sum_a cx_t[a] X(b,a)   (complete in the workgroup)
@@ -745,9 +767,11 @@ __global__ __launch_bounds__(256) void k_psweep(const SweepDesc* __restrict__ de
 // holding SMAX >= ceil(na / L) columns; a wave holds 64 / L rows at a time.
 // Coefficients are staged in LDS, zero past na, so every lane loads from a
 // valid (clamped) column and all loads of U rows are in flight together.
-// With full-wave rows the x sums of the U rows are reduced together: the
-// first butterfly steps exchange half of the rows each (transposed
-// reduction), so 4 rows cost 7 exchanges instead of 24 (2 rows: 6, not 12).
+// The x sums of a row reduce over its L lanes by DPP moves (VALU latency,
+// where shuffles through the LDS crossbar would each wait a round trip).
+// Without prefetching, full-wave rows are first exchanged across 32 and 16
+// lanes (transposed: each exchange keeps half of the rows), which spends
+// fewer VALU cycles on several terms than one DPP chain per row.
 template <typename R, int SMAX, int NT, bool PF>
 __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict__ descs, int max_slab, int max_cs,
                                                   const cplx<R>* __restrict__ tab, cplx<R>* __restrict__ ws) {
@@ -791,8 +815,6 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   int col[SMAX];
 #pragma unroll
   for (int s = 0; s < SMAX; ++s) col[s] = min(la + s * L, na - 1);
-  const bool full = L == 64;
-  const bool hi5 = (lane & 32) != 0, hi4 = (lane & 16) != 0;
   // x sums of this column slab: final, or a partial added by the second pass
   auto xout = [&](int t) -> int64_t {
     return d.ncs > 1 ? d.xpart + (int64_t)r * d.xpart_r + (int64_t)cs * d.xpart_s + t * d.xpart_t +
@@ -847,9 +869,13 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
 #pragma unroll
           for (int s = 0; s < SMAX; ++s) p[u] = cfma(cxs[t * SW + la + s * L], xv[u][s], p[u]);
         }
-        if (full) {
+        if (!PF && L == 64) {
+          // full-wave rows, reduced together: the exchanges across 32 and 16
+          // lanes each keep half of the rows (transposed), then DPP within
+          // the rows of 16 lanes
           C v;
           int ur;
+          const bool hi5 = (lane & 32) != 0, hi4 = (lane & 16) != 0;
           if constexpr (U == 4) {
             // rows {0,1} stay in the low half-wave, rows {2,3} in the high one
             const C q0 = cadd(hi5 ? p[2] : p[0], shfl_xor_c(hi5 ? p[0] : p[2], 32, 64));
@@ -863,22 +889,17 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
             v = cadd(v, shfl_xor_c(v, 16, 64));
             ur = hi5 ? 1 : 0;
           }
-#pragma unroll
-          for (int m = 8; m >= 1; m >>= 1) v = cadd(v, shfl_xor_c(v, m, 64));
+          v = group_sum_dpp(v, 16);
           const int bi = i0 + ur * RG;
-          const bool wr = U == 4 ? (lane & 15) == 0 : (lane & 31) == 0;
+          const bool wr = U == 4 ? (lane & 15) == 15 : (lane & 31) == 31;
           if (wr && bi < nrow) ws[xout(t) + b0 + bi] = v;
         } else {
+          // each row's sum over its L lanes by DPP moves, in the group's last lane
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            C v = p[u];
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) {
-              const C o = shfl_xor_c(v, m, 64);
-              if (m < L) v = cadd(v, o);
-            }
+            const C v = group_sum_dpp(p[u], L);
             const int bi = i0 + u * RG;
-            if (la == 0 && bi < nrow) ws[xout(t) + b0 + bi] = v;
+            if (la == L - 1 && bi < nrow) ws[xout(t) + b0 + bi] = v;
           }
         }
       }
