@@ -117,6 +117,9 @@ struct DstDesc {
 // (rows and z planes may be padded, rs >= na and plane >= nb*rs, so that
 // tiles of modes start on whole cache lines).
 constexpr int kMaxTerms = 4;
+// separators of each axis per interface-contraction descriptor (one read of
+// the global spectral array serves this many)
+constexpr int kMaxContractTerms = 8;
 constexpr int kMaxRefine = 16;   // refinement steps of the complex64 path
 struct SweepDesc {
   int32_t na, nb, nz, dense_in;
@@ -149,8 +152,8 @@ struct ContractDesc {
   int32_t na, nb, nz, nxt, nyt, nslab, rows, ncs;
   int32_t cols, rs;               // rs: row stride of X (>= na)
   int64_t src, src_r;
-  int64_t cx[kMaxTerms], cy[kMaxTerms];   // table offsets
-  int32_t cx_stride[kMaxTerms], cy_stride[kMaxTerms];
+  int64_t cx[kMaxContractTerms], cy[kMaxContractTerms];   // table offsets
+  int32_t cx_stride[kMaxContractTerms], cy_stride[kMaxContractTerms];
   int64_t dx, dx_t, dx_r, dx_z;
   int64_t dy, dy_t, dy_r, dy_z;
   int64_t part, part_s, part_t, part_r, part_z;

@@ -778,7 +778,7 @@ __global__ __launch_bounds__(256) void k_contract(const ContractDesc* __restrict
   using C = cplx<R>;
   constexpr int U = SMAX <= 2 ? 4 : 2;
   constexpr int SW = SMAX * 64;   // LDS stride of one x term
-  static_assert(NT <= kMaxTerms, "term count");
+  static_assert(NT <= kMaxContractTerms, "term count");
   extern __shared__ unsigned char smem_raw[];
   const ContractDesc d = descs[blockIdx.y];
   const int z = blockIdx.x / (max_slab * max_cs);
@@ -1718,12 +1718,14 @@ void sweep(int prec, const SweepDesc* d, int ndesc, int64_t max_modes, int max_n
 #undef HS_PSWEEP_L
 }
 
-void contract_split(ContractDesc& d) {
+void contract_split(ContractDesc& d, int terms) {
   // at most 256 columns per workgroup (4 per lane, which keeps the kernel at
-  // three waves per SIMD); about 16K elements per workgroup: whole planes for
-  // blocks, row slabs for the global plane so that there are enough
-  // workgroups to fill the chip
-  d.ncs = (d.na + 255) / 256;
+  // three waves per SIMD), 128 with more than 4 terms (their accumulators);
+  // about 16K elements per workgroup: whole planes for blocks, row slabs for
+  // the global plane so that there are enough workgroups to fill the chip
+  const int nt = std::max(terms, std::max(d.nxt, d.nyt));
+  const int cmax = nt > kMaxTerms ? 128 : 256;
+  d.ncs = (d.na + cmax - 1) / cmax;
   d.cols = (d.na + d.ncs - 1) / d.ncs;
   const int64_t elems = (int64_t)d.cols * d.nb;
   int nslab = int(std::max<int64_t>(1, std::min<int64_t>(d.nb, (elems + 16383) / 16384)));
@@ -1751,7 +1753,7 @@ ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec) {
     const int64_t fin = (d[i].nslab > 1 ? (int64_t)d[i].nyt * d[i].nz * d[i].na : 0) +
                         (d[i].ncs > 1 ? (int64_t)d[i].nxt * d[i].nz * d[i].nb : 0);
     L.fin_units = std::max<int64_t>(L.fin_units, fin);
-    lds_elems = std::max<size_t>(lds_elems, size_t(d[i].nyt) * d[i].rows + 3 * kMaxTerms * 64);
+    lds_elems = std::max<size_t>(lds_elems, size_t(d[i].nyt) * d[i].rows + 3 * kMaxContractTerms * 64);
     lds_x = std::max<size_t>(lds_x, size_t(d[i].nxt));
     L.max_terms = std::max(L.max_terms, std::max(d[i].nxt, d[i].nyt));
   }
@@ -1775,26 +1777,38 @@ static void launch_contract(const ContractDesc* d, const ContractLaunch& L, cons
 template <typename R, int NT>
 static void contract_nt(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
                         hipStream_t st) {
-  if (L.smax <= 1)
-    launch_contract<R, 1, NT>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 2)
-    launch_contract<R, 2, NT>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 4)
-    launch_contract<R, 4, NT>(d, L, tab, ws, nrhs, st);
-  else if (L.smax <= 6)
-    launch_contract<R, 6, NT>(d, L, tab, ws, nrhs, st);
-  else
-    launch_contract<R, 8, NT>(d, L, tab, ws, nrhs, st);
+  if constexpr (NT > kMaxTerms) {
+    // descriptors of more than kMaxTerms terms hold at most 128 columns
+    if (L.smax <= 1)
+      launch_contract<R, 1, NT>(d, L, tab, ws, nrhs, st);
+    else
+      launch_contract<R, 2, NT>(d, L, tab, ws, nrhs, st);
+  } else {
+    if (L.smax <= 1)
+      launch_contract<R, 1, NT>(d, L, tab, ws, nrhs, st);
+    else if (L.smax <= 2)
+      launch_contract<R, 2, NT>(d, L, tab, ws, nrhs, st);
+    else if (L.smax <= 4)
+      launch_contract<R, 4, NT>(d, L, tab, ws, nrhs, st);
+    else if (L.smax <= 6)
+      launch_contract<R, 6, NT>(d, L, tab, ws, nrhs, st);
+    else
+      launch_contract<R, 8, NT>(d, L, tab, ws, nrhs, st);
+  }
 }
 
-// two-term sums (the four faces of a block) get their own, smaller kernels
+// two-term sums (the four faces of a block) get their own, smaller kernels;
+// more than kMaxTerms terms (interface contractions of many separators) take
+// narrow column slabs
 template <typename R>
 static void contract_r(const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
                        hipStream_t st) {
   if (L.max_terms <= 2)
     contract_nt<R, 2>(d, L, tab, ws, nrhs, st);
-  else
+  else if (L.max_terms <= kMaxTerms)
     contract_nt<R, kMaxTerms>(d, L, tab, ws, nrhs, st);
+  else
+    contract_nt<R, kMaxContractTerms>(d, L, tab, ws, nrhs, st);
 }
 
 void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,

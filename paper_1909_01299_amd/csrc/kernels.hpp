@@ -187,15 +187,17 @@ bool sweep_chunks_ok(int chunks, int nz);
 bool sweep_rows_fixed(int chunks, int nz);
 
 // Fused two-axis contractions of spectral arrays (each array read once).
-// contract_split chooses the row slabs of a descriptor (nslab, rows) from its
-// plane size; contract_launch gathers the launch shape of a descriptor list.
+// contract_split chooses the column and row slabs of a descriptor (ncs, cols,
+// nslab, rows) from its plane size and its term count (at least `terms`:
+// every descriptor of one launch must be split with the launch's largest
+// count); contract_launch gathers the launch shape of a descriptor list.
 struct ContractLaunch {
   int ndesc = 0, max_slab = 1, max_cs = 1, smax = 1, max_nz = 0;
   int max_terms = 0;       // most x or y terms of one descriptor
   int64_t fin_units = 0;   // largest count of slab sums of a split descriptor (0: none split)
   size_t lds = 0;          // dynamic LDS bytes
 };
-void contract_split(ContractDesc& d);
+void contract_split(ContractDesc& d, int terms = 0);
 ContractLaunch contract_launch(const ContractDesc* d, int ndesc, int prec);
 void contract(int prec, const ContractDesc* d, const ContractLaunch& L, const void* tab, void* ws, int nrhs,
               hipStream_t st);

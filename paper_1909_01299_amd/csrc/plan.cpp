@@ -451,15 +451,15 @@ void Plan::layout_workspace() {
   if (decomposed) {
     for (auto& B : blocks) B.vt = take(R * NZ * B.pplane);
     // slab partial sums of contractions over planes too large for one workgroup
-    auto part_elems = [&](int na, int nb, int nxt, int nyt) -> int64_t {
+    auto part_elems = [&](int na, int nb, int nxt, int nyt, int terms) -> int64_t {
       ContractDesc c{};
-      c.na = na; c.nb = nb;
-      contract_split(c);
+      c.na = na; c.nb = nb; c.nxt = nxt; c.nyt = nyt;
+      contract_split(c, terms);
       return (c.nslab > 1 ? R * c.nslab * nyt * NZ * (int64_t)na : 0) +
              (c.ncs > 1 ? R * c.ncs * nxt * NZ * (int64_t)nb : 0);
     };
     for (auto& B : blocks) {
-      const int64_t n = part_elems(B.nbx, B.nby, 2, 2);
+      const int64_t n = part_elems(B.nbx, B.nby, 2, 2, 2);
       B.cpart = n > 0 ? take(n) : 0;
     }
     const int64_t faces = (int64_t)blocks.size() * R * 4 * NZ * NF;
@@ -474,10 +474,12 @@ void Plan::layout_workspace() {
     grs = spectral_row(NX);
     gpplane = spectral_plane((int64_t)NY * grs);
     w_gspec = take(R * NZ * gpplane);
-    // the interface contraction in groups of kMaxTerms separators per axis
+    // the interface contraction in groups of kMaxContractTerms separators per
+    // axis, split as the descriptors are (sig_terms)
     int64_t np = 0;
-    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms)
-      np += part_elems(NX, NY, std::clamp(nsx - g0, 0, kMaxTerms), std::clamp(nsy - g0, 0, kMaxTerms));
+    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxContractTerms)
+      np += part_elems(NX, NY, std::clamp(nsx - g0, 0, kMaxContractTerms), std::clamp(nsy - g0, 0, kMaxContractTerms),
+                       sig_terms());
     w_cpart = np > 0 ? take(np) : 0;
     w_F = coarse ? take(R * (int64_t)NX * NY * NZ) : 0;
   }
@@ -712,13 +714,13 @@ void Plan::build_descriptors() {
     }
     d_sweepG.push_back(g);
     // w~ contracted with the rows of W at the separators: Q_x[s](b) = sum_a W_x[s][a] w~(a,b),
-    // kMaxTerms separators of each axis per descriptor
+    // kMaxContractTerms separators of each axis per descriptor
     int64_t part_off = w_cpart;
-    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxTerms) {
+    for (int g0 = 0; g0 < std::max(nsx, nsy); g0 += kMaxContractTerms) {
       ContractDesc c{};
       c.na = NX; c.nb = NY; c.nz = NZ;
-      c.nxt = std::clamp(nsx - g0, 0, kMaxTerms);
-      c.nyt = std::clamp(nsy - g0, 0, kMaxTerms);
+      c.nxt = std::clamp(nsx - g0, 0, kMaxContractTerms);
+      c.nyt = std::clamp(nsy - g0, 0, kMaxContractTerms);
       c.src = w_gspec; c.src_r = g.out_r; c.plane = gpplane; c.rs = grs;
       for (int i = 0; i < c.nxt; ++i) { c.cx[i] = GX.inv + (int64_t)sepx[g0 + i] * NX; c.cx_stride[i] = 1; }
       for (int j = 0; j < c.nyt; ++j) { c.cy[j] = GY.inv + (int64_t)sepy[g0 + j] * NY; c.cy_stride[j] = 1; }
@@ -726,7 +728,7 @@ void Plan::build_descriptors() {
       c.dx = w_Qx + (c.nxt > 0 ? g0 * c.dx_t : 0);
       c.dy_t = (int64_t)NZ * NX; c.dy_r = (int64_t)nsy * NZ * NX; c.dy_z = NX;
       c.dy = w_Qy + (c.nyt > 0 ? g0 * c.dy_t : 0);
-      contract_split(c);
+      contract_split(c, sig_terms());
       set_part(c, part_off);
       part_off += (c.nslab > 1 ? max_rhs * c.part_r : 0) + (c.ncs > 1 ? max_rhs * c.xpart_r : 0);
       d_sig.push_back(c);

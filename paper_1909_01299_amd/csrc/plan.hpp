@@ -98,6 +98,11 @@ struct Plan {
   bool decomposed = false;
   bool dense_glob = false;        // the global right-hand side is expanded densely (else low-rank terms in the z solve)
   bool glob_forced = false;       // dense expansion required: more than kMaxTerms separators on an axis, or flag bit 3
+  // separators of one axis in the largest interface-contraction descriptor;
+  // every descriptor of that launch is split for this count
+  int sig_terms() const {
+    return int(std::min<size_t>(std::max(sepx.size(), sepy.size()), size_t(kMaxContractTerms)));
+  }
   std::vector<cd> htab;          // host FP64 table image
   std::vector<_Float16> h16;     // complex64 path: split-fp16 fragment image (8 halves per unit)
   int64_t zlo = 0, zdiag = 0, zup = 0, zsig = 0;
