@@ -206,16 +206,16 @@ constexpr int YM_NC = 16;    // complex columns per workgroup
 constexpr int YM_THREADS = 512;
 constexpr int YM_WAVES = YM_THREADS / 64;
 
-// NT output tiles (rows 16 (w + 8 j), j < NT) of one wave over all of K; the
+// NT output tiles (rows 16 (w + ws j), j < NT) of one wave over all of K; the
 // table fragments of 4 k-steps are fetched one group ahead.
 template <typename R, int NT>
-__device__ __forceinline__ void y_tiles(const R* __restrict__ ft, const R* Bs, int KS, int K2, int w, int l,
+__device__ __forceinline__ void y_tiles(const R* __restrict__ ft, const R* Bs, int KS, int K2, int w, int ws, int l,
                                         cplx<R>* base, int64_t s_k, int x, bool xok) {
   using M = mfma<R>;
   using acc_t = typename M::acc;
   const R* fj[NT];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) fj[j] = ft + (int64_t)(w + YM_WAVES * j) * KS * 64 + l;
+  for (int j = 0; j < NT; ++j) fj[j] = ft + (int64_t)(w + ws * j) * KS * 64 + l;
   R acur[4][NT], anx[4][NT];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
@@ -248,7 +248,7 @@ __device__ __forceinline__ void y_tiles(const R* __restrict__ ft, const R* Bs, i
     for (int j = 0; j < NT; ++j) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int m = (w + YM_WAVES * j) * 16 + M::row(l, e);
+        const int m = (w + ws * j) * 16 + M::row(l, e);
         if (m < K2) {
           R* o = reinterpret_cast<R*>(base + (int64_t)(m >> 1) * s_k + x);
           o[m & 1] = c[j][e];
@@ -258,45 +258,61 @@ __device__ __forceinline__ void y_tiles(const R* __restrict__ ft, const R* Bs, i
   }
 }
 
-template <typename R, int TPW>   // TPW: most 16-row output tiles per wave
+// G panels (16 columns of one plane each) per workgroup: with G > 1 the
+// waves split into G teams of 8 / G, team g takes panel blockIdx.x * G + g
+// (short axes have fewer output tiles than a workgroup has waves).
+template <typename R, int TPW, int G>   // TPW: most 16-row output tiles per wave
 __global__ __launch_bounds__(YM_THREADS) void k_xform_y_mfma(const XformYDesc* __restrict__ descs,
                                                             const cplx<R>* __restrict__ tab,
                                                             cplx<R>* __restrict__ ws) {
+  static_assert(G == 1 || G == 2 || G == 4, "panels per workgroup");
+  constexpr int TW = YM_WAVES / G;   // waves per panel
   extern __shared__ unsigned char smem_raw[];
-  R* Bs = reinterpret_cast<R*>(smem_raw);   // [KS*4][YM_NC]
   const XformYDesc d = descs[blockIdx.y];
   const int r = blockIdx.z;
   const int cblocks = (d.ncols + YM_NC - 1) / YM_NC;
-  const int p = blockIdx.x / cblocks, cb = blockIdx.x % cblocks;
-  if (p >= d.P) return;
+  const int64_t npan = (int64_t)cblocks * d.P;
+  const int64_t pan0 = (int64_t)blockIdx.x * G;
+  if (pan0 >= npan) return;
   const int n = d.n;
   const int K2 = 2 * n;
   const int KS = ((K2 + 15) / 16) * 4;     // a multiple of 4
   const int MT = (K2 + 15) / 16;
+  const int PS = KS * 4 * YM_NC;           // LDS reals of one panel
+  R* Bs0 = reinterpret_cast<R*>(smem_raw);   // [G][KS*4][YM_NC]
   const R* ft = reinterpret_cast<const R*>(tab + d.ftab);
-  cplx<R>* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
-  const int x0 = cb * YM_NC;
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
 
-  // the whole K extent of the 16 columns into LDS (rows past 2n are zero)
-  for (int e = tid; e < KS * 2 * YM_NC; e += YM_THREADS) {
-    const int i = e / YM_NC, col = e % YM_NC;
-    const int x = x0 + col;
+  // the whole K extent of each panel's 16 columns into LDS (rows past 2n and
+  // panels past the last are zero)
+  for (int e = tid; e < G * KS * 2 * YM_NC; e += YM_THREADS) {
+    const int g = e / (KS * 2 * YM_NC), e2 = e % (KS * 2 * YM_NC);
+    const int i = e2 / YM_NC, col = e2 % YM_NC;
+    const int64_t pan = pan0 + g;
     cplx<R> v = mk<R>(0, 0);
-    if (i < n && x < d.ncols) v = base[(int64_t)i * d.s_k + x];
-    Bs[(2 * i) * YM_NC + col] = v.x;
-    Bs[(2 * i + 1) * YM_NC + col] = v.y;
+    if (pan < npan) {
+      const int p = int(pan / cblocks), x = int(pan % cblocks) * YM_NC + col;
+      if (i < n && x < d.ncols) v = ws[d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p + (int64_t)i * d.s_k + x];
+    }
+    Bs0[g * PS + (2 * i) * YM_NC + col] = v.x;
+    Bs0[g * PS + (2 * i + 1) * YM_NC + col] = v.y;
   }
 
   __syncthreads();
-  // this wave's output tiles: w, w + 8, ... below MT (a wave-uniform count)
-  const int ntw = MT > w ? (MT - w + YM_WAVES - 1) / YM_WAVES : 0;
+  // this wave's panel and output tiles t, t + TW, ... below MT (wave-uniform)
+  const int g = w / TW, t = w % TW;
+  const int64_t pan = pan0 + g;
+  if (pan >= npan) return;
+  const int p = int(pan / cblocks), x0 = int(pan % cblocks) * YM_NC;
+  cplx<R>* base = ws + d.data + (int64_t)r * d.s_r + (int64_t)p * d.s_p;
+  const int ntw = MT > t ? (MT - t + TW - 1) / TW : 0;
   const int x = x0 + (l & 15);
+  const R* Bs = Bs0 + g * PS;
   switch (ntw < TPW ? ntw : TPW) {
     case 0: break;
 #define HS_YCASE(N) \
-    case N: if constexpr (N <= TPW) y_tiles<R, N>(ft, Bs, KS, K2, w, l, base, d.s_k, x, x < d.ncols); break;
+    case N: if constexpr (N <= TPW) y_tiles<R, N>(ft, Bs, KS, K2, t, TW, l, base, d.s_k, x, x < d.ncols); break;
     HS_YCASE(1) HS_YCASE(2) HS_YCASE(3) HS_YCASE(4) HS_YCASE(5) HS_YCASE(6) HS_YCASE(7) HS_YCASE(8)
 #undef HS_YCASE
     default: break;
@@ -805,20 +821,36 @@ void xform_y_mfma(int prec, const XformYDesc* d, int ndesc, int max_n, int max_t
                          st, d, (const float2*)tab, (float2*)ws);
     return;
   }
-  // output tiles per wave: ceil(2 max_n / 16 / 8) <= 4 (n <= 256) or 8 (n <= 512)
+  // output tiles per wave: ceil(2 max_n / 16 / 8) <= 4 (n <= 256) or 8 (n <= 512);
+  // axes of at most 2 (4) output tiles put 4 (2) panels in a workgroup
   const size_t rows = size_t((2 * max_n + 15) / 16) * 16;
-  const dim3 grid(max_tiles, ndesc, nrhs);
+  const int mt = (2 * max_n + 15) / 16;
+  const int G = mt <= 2 ? 4 : mt <= 4 ? 2 : 1;
+  const dim3 grid((max_tiles + G - 1) / G, ndesc, nrhs);
+  const size_t csz = prec == 0 ? sizeof(double) : sizeof(float);
+  const size_t lds = G * rows * YM_NC * csz;
   if (prec == 0) {
-    const size_t lds = rows * YM_NC * sizeof(double);
-    hipLaunchKernelGGL((k_xform_y_mfma<double, 4>), grid, dim3(YM_THREADS), lds, st, d, (const double2*)tab,
-                       (double2*)ws);
+    if (G == 4)
+      hipLaunchKernelGGL((k_xform_y_mfma<double, 1, 4>), grid, dim3(YM_THREADS), lds, st, d, (const double2*)tab,
+                         (double2*)ws);
+    else if (G == 2)
+      hipLaunchKernelGGL((k_xform_y_mfma<double, 1, 2>), grid, dim3(YM_THREADS), lds, st, d, (const double2*)tab,
+                         (double2*)ws);
+    else
+      hipLaunchKernelGGL((k_xform_y_mfma<double, 4, 1>), grid, dim3(YM_THREADS), lds, st, d, (const double2*)tab,
+                         (double2*)ws);
   } else {
-    const size_t lds = rows * YM_NC * sizeof(float);
-    if (max_n <= 256)
-      hipLaunchKernelGGL((k_xform_y_mfma<float, 4>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+    if (G == 4)
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 1, 4>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+                         (float2*)ws);
+    else if (G == 2)
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 1, 2>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+                         (float2*)ws);
+    else if (max_n <= 256)
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 4, 1>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
                          (float2*)ws);
     else
-      hipLaunchKernelGGL((k_xform_y_mfma<float, 8>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
+      hipLaunchKernelGGL((k_xform_y_mfma<float, 8, 1>), grid, dim3(YM_THREADS), lds, st, d, (const float2*)tab,
                          (float2*)ws);
   }
 }
