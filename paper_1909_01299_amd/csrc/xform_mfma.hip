@@ -717,8 +717,9 @@ void mfma_table_build(const std::complex<double>* T, int n_out, int n_in, double
 
 bool xform_lines_use_mfma(const XformDesc& d) {
   // matrix cores for long lines in numbers that fill the chip (per right-hand
-  // side, so a block takes the same kernel alone and in a batch)
-  return std::max(d.n_in, d.n_out) >= 24 && (int64_t)d.P * d.Q >= 1024;
+  // side, so a block takes the same kernel alone and in a batch; 512 lines
+  // are the two faces of a block over 256 planes)
+  return std::max(d.n_in, d.n_out) >= 24 && (int64_t)d.P * d.Q >= 512;
 }
 
 LinesLaunch xform_lines_launch(const XformDesc* d, int ndesc, bool mfma, bool real) {
@@ -866,7 +867,10 @@ static int lines_group(const XformDesc& d) {
 }
 static int y_group(int prec, const XformYDesc& d) {
   if (!xform_y_use_mfma(prec, d.n)) return 6;
-  if (d.htab >= 0) return (d.real_tab ? 0 : 2) + (h3_width(d) == 4 ? 0 : 1);
+  // short embedded axes (at most 3 output tiles) go to the compute-precision
+  // kernel, which puts several panels in a workgroup (measured: faster at 23
+  // nodes, slower than the split-fp16 kernel at 31)
+  if (d.htab >= 0 && (d.real_tab || d.n > 24)) return (d.real_tab ? 0 : 2) + (h3_width(d) == 4 ? 0 : 1);
   return d.real_tab ? 4 : 5;
 }
 
