@@ -422,6 +422,12 @@ def test_mixed_precision_decomposed(hs):
     dict(nx=100, ny=40, nz=33, pml_x=0, pml_y=6),
     # narrow block: complex FMA tiles along x, matrix cores along y
     dict(nx=20, ny=64, nz=70, pml_x=3, pml_y=0),
+    # short stretched y axes: 16 nodes (two output tiles, four panels per
+    # workgroup), 23 (three tiles, two panels; complex64 on FP32 matrix cores)
+    # and 31 (four tiles, two panels; complex64 on split-fp16)
+    dict(nx=33, ny=16, nz=20, pml_x=4, pml_y=3),
+    dict(nx=40, ny=23, nz=24, pml_x=0, pml_y=4),
+    dict(nx=28, ny=31, nz=20, pml_x=4, pml_y=4),
 ])
 def test_dense_transform_kernels_vs_oracle(hs, prec, tol, cfg):
     """Each dense-transform kernel family (real table, embedded complex table,
