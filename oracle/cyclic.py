@@ -13,7 +13,7 @@ the local correction of eq. (7)), in the paper's order:
 7.   u = v + w inside the blocks and u = w on Sigma.
 
 `nested` is the multi-level form of the remark that follows the cost
-estimate in Sec. 2: mutually embedded partitions, with step 5 of one level
+estimate in Sec. 2: nested partitions, with step 5 of one level
 solved by the same seven steps on the next coarser partition.
 
 Blocks are the maximal runs of interior nodes between separator planes (a

@@ -1,4 +1,4 @@
-"""Multi-level cyclic reduction on mutually embedded partitions (through the
+"""Multi-level cyclic reduction on nested partitions (through the
 C ABI): a plan whose interface problem (Alg. step 5) is solved by the cyclic
 reduction of a coarser plan on the same grid, to any depth, against the
 oracle in both precisions; the coarsest level a single block; k^2 updates

@@ -273,7 +273,7 @@ def test_seven_step_gridding_b_matches_sparse_lu():
 
 
 def test_nested_partitions_match_sparse_lu():
-    """Multi-level cyclic reduction on mutually embedded partitions: three
+    """Multi-level cyclic reduction on nested partitions: three
     levels (5 x 4 separators, then 2 x 2 of them, then one each) and two
     levels ending in a single block reproduce the direct solve."""
     rng = _rng(23)
