@@ -887,6 +887,8 @@ def main():
     ap.add_argument("--nz", type=int, default=200)
     ap.add_argument("--layers", type=int, default=20)
     ap.add_argument("--no-extras", action="store_true", help="headline only (no c2, c3, c4 workloads)")
+    ap.add_argument("--no-streams", action="store_true",
+                    help="skip the extra record of the headline workload as two halves on two streams")
     ap.add_argument("--c3-steps", type=int, default=5)
     ap.add_argument("--refine-steps", type=int, default=1,
                     help="FP64-residual refinement steps of the mixed-precision solves (-1: none)")
@@ -987,6 +989,10 @@ def main():
         print(json.dumps({"progress": "c4 done"}), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         extras["gridding_b"] = bench_gridding_b(3, 1, with_oracle, refine_steps=args.refine_steps)
+        print(json.dumps({"progress": "gridding B done"}), file=sys.stderr, flush=True)
+    if not args.no_extras and not args.no_streams:
+        torch.cuda.empty_cache()
+        extras["c5_two_streams"] = bench_c5_streams(3, 1)
 
     c128 = c5["c128"]
     rf = c128["roofline"]
