@@ -178,23 +178,64 @@ __global__ __launch_bounds__(16 * LT) void k_dst(const DstDesc* __restrict__ des
   const int p = gc / d.Q, q = gc % d.Q;
   const CI* sl = src + d.src + (int64_t)r * d.src_r + (int64_t)p * d.src_p + (int64_t)q * d.src_q;
   // y_j, j = t + 16 v, from x_j (element j - 1) and x_{N-j} (element N - j - 1);
-  // j = 0 loads element 0 and is zeroed, so all loads are in flight together
+  // j = 0 loads element 0 (unused).  Contiguous lines (a line's lanes in one
+  // wave) with V <= 16 load each element once and stage it in the line's LDS
+  // row at slot e + e / 16, where the lane of j reads x_{N-j}.  Other lines
+  // load x_{N-j} as well: in FP64 after every x_j load is issued (these
+  // workgroups are held to two waves per SIMD by their LDS, so the registers
+  // that takes cost no occupancy), in FP32 pair by pair (measured faster
+  // there).  `along` is uniform over the workgroup.
+  C* crow = row + li * XS;
   C a[V];
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
+  auto combine = [&](int v, const C& x1, const C& x2) {
     const int j = t + 16 * v;
-    const int e1 = j >= 1 ? j - 1 : 0, e2 = j >= 1 ? N - j - 1 : 0;
-    const C x1 = cvt<C>(sl[(int64_t)e1 * d.src_i]);
-    const C x2 = cvt<C>(sl[(int64_t)e2 * d.src_i]);
     const R sn = -tw[j * (TW_N / (2 * N))].y;   // sin(pi j / N)
     const R on = (ok && j >= 1) ? R(1) : R(0);
     a[v].x = on * fma(sn, x1.x + x2.x, R(0.5) * (x1.x - x2.x));
     a[v].y = on * fma(sn, x1.y + x2.y, R(0.5) * (x1.y - x2.y));
+  };
+  auto e1_of = [&](int v) { const int j = t + 16 * v; return j >= 1 ? j - 1 : 0; };
+  auto e2_of = [&](int v) { const int j = t + 16 * v; return j >= 1 ? N - j - 1 : 0; };
+  auto staged = [&]() {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = t + 16 * v;
+      if (j >= 1) crow[(j - 1) + (j - 1) / 16] = a[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int e2 = e2_of(v);
+      combine(v, a[v], crow[e2 + e2 / 16]);
+    }
+    __syncthreads();   // every read of the staged line is done before the row is reused
+  };
+  if constexpr (sizeof(R) == 8) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) a[v] = cvt<C>(sl[(int64_t)e1_of(v) * d.src_i]);
+    if (V <= 16 && along) {
+      staged();
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) combine(v, a[v], cvt<C>(sl[(int64_t)e2_of(v) * d.src_i]));
+    }
+  } else {
+    if (V <= 16 && along) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) a[v] = cvt<C>(sl[(int64_t)e1_of(v) * d.src_i]);
+      staged();
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const C x1 = cvt<C>(sl[(int64_t)e1_of(v) * d.src_i]);
+        const C x2 = cvt<C>(sl[(int64_t)e2_of(v) * d.src_i]);
+        combine(v, x1, x2);
+      }
+    }
   }
   fft_reg<C, V>(a, tw);
 #pragma unroll
   for (int k2 = 1; k2 < V; ++k2) a[k2] = cmul(a[k2], tw[((t * k2) % N) * (TW_N / N)]);
-  C* crow = row + li * XS;
 #pragma unroll
   for (int k2 = 0; k2 < V; ++k2) crow[k2 * 17 + t] = a[k2];
   __syncthreads();
